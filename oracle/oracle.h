@@ -1,0 +1,110 @@
+/*
+ * CPU oracle for the SMMO object heap and parallel do-all
+ * (DynaSOAr, arXiv 1809.07444).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, sequential statement of
+ * what the device path must compute.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it; the product path never
+ * links, imports or calls it, and it shares no source with the device code.
+ *
+ * Parts:
+ *   - hierarchical bitmap model (paper Sec. 3, Alg. 2; operations of Sec. 2.1),
+ *     with a configurable container width so the paper's width-4 example
+ *     (Fig. "bitmap clear example") can be replayed exactly;
+ *   - sequential heap model (Sec. 2: block states; Sec. 2.2, Alg. 1), which
+ *     gives the ideal (fully dense) block usage and checks state invariants;
+ *   - workload references: the alloc/do-all microbenchmark, Game of Life
+ *     (dense B3/S23 torus), and the Sugarscape-style agent model.
+ */
+#ifndef DSOAR_ORACLE_H
+#define DSOAR_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_LEVELS 12
+#define ORC_MAX_TYPES 8
+#define ORC_FAIL (-1)
+
+/* ------------------------------------------------------------------ RNG -- */
+uint64_t orc_mix64(uint64_t z);
+uint64_t orc_hash(uint64_t seed, uint64_t stream, uint64_t a, uint64_t b);
+int32_t orc_uniform_int(uint64_t h, int32_t lo, int32_t hi);
+
+/* ------------------------------------------------------ hierarchical bitmap */
+typedef struct {
+  int width;                        /* bits per container (64 in the heap) */
+  int nlevels;                      /* level 0 = the bitmap itself */
+  int64_t nbits[ORC_MAX_LEVELS];
+  int64_t nwords[ORC_MAX_LEVELS];
+  uint64_t *words[ORC_MAX_LEVELS];
+  /* Every successful clear, as level * 2^40 + position, in order. */
+  int64_t *trace;
+  int64_t ntrace, trace_cap;
+} orc_bitmap;
+
+int orc_bm_init(orc_bitmap *b, int64_t nbits, int width, int all_set);
+void orc_bm_free(orc_bitmap *b);
+int orc_bm_get(const orc_bitmap *b, int level, int64_t pos);
+int orc_bm_try_clear(orc_bitmap *b, int level, int64_t pos);
+int orc_bm_try_set(orc_bitmap *b, int level, int64_t pos);
+int orc_bm_clear(orc_bitmap *b, int level, int64_t pos);
+int orc_bm_set(orc_bitmap *b, int level, int64_t pos);
+int64_t orc_bm_try_find_set(const orc_bitmap *b);
+int64_t orc_bm_find_clear(orc_bitmap *b);
+int64_t orc_bm_consistency_violations(const orc_bitmap *b);
+
+/* Flat handle-based wrappers for ctypes. */
+void *orc_bm_new(int64_t nbits, int width, int all_set);
+void orc_bm_delete(void *b);
+int orc_bm_nlevels(void *b);
+int64_t orc_bm_nwords(void *b, int level);
+void orc_bm_words(void *b, int level, uint64_t *out);
+int64_t orc_bm_trace(void *b, int64_t *out, int64_t cap);
+int orc_bm_op(void *b, int op, int64_t pos, int64_t *result);
+
+/* ---------------------------------------------------------- heap model --- */
+void *orc_heap_new(int32_t num_blocks, int32_t capacity, int32_t num_types);
+void orc_heap_delete(void *h);
+int64_t orc_heap_alloc(void *h, int32_t type);
+int orc_heap_free(void *h, int64_t handle);
+int64_t orc_heap_reclaim(void *h);
+int64_t orc_heap_check(void *h);
+void orc_heap_counts(void *h, int64_t *out);
+void orc_heap_dump(void *h, uint64_t *obj_bitmap, int32_t *block_type);
+
+/* ------------------------------------------------------------- micro ----- */
+int orc_micro_run(int32_t n_init, int32_t steps, int32_t n_renew,
+                  const float *x0, const float *v0,
+                  const float *xs, const float *vs,
+                  float *out_x, float *out_v, uint8_t *out_present,
+                  int64_t *counts);
+
+/* ------------------------------------------------------- game of life ---- */
+int orc_gol_step(int32_t width, int32_t height, const uint8_t *in, uint8_t *out,
+                 int64_t *counts);
+int orc_gol_run(int32_t width, int32_t height, int32_t generations,
+                uint8_t *grid, int64_t *per_generation_counts);
+
+/* ---------------------------------------------------------- sugarscape --- */
+typedef struct {
+  int32_t max_age;
+  int32_t repro_min;
+  int32_t fertile_min;
+  int32_t fertile_max;
+} orc_sugar_rules;
+
+/* Grids are side*side, row-major; agent arrays are indexed by cell and valid
+ * where occ[cell] != 0.  counts: [births, deaths, moves] accumulated. */
+int orc_sugar_run(int32_t side, int32_t steps, int32_t step0, uint64_t seed,
+                  const orc_sugar_rules *rules, int32_t *sugar, const int32_t *cap,
+                  uint8_t *occ, int32_t *a_sugar, int32_t *a_metab,
+                  int32_t *a_vision, int32_t *a_age, int64_t *counts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

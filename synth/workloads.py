@@ -1,0 +1,127 @@
+"""Seeded synthetic inputs for the five workloads.
+
+Each generator returns plain numpy arrays and sizes; nothing here computes
+any part of the method (allocation, enumeration, or the simulations).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import rng
+
+# ---------------------------------------------------------------- micro ----
+
+
+@dataclass
+class MicroInputs:
+    n_init: int          # objects created at start, ids 0..n_init-1
+    steps: int           # update / cull / re-new rounds
+    n_renew: int         # ids 3k, k < n_renew, re-created each step
+    x0: np.ndarray       # float32 [n_init]
+    v0: np.ndarray       # float32 [n_init]
+    xs: np.ndarray       # float32 [steps, n_renew]  x of the re-created id 3k
+    vs: np.ndarray       # float32 [steps, n_renew]
+
+
+def micro_inputs(n_init: int = 65536, steps: int = 10,
+                 seed: int = rng.DEFAULT_SEED) -> MicroInputs:
+    ids = np.arange(n_init, dtype=np.uint64)
+    x0 = rng.uniform01_f32(rng.hash4(seed, rng.S_MICRO_X, 0, ids))
+    v0 = rng.irwin_hall12_f32(seed, 0, ids)
+    n_renew = (n_init + 2) // 3
+    rid = (3 * np.arange(n_renew, dtype=np.uint64))[None, :]
+    st = np.arange(1, steps + 1, dtype=np.uint64)[:, None]
+    xs = rng.uniform01_f32(rng.hash4(seed, rng.S_MICRO_X, st, rid))
+    vs = rng.irwin_hall12_f32(seed, st, rid)
+    return MicroInputs(n_init, steps, n_renew, x0, v0,
+                       np.ascontiguousarray(xs, dtype=np.float32),
+                       np.ascontiguousarray(vs, dtype=np.float32))
+
+
+# ----------------------------------------------------------- game of life --
+
+
+def gol_grid(width: int, height: int, seed: int = rng.DEFAULT_SEED,
+             threshold24: int = rng.BERNOULLI_0_1) -> np.ndarray:
+    """uint8 [height, width]; cell (x, y) is alive with probability ~0.1."""
+    p = np.arange(width * height, dtype=np.uint64)
+    alive = rng.bernoulli(rng.hash4(seed, rng.S_GOL_ALIVE, 0, p), threshold24)
+    return alive.astype(np.uint8).reshape(height, width)
+
+
+# ------------------------------------------------------------- batched -----
+
+
+def world_sides(n_worlds: int = 256, lo: int = 64, hi: int = 1024,
+                seed: int = rng.DEFAULT_SEED) -> np.ndarray:
+    """Square world sides, log-uniform in [lo, hi]: round(lo * (hi/lo)**u)."""
+    w = np.arange(n_worlds, dtype=np.uint64)
+    u = rng.uniform01_f32(rng.hash4(seed, rng.S_WORLD_SIZE, 0, w)).astype(np.float64)
+    sides = np.rint(lo * (hi / lo) ** u).astype(np.int64)
+    return np.clip(sides, lo, hi).astype(np.int32)
+
+
+def world_seeds(n_worlds: int, seed: int = rng.DEFAULT_SEED) -> np.ndarray:
+    w = np.arange(n_worlds, dtype=np.uint64)
+    return rng.hash4(seed, rng.S_WORLD_SEED, 0, w).astype(np.uint64)
+
+
+@dataclass
+class BatchInputs:
+    sides: np.ndarray          # int32 [n_worlds]
+    seeds: np.ndarray          # uint64 [n_worlds]
+    grids: list                # uint8 [side, side] per world
+    generations: int
+
+
+def batch_inputs(n_worlds: int = 256, generations: int = 100, lo: int = 64,
+                 hi: int = 1024, seed: int = rng.DEFAULT_SEED) -> BatchInputs:
+    sides = world_sides(n_worlds, lo, hi, seed)
+    seeds = world_seeds(n_worlds, seed)
+    grids = [gol_grid(int(s), int(s), int(ws)) for s, ws in zip(sides, seeds)]
+    return BatchInputs(sides, seeds, grids, generations)
+
+
+# ------------------------------------------------------------ sugarscape ---
+
+# Rule constants of the Sugarscape-style model (agents die at max_age;
+# reproduce with at least repro_min sugar while fertile_min <= age <= fertile_max).
+SUGAR_RULES = dict(max_age=100, repro_min=20, fertile_min=10, fertile_max=60)
+
+
+@dataclass
+class SugarInputs:
+    side: int
+    n_agents: int
+    seed: int
+    sugar: np.ndarray      # int32 [side*side]  (starts equal to cap)
+    cap: np.ndarray        # int32 [side*side]  U{0..4}
+    occ: np.ndarray        # uint8 [side*side]
+    a_sugar: np.ndarray    # int32 [side*side]  U{5..25} where occupied, else 0
+    a_metab: np.ndarray    # U{1..4}
+    a_vision: np.ndarray   # U{1..6}
+    a_age: np.ndarray      # U{0..max_age-1}
+
+
+def sugar_inputs(side: int = 2048, n_agents: int = 1 << 20, seed: int = rng.DEFAULT_SEED,
+                 max_age: int = SUGAR_RULES["max_age"]) -> SugarInputs:
+    n = side * side
+    if not 0 <= n_agents <= n:
+        raise ValueError("n_agents must fit on the grid")
+    cells = np.arange(n, dtype=np.uint64)
+    cap = rng.uniform_int(rng.hash4(seed, rng.S_SUGAR_CAP, 0, cells), 0, 4)
+    key = rng.hash4(seed, rng.S_SUGAR_OCC, 0, cells)
+    order = np.lexsort((cells, key))       # by key, ties by cell index
+    occ = np.zeros(n, dtype=np.uint8)
+    occ[order[:n_agents]] = 1
+    m = occ.astype(bool)
+
+    def trait(stream, lo, hi):
+        v = rng.uniform_int(rng.hash4(seed, stream, 0, cells), lo, hi)
+        return np.where(m, v, 0).astype(np.int32)
+
+    return SugarInputs(side, n_agents, seed, cap.copy(), cap, occ,
+                       trait(rng.S_SUGAR_SUGAR, 5, 25), trait(rng.S_SUGAR_METAB, 1, 4),
+                       trait(rng.S_SUGAR_VISION, 1, 6), trait(rng.S_SUGAR_AGE, 0, max_age - 1))
