@@ -1,0 +1,264 @@
+/*
+ * dsoar.h - C ABI of the MI355X object heap and parallel do-all.
+ *
+ * The method is DynaSOAr's (arXiv 1809.07444): a device-side heap of
+ * equal-size blocks, each holding objects of one type in an SOA layout
+ * (Sec. 2, "heap layout" figure), block states indexed by lock-free
+ * hierarchical bitmaps (Sec. 2 "Block States", Sec. 3, Alg. 2), allocation
+ * by Alg. 1 (Sec. 2.2) with wavefront request coalescing (Sec. 2.4), and a
+ * parallel do-all that compacts the allocated blocks of a type and assigns
+ * one wavefront lane per object slot (Sec. 2.3, "thread assignment" figure).
+ *
+ * Conventions for every entry point:
+ *  - Return value: DSOAR_OK (0) or a negative dsoar_status.  Nothing throws.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls are asynchronous and stream-ordered unless stated otherwise; every
+ *    call that touches one heap must be issued on one stream (the heap relies
+ *    on stream order for quiescence between kernels).
+ *  - Pointers named *_dev are device pointers; all others are host pointers.
+ *  - The caller owns all memory it passes in.  The heap never allocates device
+ *    memory: it lives inside the caller's buffer, which must stay allocated
+ *    until dsoar_heap_destroy.  Host metadata is owned by the heap handle.
+ *  - A heap handle must not be used from two host threads at once.
+ *
+ * Device-side `new` and `delete` are C++ device functions (dsoar_new,
+ * dsoar_delete in the package's device header) called inside kernels; the
+ * do-all methods and workload kernels listed below use them.
+ */
+#ifndef DSOAR_H
+#define DSOAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DSOAR_MAX_TYPES 8
+#define DSOAR_MAX_FIELDS 8
+#define DSOAR_NULL 0xFFFFFFFFu /* the null object handle */
+#define DSOAR_ABI_VERSION 1
+
+typedef enum {
+  DSOAR_OK = 0,
+  DSOAR_ERR_INVALID_ARG = -1,  /* bad size, type, field or pointer */
+  DSOAR_ERR_OOM = -2,          /* a device new found no free block (sticky) */
+  DSOAR_ERR_RETRY_LIMIT = -3,  /* a bounded device retry loop gave up (sticky) */
+  DSOAR_ERR_HIP = -4,          /* a HIP runtime call failed */
+  DSOAR_ERR_DOUBLE_FREE = -5,  /* delete of a slot that was not allocated (sticky) */
+  DSOAR_ERR_TOO_SMALL = -6,    /* the caller's buffer is smaller than required */
+  DSOAR_ERR_UNSUPPORTED = -7   /* method/type combination not available */
+} dsoar_status;
+
+/* Object handle: (block << 6) | slot.  DSOAR_NULL on failure. */
+typedef uint32_t dsoar_obj;
+
+typedef struct dsoar_heap dsoar_heap;
+
+/* Per-type field layout (Sec. 2: one SOA array per field inside a block).
+ * field_bytes[i] is 4 or 8. */
+typedef struct {
+  uint32_t num_fields;
+  uint32_t field_bytes[DSOAR_MAX_FIELDS];
+} dsoar_type_layout;
+
+/* Heap geometry.  num_blocks = M (1 .. 2^26).  block_capacity = slots per
+ * block, 64 (one wavefront per block, the paper's capacity for the smallest
+ * type) or 32 (two blocks per wavefront; Sec. 2 notes capacities of at least
+ * 32 keep 4-byte SOA arrays at 128 bytes).  All types are declared up front
+ * (Sec. 2, footnote on pre-declared types). */
+typedef struct {
+  uint32_t num_blocks;
+  uint32_t block_capacity;
+  uint32_t num_types;
+  uint32_t reserved; /* must be 0 */
+  dsoar_type_layout types[DSOAR_MAX_TYPES];
+} dsoar_heap_desc;
+
+/* Byte offsets of the heap's regions inside the caller's buffer, for tests
+ * and tools that inspect device memory directly. */
+typedef struct {
+  uint64_t total_bytes;
+  uint64_t data_offset;       /* block b, field f of type t at data_offset +
+                                 b*block_stride + field_offset[t][f] + slot*width */
+  uint64_t block_stride;
+  uint64_t obj_bitmap_offset; /* uint64 per block: bit s = slot s allocated */
+  uint64_t block_type_offset; /* uint32 per block: type, 0xFFFFFFFF = none */
+  uint64_t bitmaps_offset;    /* (1 + 2*num_types) hierarchical bitmaps:
+                                 0 = free, 1+2t = allocated[t], 2+2t = active[t] */
+  uint64_t bitmap_stride;     /* bytes between consecutive bitmaps */
+  uint32_t num_levels;        /* levels per bitmap (level 0 = one bit per block) */
+  uint32_t level_word_offset[8];
+  uint32_t level_words[8];
+  uint32_t field_offset[DSOAR_MAX_TYPES][DSOAR_MAX_FIELDS];
+} dsoar_heap_layout;
+
+/* Quiescent statistics, filled by dsoar_heap_stats. */
+typedef struct {
+  uint64_t allocs[DSOAR_MAX_TYPES];       /* successful device news */
+  uint64_t frees[DSOAR_MAX_TYPES];        /* successful device deletes */
+  uint64_t live_objects[DSOAR_MAX_TYPES]; /* popcount of the object bitmaps */
+  uint32_t allocated_blocks[DSOAR_MAX_TYPES];
+  uint32_t active_blocks[DSOAR_MAX_TYPES];
+  uint32_t typed_blocks[DSOAR_MAX_TYPES]; /* blocks whose type word is t */
+  uint64_t reserve_retries;               /* reservations that lost a race */
+  uint64_t slow_paths;                    /* free blocks taken (Alg. 1 slow path) */
+  uint64_t find_fails;                    /* try_find_set FAILs on active[T] */
+  uint32_t free_blocks;
+  uint32_t num_blocks;
+  uint32_t oom;                           /* sticky flags */
+  uint32_t retry_limit_hit;
+  uint32_t double_free;
+  uint32_t reserved;
+} dsoar_stats;
+
+/* Invariant codes reported by dsoar_heap_check (counts per code). */
+enum {
+  DSOAR_INV_BITMAP_RANGE = 0, /* object bits set at or above the capacity */
+  DSOAR_INV_ALLOCATED = 1,    /* allocated[T] <=> type T and non-empty */
+  DSOAR_INV_ACTIVE = 2,       /* active[T] <=> allocated[T] and not full */
+  DSOAR_INV_ACTIVE_IMPLIES_ALLOCATED = 3,
+  DSOAR_INV_FREE = 4,         /* free <=> untyped and empty; states disjoint */
+  DSOAR_INV_CONTAINER = 5,    /* nested bit = OR of its container (Sec. 3) */
+  DSOAR_INV_LIVE_COUNT = 6,   /* live = allocs - frees, per type */
+  DSOAR_INV_COUNT = 8
+};
+
+/* ------------------------------------------------------------------ heap -- */
+
+/* Device bytes a heap of this geometry needs (0 if the descriptor is invalid). */
+size_t dsoar_heap_bytes(const dsoar_heap_desc* desc);
+
+/* Creates a heap inside dev_mem (device, >= dsoar_heap_bytes, 256-byte
+ * aligned) and initialises it on `stream`: every block free (Sec. 2, "block
+ * states" figure: initially every block is free), all other bitmaps empty.
+ * *out receives the host handle.  Errors: INVALID_ARG, TOO_SMALL, HIP. */
+int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_bytes,
+                      void* stream, dsoar_heap** out);
+
+/* Frees the host handle.  Never touches dev_mem. */
+int dsoar_heap_destroy(dsoar_heap* heap);
+
+/* Returns the heap to its initial (all free) state, clears the counters and
+ * the sticky flags. */
+int dsoar_heap_reset(dsoar_heap* heap, void* stream);
+
+int dsoar_heap_get_layout(const dsoar_heap* heap, dsoar_heap_layout* out);
+
+/* Launch shape of do-all kernels: workgroups of wg_threads (64..1024, a
+ * multiple of 64) and, for persistent launches, wgs_per_cu workgroups per
+ * compute unit (1..64).  Defaults 256 and 8. */
+int dsoar_heap_set_launch(dsoar_heap* heap, uint32_t wg_threads, uint32_t wgs_per_cu);
+
+/* The HIP error code of the last failed HIP call made for this heap. */
+int dsoar_last_hip_error(const dsoar_heap* heap);
+
+/* Parallel enumeration (Sec. 2.3, two steps): compacts the set bits of
+ * allocated[type] into the heap's index array R (ascending block ids) with a
+ * snapshot S of each block's object bitmap, and the count, all on the device.
+ * Blocks of `type` that are empty are first returned to the free state
+ * (quiescent reclamation).  Must be ordered after every kernel that mutates
+ * the heap. */
+int dsoar_enumerate(dsoar_heap* heap, uint32_t type, void* stream);
+
+/* Reads back the count of the last enumeration of `type` (synchronises). */
+int dsoar_enum_count(dsoar_heap* heap, uint32_t type, uint32_t* count, void* stream);
+
+/* Device addresses of the enumeration arrays of `type`: R (uint32 block ids)
+ * and S (uint64 object-bitmap snapshots), valid until the heap is destroyed. */
+int dsoar_enum_arrays(dsoar_heap* heap, uint32_t type, uint64_t* R_dev, uint64_t* S_dev);
+
+/* Returns every empty typed block, of every type, to the free state. */
+int dsoar_reclaim(dsoar_heap* heap, void* stream);
+
+/* Do-all flags. */
+#define DSOAR_DO_PERSISTENT 0u  /* fixed grid, loops over the device count (graph-safe) */
+#define DSOAR_DO_PLAIN 1u       /* reads the count back (synchronises) and launches
+                                   exactly count*capacity/64 wavefronts */
+#define DSOAR_DO_REUSE_ENUM 2u  /* skip enumeration: reuse R/S/count of the last
+                                   dsoar_enumerate of this type (valid only if no
+                                   object of the type was created or deleted since) */
+
+/* Built-in do-all methods. */
+enum {
+  DSOAR_METHOD_VISIT_COUNT = 1,  /* args: dsoar_visit_args.  counts_dev[obj] += 1 */
+  DSOAR_METHOD_DELETE_IF_MOD = 2,/* args: dsoar_mod_args.  delete this if the
+                                    int32 field % modulus == residue */
+  DSOAR_METHOD_MICRO_UPDATE = 3, /* args: none.  x = fma(0.01f, v, x) on the
+                                    microbenchmark type {int32 id, f32 x, f32 v} */
+  DSOAR_METHOD_MICRO_CULL = 4,   /* args: none.  delete this if id % 3 == 0 */
+  DSOAR_METHOD_FIELD_GATHER = 5  /* args: dsoar_gather_args.  out_dev[key] = field */
+};
+
+typedef struct { uint32_t* counts_dev; } dsoar_visit_args;            /* num_blocks*64 entries */
+typedef struct { uint32_t field; int32_t modulus; int32_t residue; } dsoar_mod_args;
+typedef struct { uint32_t key_field; uint32_t field; uint32_t num_keys; uint32_t reserved;
+                 void* out_dev; uint8_t* present_dev; } dsoar_gather_args;
+
+/* Runs `method` once for every object of `type` that is live when the
+ * enumeration runs (Sec. 2.3: c consecutive lanes per allocated block, lane
+ * tid % c handles slot tid % c when that slot is allocated).  Objects created
+ * during the do-all are not visited; a method may delete only `this`, which
+ * takes effect when its wavefront finishes the block.  Errors: INVALID_ARG,
+ * UNSUPPORTED (unknown method), HIP. */
+int dsoar_parallel_do(dsoar_heap* heap, uint32_t type, uint32_t method,
+                      const void* args, size_t args_bytes, uint32_t flags, void* stream);
+
+/* Counters, sticky flags and block/object counts.  Synchronises `stream`.
+ * Returns OOM / RETRY_LIMIT / DOUBLE_FREE if the matching sticky flag is set
+ * (the struct is filled in either way). */
+int dsoar_heap_stats(dsoar_heap* heap, dsoar_stats* out, void* stream);
+
+/* Reclaims all empty blocks, then checks the block-state invariants at
+ * quiescence; violations[DSOAR_INV_COUNT] receives the number of violations
+ * per code.  Synchronises `stream`. */
+int dsoar_heap_check(dsoar_heap* heap, uint32_t* violations, void* stream);
+
+/* Device entry points for callers without their own kernels: n lanes each
+ * call device new (out_dev[i] = handle or DSOAR_NULL), or each delete
+ * objs_dev[i] (DSOAR_NULL entries are skipped). */
+int dsoar_alloc_n(dsoar_heap* heap, uint32_t type, uint32_t n, dsoar_obj* out_dev, void* stream);
+int dsoar_free_n(dsoar_heap* heap, const dsoar_obj* objs_dev, uint32_t n, void* stream);
+
+/* Copies a 4-byte field of n objects to/from a dense device array. */
+int dsoar_field_read(dsoar_heap* heap, uint32_t type, uint32_t field, const dsoar_obj* objs_dev,
+                     uint32_t n, uint32_t* out_dev, void* stream);
+int dsoar_field_write(dsoar_heap* heap, uint32_t type, uint32_t field, const dsoar_obj* objs_dev,
+                      uint32_t n, const uint32_t* in_dev, void* stream);
+
+const char* dsoar_error_string(int status);
+int dsoar_abi_version(void);
+
+/* ------------------------------------------------------- hierarchical bitmap
+ * A stand-alone device bitmap with the heap's operations (Sec. 2.1, Sec. 3,
+ * Alg. 2), for testing them in isolation.  Each op runs on its own
+ * wavefront, all ops of one call concurrently. */
+enum {
+  DSOAR_BM_TRY_SET = 0, DSOAR_BM_TRY_CLEAR = 1, DSOAR_BM_SET = 2, DSOAR_BM_CLEAR = 3,
+  DSOAR_BM_TRY_FIND_SET = 4, DSOAR_BM_FIND_CLEAR = 5
+};
+/* Bytes for a bitmap of nbits bits (all levels).  0 if nbits is 0 or > 2^30. */
+size_t dsoar_bitmap_bytes(uint32_t nbits);
+/* Initialises all levels: every bit clear (all_set = 0) or every bit < nbits set. */
+int dsoar_bitmap_init(void* bm_dev, uint32_t nbits, int all_set, void* stream);
+/* ops_dev: n pairs (kind, pos).  results_dev[i]: 1/0 for try_*, 0 for set/clear
+ * (-3 if the retry limit was hit), the position found or -1 (FAIL) for the
+ * finds.  start_dev (optional, n entries) gives each find's rotation start. */
+int dsoar_bitmap_run(void* bm_dev, uint32_t nbits, const uint32_t* ops_dev, uint32_t n,
+                     const uint32_t* start_dev, int32_t* results_dev, void* stream);
+
+/* --------------------------------------------- microbenchmark workload ----
+ * Type {int32 id, float32 x, float32 v} (fields 0, 1, 2). */
+/* n lanes each create one object: id = lane, x = x0_dev[id], v = v0_dev[id]. */
+int dsoar_micro_init(dsoar_heap* heap, uint32_t type, uint32_t n, const float* x0_dev,
+                     const float* v0_dev, void* stream);
+/* One step: do-all x = fma(0.01f, v, x); do-all delete id % 3 == 0; then
+ * n_renew lanes create id = 3k with x = xs_dev[k], v = vs_dev[k]. */
+int dsoar_micro_step(dsoar_heap* heap, uint32_t type, uint32_t n_renew, const float* xs_dev,
+                     const float* vs_dev, uint32_t flags, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSOAR_H */

@@ -1,0 +1,128 @@
+"""ctypes declarations of the C ABI in include/dsoar.h (argument marshalling only).
+
+Loading fails loudly when libdsoar.so is missing: there is no fallback path."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdsoar.so")
+
+MAX_TYPES = 8
+MAX_FIELDS = 8
+NULL = 0xFFFFFFFF
+
+OK = 0
+ERRORS = {
+    -1: "DSOAR_ERR_INVALID_ARG", -2: "DSOAR_ERR_OOM", -3: "DSOAR_ERR_RETRY_LIMIT",
+    -4: "DSOAR_ERR_HIP", -5: "DSOAR_ERR_DOUBLE_FREE", -6: "DSOAR_ERR_TOO_SMALL",
+    -7: "DSOAR_ERR_UNSUPPORTED",
+}
+ERR_OOM, ERR_RETRY_LIMIT, ERR_DOUBLE_FREE = -2, -3, -5
+
+DO_PERSISTENT, DO_PLAIN, DO_REUSE_ENUM = 0, 1, 2
+METHOD_VISIT_COUNT, METHOD_DELETE_IF_MOD, METHOD_MICRO_UPDATE, METHOD_MICRO_CULL, METHOD_FIELD_GATHER = 1, 2, 3, 4, 5
+BM_TRY_SET, BM_TRY_CLEAR, BM_SET, BM_CLEAR, BM_TRY_FIND_SET, BM_FIND_CLEAR = range(6)
+INV_NAMES = ["bitmap_range", "allocated", "active", "active_implies_allocated", "free",
+             "container", "live_count", "reserved"]
+
+u32, u64, i32, vp, sz = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
+
+
+class TypeLayout(ctypes.Structure):
+    _fields_ = [("num_fields", u32), ("field_bytes", u32 * MAX_FIELDS)]
+
+
+class HeapDesc(ctypes.Structure):
+    _fields_ = [("num_blocks", u32), ("block_capacity", u32), ("num_types", u32), ("reserved", u32),
+                ("types", TypeLayout * MAX_TYPES)]
+
+
+class HeapLayout(ctypes.Structure):
+    _fields_ = [("total_bytes", u64), ("data_offset", u64), ("block_stride", u64),
+                ("obj_bitmap_offset", u64), ("block_type_offset", u64), ("bitmaps_offset", u64),
+                ("bitmap_stride", u64), ("num_levels", u32), ("level_word_offset", u32 * 8),
+                ("level_words", u32 * 8), ("field_offset", (u32 * MAX_FIELDS) * MAX_TYPES)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("allocs", u64 * MAX_TYPES), ("frees", u64 * MAX_TYPES), ("live_objects", u64 * MAX_TYPES),
+                ("allocated_blocks", u32 * MAX_TYPES), ("active_blocks", u32 * MAX_TYPES),
+                ("typed_blocks", u32 * MAX_TYPES), ("reserve_retries", u64), ("slow_paths", u64),
+                ("find_fails", u64), ("free_blocks", u32), ("num_blocks", u32), ("oom", u32),
+                ("retry_limit_hit", u32), ("double_free", u32), ("reserved", u32)]
+
+
+class VisitArgs(ctypes.Structure):
+    _fields_ = [("counts_dev", vp)]
+
+
+class ModArgs(ctypes.Structure):
+    _fields_ = [("field", u32), ("modulus", i32), ("residue", i32)]
+
+
+class GatherArgs(ctypes.Structure):
+    _fields_ = [("key_field", u32), ("field", u32), ("num_keys", u32), ("reserved", u32),
+                ("out_dev", vp), ("present_dev", vp)]
+
+
+H = vp  # dsoar_heap*
+
+SIGNATURES = {
+    "dsoar_heap_bytes": (sz, [ctypes.POINTER(HeapDesc)]),
+    "dsoar_heap_create": (ctypes.c_int, [ctypes.POINTER(HeapDesc), vp, sz, vp, ctypes.POINTER(vp)]),
+    "dsoar_heap_destroy": (ctypes.c_int, [H]),
+    "dsoar_heap_reset": (ctypes.c_int, [H, vp]),
+    "dsoar_heap_get_layout": (ctypes.c_int, [H, ctypes.POINTER(HeapLayout)]),
+    "dsoar_heap_set_launch": (ctypes.c_int, [H, u32, u32]),
+    "dsoar_last_hip_error": (ctypes.c_int, [H]),
+    "dsoar_enumerate": (ctypes.c_int, [H, u32, vp]),
+    "dsoar_enum_count": (ctypes.c_int, [H, u32, ctypes.POINTER(u32), vp]),
+    "dsoar_enum_arrays": (ctypes.c_int, [H, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+    "dsoar_reclaim": (ctypes.c_int, [H, vp]),
+    "dsoar_parallel_do": (ctypes.c_int, [H, u32, u32, vp, sz, u32, vp]),
+    "dsoar_heap_stats": (ctypes.c_int, [H, ctypes.POINTER(Stats), vp]),
+    "dsoar_heap_check": (ctypes.c_int, [H, ctypes.POINTER(u32), vp]),
+    "dsoar_alloc_n": (ctypes.c_int, [H, u32, u32, vp, vp]),
+    "dsoar_free_n": (ctypes.c_int, [H, vp, u32, vp]),
+    "dsoar_field_read": (ctypes.c_int, [H, u32, u32, vp, u32, vp, vp]),
+    "dsoar_field_write": (ctypes.c_int, [H, u32, u32, vp, u32, vp, vp]),
+    "dsoar_error_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "dsoar_abi_version": (ctypes.c_int, []),
+    "dsoar_bitmap_bytes": (sz, [u32]),
+    "dsoar_bitmap_init": (ctypes.c_int, [vp, u32, ctypes.c_int, vp]),
+    "dsoar_bitmap_run": (ctypes.c_int, [vp, u32, vp, u32, vp, vp, vp]),
+    "dsoar_micro_init": (ctypes.c_int, [H, u32, u32, vp, vp, vp]),
+    "dsoar_micro_step": (ctypes.c_int, [H, u32, u32, vp, vp, u32, vp]),
+}
+
+_lib = None
+
+
+class DsoarError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {ERRORS.get(code, code)}")
+
+
+def load() -> ctypes.CDLL:
+    """Loads libdsoar.so from the package directory (never builds, never falls back)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1809_07444_amd.build` (hipcc, gfx950)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(code: int, what: str) -> int:
+    if code != OK:
+        raise DsoarError(code, what)
+    return code

@@ -1,0 +1,446 @@
+// Device side of the object heap: hierarchical bitmaps (Sec. 3, Alg. 2),
+// wavefront-aggregated new (Sec. 2.2 Alg. 1 + request coalescing, Sec. 2.4),
+// delete, SOA field addressing (Sec. 2), for gfx950 wave64.
+//
+// Execution model.  Every heap operation here is a *wavefront* operation: it
+// is called by the lanes of one wavefront that want it (any subset), runs in
+// wave-uniform control flow, and issues its atomics from one leader lane,
+// broadcasting results with readfirstlane.  A lane never spins on another
+// lane of its own wavefront, so the retry loops of the paper's lock-free
+// algorithms cannot deadlock under lockstep execution.
+//
+// Memory model.  Bitmap words and object bitmaps are read with agent-scope
+// relaxed atomic loads (global_load ... sc1) and updated with agent-scope
+// relaxed atomic RMWs, so all eight XCDs observe one coherent order per word.
+// The object bitmap word is the linearisation point (Sec. 2, "Concurrency");
+// block-state bitmaps are eventually consistent hints.  No release/acquire
+// fences are used: object fields written in one kernel are read in later
+// kernels (kernel boundaries order them), and a method that deletes `this`
+// must not write this's fields in the same call.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsoar {
+
+constexpr uint32_t kMaxTypes = 8;
+constexpr uint32_t kMaxFields = 8;
+constexpr uint32_t kMaxLevels = 8;
+constexpr uint32_t kNull = 0xFFFFFFFFu;
+constexpr uint32_t kTypeNone = 0xFFFFFFFFu;
+constexpr int32_t kFail = -1;
+constexpr uint32_t kSpinLimit = 1u << 20;  // bound of every retry loop
+constexpr uint32_t kShards = 64;           // counter shards (spread atomics)
+
+// Control words (uint64 array at DevHeap::ctrl).
+enum : uint32_t {
+  kCtlOom = 0,
+  kCtlRetryLimit = 1,
+  kCtlDoubleFree = 2,
+  kCtlWords = 8,
+  // Counter shards follow: shard s occupies kCtlWords + s*kShardStride ...
+  kCntAllocs = 0,                  // + type
+  kCntFrees = kMaxTypes,           // + type
+  kCntReserveRetries = 2 * kMaxTypes,
+  kCntSlowPaths = 2 * kMaxTypes + 1,
+  kCntFindFails = 2 * kMaxTypes + 2,
+  kShardStride = 32,
+};
+
+struct DevHeap {
+  uint8_t* data;            // M * block_stride bytes of SOA segments
+  uint64_t* obj_bitmap;     // M words: bit s = slot s holds an object
+  uint32_t* block_type;     // M words: type of the block, kTypeNone if free
+  uint64_t* bitmaps;        // (1 + 2T) hierarchical bitmaps, bm_words apart
+  uint64_t* ctrl;           // flags + counter shards
+  uint64_t block_stride;
+  uint64_t cap_mask;        // low `capacity` bits
+  uint32_t num_blocks;
+  uint32_t capacity;        // 32 or 64
+  uint32_t num_types;
+  uint32_t nlevels;
+  uint32_t bm_words;        // words per bitmap (all levels, padded)
+  uint32_t field_off[kMaxTypes][kMaxFields];
+  uint8_t field_shift[kMaxTypes][kMaxFields];  // log2(field width)
+};
+
+// ------------------------------------------------------------ wave helpers --
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t active_mask() { return __ballot(1); }
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t bcast32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t bcast64(uint64_t v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ bool is_first_active() {
+  return lane_id() == (uint32_t)(__ffsll((unsigned long long)active_mask()) - 1);
+}
+
+// Position of the k-th (0-based) set bit of m; m must have more than k bits.
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t k) {
+  uint32_t pos = 0;
+#pragma unroll
+  for (uint32_t w = 32; w >= 1; w >>= 1) {
+    uint32_t c = __popcll(m & ((1ull << w) - 1));
+    if (k >= c) {
+      k -= c;
+      m >>= w;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+// Lowest n set bits of m (n <= popcount(m)).
+__device__ __forceinline__ uint64_t lowest_bits(uint64_t m, uint32_t n) {
+  if (n >= (uint32_t)__popcll(m)) return m;
+  if (n == 0) return 0;
+  uint32_t p = nth_set_bit(m, n);  // first bit not taken
+  return m & ((1ull << p) - 1);
+}
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// ----------------------------------------------------------- memory access --
+
+// Agent-coherent load, made wave-uniform.
+__device__ __forceinline__ uint64_t load_u64(const uint64_t* p) {
+  return bcast64(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Leader-issued RMWs; all calling lanes receive the previous value.
+__device__ __forceinline__ uint64_t lead_or(uint64_t* p, uint64_t v) {
+  uint64_t r = 0;
+  if (is_first_active()) r = __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return bcast64(r);
+}
+
+__device__ __forceinline__ uint64_t lead_and(uint64_t* p, uint64_t v) {
+  uint64_t r = 0;
+  if (is_first_active()) r = __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return bcast64(r);
+}
+
+__device__ __forceinline__ void lead_add(uint64_t* p, uint64_t v) {
+  if (is_first_active()) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void lead_flag(uint64_t* p) {
+  if (is_first_active()) __hip_atomic_store(p, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t* shard(const DevHeap& h) {
+  return h.ctrl + kCtlWords + (blockIdx.x & (kShards - 1)) * kShardStride;
+}
+
+// ------------------------------------------------------ hierarchical bitmap --
+// Bitmap k of the heap: k = 0 free, 1 + 2t allocated[t], 2 + 2t active[t].
+// Level l + 1 holds one bit per word of level l; the top level is one word.
+
+// Word offset of level l in a bitmap of nbits bits: levels are stored
+// bottom-up, level k holding ceil(nbits / 64^(k+1)) words.
+__device__ __forceinline__ uint32_t level_offset(uint32_t nbits, uint32_t l) {
+  uint32_t off = 0;
+  for (uint32_t k = 0; k < l; ++k) off += ((nbits - 1) >> (6 * k + 6)) + 1;
+  return off;
+}
+
+// Levels of a bitmap: a nested bitmap exists iff the bitmap has more than 64
+// bits (Sec. 3, "Data Structure").
+__host__ __device__ __forceinline__ uint32_t num_levels(uint32_t nbits) {
+  uint32_t l = 1;
+  while (nbits > 64) {
+    nbits = (nbits + 63) >> 6;
+    ++l;
+  }
+  return l;
+}
+
+struct Bitmap {
+  uint64_t* words;
+  uint32_t nbits;
+  uint32_t nlevels;
+  uint64_t* retry_flag;
+
+  __device__ __forceinline__ uint64_t* word(uint32_t level, uint32_t idx) const {
+    return words + level_offset(nbits, level) + idx;
+  }
+};
+
+__device__ __forceinline__ Bitmap heap_bitmap(const DevHeap& h, uint32_t k) {
+  return Bitmap{h.bitmaps + (uint64_t)k * h.bm_words, h.num_blocks, h.nlevels, h.ctrl + kCtlRetryLimit};
+}
+__device__ __forceinline__ Bitmap free_bm(const DevHeap& h) { return heap_bitmap(h, 0); }
+__device__ __forceinline__ Bitmap allocated_bm(const DevHeap& h, uint32_t t) { return heap_bitmap(h, 1 + 2 * t); }
+__device__ __forceinline__ Bitmap active_bm(const DevHeap& h, uint32_t t) { return heap_bitmap(h, 2 + 2 * t); }
+
+// set(pos) / clear(pos) of Sec. 2.1: retry the try_ operation until it
+// succeeds, then do the nested update this success made us responsible for
+// (Alg. 2: the clear that empties a container clears its nested bit; the set
+// that makes a container non-empty sets it).  Iterative, one level at a time.
+// Returns false only if the retry limit was hit (sticky flag set).
+__device__ inline bool bm_set_from(const Bitmap& b, uint32_t level, uint32_t pos) {
+  for (;;) {
+    const uint64_t mask = 1ull << (pos & 63);
+    uint64_t* w = b.word(level, pos >> 6);
+    uint64_t prev;
+    uint32_t spins = 0;
+    for (;;) {
+      prev = lead_or(w, mask);
+      if (!(prev & mask)) break;
+      if (++spins >= kSpinLimit) {
+        lead_flag(b.retry_flag);
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (prev != 0 || level + 1 >= b.nlevels) return true;
+    pos >>= 6;
+    ++level;
+  }
+}
+
+__device__ inline bool bm_clear_from(const Bitmap& b, uint32_t level, uint32_t pos) {
+  for (;;) {
+    const uint64_t mask = 1ull << (pos & 63);
+    uint64_t* w = b.word(level, pos >> 6);
+    uint64_t prev;
+    uint32_t spins = 0;
+    for (;;) {
+      prev = lead_and(w, ~mask);
+      if (prev & mask) break;
+      if (++spins >= kSpinLimit) {
+        lead_flag(b.retry_flag);
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (__popcll(prev) != 1 || level + 1 >= b.nlevels) return true;
+    pos >>= 6;
+    ++level;
+  }
+}
+
+__device__ __forceinline__ bool bm_set(const Bitmap& b, uint32_t pos) { return bm_set_from(b, 0, pos); }
+__device__ __forceinline__ bool bm_clear(const Bitmap& b, uint32_t pos) { return bm_clear_from(b, 0, pos); }
+
+// try_set(pos): one atomic OR; on success from an empty container, set the
+// nested bit (retrying).
+__device__ inline bool bm_try_set(const Bitmap& b, uint32_t pos) {
+  const uint64_t mask = 1ull << (pos & 63);
+  const uint64_t prev = lead_or(b.word(0, pos >> 6), mask);
+  const bool ok = !(prev & mask);
+  if (ok && prev == 0 && b.nlevels > 1) bm_set_from(b, 1, pos >> 6);
+  return ok;
+}
+
+// Alg. 2, try_clear(pos): one atomic AND; success if the bit was set; if this
+// cleared the container's last bit, clear the nested bit (retrying).
+__device__ inline bool bm_try_clear(const Bitmap& b, uint32_t pos) {
+  const uint64_t mask = 1ull << (pos & 63);
+  const uint64_t prev = lead_and(b.word(0, pos >> 6), ~mask);
+  const bool ok = (prev & mask) != 0;
+  if (ok && __popcll(prev) == 1 && b.nlevels > 1) bm_clear_from(b, 1, pos >> 6);
+  return ok;
+}
+
+// try_find_set(): descend from the top word, one load per level (a
+// logarithmic number of accesses, Sec. 2.4).  At each level take the first
+// set bit at or after the matching base-64 digit of `start` (wrapping), which
+// spreads concurrent searches over the bitmap.  An empty word on the way down
+// means the summary is momentarily ahead of its container: FAIL.
+__device__ inline int32_t bm_try_find_set(const Bitmap& b, uint32_t start) {
+  uint32_t idx = 0;
+  for (int32_t l = (int32_t)b.nlevels - 1; l >= 0; --l) {
+    const uint64_t w = load_u64(b.word((uint32_t)l, idx));
+    if (w == 0) return kFail;
+    const uint32_t d = (6 * (uint32_t)l < 32) ? ((start >> (6 * (uint32_t)l)) & 63u) : 0u;
+    const uint64_t r = (w >> d) | (d ? (w << (64 - d)) : 0ull);
+    const uint32_t bit = ((uint32_t)__builtin_ctzll(r) + d) & 63u;
+    idx = (idx << 6) | bit;
+  }
+  return idx < b.nbits ? (int32_t)idx : kFail;
+}
+
+// clear() of Sec. 2.1: find a set bit and clear it, repeating until this
+// wavefront's clear succeeds.  FAIL when the top word is empty: callers use
+// this only on bitmaps that are never set during a kernel (the free bitmap is
+// refilled only at quiescence), so an empty top word means an empty bitmap.
+__device__ inline int32_t bm_find_clear(const Bitmap& b, uint32_t start) {
+  for (uint32_t spins = 0; spins < kSpinLimit; ++spins) {
+    if (load_u64(b.word(b.nlevels - 1, 0)) == 0) return kFail;
+    const int32_t i = bm_try_find_set(b, start);
+    if (i != kFail && bm_try_clear(b, (uint32_t)i)) return i;
+    start = hash32(start + 0x9e3779b9u + spins);
+  }
+  lead_flag(b.retry_flag);
+  return kFail;
+}
+
+// ------------------------------------------------------------------ objects --
+
+__device__ __forceinline__ uint32_t obj_block(uint32_t obj) { return obj >> 6; }
+__device__ __forceinline__ uint32_t obj_slot(uint32_t obj) { return obj & 63u; }
+__device__ __forceinline__ uint32_t make_obj(uint32_t block, uint32_t slot) { return (block << 6) | slot; }
+
+template <class F>
+__device__ __forceinline__ F* field_ptr(const DevHeap& h, uint32_t obj, uint32_t type, uint32_t field) {
+  return reinterpret_cast<F*>(h.data + (uint64_t)obj_block(obj) * h.block_stride + h.field_off[type][field] +
+                              ((uint64_t)obj_slot(obj) << h.field_shift[type][field]));
+}
+
+// Alg. 1 for all lanes of this wavefront that call it with the same `type`
+// (the caller guarantees a wave-uniform type).  Returns this lane's handle,
+// or kNull if the heap ran out of free blocks (sticky OOM flag set).
+//
+// Request coalescing (Sec. 2.4): the n requesting lanes are served together.
+// Each round looks up an active block of the type; if none is found it takes
+// a free block (slow path: set the type, mark it allocated, and - unless this
+// round fills it - active).  Reservation is one atomic OR of the lowest free
+// bits the snapshot shows; the bits actually gained are take & ~prev.  The
+// round whose OR fills the block clears active[type] (Alg. 1, FULL case).
+// Lanes receive slots in rank order.
+__device__ inline uint32_t new_uniform(const DevHeap& h, uint32_t type) {
+  const uint64_t group = active_mask();
+  const uint32_t n = (uint32_t)__popcll(group);
+  const uint32_t rank = lanes_below(group);
+  const Bitmap active = active_bm(h, type);
+  uint32_t result = kNull;
+  uint32_t served = 0;
+  uint32_t start = bcast32(hash32((blockIdx.x << 4) ^ (threadIdx.x >> 6) ^ 0x5bd1e995u));
+  uint32_t retries = 0, slow = 0, fails = 0;
+  bool oom = false;
+  for (uint32_t it = 0; served < n; ++it) {
+    if (it >= kSpinLimit) {
+      lead_flag(h.ctrl + kCtlRetryLimit);
+      break;
+    }
+    int32_t bid = bm_try_find_set(active, start);
+    uint64_t got;
+    if (bid == kFail) {
+      ++fails;
+      bid = bm_find_clear(free_bm(h), start);
+      if (bid == kFail) {
+        oom = true;
+        break;
+      }
+      ++slow;
+      // Fresh block: nobody else can see it until it is marked active.
+      const uint32_t want = n - served;
+      got = want >= h.capacity ? h.cap_mask : ((1ull << want) - 1);
+      if (is_first_active()) {
+        h.block_type[bid] = type;
+        __hip_atomic_fetch_or(h.obj_bitmap + bid, got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      bm_set(allocated_bm(h, type), (uint32_t)bid);
+      if (got != h.cap_mask) bm_set(active, (uint32_t)bid);
+    } else {
+      const uint64_t snap = load_u64(h.obj_bitmap + bid);
+      const uint64_t avail = ~snap & h.cap_mask;
+      if (avail == 0) {  // filled since the lookup; its filler clears the bit
+        ++retries;
+        start = hash32(start + it + 1);
+        continue;
+      }
+      const uint64_t take = lowest_bits(avail, n - served);
+      const uint64_t prev = lead_or(h.obj_bitmap + bid, take);
+      got = take & ~prev;
+      if (got != take) ++retries;
+      const uint64_t after = (prev | take) & h.cap_mask;
+      if (after == h.cap_mask && (prev & h.cap_mask) != h.cap_mask) bm_clear(active, (uint32_t)bid);
+      if (got == 0) {
+        start = hash32(start + it + 1);
+        continue;
+      }
+    }
+    const uint32_t cnt = (uint32_t)__popcll(got);
+    if (rank >= served && rank < served + cnt) result = make_obj((uint32_t)bid, nth_set_bit(got, rank - served));
+    served += cnt;
+  }
+  if (oom) lead_flag(h.ctrl + kCtlOom);
+  uint64_t* sh = shard(h);
+  if (served) lead_add(sh + kCntAllocs + type, served);
+  if (retries) lead_add(sh + kCntReserveRetries, retries);
+  if (slow) lead_add(sh + kCntSlowPaths, slow);
+  if (fails) lead_add(sh + kCntFindFails, fails);
+  return result;
+}
+
+// Device `new`: lanes may pass different types; each distinct type is served
+// as one coalesced request.
+__device__ inline uint32_t dsoar_new(const DevHeap& h, uint32_t type) {
+  uint32_t result = kNull;
+  for (;;) {
+    const uint32_t t0 = bcast32(type);
+    if (type == t0) {
+      result = new_uniform(h, t0);
+      break;
+    }
+  }
+  return result;
+}
+
+// Delete a set of slots of one block (a wavefront's lanes, coalesced): one
+// atomic AND on the object bitmap.  A block that was full becomes active
+// again.  Blocks that become empty stay allocated until quiescent reclaim.
+__device__ inline void delete_mask(const DevHeap& h, uint32_t type, uint32_t bid, uint64_t mask) {
+  const uint64_t prev = lead_and(h.obj_bitmap + bid, ~mask);
+  if ((prev & mask) != mask) lead_flag(h.ctrl + kCtlDoubleFree);
+  const uint64_t removed = prev & mask;
+  if (removed && (prev & h.cap_mask) == h.cap_mask) bm_set(active_bm(h, type), bid);
+  if (removed) lead_add(shard(h) + kCntFrees + type, (uint64_t)__popcll(removed));
+}
+
+// OR of (1 << slot) over the lanes in `lanes` (all of them active); reads
+// each lane with readlane, so inactive lanes of a divergent caller are never
+// touched.
+__device__ __forceinline__ uint64_t slots_of(uint64_t lanes, uint32_t slot) {
+  uint64_t m = 0;
+  while (lanes) {
+    const uint32_t l = (uint32_t)__builtin_ctzll(lanes);
+    m |= 1ull << (__builtin_amdgcn_readlane(slot, l) & 63u);
+    lanes &= lanes - 1;
+  }
+  return m;
+}
+
+// Device `delete` of arbitrary objects: lanes are grouped by block; each group
+// is one coalesced delete_mask.  NULL handles are ignored.
+__device__ inline void dsoar_delete(const DevHeap& h, uint32_t obj) {
+  const bool valid = obj == kNull || (obj >> 6) < h.num_blocks;
+  if (!__builtin_expect(__ballot(!valid) == 0, 1)) lead_flag(h.ctrl + kCtlDoubleFree);
+  const bool mine = obj != kNull && valid;
+  uint64_t pending = __ballot(mine);
+  while (pending) {
+    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)pending) - 1;
+    const uint32_t b0 = __builtin_amdgcn_readlane(obj, leader) >> 6;
+    const bool in = mine && (obj >> 6) == b0 && ((pending >> lane_id()) & 1);
+    const uint64_t grp = __ballot(in);
+    const uint64_t m = slots_of(grp, obj_slot(obj));
+    const uint32_t type = bcast32(__hip_atomic_load(h.block_type + b0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (type < h.num_types) delete_mask(h, type, b0, m);
+    else lead_flag(h.ctrl + kCtlDoubleFree);
+    pending &= ~grp;
+  }
+}
+
+}  // namespace dsoar

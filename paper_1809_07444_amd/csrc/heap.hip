@@ -1,0 +1,844 @@
+// Heap creation and layout, quiescent reclamation, parallel enumeration,
+// statistics and invariant checks, the stand-alone bitmap entry points, and
+// the C ABI of the heap.
+#include <string.h>
+
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace dsoar {
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// Words of all levels of a bitmap of nbits bits (levels bottom-up, each
+// ceil(nbits / 64^(l+1)) words), padded to 256 bytes.
+uint32_t bitmap_words(uint32_t nbits) {
+  uint32_t words = 0;
+  const uint32_t L = num_levels(nbits);
+  for (uint32_t k = 0; k < L; ++k) words += ((nbits - 1) >> (6 * k + 6)) + 1;
+  return (uint32_t)align_up(words, 32);
+}
+
+uint32_t level_word_offset_host(uint32_t nbits, uint32_t l) {
+  uint32_t off = 0;
+  for (uint32_t k = 0; k < l; ++k) off += ((nbits - 1) >> (6 * k + 6)) + 1;
+  return off;
+}
+
+bool desc_valid(const dsoar_heap_desc* d) {
+  if (!d || d->reserved != 0) return false;
+  if (d->num_blocks < 1 || d->num_blocks > (1u << 26)) return false;
+  if (d->block_capacity != 32 && d->block_capacity != 64) return false;
+  if (d->num_types < 1 || d->num_types > DSOAR_MAX_TYPES) return false;
+  for (uint32_t t = 0; t < d->num_types; ++t) {
+    const dsoar_type_layout& L = d->types[t];
+    if (L.num_fields < 1 || L.num_fields > DSOAR_MAX_FIELDS) return false;
+    for (uint32_t f = 0; f < L.num_fields; ++f)
+      if (L.field_bytes[f] != 4 && L.field_bytes[f] != 8) return false;
+  }
+  return true;
+}
+
+// Computes the layout of a heap in one caller buffer.  Block b's data segment
+// holds, for its type, one SOA array per field (Sec. 2), each array padded to
+// 128 bytes (Sec. 2 "Coalesced Access"); every block has the size of the
+// widest type's segment so all blocks are equal in bytes.
+struct Plan {
+  dsoar_heap_layout L;
+  uint64_t ctrl_off, stats_off;
+  uint64_t R_off[kMaxTypes], S_off[kMaxTypes], scan_off[kMaxTypes];
+  uint32_t num_tiles;
+};
+
+Plan make_plan(const dsoar_heap_desc* d) {
+  Plan p;
+  memset(&p, 0, sizeof(p));
+  const uint64_t M = d->num_blocks, c = d->block_capacity;
+  uint64_t stride = 0;
+  for (uint32_t t = 0; t < d->num_types; ++t) {
+    uint64_t off = 0;
+    for (uint32_t f = 0; f < d->types[t].num_fields; ++f) {
+      p.L.field_offset[t][f] = (uint32_t)off;
+      off += align_up(c * d->types[t].field_bytes[f], 128);
+    }
+    stride = std::max(stride, off);
+  }
+  p.L.block_stride = align_up(stride, kAlign);
+  uint64_t off = 0;
+  p.L.data_offset = off;
+  off = align_up(off + M * p.L.block_stride, kAlign);
+  p.L.obj_bitmap_offset = off;
+  off = align_up(off + M * 8, kAlign);
+  p.L.block_type_offset = off;
+  off = align_up(off + M * 4, kAlign);
+  p.L.bitmaps_offset = off;
+  const uint32_t bm_words = bitmap_words((uint32_t)M);
+  p.L.bitmap_stride = (uint64_t)bm_words * 8;
+  p.L.num_levels = num_levels((uint32_t)M);
+  for (uint32_t l = 0; l < p.L.num_levels && l < 8; ++l) {
+    p.L.level_word_offset[l] = level_word_offset_host((uint32_t)M, l);
+    p.L.level_words[l] = (uint32_t)(((M - 1) >> (6 * l + 6)) + 1);
+  }
+  off = align_up(off + (1 + 2 * (uint64_t)d->num_types) * p.L.bitmap_stride, kAlign);
+  p.ctrl_off = off;
+  off = align_up(off + (kCtlWords + kShards * kShardStride) * 8, kAlign);
+  p.stats_off = off;
+  off = align_up(off + sizeof(StatsOut), kAlign);
+  const uint64_t W0 = (M + 63) / 64;
+  p.num_tiles = (uint32_t)((W0 + kEnumTileWords - 1) / kEnumTileWords);
+  for (uint32_t t = 0; t < d->num_types; ++t) {
+    p.R_off[t] = off;
+    off = align_up(off + M * 4, kAlign);
+    p.S_off[t] = off;
+    off = align_up(off + M * 8, kAlign);
+    p.scan_off[t] = off;
+    off = align_up(off + sizeof(ScanState) + (uint64_t)p.num_tiles * 8, kAlign);
+  }
+  p.L.total_bytes = off;
+  return p;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// Bitmap initialisation: level l word i covers bits [64i, 64i+64) of level l;
+// when all_set, exactly the bits below the level's size are set (so every
+// level is the OR of the level below).
+__device__ inline uint64_t full_word(uint32_t nbits_level, uint32_t i) {
+  const uint32_t lo = i * 64;
+  if (lo >= nbits_level) return 0;
+  const uint32_t n = nbits_level - lo;
+  return n >= 64 ? ~0ull : ((1ull << n) - 1);
+}
+
+__global__ void init_bitmap_kernel(uint64_t* bm, uint32_t nbits, uint32_t total_words, int all_set) {
+  const uint32_t L = num_levels(nbits);
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < total_words; w += gridDim.x * blockDim.x) {
+    uint64_t v = 0;
+    if (all_set) {
+      uint32_t off = 0, n = nbits;
+      for (uint32_t l = 0; l < L; ++l) {
+        const uint32_t words = ((nbits - 1) >> (6 * l + 6)) + 1;
+        if (w >= off && w < off + words) {
+          v = full_word(n, w - off);
+          break;
+        }
+        off += words;
+        n = words;
+      }
+    }
+    bm[w] = v;
+  }
+}
+
+__global__ void init_heap_kernel(DevHeap h, uint64_t ctrl_words) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nth = gridDim.x * blockDim.x;
+  for (uint32_t b = tid; b < h.num_blocks; b += nth) {
+    h.obj_bitmap[b] = 0;
+    h.block_type[b] = kTypeNone;
+  }
+  for (uint64_t w = tid; w < ctrl_words; w += nth) h.ctrl[w] = 0;
+  // Bitmap 0 (free) all set, the others clear.
+  const uint32_t L = h.nlevels;
+  const uint64_t total = (uint64_t)(1 + 2 * h.num_types) * h.bm_words;
+  for (uint64_t w = tid; w < total; w += nth) {
+    const uint32_t k = (uint32_t)(w / h.bm_words);
+    const uint32_t i = (uint32_t)(w % h.bm_words);
+    uint64_t v = 0;
+    if (k == 0) {
+      uint32_t off = 0, n = h.num_blocks;
+      for (uint32_t l = 0; l < L; ++l) {
+        const uint32_t words = ((h.num_blocks - 1) >> (6 * l + 6)) + 1;
+        if (i >= off && i < off + words) {
+          v = full_word(n, i - off);
+          break;
+        }
+        off += words;
+        n = words;
+      }
+    }
+    h.bitmaps[w] = v;
+  }
+}
+
+__global__ void init_scan_kernel(ScanState* st, uint64_t* flags, uint32_t num_tiles) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid == 0) {
+    st->tile_counter = 0;
+    st->epoch = 1;
+    st->count = 0;
+    st->pad = 0;
+  }
+  for (uint32_t i = tid; i < num_tiles; i += gridDim.x * blockDim.x) flags[i] = 0;
+}
+
+// Clear / set several bits of one level-0 word with one atomic, with the
+// nested update the paper's single-bit operations would make (Alg. 2).
+__device__ inline void clear_bits0(const Bitmap& b, uint32_t word, uint64_t m) {
+  const uint64_t prev = lead_and(b.word(0, word), ~m);
+  if ((prev & m) && (prev & ~m) == 0 && b.nlevels > 1) bm_clear_from(b, 1, word);
+}
+__device__ inline void set_bits0(const Bitmap& b, uint32_t word, uint64_t m) {
+  const uint64_t prev = lead_or(b.word(0, word), m);
+  if (prev == 0 && (m & ~prev) && b.nlevels > 1) bm_set_from(b, 1, word);
+}
+
+// Quiescent reclamation of the blocks in `rc` (a wave's lanes, word `word`),
+// all of type t and empty: they leave allocated[t] and active[t] and become
+// free again (the block-state figure's transition back to free).
+__device__ inline void reclaim_word(const DevHeap& h, uint32_t t, uint32_t word, uint64_t rc) {
+  if ((rc >> lane_id()) & 1ull) h.block_type[word * 64 + lane_id()] = kTypeNone;
+  clear_bits0(allocated_bm(h, t), word, rc);
+  const uint64_t act = load_u64(active_bm(h, t).word(0, word)) & rc;
+  if (act) clear_bits0(active_bm(h, t), word, act);
+  set_bits0(free_bm(h), word, rc);
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  for (int off = 32; off >= 1; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off);
+  return v;
+}
+
+constexpr uint64_t kFlagAgg = 1ull << 30, kFlagIncl = 2ull << 30;
+__device__ __forceinline__ uint64_t pack_flag(uint32_t epoch, uint64_t status, uint32_t value) {
+  return ((uint64_t)epoch << 32) | status | (uint64_t)value;
+}
+
+// Parallel enumeration (Sec. 2.3): scan allocated[type] level 0 (step 1, set
+// bits -> block ids), drop the empty blocks (reclaiming them) and compact the
+// rest into R with their object-bitmap snapshots (step 2, prefix sum).  One
+// pass: tile prefixes come from a decoupled look-back over per-tile flags,
+// tiles taken in launch order from a ticket counter.
+__global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeap h, uint32_t type, EnumOut out) {
+  __shared__ uint32_t s_tile, s_epoch, s_prefix;
+  __shared__ uint32_t s_wave_total[kEnumWaves];
+  if (threadIdx.x == 0) {
+    s_epoch = __hip_atomic_load(&out.st->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_tile = __hip_atomic_fetch_add(&out.st->tile_counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  const uint32_t tile = s_tile, epoch = s_epoch;
+  const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
+  const uint32_t W0 = (h.num_blocks + 63) >> 6;
+  const Bitmap alloc = allocated_bm(h, type);
+  uint64_t live[kEnumWordsPerWave], snap[kEnumWordsPerWave];
+  uint32_t wave_total = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kEnumWordsPerWave; ++j) {
+    const uint32_t word = tile * kEnumTileWords + wave * kEnumWordsPerWave + j;
+    live[j] = 0;
+    snap[j] = 0;
+    if (word < W0) {
+      const uint64_t w = load_u64(alloc.word(0, word));
+      const bool bit = ((w >> lane) & 1ull) && word * 64 + lane < h.num_blocks;
+      const uint64_t o = bit ? h.obj_bitmap[word * 64 + lane] : 0ull;
+      const uint64_t lv = __ballot(bit && o != 0);
+      const uint64_t rc = __ballot(bit && o == 0);
+      if (rc) reclaim_word(h, type, word, rc);
+      live[j] = lv;
+      snap[j] = o;
+      wave_total += (uint32_t)__popcll(lv);
+    }
+  }
+  if (lane == 0) s_wave_total[wave] = wave_total;
+  __syncthreads();
+  uint32_t wave_off = 0, tile_total = 0;
+  for (uint32_t k = 0; k < kEnumWaves; ++k) {
+    const uint32_t v = s_wave_total[k];
+    wave_off += k < wave ? v : 0u;
+    tile_total += v;
+  }
+  if (wave == 0) {
+    uint32_t exclusive = 0;
+    if (tile == 0) {
+      if (lane == 0)
+        __hip_atomic_store(out.flags + tile, pack_flag(epoch, kFlagIncl, tile_total), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      if (lane == 0)
+        __hip_atomic_store(out.flags + tile, pack_flag(epoch, kFlagAgg, tile_total), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      int32_t pred = (int32_t)tile - 1;
+      for (uint32_t spins = 0;; ++spins) {
+        const int32_t t = pred - (int32_t)lane;
+        uint64_t f = t >= 0 ? __hip_atomic_load(out.flags + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : pack_flag(epoch, kFlagIncl, 0);
+        const bool ready = (uint32_t)(f >> 32) == epoch && (f & (3ull << 30)) != 0;
+        const bool incl = ready && (f & (3ull << 30)) == kFlagIncl;
+        const uint64_t inclm = __ballot(incl), notready = __ballot(!ready);
+        const uint32_t first = inclm ? (uint32_t)__builtin_ctzll(inclm) : 64u;
+        const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+        if (notready & need) {
+          if (spins >= kSpinLimit) {
+            lead_flag(h.ctrl + kCtlRetryLimit);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        exclusive += wave_sum(lane <= first ? (uint32_t)(f & ((1ull << 30) - 1)) : 0u);
+        if (first < 64) break;
+        pred -= 64;
+      }
+      if (lane == 0)
+        __hip_atomic_store(out.flags + tile, pack_flag(epoch, kFlagIncl, exclusive + tile_total),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane == 0) s_prefix = exclusive;
+  }
+  __syncthreads();
+  uint32_t base = s_prefix + wave_off;
+#pragma unroll
+  for (uint32_t j = 0; j < kEnumWordsPerWave; ++j) {
+    const uint32_t word = tile * kEnumTileWords + wave * kEnumWordsPerWave + j;
+    if ((live[j] >> lane) & 1ull) {
+      const uint32_t pos = base + lanes_below(live[j]);
+      out.R[pos] = word * 64 + lane;
+      out.S[pos] = snap[j];
+    }
+    base += (uint32_t)__popcll(live[j]);
+  }
+  if (tile == out.num_tiles - 1 && threadIdx.x == 0) {
+    __hip_atomic_store(&out.st->count, s_prefix + tile_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&out.st->tile_counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&out.st->epoch, epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Reclaims every empty typed block (all types), one wavefront per 64 blocks.
+__global__ void reclaim_kernel(DevHeap h) {
+  const uint32_t W0 = (h.num_blocks + 63) >> 6;
+  const uint32_t wpb = blockDim.x >> 6;
+  const uint32_t lane = lane_id();
+  for (uint32_t word = blockIdx.x * wpb + (threadIdx.x >> 6); word < W0; word += gridDim.x * wpb) {
+    const uint32_t b = word * 64 + lane;
+    const bool in = b < h.num_blocks;
+    const uint32_t t = in ? h.block_type[b] : kTypeNone;
+    const bool empty = in && t != kTypeNone && h.obj_bitmap[b] == 0;
+    uint64_t pending = __ballot(empty);
+    while (pending) {
+      const uint32_t t0 = __builtin_amdgcn_readlane(t, (uint32_t)__builtin_ctzll(pending));
+      const uint64_t rc = __ballot(empty && t == t0);
+      if (t0 < h.num_types) reclaim_word(h, t0, word, rc);
+      pending &= ~rc;
+    }
+  }
+}
+
+// Statistics and invariants at quiescence, one wavefront per 64 blocks, plus
+// container consistency of every level of every bitmap.
+__global__ void stats_kernel(DevHeap h, StatsOut* out, int check) {
+  const uint32_t W0 = (h.num_blocks + 63) >> 6;
+  const uint32_t wpb = blockDim.x >> 6;
+  const uint32_t lane = lane_id();
+  const uint32_t gw = blockIdx.x * wpb + (threadIdx.x >> 6), nw = gridDim.x * wpb;
+  for (uint32_t word = gw; word < W0; word += nw) {
+    const uint32_t b = word * 64 + lane;
+    const bool in = b < h.num_blocks;
+    const uint32_t t = in ? h.block_type[b] : kTypeNone;
+    const uint64_t ob = in ? h.obj_bitmap[b] : 0;
+    const uint64_t obc = ob & h.cap_mask;
+    const bool fr = (free_bm(h).word(0, word)[0] >> lane) & 1ull;
+    uint32_t v[DSOAR_INV_COUNT] = {0};
+    if (in) {
+      v[DSOAR_INV_BITMAP_RANGE] += (ob & ~h.cap_mask) != 0;
+      v[DSOAR_INV_FREE] += fr != (t == kTypeNone && obc == 0);
+      if (t != kTypeNone && t >= h.num_types) v[DSOAR_INV_FREE] += 1;
+    }
+    for (uint32_t u = 0; u < h.num_types; ++u) {
+      const bool al = (allocated_bm(h, u).word(0, word)[0] >> lane) & 1ull;
+      const bool ac = (active_bm(h, u).word(0, word)[0] >> lane) & 1ull;
+      if (in) {
+        v[DSOAR_INV_ALLOCATED] += al != (t == u && obc != 0);
+        v[DSOAR_INV_ACTIVE] += ac != (al && obc != h.cap_mask);
+        v[DSOAR_INV_ACTIVE_IMPLIES_ALLOCATED] += ac && !al;
+        v[DSOAR_INV_FREE] += (al || ac) && fr;
+      } else {
+        v[DSOAR_INV_ALLOCATED] += al;
+        v[DSOAR_INV_ACTIVE] += ac;
+      }
+      const uint64_t al_w = __ballot(al), ac_w = __ballot(ac);
+      const uint32_t live = wave_sum(in && t == u ? (uint32_t)__popcll(obc) : 0u);
+      const uint32_t typed = (uint32_t)__popcll(__ballot(in && t == u));
+      if (lane == 0) {
+        atomicAdd((unsigned long long*)&out->live[u], (unsigned long long)live);
+        atomicAdd(&out->allocated[u], (uint32_t)__popcll(al_w));
+        atomicAdd(&out->active[u], (uint32_t)__popcll(ac_w));
+        atomicAdd(&out->typed[u], typed);
+      }
+    }
+    if (!in) v[DSOAR_INV_FREE] += fr;
+    const uint32_t nfree = (uint32_t)__popcll(__ballot(fr && in));
+    if (lane == 0) atomicAdd(&out->free_blocks, nfree);
+    if (check)
+      for (uint32_t k = 0; k < DSOAR_INV_COUNT; ++k) {
+        const uint32_t s = wave_sum(v[k]);
+        if (lane == 0 && s) atomicAdd(&out->viol[k], s);
+      }
+  }
+  if (!check) return;
+  // Container consistency (Sec. 3): bit i of level l+1 == (word i of level l != 0),
+  // and no bit set at or beyond a level's size.
+  const uint32_t nbm = 1 + 2 * h.num_types;
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
+  for (uint32_t k = 0; k < nbm; ++k) {
+    const Bitmap bm = heap_bitmap(h, k);
+    uint32_t n = h.num_blocks;
+    for (uint32_t l = 0; l < bm.nlevels; ++l) {
+      const uint32_t words = ((n - 1) >> 6) + 1;
+      for (uint32_t i = tid; i < words; i += nth) {
+        const uint64_t w = bm.word(l, i)[0];
+        uint32_t bad = (w & ~full_word(n, i)) != 0;
+        if (l + 1 < bm.nlevels) {
+          const bool up = (bm.word(l + 1, i >> 6)[0] >> (i & 63)) & 1ull;
+          bad += up != (w != 0);
+        }
+        if (bad) atomicAdd(&out->viol[DSOAR_INV_CONTAINER], bad);
+      }
+      n = words;
+    }
+  }
+}
+
+__global__ void zero_kernel(uint32_t* p, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// ---------------------------------------------------- stand-alone bitmap ops
+// One wavefront per op, all lanes of the wavefront running it together.
+__global__ void bitmap_ops_kernel(uint64_t* words, uint32_t nbits, const uint32_t* ops, uint32_t n,
+                                  const uint32_t* starts, int32_t* results, uint64_t* retry_flag) {
+  const uint32_t op = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (op >= n) return;
+  const Bitmap b{words, nbits, num_levels(nbits), retry_flag};
+  const uint32_t kind = ops[2 * op], pos = ops[2 * op + 1];
+  const uint32_t start = starts ? starts[op] : 0u;
+  int32_t r = 0;
+  const bool pos_ok = pos < nbits;
+  switch (kind) {
+    case DSOAR_BM_TRY_SET: r = pos_ok ? (bm_try_set(b, pos) ? 1 : 0) : -2; break;
+    case DSOAR_BM_TRY_CLEAR: r = pos_ok ? (bm_try_clear(b, pos) ? 1 : 0) : -2; break;
+    case DSOAR_BM_SET: r = pos_ok ? (bm_set(b, pos) ? 0 : -3) : -2; break;
+    case DSOAR_BM_CLEAR: r = pos_ok ? (bm_clear(b, pos) ? 0 : -3) : -2; break;
+    case DSOAR_BM_TRY_FIND_SET: r = bm_try_find_set(b, start); break;
+    case DSOAR_BM_FIND_CLEAR: r = bm_find_clear(b, start); break;
+    default: r = -2;
+  }
+  if (lane_id() == 0) results[op] = r;
+}
+
+// -------------------------------------------------------- generic kernels
+__global__ void alloc_n_kernel(DevHeap h, uint32_t type, uint32_t n, uint32_t* out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = dsoar_new(h, type);
+}
+
+__global__ void free_n_kernel(DevHeap h, const uint32_t* objs, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dsoar_delete(h, objs[i]);
+}
+
+__global__ void field_rw_kernel(DevHeap h, uint32_t type, uint32_t field, const uint32_t* objs, uint32_t n,
+                                uint32_t* data, int write) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t o = objs[i];
+  if (o == kNull) return;
+  uint32_t* p = field_ptr<uint32_t>(h, o, type, field);
+  if (write) *p = data[i];
+  else data[i] = *p;
+}
+
+// ---------------------------------------------------------- built-in methods
+struct VisitCount {
+  struct Args { uint32_t* counts; };
+  static __device__ bool run(const DevHeap&, uint32_t, uint32_t self, const Args& a) {
+    atomicAdd(a.counts + self, 1u);
+    return false;
+  }
+};
+
+struct DeleteIfMod {
+  struct Args { uint32_t field; int32_t modulus; int32_t residue; };
+  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& a) {
+    const int32_t v = *field_ptr<int32_t>(h, self, type, a.field);
+    return (v % a.modulus) == a.residue;
+  }
+};
+
+struct FieldGather {
+  struct Args { uint32_t key_field, field, num_keys, wide; uint8_t* out; uint8_t* present; };
+  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& a) {
+    const uint32_t key = *field_ptr<uint32_t>(h, self, type, a.key_field);
+    if (key >= a.num_keys) return false;
+    if (a.wide) reinterpret_cast<uint64_t*>(a.out)[key] = *field_ptr<uint64_t>(h, self, type, a.field);
+    else reinterpret_cast<uint32_t*>(a.out)[key] = *field_ptr<uint32_t>(h, self, type, a.field);
+    if (a.present) a.present[key] = 1;
+    return false;
+  }
+};
+
+}  // namespace
+
+// ------------------------------------------------------ shared host helpers
+
+int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s) {
+  hipLaunchKernelGGL(enumerate_kernel, dim3(h->num_tiles), dim3(kEnumWaves * 64), 0, s, h->dev, type,
+                     h->enum_out[type]);
+  DSOAR_LAUNCHED(h);
+  return DSOAR_OK;
+}
+
+int read_count(dsoar_heap* h, uint32_t type, hipStream_t s, uint32_t* count) {
+  DSOAR_HIP(h, hipMemcpyAsync(count, &h->enum_out[type].st->count, 4, hipMemcpyDeviceToHost, s));
+  DSOAR_HIP(h, hipStreamSynchronize(s));
+  return DSOAR_OK;
+}
+
+// Do-all methods implemented in the workload translation units.
+int micro_doall(dsoar_heap* h, uint32_t type, uint32_t method, uint32_t flags, hipStream_t s);
+
+}  // namespace dsoar
+
+using namespace dsoar;
+
+namespace {
+
+uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t cap = 65535u * 16u) {
+  uint64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  return (uint32_t)std::min<uint64_t>(g, cap);
+}
+
+int init_device_state(dsoar_heap* h, hipStream_t s) {
+  const uint64_t ctrl_words = kCtlWords + kShards * kShardStride;
+  const uint64_t work = std::max<uint64_t>(h->desc.num_blocks, (1 + 2 * h->desc.num_types) * (uint64_t)h->dev.bm_words);
+  hipLaunchKernelGGL(init_heap_kernel, dim3(grid_for(work, 256, 8192)), dim3(256), 0, s, h->dev, ctrl_words);
+  DSOAR_LAUNCHED(h);
+  for (uint32_t t = 0; t < h->desc.num_types; ++t) {
+    hipLaunchKernelGGL(init_scan_kernel, dim3(grid_for(h->num_tiles, 256, 1024)), dim3(256), 0, s,
+                       h->enum_out[t].st, h->enum_out[t].flags, h->num_tiles);
+    DSOAR_LAUNCHED(h);
+  }
+  return DSOAR_OK;
+}
+
+int sticky_status(const dsoar_stats& st) {
+  if (st.oom) return DSOAR_ERR_OOM;
+  if (st.retry_limit_hit) return DSOAR_ERR_RETRY_LIMIT;
+  if (st.double_free) return DSOAR_ERR_DOUBLE_FREE;
+  return DSOAR_OK;
+}
+
+int collect_stats(dsoar_heap* h, dsoar_stats* out, uint32_t* viol, int check, hipStream_t s) {
+  const uint32_t n32 = sizeof(StatsOut) / 4;
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(256), 0, s, (uint32_t*)h->stats_dev, n32);
+  DSOAR_LAUNCHED(h);
+  const uint32_t W0 = (h->desc.num_blocks + 63) / 64;
+  hipLaunchKernelGGL(stats_kernel, dim3(grid_for((uint64_t)W0 * 64, 256, 4096)), dim3(256), 0, s, h->dev,
+                     h->stats_dev, check);
+  DSOAR_LAUNCHED(h);
+  StatsOut so;
+  const uint64_t ctrl_words = kCtlWords + kShards * kShardStride;
+  static thread_local uint64_t ctrl[kCtlWords + kShards * kShardStride];
+  DSOAR_HIP(h, hipMemcpyAsync(&so, h->stats_dev, sizeof(so), hipMemcpyDeviceToHost, s));
+  DSOAR_HIP(h, hipMemcpyAsync(ctrl, h->dev.ctrl, ctrl_words * 8, hipMemcpyDeviceToHost, s));
+  DSOAR_HIP(h, hipStreamSynchronize(s));
+  dsoar_stats st;
+  memset(&st, 0, sizeof(st));
+  for (uint32_t sh = 0; sh < kShards; ++sh) {
+    const uint64_t* c = ctrl + kCtlWords + sh * kShardStride;
+    for (uint32_t t = 0; t < kMaxTypes; ++t) {
+      st.allocs[t] += c[kCntAllocs + t];
+      st.frees[t] += c[kCntFrees + t];
+    }
+    st.reserve_retries += c[kCntReserveRetries];
+    st.slow_paths += c[kCntSlowPaths];
+    st.find_fails += c[kCntFindFails];
+  }
+  for (uint32_t t = 0; t < kMaxTypes; ++t) {
+    st.live_objects[t] = so.live[t];
+    st.allocated_blocks[t] = so.allocated[t];
+    st.active_blocks[t] = so.active[t];
+    st.typed_blocks[t] = so.typed[t];
+  }
+  st.free_blocks = so.free_blocks;
+  st.num_blocks = h->desc.num_blocks;
+  st.oom = ctrl[kCtlOom] != 0;
+  st.retry_limit_hit = ctrl[kCtlRetryLimit] != 0;
+  st.double_free = ctrl[kCtlDoubleFree] != 0;
+  if (out) *out = st;
+  if (viol) {
+    for (uint32_t k = 0; k < DSOAR_INV_COUNT; ++k) viol[k] = so.viol[k];
+    for (uint32_t t = 0; t < h->desc.num_types; ++t)
+      if (st.live_objects[t] != st.allocs[t] - st.frees[t]) viol[DSOAR_INV_LIVE_COUNT] += 1;
+  }
+  return sticky_status(st);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dsoar_heap_bytes(const dsoar_heap_desc* desc) {
+  if (!desc_valid(desc)) return 0;
+  return (size_t)make_plan(desc).L.total_bytes;
+}
+
+int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_bytes, void* stream,
+                      dsoar_heap** out) {
+  if (!out) return DSOAR_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!desc_valid(desc) || !dev_mem || ((uintptr_t)dev_mem & 255u)) return DSOAR_ERR_INVALID_ARG;
+  const Plan p = make_plan(desc);
+  if (dev_bytes < p.L.total_bytes) return DSOAR_ERR_TOO_SMALL;
+  dsoar_heap* h = new (std::nothrow) dsoar_heap;
+  if (!h) return DSOAR_ERR_INVALID_ARG;
+  memset(h, 0, sizeof(*h));
+  h->desc = *desc;
+  h->layout = p.L;
+  h->base = (uint8_t*)dev_mem;
+  h->bytes = dev_bytes;
+  h->num_tiles = p.num_tiles;
+  DevHeap& d = h->dev;
+  d.data = h->base + p.L.data_offset;
+  d.obj_bitmap = (uint64_t*)(h->base + p.L.obj_bitmap_offset);
+  d.block_type = (uint32_t*)(h->base + p.L.block_type_offset);
+  d.bitmaps = (uint64_t*)(h->base + p.L.bitmaps_offset);
+  d.ctrl = (uint64_t*)(h->base + p.ctrl_off);
+  d.block_stride = p.L.block_stride;
+  d.capacity = desc->block_capacity;
+  d.cap_mask = desc->block_capacity == 64 ? ~0ull : ((1ull << desc->block_capacity) - 1);
+  d.num_blocks = desc->num_blocks;
+  d.num_types = desc->num_types;
+  d.nlevels = p.L.num_levels;
+  d.bm_words = (uint32_t)(p.L.bitmap_stride / 8);
+  for (uint32_t t = 0; t < desc->num_types; ++t)
+    for (uint32_t f = 0; f < desc->types[t].num_fields; ++f) {
+      d.field_off[t][f] = p.L.field_offset[t][f];
+      d.field_shift[t][f] = desc->types[t].field_bytes[f] == 8 ? 3 : 2;
+    }
+  h->stats_dev = (StatsOut*)(h->base + p.stats_off);
+  for (uint32_t t = 0; t < desc->num_types; ++t) {
+    EnumOut& e = h->enum_out[t];
+    e.R = (uint32_t*)(h->base + p.R_off[t]);
+    e.S = (uint64_t*)(h->base + p.S_off[t]);
+    e.st = (ScanState*)(h->base + p.scan_off[t]);
+    e.flags = (uint64_t*)(h->base + p.scan_off[t] + sizeof(ScanState));
+    e.num_tiles = p.num_tiles;
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete h;
+    return DSOAR_ERR_HIP;
+  }
+  h->num_cus = (uint32_t)prop.multiProcessorCount;
+  h->doall_wg_threads = 256;
+  h->doall_wgs_per_cu = 8;
+  const int rc = init_device_state(h, (hipStream_t)stream);
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return DSOAR_OK;
+}
+
+int dsoar_heap_destroy(dsoar_heap* h) {
+  if (!h) return DSOAR_ERR_INVALID_ARG;
+  delete h;
+  return DSOAR_OK;
+}
+
+int dsoar_heap_reset(dsoar_heap* h, void* stream) {
+  if (!heap_ok(h)) return DSOAR_ERR_INVALID_ARG;
+  return init_device_state(h, (hipStream_t)stream);
+}
+
+int dsoar_heap_get_layout(const dsoar_heap* h, dsoar_heap_layout* out) {
+  if (!heap_ok(h) || !out) return DSOAR_ERR_INVALID_ARG;
+  *out = h->layout;
+  return DSOAR_OK;
+}
+
+int dsoar_heap_set_launch(dsoar_heap* h, uint32_t wg_threads, uint32_t wgs_per_cu) {
+  if (!heap_ok(h) || wg_threads < 64 || wg_threads > 1024 || (wg_threads & 63) || wgs_per_cu < 1 ||
+      wgs_per_cu > 64)
+    return DSOAR_ERR_INVALID_ARG;
+  h->doall_wg_threads = wg_threads;
+  h->doall_wgs_per_cu = wgs_per_cu;
+  return DSOAR_OK;
+}
+
+int dsoar_enumerate(dsoar_heap* h, uint32_t type, void* stream) {
+  if (!heap_ok(h) || type >= h->desc.num_types) return DSOAR_ERR_INVALID_ARG;
+  return launch_enumerate(h, type, (hipStream_t)stream);
+}
+
+int dsoar_enum_count(dsoar_heap* h, uint32_t type, uint32_t* count, void* stream) {
+  if (!heap_ok(h) || type >= h->desc.num_types || !count) return DSOAR_ERR_INVALID_ARG;
+  return read_count(h, type, (hipStream_t)stream, count);
+}
+
+int dsoar_enum_arrays(dsoar_heap* h, uint32_t type, uint64_t* R_dev, uint64_t* S_dev) {
+  if (!heap_ok(h) || type >= h->desc.num_types || !R_dev || !S_dev) return DSOAR_ERR_INVALID_ARG;
+  *R_dev = (uint64_t)(uintptr_t)h->enum_out[type].R;
+  *S_dev = (uint64_t)(uintptr_t)h->enum_out[type].S;
+  return DSOAR_OK;
+}
+
+int dsoar_reclaim(dsoar_heap* h, void* stream) {
+  if (!heap_ok(h)) return DSOAR_ERR_INVALID_ARG;
+  const uint32_t W0 = (h->desc.num_blocks + 63) / 64;
+  hipLaunchKernelGGL(reclaim_kernel, dim3(grid_for((uint64_t)W0 * 64, 256, 8192)), dim3(256), 0,
+                     (hipStream_t)stream, h->dev);
+  DSOAR_LAUNCHED(h);
+  return DSOAR_OK;
+}
+
+int dsoar_parallel_do(dsoar_heap* h, uint32_t type, uint32_t method, const void* args, size_t args_bytes,
+                      uint32_t flags, void* stream) {
+  if (!heap_ok(h) || type >= h->desc.num_types) return DSOAR_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  switch (method) {
+    case DSOAR_METHOD_VISIT_COUNT: {
+      if (!args || args_bytes != sizeof(dsoar_visit_args)) return DSOAR_ERR_INVALID_ARG;
+      const dsoar_visit_args* a = (const dsoar_visit_args*)args;
+      if (!a->counts_dev) return DSOAR_ERR_INVALID_ARG;
+      return launch_doall<VisitCount>(h, type, VisitCount::Args{a->counts_dev}, flags, s);
+    }
+    case DSOAR_METHOD_DELETE_IF_MOD: {
+      if (!args || args_bytes != sizeof(dsoar_mod_args)) return DSOAR_ERR_INVALID_ARG;
+      const dsoar_mod_args* a = (const dsoar_mod_args*)args;
+      if (a->field >= h->desc.types[type].num_fields || h->desc.types[type].field_bytes[a->field] != 4 ||
+          a->modulus <= 0)
+        return DSOAR_ERR_INVALID_ARG;
+      return launch_doall<DeleteIfMod>(h, type, DeleteIfMod::Args{a->field, a->modulus, a->residue}, flags, s);
+    }
+    case DSOAR_METHOD_FIELD_GATHER: {
+      if (!args || args_bytes != sizeof(dsoar_gather_args)) return DSOAR_ERR_INVALID_ARG;
+      const dsoar_gather_args* a = (const dsoar_gather_args*)args;
+      const dsoar_type_layout& L = h->desc.types[type];
+      if (a->key_field >= L.num_fields || a->field >= L.num_fields || L.field_bytes[a->key_field] != 4 ||
+          !a->out_dev)
+        return DSOAR_ERR_INVALID_ARG;
+      FieldGather::Args g{a->key_field, a->field, a->num_keys, L.field_bytes[a->field] == 8 ? 1u : 0u,
+                          (uint8_t*)a->out_dev, a->present_dev};
+      return launch_doall<FieldGather>(h, type, g, flags, s);
+    }
+    case DSOAR_METHOD_MICRO_UPDATE:
+    case DSOAR_METHOD_MICRO_CULL:
+      return micro_doall(h, type, method, flags, s);
+    default:
+      return DSOAR_ERR_UNSUPPORTED;
+  }
+}
+
+int dsoar_heap_stats(dsoar_heap* h, dsoar_stats* out, void* stream) {
+  if (!heap_ok(h) || !out) return DSOAR_ERR_INVALID_ARG;
+  return collect_stats(h, out, nullptr, 0, (hipStream_t)stream);
+}
+
+int dsoar_heap_check(dsoar_heap* h, uint32_t* violations, void* stream) {
+  if (!heap_ok(h) || !violations) return DSOAR_ERR_INVALID_ARG;
+  int rc = dsoar_reclaim(h, stream);
+  if (rc) return rc;
+  return collect_stats(h, nullptr, violations, 1, (hipStream_t)stream);
+}
+
+int dsoar_alloc_n(dsoar_heap* h, uint32_t type, uint32_t n, dsoar_obj* out_dev, void* stream) {
+  if (!heap_ok(h) || type >= h->desc.num_types || (!out_dev && n)) return DSOAR_ERR_INVALID_ARG;
+  if (n == 0) return DSOAR_OK;
+  hipLaunchKernelGGL(alloc_n_kernel, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, (hipStream_t)stream, h->dev,
+                     type, n, out_dev);
+  DSOAR_LAUNCHED(h);
+  return DSOAR_OK;
+}
+
+int dsoar_free_n(dsoar_heap* h, const dsoar_obj* objs_dev, uint32_t n, void* stream) {
+  if (!heap_ok(h) || (!objs_dev && n)) return DSOAR_ERR_INVALID_ARG;
+  if (n == 0) return DSOAR_OK;
+  hipLaunchKernelGGL(free_n_kernel, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, (hipStream_t)stream, h->dev,
+                     objs_dev, n);
+  DSOAR_LAUNCHED(h);
+  return DSOAR_OK;
+}
+
+static int field_rw(dsoar_heap* h, uint32_t type, uint32_t field, const dsoar_obj* objs, uint32_t n, uint32_t* data,
+                    int write, void* stream) {
+  if (!heap_ok(h) || type >= h->desc.num_types || field >= h->desc.types[type].num_fields ||
+      h->desc.types[type].field_bytes[field] != 4 || (n && (!objs || !data)))
+    return DSOAR_ERR_INVALID_ARG;
+  if (n == 0) return DSOAR_OK;
+  hipLaunchKernelGGL(field_rw_kernel, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, (hipStream_t)stream, h->dev,
+                     type, field, objs, n, data, write);
+  DSOAR_LAUNCHED(h);
+  return DSOAR_OK;
+}
+
+int dsoar_field_read(dsoar_heap* h, uint32_t type, uint32_t field, const dsoar_obj* objs, uint32_t n,
+                     uint32_t* out_dev, void* stream) {
+  return field_rw(h, type, field, objs, n, out_dev, 0, stream);
+}
+
+int dsoar_field_write(dsoar_heap* h, uint32_t type, uint32_t field, const dsoar_obj* objs, uint32_t n,
+                      const uint32_t* in_dev, void* stream) {
+  return field_rw(h, type, field, objs, n, (uint32_t*)in_dev, 1, stream);
+}
+
+const char* dsoar_error_string(int status) {
+  switch (status) {
+    case DSOAR_OK: return "ok";
+    case DSOAR_ERR_INVALID_ARG: return "invalid argument";
+    case DSOAR_ERR_OOM: return "out of memory: a device new found no free block";
+    case DSOAR_ERR_RETRY_LIMIT: return "a bounded device retry loop gave up";
+    case DSOAR_ERR_HIP: return "HIP runtime error";
+    case DSOAR_ERR_DOUBLE_FREE: return "delete of an unallocated slot";
+    case DSOAR_ERR_TOO_SMALL: return "device buffer too small";
+    case DSOAR_ERR_UNSUPPORTED: return "unsupported method";
+    default: return "unknown status";
+  }
+}
+
+int dsoar_abi_version(void) { return DSOAR_ABI_VERSION; }
+
+int dsoar_last_hip_error(const dsoar_heap* h) { return h ? (int)h->last_hip : -1; }
+
+size_t dsoar_bitmap_bytes(uint32_t nbits) {
+  if (nbits == 0 || nbits > (1u << 30)) return 0;
+  return (size_t)bitmap_words(nbits) * 8 + 256;  // + a retry-flag word
+}
+
+int dsoar_bitmap_init(void* bm_dev, uint32_t nbits, int all_set, void* stream) {
+  if (!bm_dev || nbits == 0 || nbits > (1u << 30) || ((uintptr_t)bm_dev & 7u)) return DSOAR_ERR_INVALID_ARG;
+  const uint32_t words = bitmap_words(nbits) + 32;
+  hipLaunchKernelGGL(init_bitmap_kernel, dim3(grid_for(words, 256, 8192)), dim3(256), 0, (hipStream_t)stream,
+                     (uint64_t*)bm_dev, nbits, words, all_set);
+  // The padding and flag words after the levels are cleared by the same kernel
+  // (full_word is 0 past the last level).
+  if (hipGetLastError() != hipSuccess) return DSOAR_ERR_HIP;
+  return DSOAR_OK;
+}
+
+int dsoar_bitmap_run(void* bm_dev, uint32_t nbits, const uint32_t* ops_dev, uint32_t n, const uint32_t* start_dev,
+                     int32_t* results_dev, void* stream) {
+  if (!bm_dev || nbits == 0 || nbits > (1u << 30) || (n && (!ops_dev || !results_dev)))
+    return DSOAR_ERR_INVALID_ARG;
+  if (n == 0) return DSOAR_OK;
+  uint64_t* words = (uint64_t*)bm_dev;
+  uint64_t* flag = words + bitmap_words(nbits);
+  hipLaunchKernelGGL(bitmap_ops_kernel, dim3(grid_for((uint64_t)n * 64, 256, 1u << 30)), dim3(256), 0,
+                     (hipStream_t)stream, words, nbits, ops_dev, n, start_dev, results_dev, flag);
+  if (hipGetLastError() != hipSuccess) return DSOAR_ERR_HIP;
+  return DSOAR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Alloc/do-all microbenchmark: objects {int32 id, float32 x, float32 v};
+// each step updates every object, deletes every id % 3 == 0 and creates the
+// same ids again.
+#include "internal.hpp"
+
+namespace dsoar {
+
+namespace {
+
+enum : uint32_t { kId = 0, kX = 1, kV = 2 };
+
+struct MicroUpdate {
+  struct Args { uint32_t unused; };
+  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args&) {
+    float* x = field_ptr<float>(h, self, type, kX);
+    const float v = *field_ptr<float>(h, self, type, kV);
+    *x = __builtin_fmaf(0.01f, v, *x);  // one rounding
+    return false;
+  }
+};
+
+struct MicroCull {
+  struct Args { uint32_t unused; };
+  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args&) {
+    return (*field_ptr<int32_t>(h, self, type, kId) % 3) == 0;
+  }
+};
+
+// Lane i creates an object with id = id_mul * i and the i-th input values.
+__global__ void micro_create_kernel(DevHeap h, uint32_t type, uint32_t n, uint32_t id_mul, const float* xs,
+                                    const float* vs) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t o = dsoar_new(h, type);
+  if (o == kNull) return;
+  *field_ptr<int32_t>(h, o, type, kId) = (int32_t)(id_mul * i);
+  *field_ptr<float>(h, o, type, kX) = xs[i];
+  *field_ptr<float>(h, o, type, kV) = vs[i];
+}
+
+bool micro_type_ok(const dsoar_heap* h, uint32_t type) {
+  if (type >= h->desc.num_types) return false;
+  const dsoar_type_layout& L = h->desc.types[type];
+  return L.num_fields >= 3 && L.field_bytes[kId] == 4 && L.field_bytes[kX] == 4 && L.field_bytes[kV] == 4;
+}
+
+int launch_create(dsoar_heap* h, uint32_t type, uint32_t n, uint32_t id_mul, const float* xs, const float* vs,
+                  hipStream_t s) {
+  if (n == 0) return DSOAR_OK;
+  hipLaunchKernelGGL(micro_create_kernel, dim3((n + 255) / 256), dim3(256), 0, s, h->dev, type, n, id_mul, xs, vs);
+  DSOAR_LAUNCHED(h);
+  return DSOAR_OK;
+}
+
+}  // namespace
+
+int micro_doall(dsoar_heap* h, uint32_t type, uint32_t method, uint32_t flags, hipStream_t s) {
+  if (!micro_type_ok(h, type)) return DSOAR_ERR_INVALID_ARG;
+  if (method == DSOAR_METHOD_MICRO_UPDATE) return launch_doall<MicroUpdate>(h, type, {0}, flags, s);
+  return launch_doall<MicroCull>(h, type, {0}, flags, s);
+}
+
+}  // namespace dsoar
+
+using namespace dsoar;
+
+extern "C" {
+
+int dsoar_micro_init(dsoar_heap* h, uint32_t type, uint32_t n, const float* x0_dev, const float* v0_dev,
+                     void* stream) {
+  if (!heap_ok(h) || !micro_type_ok(h, type) || (n && (!x0_dev || !v0_dev)) || n > (1u << 31))
+    return DSOAR_ERR_INVALID_ARG;
+  return launch_create(h, type, n, 1, x0_dev, v0_dev, (hipStream_t)stream);
+}
+
+int dsoar_micro_step(dsoar_heap* h, uint32_t type, uint32_t n_renew, const float* xs_dev, const float* vs_dev,
+                     uint32_t flags, void* stream) {
+  if (!heap_ok(h) || !micro_type_ok(h, type) || (n_renew && (!xs_dev || !vs_dev)) || n_renew > (1u << 30))
+    return DSOAR_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t base = flags & DSOAR_DO_PLAIN;
+  int rc = launch_doall<MicroUpdate>(h, type, {0}, base, s);
+  if (rc) return rc;
+  // Update neither creates nor deletes, so the cull reuses its enumeration.
+  rc = launch_doall<MicroCull>(h, type, {0}, base | DSOAR_DO_REUSE_ENUM, s);
+  if (rc) return rc;
+  return launch_create(h, type, n_renew, 3, xs_dev, vs_dev, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+"""The C-ABI library loads without a GPU and exports every function that
+include/dsoar.h declares; host-only entry points validate their arguments."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1809_07444_amd import _capi as C
+from paper_1809_07444_amd.heap import make_desc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")]
+
+
+def declared_functions():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**(dsoar_[a-z0-9_]+)\s*\(", text, re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_core_calls():
+    names = declared_functions()
+    for n in ["dsoar_heap_create", "dsoar_heap_destroy", "dsoar_parallel_do", "dsoar_heap_stats",
+              "dsoar_heap_check", "dsoar_enumerate", "dsoar_alloc_n", "dsoar_free_n"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported():
+    lib = C.load()
+    missing = [n for n in sorted(declared_functions()) if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_binding_covers_every_declared_symbol():
+    assert declared_functions() <= set(C.SIGNATURES)
+
+
+def test_version_and_errors():
+    lib = C.load()
+    assert lib.dsoar_abi_version() == 1
+    assert lib.dsoar_error_string(-2).startswith(b"out of memory")
+    assert lib.dsoar_error_string(12345) == b"unknown status"
+
+
+def test_heap_bytes_validates():
+    lib = C.load()
+    ok = make_desc(4096, 64, [(4, 4, 4)])
+    n = lib.dsoar_heap_bytes(ctypes.byref(ok))
+    # data: 4096 blocks x 3 arrays x 256 B; plus bitmaps, scan arrays, counters.
+    assert n >= 4096 * 768 + 4096 * 12
+    for bad in [make_desc(0, 64, [(4,)]), make_desc(16, 48, [(4,)]), make_desc(16, 64, [(3,)]),
+                make_desc(16, 64, [])]:
+        assert lib.dsoar_heap_bytes(ctypes.byref(bad)) == 0
+
+
+def test_create_rejects_bad_buffers():
+    lib = C.load()
+    d = make_desc(64, 64, [(4,)])
+    h = ctypes.c_void_p()
+    assert lib.dsoar_heap_create(ctypes.byref(d), None, 1 << 20, None, ctypes.byref(h)) == -1
+    assert lib.dsoar_heap_create(ctypes.byref(d), 256, 16, None, ctypes.byref(h)) == -6
+    assert lib.dsoar_heap_create(ctypes.byref(d), 257, 1 << 20, None, ctypes.byref(h)) == -1
+    assert lib.dsoar_parallel_do(None, 0, 1, None, 0, 0, None) == -1
+    assert lib.dsoar_heap_destroy(None) == -1
+
+
+def test_bitmap_bytes():
+    lib = C.load()
+    assert lib.dsoar_bitmap_bytes(0) == 0
+    assert lib.dsoar_bitmap_bytes(64) == 256 + 256
+    assert lib.dsoar_bitmap_bytes(1 << 30) > (1 << 27)

@@ -1,0 +1,121 @@
+"""Device hierarchical bitmap (Sec. 2.1 operations, Sec. 3 / Alg. 2) against
+the paper's cascade example, exact outcomes of concurrent storms, and
+container consistency at quiescence."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+from paper_1809_07444_amd import _capi as C  # noqa: E402
+from paper_1809_07444_amd.heap import DeviceBitmap  # noqa: E402
+
+
+def words_np(bm):
+    return [w.cpu().numpy().view(np.uint64) for w in bm.level_words()]
+
+
+def assert_consistent(bm):
+    lv = words_np(bm)
+    n = bm.nbits
+    for l, w in enumerate(lv):
+        # no bits at or beyond the level's size
+        for i, x in enumerate(w):
+            lo = 64 * i
+            if n - lo < 64:
+                assert int(x) >> max(n - lo, 0) == 0, (l, i)
+        if l + 1 < len(lv):
+            up = lv[l + 1]
+            for i, x in enumerate(w):
+                assert ((int(up[i // 64]) >> (i % 64)) & 1) == (1 if int(x) else 0), (l, i)
+        n = len(w)
+
+
+def ops_tensor(kinds, poss):
+    return torch.tensor(np.stack([kinds, poss], axis=1).astype(np.int32), device="cuda")
+
+
+def test_width64_cascade_analogue_of_paper_example():
+    # The paper's example (N = 32, 4-bit containers) at the real width: with
+    # 64^3 bits, clearing the only set bit of container 1152 empties it, which
+    # clears level-1 bit 1152 (emptying level-1 container 18), which clears
+    # top bit 18.  Bit 3 keeps the branch of top bit 0 alive.
+    bm = DeviceBitmap(64 ** 3)
+    p1 = 18 * 4096
+    r = bm.run(ops_tensor([C.BM_TRY_SET, C.BM_TRY_SET], [p1, 3]))
+    assert r.tolist() == [1, 1]
+    lv = words_np(bm)
+    assert int(lv[2][0]) == (1 << 18) | 1
+    r = bm.run(ops_tensor([C.BM_CLEAR], [p1]))
+    assert r.tolist() == [0]
+    lv = words_np(bm)
+    assert int(lv[0][1152]) == 0 and int(lv[1][18]) == 0 and int(lv[2][0]) == 1
+    assert_consistent(bm)
+
+
+@pytest.mark.parametrize("nbits,seed", [(4096, 1), (5000, 2), (64 ** 3 + 17, 3)])
+def test_concurrent_try_ops_exact(nbits, seed):
+    rng = np.random.default_rng(seed)
+    init = rng.random(nbits) < 0.3
+    bm = DeviceBitmap(nbits)
+    pos0 = np.nonzero(init)[0]
+    assert (bm.run(ops_tensor(np.full(len(pos0), C.BM_TRY_SET), pos0)).cpu().numpy() == 1).all()
+    assert_consistent(bm)
+    # One op per position, all concurrent: many wavefronts hit the same
+    # containers, so cascades race with sets in the same container.
+    n = min(nbits, 20000)
+    pos = rng.permutation(nbits)[:n]
+    kinds = rng.integers(0, 2, size=n)  # 0 try_set, 1 try_clear
+    res = bm.run(ops_tensor(kinds, pos)).cpu().numpy()
+    exp_res = np.where(kinds == 0, ~init[pos], init[pos]).astype(np.int32)
+    assert np.array_equal(res, exp_res)
+    final = init.copy()
+    final[pos[kinds == 0]] = True
+    final[pos[kinds == 1]] = False
+    lv0 = words_np(bm)[0]
+    got = np.unpackbits(lv0.view(np.uint8), bitorder="little")[:nbits].astype(bool)
+    assert np.array_equal(got, final)
+    assert_consistent(bm)
+
+
+@pytest.mark.parametrize("nbits", [1, 64, 65, 4097, 30000])
+def test_find_clear_drains_exactly(nbits):
+    bm = DeviceBitmap(nbits, all_set=True)
+    assert_consistent(bm)
+    n = nbits + 100
+    rng = np.random.default_rng(nbits)
+    starts = torch.tensor(rng.integers(0, 2 ** 31, size=n).astype(np.int32), device="cuda")
+    res = bm.run(ops_tensor(np.full(n, C.BM_FIND_CLEAR), np.zeros(n, np.int64)), starts).cpu().numpy()
+    got = res[res >= 0]
+    assert len(got) == nbits and len(set(got.tolist())) == nbits     # each bit handed out once
+    assert (res[res < 0] == -1).sum() == 100
+    assert all(int(w.abs().sum()) == 0 for w in bm.level_words())
+
+
+def test_try_find_set_at_quiescence_brute_force():
+    rng = np.random.default_rng(5)
+    for nbits, density in [(300, 0.0), (300, 0.01), (4096, 0.001), (70000, 0.0001)]:
+        bm = DeviceBitmap(nbits)
+        init = rng.random(nbits) < density
+        pos0 = np.nonzero(init)[0]
+        if len(pos0):
+            bm.run(ops_tensor(np.full(len(pos0), C.BM_TRY_SET), pos0))
+        n = 256
+        starts = torch.tensor(rng.integers(0, 2 ** 31, size=n).astype(np.int32), device="cuda")
+        res = bm.run(ops_tensor(np.full(n, C.BM_TRY_FIND_SET), np.zeros(n, np.int64)), starts).cpu().numpy()
+        if len(pos0) == 0:
+            assert (res == -1).all()
+        else:
+            assert np.isin(res, pos0).all()
+
+
+def test_set_clear_pairs_meet():
+    # set(pos) and clear(pos) issued together on a clear bit: clear retries
+    # until the set lands (Sec. 2.1), so both finish and the bit ends clear.
+    nbits = 8192
+    bm = DeviceBitmap(nbits)
+    pos = np.arange(0, nbits, 8)
+    kinds = np.concatenate([np.full(len(pos), C.BM_CLEAR), np.full(len(pos), C.BM_SET)])
+    res = bm.run(ops_tensor(kinds, np.concatenate([pos, pos]))).cpu().numpy()
+    assert (res == 0).all()
+    assert all(int(w.abs().sum()) == 0 for w in bm.level_words())

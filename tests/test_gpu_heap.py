@@ -1,0 +1,162 @@
+"""Device heap: new/delete (Alg. 1 with request coalescing), quiescent
+reclamation, enumeration and do-all, checked against the definitions of the
+block states (Sec. 2), brute-force scans of the raw bitmaps, and the oracle's
+ideal block counts."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+from paper_1809_07444_amd import _capi as C  # noqa: E402
+from paper_1809_07444_amd.heap import Heap  # noqa: E402
+
+
+def live_set(heap, t=None):
+    raw = heap.raw()
+    ob = raw["obj_bitmap"].cpu().numpy().view(np.uint64)
+    bt = raw["block_type"].cpu().numpy().view(np.uint32)
+    out = set()
+    for b in np.nonzero(ob)[0]:
+        if t is not None and bt[b] != t:
+            continue
+        w = int(ob[b])
+        for s in range(64):
+            if (w >> s) & 1:
+                out.add(int(b) * 64 + s)
+    return out
+
+
+@pytest.mark.parametrize("cap", [64, 32])
+def test_bulk_alloc_dense_and_distinct(cap):
+    M = 4096
+    heap = Heap(M, cap, [(4, 4, 4)])
+    n = 65536 if cap == 64 else 65536 // 2
+    h = heap.alloc_n(0, n).cpu().numpy().view(np.uint32)
+    assert (h != C.NULL).all()
+    assert len(np.unique(h)) == n                           # I1: no slot handed out twice
+    assert ((h & 63) < cap).all()
+    assert live_set(heap) == set(h.tolist())
+    st = heap.stats()
+    assert st["live"] == [n] and st["allocs"] == [n] and st["frees"] == [0]
+    # Dense policy: every wavefront of 64 lanes fills fresh blocks completely.
+    assert st["allocated_blocks"] == [n // cap] and st["active_blocks"] == [0]
+    assert heap.check() == {}
+
+
+def test_ragged_alloc_and_oom():
+    heap = Heap(16, 64, [(4,)])
+    h = heap.alloc_n(0, 16 * 64 + 100).cpu().numpy().view(np.uint32)
+    ok = h[h != C.NULL]
+    assert len(ok) == 16 * 64 and len(np.unique(ok)) == 16 * 64
+    assert (h == C.NULL).sum() == 100
+    st = heap.stats(raise_sticky=False)
+    assert st["oom"] == 1 and st["status"] == C.ERR_OOM and st["free_blocks"] == 0
+    chk = heap.check()
+    assert chk == {"sticky": "DSOAR_ERR_OOM"}
+
+
+@pytest.mark.parametrize("cap,ntypes", [(64, 1), (64, 3), (32, 2)])
+def test_churn_invariants_and_visits(cap, ntypes):
+    rng = np.random.default_rng(cap + ntypes)
+    M = 512
+    heap = Heap(M, cap, [(4, 8)] * ntypes)
+    live = {}
+    for rnd in range(6):
+        for t in range(ntypes):
+            n = int(rng.integers(1, 3000))
+            h = heap.alloc_n(t, n).cpu().numpy().view(np.uint32)
+            h = h[h != C.NULL]
+            for x in h.tolist():
+                assert x not in live
+                live[x] = t
+        # delete a random subset (grouped by block inside the kernel)
+        keys = np.array(sorted(live), dtype=np.uint32)
+        kill = keys[rng.random(len(keys)) < 0.5]
+        heap.free_n(torch.tensor(kill.view(np.int32), device="cuda"))
+        for x in kill.tolist():
+            del live[x]
+        st = heap.stats()
+        for t in range(ntypes):
+            assert st["live"][t] == sum(1 for v in live.values() if v == t)
+            assert st["live"][t] == st["allocs"][t] - st["frees"][t]
+        assert live_set(heap) == set(live)
+        for t in range(ntypes):
+            # I8: the do-all visits each live object once and nothing else.
+            counts = heap.visit_counts(t).cpu().numpy()
+            exp = np.zeros(M * 64, dtype=np.int32)
+            idx = [x for x, v in live.items() if v == t]
+            exp[idx] = 1
+            assert np.array_equal(counts, exp)
+        assert heap.check() == {}
+        st = heap.stats()
+        for t in range(ntypes):
+            assert st["allocated_blocks"][t] >= -(-st["live"][t] // cap)
+
+
+def test_double_free_flagged():
+    heap = Heap(8, 64, [(4,)])
+    h = heap.alloc_n(0, 10)
+    heap.free_n(h[:3])
+    heap.free_n(h[:1])
+    st = heap.stats(raise_sticky=False)
+    assert st["double_free"] == 1 and st["live"] == [7] and st["frees"] == [3]
+
+
+def test_field_roundtrip_and_delete_if_mod():
+    heap = Heap(64, 64, [(4, 4)])
+    h = heap.alloc_n(0, 1000)
+    ids = torch.arange(1000, dtype=torch.int32, device="cuda")
+    heap.field_write(0, 0, h, ids)
+    heap.field_write(0, 1, h, ids * 7)
+    assert torch.equal(heap.field_read(0, 1, h), ids * 7)
+    heap.delete_if_mod(0, 0, 3, 0)
+    out, present = heap.gather(0, 0, 1, 1000)
+    p = present.cpu().numpy().astype(bool)
+    assert np.array_equal(p, np.arange(1000) % 3 != 0)
+    assert np.array_equal(out.cpu().numpy()[p], (np.arange(1000) * 7)[p])
+    assert heap.check() == {}
+
+
+def test_enumeration_matches_brute_force_and_reclaims():
+    rng = np.random.default_rng(3)
+    M = 3000  # ragged: not a multiple of 64, several scan tiles
+    heap = Heap(M, 64, [(4,), (4,)])
+    a = heap.alloc_n(0, 100000)
+    b = heap.alloc_n(1, 50000)
+    kill = a[torch.tensor(rng.random(100000) < 0.7, device="cuda")]
+    heap.free_n(kill)
+    heap.free_n(b)                                           # type 1 becomes empty
+    heap.enumerate(0)
+    cnt = heap.enum_count(0)
+    R, S = heap.enum_arrays(0, cnt)
+    raw = heap.raw()
+    ob = raw["obj_bitmap"].cpu().numpy().view(np.uint64)
+    bt = raw["block_type"].cpu().numpy()
+    exp_blocks = [i for i in range(M) if bt[i] == 0 and ob[i] != 0]
+    assert R.cpu().numpy().tolist() == exp_blocks            # ascending, exactly the non-empty blocks
+    assert np.array_equal(S.cpu().numpy().view(np.uint64), ob[exp_blocks])
+    heap.enumerate(1)
+    assert heap.enum_count(1) == 0
+    st = heap.stats()
+    assert st["allocated_blocks"][1] == 0 and st["typed_blocks"][1] == 0
+    assert heap.check() == {}
+    # reused blocks take the other type after reclamation
+    c = heap.alloc_n(1, 64 * 10)
+    assert (c.cpu().numpy().view(np.uint32) != C.NULL).all()
+    assert heap.check() == {}
+
+
+@pytest.mark.parametrize("flags", [C.DO_PERSISTENT, C.DO_PLAIN])
+def test_enumeration_large_many_tiles(flags):
+    M = 1 << 18  # 4096 level-0 words, 128 scan tiles, 3 levels
+    heap = Heap(M, 64, [(4,)])
+    n = 3_000_000
+    h = heap.alloc_n(0, n)
+    keep = torch.rand(n, device="cuda") < 0.5
+    heap.free_n(h[~keep])
+    counts = heap.visit_counts(0, flags)
+    exp = torch.zeros(M * 64, dtype=torch.int32, device="cuda")
+    exp[h[keep].long()] = 1
+    assert torch.equal(counts, exp)
+    assert heap.check() == {}
