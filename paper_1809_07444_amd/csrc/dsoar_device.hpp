@@ -32,6 +32,7 @@ constexpr uint32_t kTypeNone = 0xFFFFFFFFu;
 constexpr int32_t kFail = -1;
 constexpr uint32_t kSpinLimit = 1u << 20;  // bound of every retry loop
 constexpr uint32_t kShards = 64;           // counter shards (spread atomics)
+constexpr uint32_t kOomRetries = 4;        // active lookups retried before OOM
 
 // Control words (uint64 array at DevHeap::ctrl).
 enum : uint32_t {
@@ -327,7 +328,7 @@ __device__ inline uint32_t new_uniform(const DevHeap& h, uint32_t type) {
   uint32_t result = kNull;
   uint32_t served = 0;
   uint32_t start = bcast32(hash32((blockIdx.x << 4) ^ (threadIdx.x >> 6) ^ 0x5bd1e995u));
-  uint32_t retries = 0, slow = 0, fails = 0;
+  uint32_t retries = 0, slow = 0, fails = 0, oom_rounds = 0;
   bool oom = false;
   for (uint32_t it = 0; served < n; ++it) {
     if (it >= kSpinLimit) {
@@ -340,6 +341,13 @@ __device__ inline uint32_t new_uniform(const DevHeap& h, uint32_t type) {
       ++fails;
       bid = bm_find_clear(free_bm(h), start);
       if (bid == kFail) {
+        // No free block.  A block another wavefront is just opening may not
+        // be marked active yet; look again a few times before giving up.
+        if (++oom_rounds <= kOomRetries) {
+          __builtin_amdgcn_s_sleep(8);
+          start = hash32(start + it + 1);
+          continue;
+        }
         oom = true;
         break;
       }
