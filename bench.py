@@ -1,0 +1,257 @@
+"""Benchmark of the object heap + parallel do-all on one MI355X.
+
+Default workload: Game of Life as objects on a 1024 x 1024 torus, Bernoulli(0.1)
+alive, 200 generations.  One step = reset the heap, create the initial objects
+and run the 200 generations (4 do-alls each, replayed from a HIP graph), with
+the seeded input grid already resident in device memory.
+
+Prints one JSON line with the headline throughput (allocations + frees per
+second), do-all objects per second, the roofline entry of the dominant kernel
+(per-launch HIP-event timing over a profiled pass of the same workload) and
+the CPU baseline (the oracle, single thread, on a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "allocs+frees/sec and do-all objects/sec (HBM GB/s % peak); batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", default="gol", choices=["gol", "micro", "micro_scaled"])
+    p.add_argument("--seed", type=int, default=24301)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-graph", action="store_true")
+    p.add_argument("--traffic-probe", action="store_true",
+                   help="after the run, launch one elementwise kernel over 256 MiB (counter calibration)")
+    p.add_argument("--scaled-blocks", type=int, default=1 << 22)
+    return p.parse_args()
+
+
+# ------------------------------------------------------------- bytes model --
+# Algorithmic bytes each kernel kind must move (this-object fields, other
+# objects' fields, new objects' fields, the compacted list), from the heap's
+# counters over the profiled pass.  See the design notes for the derivation.
+
+def gol_kernel_bytes(kind, launches, st, M):
+    A, K = 1, 2  # Alive, Candidate type ids
+    va, vk = st["visits"][A] / 2, st["visits"][K] / 2     # each type is visited by two do-alls
+    if kind == "gol_alive_prep":
+        return va * (12 + 64) + st["allocs"][K] * 16 + va / 64 * 12
+    if kind == "gol_cand_prep":
+        return vk * (12 + 64) + vk / 64 * 12
+    if kind == "gol_alive_update":
+        return va * 4 + st["frees"][A] * 12 + va / 64 * 12
+    if kind == "gol_cand_update":
+        births = st["allocs"][A]
+        return vk * 20 + births * 16 + vk / 64 * 12
+    if kind == "enumerate":
+        return launches * (M / 8) + (va + vk) / 64 * 20
+    return None
+
+
+def micro_kernel_bytes(kind, launches, st, M):
+    v = st["visits"][0] / 2  # update and cull visit the same objects
+    if kind == "micro_update":
+        return v * 12 + v / 64 * 12
+    if kind == "micro_cull":
+        return v * 4 + st["frees"][0] * 0 + v / 64 * 12 + v / 64 * 8
+    if kind == "enumerate":
+        return launches * (M / 8) + v / 64 * 20
+    return None
+
+
+# --------------------------------------------------------------- workloads --
+
+class GolWorkload:
+    name = "gol"
+
+    def __init__(self, args):
+        import torch
+        from paper_1809_07444_amd import _capi as C
+        from paper_1809_07444_amd import apps
+        from synth import workloads as W
+        self.C = C
+        self.side, self.gens = 1024, 200
+        self.grid = W.gol_grid(self.side, self.side, seed=args.seed)
+        self.gol = apps.GameOfLife([self.grid])
+        self.flags = C.DO_PERSISTENT | (0 if args.no_graph else C.GOL_GRAPH)
+        self.M = self.gol.heap.num_blocks
+        self.stream = self.gol.stream
+        self.torch = torch
+        self.config = {"workload": f"gol-{self.side}x{self.side}-bernoulli0.1-{self.gens}gen",
+                       "worlds": 1, "cells": self.side ** 2, "generations": self.gens,
+                       "heap_blocks": self.M, "block_capacity": 64, "graph": not args.no_graph,
+                       "seed": args.seed}
+
+    def step(self):
+        self.gol.init()
+        self.gol.step(self.gens, self.flags)
+
+    def profiled_step(self):
+        # Same work, eager persistent launches, so each kernel is bracketed by events.
+        self.gol.init()
+        self.gol.step(self.gens, self.C.DO_PERSISTENT)
+
+    def stats(self):
+        return self.gol.heap.stats()
+
+    def kernel_bytes(self, kind, launches, st):
+        return gol_kernel_bytes(kind, launches, st, self.M)
+
+    def heap(self):
+        return self.gol.heap
+
+    def cpu_baseline(self):
+        import oracle
+        t0 = time.perf_counter()
+        _, counts = oracle.gol_run(self.grid, self.gens)
+        dt = time.perf_counter() - t0
+        # The object model's allocations and frees for the same generations:
+        # candidates are created and deleted, births create, deaths delete.
+        ops = int(2 * counts[:, 0].sum() + counts[:, 1].sum() + counts[:, 2].sum())
+        return {"value": ops / dt, "unit": "allocs+frees/s", "cores": 1, "kind": "oracle",
+                "sample": f"dense B3/S23 oracle, full {self.side}x{self.side} torus, {self.gens} generations, "
+                          f"{dt:.2f} s; rate = object-model allocs+frees of those generations / oracle time"}
+
+
+class MicroWorkload:
+    name = "micro"
+
+    def __init__(self, args, scaled=False):
+        import torch
+        from paper_1809_07444_amd import _capi as C
+        from paper_1809_07444_amd import apps
+        from synth import workloads as W
+        self.C = C
+        if scaled:
+            self.M = args.scaled_blocks
+            n, steps = 16 * self.M, 2
+        else:
+            self.M, n, steps = 4096, 65536, 10
+        self.inp = W.micro_inputs(n, steps, seed=args.seed)
+        self.mb = apps.MicroBench(self.inp, self.M, 64)
+        self.torch = torch
+        self.stream = None
+        self.config = {"workload": f"micro-{n}obj-{self.M}blocks-{steps}steps" + ("-scaled" if scaled else ""),
+                       "objects": n, "heap_blocks": self.M, "block_capacity": 64, "steps": steps,
+                       "seed": args.seed}
+
+    def step(self):
+        self.mb.run()
+
+    profiled_step = step
+
+    def stats(self):
+        return self.mb.heap.stats()
+
+    def kernel_bytes(self, kind, launches, st):
+        return micro_kernel_bytes(kind, launches, st, self.M)
+
+    def heap(self):
+        return self.mb.heap
+
+    def cpu_baseline(self):
+        import oracle
+        from synth import workloads as W
+        n = min(self.inp.n_init, 1 << 22)
+        inp = self.inp if n == self.inp.n_init else W.micro_inputs(n, self.inp.steps)
+        t0 = time.perf_counter()
+        r = oracle.micro_run(inp)
+        dt = time.perf_counter() - t0
+        return {"value": (r.allocs + r.frees) / dt, "unit": "allocs+frees/s", "cores": 1, "kind": "oracle",
+                "sample": f"micro oracle, {n} objects x {inp.steps} steps, {dt:.3f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(sharding across GPUs is described in the design notes, not built)"}))
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.workload == "gol":
+        wl = GolWorkload(args)
+    else:
+        wl = MicroWorkload(args, scaled=args.workload == "micro_scaled")
+
+    for _ in range(args.warmup):
+        wl.step()
+    torch.cuda.synchronize()
+    st0 = wl.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        wl.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st1 = wl.stats()
+    # Counters accumulate until a reset; init() resets the heap, so the stats
+    # after the timed loop describe exactly the last step.
+    per_step_ops = sum(st1["allocs"]) + sum(st1["frees"])
+    per_step_visits = sum(st1["visits"])
+    ms = dt / max(args.steps, 1) * 1e3
+    value = per_step_ops / (ms / 1e3)
+
+    # Profiled pass: per-launch HIP events on the launch stream.
+    heap = wl.heap()
+    heap.set_timing(True)
+    wl.profiled_step()
+    kern = heap.timing()
+    stp = wl.stats()
+    heap.set_timing(False)
+    kernels = {}
+    best = None
+    for kind, (launches, tot_ms) in kern.items():
+        b = wl.kernel_bytes(kind, launches, stp)
+        kernels[kind] = {"launches": launches, "avg_us": tot_ms / launches * 1e3, "total_ms": tot_ms,
+                         "gbs": (b / (tot_ms / 1e3) / 1e9) if b is not None and tot_ms > 0 else None}
+        if best is None or tot_ms > kern[best][1]:
+            best = kind
+    roof = None
+    if best is not None and kernels[best]["gbs"] is not None:
+        ach = kernels[best]["gbs"]
+        roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": best,
+                "avg_launch_us": round(kernels[best]["avg_us"], 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = wl.cpu_baseline()
+
+    if args.traffic_probe:
+        a = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.add(a, 1, out=b)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "allocs+frees/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32/u64", "data": "synthetic", "config": wl.config,
+        "doall_objects_per_s": per_step_visits / (ms / 1e3),
+        "per_step": {"allocs": st1["allocs"], "frees": st1["frees"], "doall_visits": st1["visits"],
+                     "reserve_retries": st1["reserve_retries"], "slow_paths": st1["slow_paths"]},
+        "roofline": roof, "cpu_baseline": cpu, "kernels": kernels,
+    }
+    del st0
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -99,6 +99,7 @@ typedef struct {
   uint64_t allocs[DSOAR_MAX_TYPES];       /* successful device news */
   uint64_t frees[DSOAR_MAX_TYPES];        /* successful device deletes */
   uint64_t live_objects[DSOAR_MAX_TYPES]; /* popcount of the object bitmaps */
+  uint64_t visits[DSOAR_MAX_TYPES];       /* objects visited by do-all methods */
   uint32_t allocated_blocks[DSOAR_MAX_TYPES];
   uint32_t active_blocks[DSOAR_MAX_TYPES];
   uint32_t typed_blocks[DSOAR_MAX_TYPES]; /* blocks whose type word is t */
@@ -150,6 +151,17 @@ int dsoar_heap_get_layout(const dsoar_heap* heap, dsoar_heap_layout* out);
  * multiple of 64) and, for persistent launches, wgs_per_cu workgroups per
  * compute unit (1..64).  Defaults 256 and 8. */
 int dsoar_heap_set_launch(dsoar_heap* heap, uint32_t wg_threads, uint32_t wgs_per_cu);
+
+/* Per-launch timing: when enabled, every enumeration and do-all launch of
+ * this heap is bracketed by a pair of HIP events on its stream (at most 8192
+ * launches are recorded between reports).  dsoar_heap_timing synchronises on
+ * the last event, aggregates the recorded launches by kernel kind (1 =
+ * enumeration; do-all kinds: 10 visit count, 11 delete-if-mod, 12 gather,
+ * 20/21 micro update/cull, 30..33 Game of Life phases 1..4, 40.. Sugarscape
+ * phases) into kinds/counts/total_ms, and clears the records. */
+int dsoar_heap_set_timing(dsoar_heap* heap, int enable);
+int dsoar_heap_timing(dsoar_heap* heap, uint32_t* kinds, uint32_t* counts, double* total_ms,
+                      uint32_t max_kinds, uint32_t* num_kinds);
 
 /* The HIP error code of the last failed HIP call made for this heap. */
 int dsoar_last_hip_error(const dsoar_heap* heap);
@@ -257,6 +269,36 @@ int dsoar_micro_init(dsoar_heap* heap, uint32_t type, uint32_t n, const float* x
  * n_renew lanes create id = 3k with x = xs_dev[k], v = vs_dev[k]. */
 int dsoar_micro_step(dsoar_heap* heap, uint32_t type, uint32_t n_renew, const float* xs_dev,
                      const float* vs_dev, uint32_t flags, void* stream);
+
+/* ------------------------------------------------- Game of Life as objects
+ * The paper's game-of-life application (Sec. 4, applications figure) on
+ * square tori, one or many worlds in one heap.  The heap must declare, in
+ * this order, Cell {int32 alive, int32 cand}, Alive {int32 cell, int32 world,
+ * int32 action} and Candidate {int32 cell, int32 world, int32 action}.  One
+ * generation is four do-alls (Alive, Candidate, Alive, Candidate); Candidate
+ * and Alive objects are created and deleted with device new/delete. */
+typedef struct dsoar_gol dsoar_gol;
+#define DSOAR_GOL_GRAPH 0x100u /* capture one generation once into a HIP graph and
+                                  replay it (needs a non-default stream) */
+/* Device bytes for the world table and the cell index (0 if invalid).  sides:
+ * host array of num_worlds side lengths (1..65535, total cells < 2^32). */
+size_t dsoar_gol_bytes(uint32_t num_worlds, const uint32_t* sides);
+/* World w's cell (x, y) has global index off[w] + y*side[w] + x, off being
+ * the prefix sum of side^2.  dev_mem: >= dsoar_gol_bytes, 256-byte aligned,
+ * caller-owned.  Synchronises `stream` once (uploads the world table). */
+int dsoar_gol_create(dsoar_heap* heap, uint32_t num_worlds, const uint32_t* sides, void* dev_mem,
+                     size_t dev_bytes, void* stream, dsoar_gol** out);
+int dsoar_gol_destroy(dsoar_gol* gol);
+/* Creates the objects of the initial state: grid_dev[g] != 0 means cell g is
+ * alive (uint8 per global cell).  The heap should be freshly reset. */
+int dsoar_gol_init(dsoar_gol* gol, const uint8_t* grid_dev, void* stream);
+/* Advances every world by `generations` synchronous B3/S23 generations.
+ * flags: DSOAR_DO_PLAIN or DSOAR_DO_PERSISTENT, optionally | DSOAR_GOL_GRAPH
+ * (persistent only). */
+int dsoar_gol_step(dsoar_gol* gol, uint32_t generations, uint32_t flags, void* stream);
+/* grid_dev[g] = 1 if cell g is alive, else 0 (uint8 per global cell). */
+int dsoar_gol_read(dsoar_gol* gol, uint8_t* grid_dev, void* stream);
+uint32_t dsoar_gol_total_cells(const dsoar_gol* gol);
 
 #ifdef __cplusplus
 }

@@ -22,8 +22,12 @@ ERRORS = {
 ERR_OOM, ERR_RETRY_LIMIT, ERR_DOUBLE_FREE = -2, -3, -5
 
 DO_PERSISTENT, DO_PLAIN, DO_REUSE_ENUM = 0, 1, 2
+GOL_GRAPH = 0x100
 METHOD_VISIT_COUNT, METHOD_DELETE_IF_MOD, METHOD_MICRO_UPDATE, METHOD_MICRO_CULL, METHOD_FIELD_GATHER = 1, 2, 3, 4, 5
 BM_TRY_SET, BM_TRY_CLEAR, BM_SET, BM_CLEAR, BM_TRY_FIND_SET, BM_FIND_CLEAR = range(6)
+KIND_NAMES = {1: "enumerate", 10: "visit_count", 11: "delete_if_mod", 12: "gather", 20: "micro_update",
+              21: "micro_cull", 30: "gol_alive_prep", 31: "gol_cand_prep", 32: "gol_alive_update",
+              33: "gol_cand_update"}
 INV_NAMES = ["bitmap_range", "allocated", "active", "active_implies_allocated", "free",
              "container", "live_count", "reserved"]
 
@@ -48,6 +52,7 @@ class HeapLayout(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("allocs", u64 * MAX_TYPES), ("frees", u64 * MAX_TYPES), ("live_objects", u64 * MAX_TYPES),
+                ("visits", u64 * MAX_TYPES),
                 ("allocated_blocks", u32 * MAX_TYPES), ("active_blocks", u32 * MAX_TYPES),
                 ("typed_blocks", u32 * MAX_TYPES), ("reserve_retries", u64), ("slow_paths", u64),
                 ("find_fails", u64), ("free_blocks", u32), ("num_blocks", u32), ("oom", u32),
@@ -77,6 +82,8 @@ SIGNATURES = {
     "dsoar_heap_get_layout": (ctypes.c_int, [H, ctypes.POINTER(HeapLayout)]),
     "dsoar_heap_set_launch": (ctypes.c_int, [H, u32, u32]),
     "dsoar_last_hip_error": (ctypes.c_int, [H]),
+    "dsoar_heap_set_timing": (ctypes.c_int, [H, ctypes.c_int]),
+    "dsoar_heap_timing": (ctypes.c_int, [H, vp, vp, vp, u32, ctypes.POINTER(u32)]),
     "dsoar_enumerate": (ctypes.c_int, [H, u32, vp]),
     "dsoar_enum_count": (ctypes.c_int, [H, u32, ctypes.POINTER(u32), vp]),
     "dsoar_enum_arrays": (ctypes.c_int, [H, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
@@ -95,6 +102,13 @@ SIGNATURES = {
     "dsoar_bitmap_run": (ctypes.c_int, [vp, u32, vp, u32, vp, vp, vp]),
     "dsoar_micro_init": (ctypes.c_int, [H, u32, u32, vp, vp, vp]),
     "dsoar_micro_step": (ctypes.c_int, [H, u32, u32, vp, vp, u32, vp]),
+    "dsoar_gol_bytes": (sz, [u32, vp]),
+    "dsoar_gol_create": (ctypes.c_int, [H, u32, vp, vp, sz, vp, ctypes.POINTER(vp)]),
+    "dsoar_gol_destroy": (ctypes.c_int, [vp]),
+    "dsoar_gol_init": (ctypes.c_int, [vp, vp, vp]),
+    "dsoar_gol_step": (ctypes.c_int, [vp, u32, u32, vp]),
+    "dsoar_gol_read": (ctypes.c_int, [vp, vp, vp]),
+    "dsoar_gol_total_cells": (u32, [vp]),
 }
 
 _lib = None

@@ -1,6 +1,7 @@
 """Host drivers of the workloads over the C ABI (argument marshalling only)."""
 from __future__ import annotations
 
+import ctypes
 from dataclasses import dataclass
 
 import numpy as np
@@ -64,3 +65,76 @@ def micro_run(inp, num_blocks: int = 4096, capacity: int = 64, flags: int = C.DO
     mb = MicroBench(inp, num_blocks, capacity, flags)
     mb.run()
     return mb.result()
+
+
+# ------------------------------------------------------------ game of life --
+
+GOL_TYPES = [(4, 4), (4, 4, 4), (4, 4, 4)]  # Cell, Alive, Candidate
+GOL_CELL, GOL_ALIVE, GOL_CAND = 0, 1, 2
+
+
+def gol_blocks_for(total_cells: int, capacity: int = 64) -> int:
+    """Heap size for a Game of Life state: one block per `capacity` cells for
+    the Cells and twice as many again for Alive and Candidate objects (at most
+    one of them per cell, plus partly filled blocks), rounded up to a power of
+    two."""
+    need = max(64, 3 * -(-total_cells // capacity))
+    return 1 << (need - 1).bit_length()
+
+
+class GameOfLife:
+    """One or many square Game-of-Life worlds as objects in one device heap."""
+
+    def __init__(self, grids, capacity: int = 64, num_blocks: int | None = None, stream=None,
+                 device="cuda"):
+        self.sides = np.array([g.shape[0] for g in grids], dtype=np.uint32)
+        for g in grids:
+            assert g.shape[0] == g.shape[1], "worlds are square"
+        self.total = int((self.sides.astype(np.int64) ** 2).sum())
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        blocks = num_blocks or gol_blocks_for(self.total, capacity)
+        self.heap = Heap(blocks, capacity, GOL_TYPES, device=device, stream=self.stream)
+        self.lib = self.heap.lib
+        nbytes = int(self.lib.dsoar_gol_bytes(len(grids), self.sides.ctypes.data))
+        if nbytes == 0:
+            raise ValueError("bad world sizes")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        flat = np.concatenate([np.ascontiguousarray(g, dtype=np.uint8).ravel() for g in grids])
+        with torch.cuda.stream(self.stream):
+            self.grid0 = torch.from_numpy(flat).to(device)
+        self.out = torch.empty(self.total, dtype=torch.uint8, device=device)
+        g = ctypes.c_void_p()
+        C.check(self.lib.dsoar_gol_create(self.heap.h, len(grids), self.sides.ctypes.data, self.buf.data_ptr(),
+                                          nbytes, self.heap._s(), ctypes.byref(g)), "dsoar_gol_create")
+        self.g = g
+
+    def close(self):
+        if getattr(self, "g", None):
+            self.lib.dsoar_gol_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self):
+        self.heap.reset()
+        C.check(self.lib.dsoar_gol_init(self.g, self.grid0.data_ptr(), self.heap._s()), "dsoar_gol_init")
+
+    def step(self, generations: int, flags: int = C.DO_PERSISTENT):
+        C.check(self.lib.dsoar_gol_step(self.g, generations, flags, self.heap._s()), "dsoar_gol_step")
+
+    def read(self) -> list:
+        C.check(self.lib.dsoar_gol_read(self.g, self.out.data_ptr(), self.heap._s()), "dsoar_gol_read")
+        self.stream.synchronize()
+        flat = self.out.cpu().numpy()
+        grids, off = [], 0
+        for s in self.sides.tolist():
+            grids.append(flat[off: off + s * s].reshape(s, s))
+            off += s * s
+        return grids
+
+    def synchronize(self):
+        self.stream.synchronize()

@@ -46,6 +46,7 @@ enum : uint32_t {
   kCntReserveRetries = 2 * kMaxTypes,
   kCntSlowPaths = 2 * kMaxTypes + 1,
   kCntFindFails = 2 * kMaxTypes + 2,
+  kCntVisits = 2 * kMaxTypes + 3,  // + type: objects visited by do-alls
   kShardStride = 32,
 };
 

@@ -1,0 +1,328 @@
+// Game of Life as objects (B3/S23 on square tori), for one world or many
+// worlds sharing one heap.
+//
+// Types: Cell {alive, cand} is created once per grid position and found
+// through a position -> handle index; Alive {cell, world, action} exists for
+// every live cell; Candidate {cell, world, action} exists during a generation
+// for every dead cell next to a live one.  One generation is four do-alls:
+//   1 Alive:     count live neighbours -> action (die unless 2 or 3); for each
+//                dead neighbour, the lane that flips the Cell's cand flag from
+//                0 to 1 creates that cell's Candidate.
+//   2 Candidate: action = born iff exactly 3 live neighbours.
+//   3 Alive:     dying ones clear their Cell's alive flag and delete themselves.
+//   4 Candidate: clear the Cell's cand flag; born ones set alive and create an
+//                Alive; every Candidate deletes itself.
+// Live flags are only read in phases 1-2 and only written in 3-4, so the
+// kernel boundaries make the update synchronous.
+#include <string.h>
+
+#include <new>
+
+#include "internal.hpp"
+
+namespace dsoar {
+namespace {
+
+enum : uint32_t { kCell = 0, kAlive = 1, kCand = 2 };
+enum : uint32_t { kCAlive = 0, kCCand = 1 };
+enum : uint32_t { kACell = 0, kAWorld = 1, kAAction = 2 };
+
+struct World {
+  const uint32_t* cells;  // global cell index -> Cell handle
+  const uint32_t* off;    // world -> first global cell index (num_worlds + 1 entries)
+  const uint32_t* side;   // world -> side length
+};
+
+// Field f of the Cell at global index g; a scratch word when the Cell is
+// missing (only after an out-of-memory init, which the OOM flag reports).
+__device__ __forceinline__ uint32_t* cell_field(const DevHeap& h, const World& w, uint32_t g, uint32_t f) {
+  const uint32_t hc = w.cells[g];
+  return hc == kNull ? reinterpret_cast<uint32_t*>(h.ctrl + kCtlWords - 1) : field_ptr<uint32_t>(h, hc, kCell, f);
+}
+
+// The eight torus neighbours of global cell g of world wid.
+template <class F>
+__device__ __forceinline__ void for_neighbours(const World& w, uint32_t wid, uint32_t g, F&& f) {
+  const uint32_t off = w.off[wid], side = w.side[wid];
+  const uint32_t local = g - off;
+  const uint32_t y = local / side, x = local - y * side;
+  const uint32_t xm = x == 0 ? side - 1 : x - 1, xp = x + 1 == side ? 0 : x + 1;
+  const uint32_t ym = y == 0 ? side - 1 : y - 1, yp = y + 1 == side ? 0 : y + 1;
+  const uint32_t rm = off + ym * side, r0 = off + y * side, rp = off + yp * side;
+  f(rm + xm); f(rm + x); f(rm + xp);
+  f(r0 + xm);            f(r0 + xp);
+  f(rp + xm); f(rp + x); f(rp + xp);
+}
+
+struct AlivePrep {
+  static constexpr uint32_t kKind = 30;
+  using Args = World;
+  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& w) {
+    const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
+    const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
+    uint32_t live = 0;
+    for_neighbours(w, wid, g, [&](uint32_t n) {
+      const uint32_t hc = w.cells[n];
+      if (hc == kNull) return;  // only after an out-of-memory init
+      const uint32_t alive = *field_ptr<uint32_t>(h, hc, kCell, kCAlive);
+      live += alive;
+      bool create = false;
+      if (!alive) {
+        uint32_t* cand = field_ptr<uint32_t>(h, hc, kCell, kCCand);
+        if (__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+          create = atomicCAS(cand, 0u, 1u) == 0u;
+      }
+      if (create) {
+        const uint32_t o = dsoar_new(h, kCand);
+        if (o != kNull) {
+          *field_ptr<uint32_t>(h, o, kCand, kACell) = n;
+          *field_ptr<uint32_t>(h, o, kCand, kAWorld) = wid;
+          *field_ptr<uint32_t>(h, o, kCand, kAAction) = 0;
+        }
+      }
+    });
+    *field_ptr<uint32_t>(h, self, type, kAAction) = (live == 2 || live == 3) ? 0u : 1u;
+    return false;
+  }
+};
+
+struct CandPrep {
+  static constexpr uint32_t kKind = 31;
+  using Args = World;
+  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& w) {
+    const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
+    const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
+    uint32_t live = 0;
+    for_neighbours(w, wid, g, [&](uint32_t n) { live += *cell_field(h, w, n, kCAlive); });
+    *field_ptr<uint32_t>(h, self, type, kAAction) = live == 3 ? 1u : 0u;
+    return false;
+  }
+};
+
+struct AliveUpdate {
+  static constexpr uint32_t kKind = 32;
+  using Args = World;
+  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& w) {
+    if (*field_ptr<uint32_t>(h, self, type, kAAction) == 0) return false;
+    *cell_field(h, w, *field_ptr<uint32_t>(h, self, type, kACell), kCAlive) = 0;
+    return true;
+  }
+};
+
+struct CandUpdate {
+  static constexpr uint32_t kKind = 33;
+  using Args = World;
+  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& w) {
+    const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
+    const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
+    const bool born = *field_ptr<uint32_t>(h, self, type, kAAction) != 0;
+    *cell_field(h, w, g, kCCand) = 0;
+    if (born) {
+      *cell_field(h, w, g, kCAlive) = 1;
+      const uint32_t o = dsoar_new(h, kAlive);
+      if (o != kNull) {
+        *field_ptr<uint32_t>(h, o, kAlive, kACell) = g;
+        *field_ptr<uint32_t>(h, o, kAlive, kAWorld) = wid;
+        *field_ptr<uint32_t>(h, o, kAlive, kAAction) = 0;
+      }
+    }
+    return true;
+  }
+};
+
+__device__ __forceinline__ uint32_t world_of(const uint32_t* off, uint32_t num_worlds, uint32_t g) {
+  uint32_t lo = 0, hi = num_worlds;  // off[lo] <= g < off[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Creates every Cell (in position order) and an Alive for every live cell.
+__global__ void gol_init_kernel(DevHeap h, World w, uint32_t num_worlds, uint32_t total, const uint8_t* grid) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const uint32_t hc = dsoar_new(h, kCell);
+  const uint32_t alive = grid[g] ? 1u : 0u;
+  if (hc != kNull) {
+    *field_ptr<uint32_t>(h, hc, kCell, kCAlive) = alive;
+    *field_ptr<uint32_t>(h, hc, kCell, kCCand) = 0;
+  }
+  const_cast<uint32_t*>(w.cells)[g] = hc;
+  if (alive) {
+    const uint32_t o = dsoar_new(h, kAlive);
+    if (o != kNull) {
+      *field_ptr<uint32_t>(h, o, kAlive, kACell) = g;
+      *field_ptr<uint32_t>(h, o, kAlive, kAWorld) = world_of(w.off, num_worlds, g);
+      *field_ptr<uint32_t>(h, o, kAlive, kAAction) = 0;
+    }
+  }
+}
+
+__global__ void gol_read_kernel(DevHeap h, World w, uint32_t total, uint8_t* out) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const uint32_t hc = w.cells[g];
+  out[g] = hc == kNull ? 0xFF : (uint8_t)*field_ptr<uint32_t>(h, hc, kCell, kCAlive);
+}
+
+bool gol_heap_ok(const dsoar_heap* h) {
+  if (h->desc.num_types < 3) return false;
+  const uint32_t want[3] = {2, 3, 3};
+  for (uint32_t t = 0; t < 3; ++t) {
+    const dsoar_type_layout& L = h->desc.types[t];
+    if (L.num_fields < want[t]) return false;
+    for (uint32_t f = 0; f < want[t]; ++f)
+      if (L.field_bytes[f] != 4) return false;
+  }
+  return true;
+}
+
+uint64_t gol_total_cells(uint32_t num_worlds, const uint32_t* sides) {
+  uint64_t t = 0;
+  for (uint32_t i = 0; i < num_worlds; ++i) t += (uint64_t)sides[i] * sides[i];
+  return t;
+}
+
+}  // namespace
+}  // namespace dsoar
+
+using namespace dsoar;
+
+struct dsoar_gol {
+  dsoar_heap* heap;
+  World w;
+  uint32_t num_worlds;
+  uint32_t total;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  uint32_t graph_flags;
+};
+
+namespace {
+
+int gol_generation(dsoar_gol* g, uint32_t flags, hipStream_t s) {
+  dsoar_heap* h = g->heap;
+  const uint32_t base = flags & DSOAR_DO_PLAIN;
+  int rc = launch_doall<AlivePrep>(h, kAlive, g->w, base, s);
+  if (!rc) rc = launch_doall<CandPrep>(h, kCand, g->w, base, s);
+  // Phase 2 creates and deletes nothing, phase 3 touches only Alive objects:
+  // phases 3 and 4 reuse the enumerations of phases 1 and 2.
+  if (!rc) rc = launch_doall<AliveUpdate>(h, kAlive, g->w, base | DSOAR_DO_REUSE_ENUM, s);
+  if (!rc) rc = launch_doall<CandUpdate>(h, kCand, g->w, base | DSOAR_DO_REUSE_ENUM, s);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dsoar_gol_bytes(uint32_t num_worlds, const uint32_t* sides) {
+  if (num_worlds == 0 || !sides) return 0;
+  for (uint32_t i = 0; i < num_worlds; ++i)
+    if (sides[i] < 1 || sides[i] > 65535) return 0;
+  const uint64_t total = gol_total_cells(num_worlds, sides);
+  if (total >= (1ull << 32)) return 0;
+  return (size_t)(((uint64_t)(2 * num_worlds + 1) * 4 + 255) / 256 * 256 + total * 4);
+}
+
+int dsoar_gol_create(dsoar_heap* heap, uint32_t num_worlds, const uint32_t* sides, void* dev_mem, size_t dev_bytes,
+                     void* stream, dsoar_gol** out) {
+  if (!out) return DSOAR_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!heap_ok(heap) || !gol_heap_ok(heap) || !dev_mem || ((uintptr_t)dev_mem & 255u)) return DSOAR_ERR_INVALID_ARG;
+  const size_t need = dsoar_gol_bytes(num_worlds, sides);
+  if (need == 0) return DSOAR_ERR_INVALID_ARG;
+  if (dev_bytes < need) return DSOAR_ERR_TOO_SMALL;
+  dsoar_gol* g = new (std::nothrow) dsoar_gol;
+  if (!g) return DSOAR_ERR_INVALID_ARG;
+  memset(g, 0, sizeof(*g));
+  g->heap = heap;
+  g->num_worlds = num_worlds;
+  g->total = (uint32_t)gol_total_cells(num_worlds, sides);
+  uint32_t* tab = (uint32_t*)dev_mem;
+  const uint64_t head = ((uint64_t)(2 * num_worlds + 1) * 4 + 255) / 256 * 256;
+  g->w.off = tab;
+  g->w.side = tab + num_worlds + 1;
+  g->w.cells = (const uint32_t*)((uint8_t*)dev_mem + head);
+  uint32_t* host = (uint32_t*)malloc((size_t)(2 * num_worlds + 1) * 4);
+  if (!host) {
+    delete g;
+    return DSOAR_ERR_INVALID_ARG;
+  }
+  uint32_t acc = 0;
+  for (uint32_t i = 0; i < num_worlds; ++i) {
+    host[i] = acc;
+    host[num_worlds + 1 + i] = sides[i];
+    acc += sides[i] * sides[i];
+  }
+  host[num_worlds] = acc;
+  hipError_t e = hipMemcpyAsync(tab, host, (size_t)(2 * num_worlds + 1) * 4, hipMemcpyHostToDevice, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  free(host);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(heap, e);
+  }
+  *out = g;
+  return DSOAR_OK;
+}
+
+int dsoar_gol_destroy(dsoar_gol* g) {
+  if (!g) return DSOAR_ERR_INVALID_ARG;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return DSOAR_OK;
+}
+
+int dsoar_gol_init(dsoar_gol* g, const uint8_t* grid_dev, void* stream) {
+  if (!g || !grid_dev) return DSOAR_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(gol_init_kernel, dim3((g->total + 255) / 256), dim3(256), 0, (hipStream_t)stream, g->heap->dev,
+                     g->w, g->num_worlds, g->total, grid_dev);
+  DSOAR_LAUNCHED(g->heap);
+  return DSOAR_OK;
+}
+
+int dsoar_gol_step(dsoar_gol* g, uint32_t generations, uint32_t flags, void* stream) {
+  if (!g) return DSOAR_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  dsoar_heap* h = g->heap;
+  if (flags & DSOAR_GOL_GRAPH) {
+    if (flags & DSOAR_DO_PLAIN) return DSOAR_ERR_INVALID_ARG;  // plain mode synchronises
+    if (!g->exec) {
+      DSOAR_HIP(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const int rc = gol_generation(g, 0, s);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(s, &graph);
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (e != hipSuccess) return hip_fail(h, e);
+      g->graph = graph;
+      DSOAR_HIP(h, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    }
+    for (uint32_t i = 0; i < generations; ++i) DSOAR_HIP(h, hipGraphLaunch(g->exec, s));
+    return DSOAR_OK;
+  }
+  for (uint32_t i = 0; i < generations; ++i) {
+    const int rc = gol_generation(g, flags, s);
+    if (rc) return rc;
+  }
+  return DSOAR_OK;
+}
+
+int dsoar_gol_read(dsoar_gol* g, uint8_t* grid_dev, void* stream) {
+  if (!g || !grid_dev) return DSOAR_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(gol_read_kernel, dim3((g->total + 255) / 256), dim3(256), 0, (hipStream_t)stream, g->heap->dev,
+                     g->w, g->total, grid_dev);
+  DSOAR_LAUNCHED(g->heap);
+  return DSOAR_OK;
+}
+
+uint32_t dsoar_gol_total_cells(const dsoar_gol* g) { return g ? g->total : 0; }
+
+}  // extern "C"

@@ -458,6 +458,7 @@ __global__ void field_rw_kernel(DevHeap h, uint32_t type, uint32_t field, const 
 
 // ---------------------------------------------------------- built-in methods
 struct VisitCount {
+  static constexpr uint32_t kKind = 10;
   struct Args { uint32_t* counts; };
   static __device__ bool run(const DevHeap&, uint32_t, uint32_t self, const Args& a) {
     atomicAdd(a.counts + self, 1u);
@@ -466,6 +467,7 @@ struct VisitCount {
 };
 
 struct DeleteIfMod {
+  static constexpr uint32_t kKind = 11;
   struct Args { uint32_t field; int32_t modulus; int32_t residue; };
   static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& a) {
     const int32_t v = *field_ptr<int32_t>(h, self, type, a.field);
@@ -474,6 +476,7 @@ struct DeleteIfMod {
 };
 
 struct FieldGather {
+  static constexpr uint32_t kKind = 12;
   struct Args { uint32_t key_field, field, num_keys, wide; uint8_t* out; uint8_t* present; };
   static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& a) {
     const uint32_t key = *field_ptr<uint32_t>(h, self, type, a.key_field);
@@ -490,8 +493,10 @@ struct FieldGather {
 // ------------------------------------------------------ shared host helpers
 
 int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s) {
+  const int rec = timing_begin(h, kKindEnumerate, s);
   hipLaunchKernelGGL(enumerate_kernel, dim3(h->num_tiles), dim3(kEnumWaves * 64), 0, s, h->dev, type,
                      h->enum_out[type]);
+  timing_end(h, rec, s);
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }
@@ -558,6 +563,7 @@ int collect_stats(dsoar_heap* h, dsoar_stats* out, uint32_t* viol, int check, hi
     for (uint32_t t = 0; t < kMaxTypes; ++t) {
       st.allocs[t] += c[kCntAllocs + t];
       st.frees[t] += c[kCntFrees + t];
+      st.visits[t] += c[kCntVisits + t];
     }
     st.reserve_retries += c[kCntReserveRetries];
     st.slow_paths += c[kCntSlowPaths];
@@ -652,9 +658,72 @@ int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_byt
   return DSOAR_OK;
 }
 
+static void timing_free(dsoar_heap* h) {
+  if (h->ev_pool) {
+    for (uint32_t i = 0; i < 2 * kTimingCap; ++i) (void)hipEventDestroy(h->ev_pool[i]);
+    free(h->ev_pool);
+    free(h->rec_kind);
+  }
+  h->ev_pool = nullptr;
+  h->rec_kind = nullptr;
+  h->rec_used = 0;
+  h->timing = 0;
+}
+
 int dsoar_heap_destroy(dsoar_heap* h) {
   if (!h) return DSOAR_ERR_INVALID_ARG;
+  timing_free(h);
   delete h;
+  return DSOAR_OK;
+}
+
+int dsoar_heap_set_timing(dsoar_heap* h, int enable) {
+  if (!heap_ok(h)) return DSOAR_ERR_INVALID_ARG;
+  if (!enable) {
+    timing_free(h);
+    return DSOAR_OK;
+  }
+  if (!h->ev_pool) {
+    h->ev_pool = (hipEvent_t*)calloc(2 * kTimingCap, sizeof(hipEvent_t));
+    h->rec_kind = (uint32_t*)calloc(kTimingCap, sizeof(uint32_t));
+    if (!h->ev_pool || !h->rec_kind) {
+      free(h->ev_pool);
+      free(h->rec_kind);
+      h->ev_pool = nullptr;
+      h->rec_kind = nullptr;
+      return DSOAR_ERR_INVALID_ARG;
+    }
+    for (uint32_t i = 0; i < 2 * kTimingCap; ++i) DSOAR_HIP(h, hipEventCreate(&h->ev_pool[i]));
+  }
+  h->rec_used = 0;
+  h->timing = 1;
+  return DSOAR_OK;
+}
+
+int dsoar_heap_timing(dsoar_heap* h, uint32_t* kinds, uint32_t* counts, double* total_ms, uint32_t max_kinds,
+                      uint32_t* num_kinds) {
+  if (!heap_ok(h) || !num_kinds || (max_kinds && (!kinds || !counts || !total_ms))) return DSOAR_ERR_INVALID_ARG;
+  *num_kinds = 0;
+  if (!h->timing) return DSOAR_OK;
+  if (h->rec_used) DSOAR_HIP(h, hipEventSynchronize(h->ev_pool[2 * (h->rec_used - 1) + 1]));
+  uint32_t n = 0;
+  for (uint32_t r = 0; r < h->rec_used; ++r) {
+    float ms = 0.f;
+    DSOAR_HIP(h, hipEventElapsedTime(&ms, h->ev_pool[2 * r], h->ev_pool[2 * r + 1]));
+    uint32_t k = 0;
+    while (k < n && kinds[k] != h->rec_kind[r]) ++k;
+    if (k == n) {
+      if (n == max_kinds) continue;
+      kinds[n] = h->rec_kind[r];
+      counts[n] = 0;
+      total_ms[n] = 0.0;
+      ++n;
+    }
+    counts[k] += 1;
+    total_ms[k] += ms;
+  }
+  *num_kinds = n;
+  h->rec_used = 0;
   return DSOAR_OK;
 }
 

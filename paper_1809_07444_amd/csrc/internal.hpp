@@ -59,6 +59,11 @@ struct dsoar_heap {
   uint32_t doall_wg_threads;   // workgroup size of do-all launches
   uint32_t doall_wgs_per_cu;   // persistent grid = num_cus * this
   hipError_t last_hip;
+  // Optional per-launch timing with HIP events on the launch stream.
+  int timing;
+  hipEvent_t* ev_pool;         // 2 * kTimingCap events, created on enable
+  uint32_t* rec_kind;          // kind of each recorded launch
+  uint32_t rec_used;
 };
 
 namespace dsoar {
@@ -76,6 +81,22 @@ inline int hip_fail(dsoar_heap* h, hipError_t e) {
 
 #define DSOAR_LAUNCHED(h) DSOAR_HIP(h, hipGetLastError())
 
+constexpr uint32_t kTimingCap = 8192;
+constexpr uint32_t kKindEnumerate = 1;
+
+// Brackets one launch with a pair of events when timing is on.  Returns the
+// record index (or -1 when off or full).
+inline int timing_begin(dsoar_heap* h, uint32_t kind, hipStream_t s) {
+  if (!h->timing || h->rec_used >= kTimingCap) return -1;
+  const int r = (int)h->rec_used++;
+  h->rec_kind[r] = kind;
+  (void)hipEventRecord(h->ev_pool[2 * r], s);
+  return r;
+}
+inline void timing_end(dsoar_heap* h, int r, hipStream_t s) {
+  if (r >= 0) (void)hipEventRecord(h->ev_pool[2 * r + 1], s);
+}
+
 int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s);
 int read_count(dsoar_heap* h, uint32_t type, hipStream_t s, uint32_t* count);
 
@@ -85,7 +106,8 @@ int read_count(dsoar_heap* h, uint32_t type, hipStream_t s, uint32_t* count);
 // the snapshot S[e] is set.  Deletes of `this` are collected with a ballot and
 // applied as one atomic AND per block when the wavefront finishes the block.
 //
-// Method: struct with `struct Args` and
+// Method: struct with `struct Args`, a `static constexpr uint32_t kKind`
+// (an id for per-kernel timing) and
 //   static __device__ bool run(const DevHeap&, uint32_t type, uint32_t self, const Args&)
 // returning true to delete self.
 template <class Method>
@@ -97,10 +119,12 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
   const uint32_t gw = blockIdx.x * wpb + (threadIdx.x >> 6);
   const uint32_t nw = gridDim.x * wpb;
   const uint32_t count = bcast32(*count_ptr);
+  uint32_t visits = 0;
   if (h.capacity == 64) {
     for (uint32_t e = gw; e < count; e += nw) {
       const uint32_t bid = R[e];
       const uint64_t snap = S[e];
+      visits += (uint32_t)__popcll(snap);
       bool del = false;
       if ((snap >> lane) & 1ull) del = Method::run(h, type, make_obj(bid, lane), args);
       const uint64_t dm = __ballot(del);
@@ -113,6 +137,7 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
       const bool valid = e < count;
       const uint32_t bid = valid ? R[e] : 0u;
       const uint64_t snap = valid ? S[e] : 0ull;
+      visits += (uint32_t)__popcll(__ballot((snap >> slot) & 1ull));
       bool del = false;
       if ((snap >> slot) & 1ull) del = Method::run(h, type, make_obj(bid, slot), args);
       const uint64_t dm = __ballot(del);
@@ -120,6 +145,7 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
       if (dm >> 32) delete_mask(h, type, __builtin_amdgcn_readlane(bid, 32), dm >> 32);
     }
   }
+  if (visits) lead_add(shard(h) + kCntVisits + type, visits);
 }
 
 // Enumerate (unless reusing) and launch the do-all of Method over `type`.
@@ -145,8 +171,10 @@ int launch_doall(dsoar_heap* h, uint32_t type, const typename Method::Args& args
   } else {
     grid = h->num_cus * h->doall_wgs_per_cu;
   }
+  const int rec = timing_begin(h, Method::kKind, s);
   hipLaunchKernelGGL(doall_kernel<Method>, dim3(grid), dim3(threads), 0, s, h->dev, type, eo.R, eo.S,
                      &eo.st->count, args);
+  timing_end(h, rec, s);
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }

@@ -10,6 +10,7 @@ namespace {
 enum : uint32_t { kId = 0, kX = 1, kV = 2 };
 
 struct MicroUpdate {
+  static constexpr uint32_t kKind = 20;
   struct Args { uint32_t unused; };
   static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args&) {
     float* x = field_ptr<float>(h, self, type, kX);
@@ -20,6 +21,7 @@ struct MicroUpdate {
 };
 
 struct MicroCull {
+  static constexpr uint32_t kKind = 21;
   struct Args { uint32_t unused; };
   static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args&) {
     return (*field_ptr<int32_t>(h, self, type, kId) % 3) == 0;

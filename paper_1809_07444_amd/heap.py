@@ -78,6 +78,21 @@ class Heap:
     def set_launch(self, wg_threads: int, wgs_per_cu: int):
         C.check(self.lib.dsoar_heap_set_launch(self.h, wg_threads, wgs_per_cu), "dsoar_heap_set_launch")
 
+    def set_timing(self, enable: bool):
+        C.check(self.lib.dsoar_heap_set_timing(self.h, 1 if enable else 0), "dsoar_heap_set_timing")
+
+    def timing(self) -> dict:
+        """{kind name: (launches, total ms)} since the last report."""
+        import numpy as np
+        kinds = np.zeros(64, np.uint32)
+        counts = np.zeros(64, np.uint32)
+        ms = np.zeros(64, np.float64)
+        n = ctypes.c_uint32()
+        C.check(self.lib.dsoar_heap_timing(self.h, kinds.ctypes.data, counts.ctypes.data, ms.ctypes.data, 64,
+                                           ctypes.byref(n)), "dsoar_heap_timing")
+        return {C.KIND_NAMES.get(int(kinds[i]), str(int(kinds[i]))): (int(counts[i]), float(ms[i]))
+                for i in range(n.value)}
+
     def layout(self) -> C.HeapLayout:
         L = C.HeapLayout()
         C.check(self.lib.dsoar_heap_get_layout(self.h, ctypes.byref(L)), "dsoar_heap_get_layout")
@@ -91,6 +106,7 @@ class Heap:
         nt = len(self.types)
         return dict(
             allocs=list(st.allocs[:nt]), frees=list(st.frees[:nt]), live=list(st.live_objects[:nt]),
+            visits=list(st.visits[:nt]),
             allocated_blocks=list(st.allocated_blocks[:nt]), active_blocks=list(st.active_blocks[:nt]),
             typed_blocks=list(st.typed_blocks[:nt]), reserve_retries=st.reserve_retries,
             slow_paths=st.slow_paths, find_fails=st.find_fails, free_blocks=st.free_blocks,

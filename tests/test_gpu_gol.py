@@ -1,0 +1,90 @@
+"""Game of Life as objects on the device against the oracle's dense B3/S23
+torus: exact final grids, and exact object churn (every Candidate is one
+dead cell next to a live one; births and deaths are the oracle's)."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_1809_07444_amd import _capi as C  # noqa: E402
+from paper_1809_07444_amd import apps  # noqa: E402
+from synth import workloads as W  # noqa: E402
+
+
+def expected_counts(grids, gens):
+    allocs = [0, 0, 0]
+    frees = [0, 0, 0]
+    finals = []
+    for g in grids:
+        final, c = oracle.gol_run(g, gens)
+        finals.append(final)
+        allocs[0] += g.size
+        allocs[1] += int(g.astype(bool).sum()) + int(c[:, 1].sum())
+        frees[1] += int(c[:, 2].sum())
+        allocs[2] += int(c[:, 0].sum())
+        frees[2] += int(c[:, 0].sum())
+    return finals, allocs, frees
+
+
+def run_and_compare(grids, gens, flags=C.DO_PERSISTENT, capacity=64, split=None):
+    gol = apps.GameOfLife(grids, capacity=capacity)
+    gol.init()
+    if split:
+        for k in split:
+            gol.step(k, flags)
+    else:
+        gol.step(gens, flags)
+    got = gol.read()
+    finals, allocs, frees = expected_counts(grids, gens)
+    for a, b in zip(got, finals):
+        assert np.array_equal(a, b)
+    st = gol.heap.stats()
+    assert st["allocs"] == allocs and st["frees"] == frees
+    assert st["live"] == [gol.total, int(sum(f.sum() for f in finals)), 0]
+    assert gol.heap.check() == {}
+    return gol
+
+
+def grid_with(n, cells):
+    g = np.zeros((n, n), np.uint8)
+    for x, y in cells:
+        g[y % n, x % n] = 1
+    return g
+
+
+def test_glider_returns_after_full_lap():
+    glider = [(1, 0), (2, 1), (0, 2), (1, 2), (2, 2)]
+    g0 = grid_with(16, glider)
+    gol = run_and_compare([g0], 64)
+    assert np.array_equal(gol.read()[0], g0)
+
+
+def test_still_life_blinker_and_empty_worlds_together():
+    worlds = [grid_with(8, [(1, 1), (2, 1), (1, 2), (2, 2)]),        # block
+              grid_with(5, [(2, 1), (2, 2), (2, 3)]),                # blinker
+              np.zeros((7, 7), np.uint8),                             # empty
+              np.ones((1, 1), np.uint8), np.ones((2, 2), np.uint8)]  # degenerate tori
+    run_and_compare(worlds, 7)
+
+
+@pytest.mark.parametrize("seed,capacity", [(1, 64), (2, 32), (3, 64), (4, 32), (5, 64)])
+def test_random_small_worlds(seed, capacity):
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(3, 70, size=6)
+    grids = [W.gol_grid(int(s), int(s), seed=seed * 100 + i, threshold24=int(rng.integers(1, 1 << 23)))
+             for i, s in enumerate(sides)]
+    run_and_compare(grids, 50, capacity=capacity)
+
+
+@pytest.mark.parametrize("flags", [C.DO_PLAIN, C.DO_PERSISTENT | C.GOL_GRAPH])
+def test_modes_agree_medium(flags):
+    grids = [W.gol_grid(200, 200, seed=11), W.gol_grid(97, 97, seed=12)]
+    run_and_compare(grids, 40, flags=flags, split=[1, 13, 26])
+
+
+def test_full_config_1024_200_generations():
+    # 1024 x 1024 torus, Bernoulli(0.1) alive, 200 generations (graph replay).
+    g0 = W.gol_grid(1024, 1024)
+    run_and_compare([g0], 200, flags=C.DO_PERSISTENT | C.GOL_GRAPH)
