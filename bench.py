@@ -246,7 +246,8 @@ def main():
         "vs_baseline": None, "dtype": "int32/u64", "data": "synthetic", "config": wl.config,
         "doall_objects_per_s": per_step_visits / (ms / 1e3),
         "per_step": {"allocs": st1["allocs"], "frees": st1["frees"], "doall_visits": st1["visits"],
-                     "reserve_retries": st1["reserve_retries"], "slow_paths": st1["slow_paths"]},
+                     "reserve_retries": st1["reserve_retries"], "slow_paths": st1["slow_paths"],
+                     "find_fails": st1["find_fails"], "allocated_blocks_end": st1["allocated_blocks"]},
         "roofline": roof, "cpu_baseline": cpu, "kernels": kernels,
     }
     del st0

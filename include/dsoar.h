@@ -103,7 +103,7 @@ typedef struct {
   uint32_t allocated_blocks[DSOAR_MAX_TYPES];
   uint32_t active_blocks[DSOAR_MAX_TYPES];
   uint32_t typed_blocks[DSOAR_MAX_TYPES]; /* blocks whose type word is t */
-  uint64_t reserve_retries;               /* reservations that lost a race */
+  uint64_t reserve_retries;               /* reservations that gained fewer bits than tried */
   uint64_t slow_paths;                    /* free blocks taken (Alg. 1 slow path) */
   uint64_t find_fails;                    /* try_find_set FAILs on active[T] */
   uint32_t free_blocks;

@@ -113,6 +113,17 @@ __device__ __forceinline__ uint64_t lowest_bits(uint64_t m, uint32_t n) {
   return m & ((1ull << p) - 1);
 }
 
+// The n set bits of m found by scanning upwards from bit r and wrapping
+// (n <= popcount(m), r < 64).  Wavefronts that start at different r take
+// disjoint slots of the same block more often.
+__device__ __forceinline__ uint64_t take_from(uint64_t m, uint32_t n, uint32_t r) {
+  const uint64_t below = (1ull << r) - 1;
+  const uint64_t hi = m & ~below;
+  const uint32_t c = (uint32_t)__popcll(hi);
+  if (n <= c) return lowest_bits(hi, n);
+  return hi | lowest_bits(m & below, n - c);
+}
+
 __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
@@ -289,13 +300,48 @@ __device__ inline int32_t bm_try_find_set(const Bitmap& b, uint32_t start) {
 // refilled only at quiescence), so an empty top word means an empty bitmap.
 __device__ inline int32_t bm_find_clear(const Bitmap& b, uint32_t start) {
   for (uint32_t spins = 0; spins < kSpinLimit; ++spins) {
-    if (load_u64(b.word(b.nlevels - 1, 0)) == 0) return kFail;
     const int32_t i = bm_try_find_set(b, start);
     if (i != kFail && bm_try_clear(b, (uint32_t)i)) return i;
+    if (i == kFail && load_u64(b.word(b.nlevels - 1, 0)) == 0) return kFail;
     start = hash32(start + 0x9e3779b9u + spins);
   }
   lead_flag(b.retry_flag);
   return kFail;
+}
+
+// Takes up to `want` (1..64) set bits of one level-0 word of a bitmap that is
+// only cleared during kernels (the free bitmap): descend as try_find_set to a
+// non-empty word, clear the chosen bits with one atomic AND, and clear the
+// word's nested bit if this emptied it (Alg. 2 for several bits at once).
+// Returns the bits gained (0 = the bitmap is empty) and the word in *word.
+__device__ inline uint64_t bm_take_word(const Bitmap& b, uint32_t start, uint32_t want, uint32_t* word) {
+  for (uint32_t spins = 0; spins < kSpinLimit; ++spins) {
+    uint32_t idx = 0;
+    uint64_t w = 0;
+    for (int32_t l = (int32_t)b.nlevels - 1; l >= 0; --l) {
+      w = load_u64(b.word((uint32_t)l, idx));
+      if (w == 0) break;
+      if (l == 0) break;
+      const uint32_t d = (6 * (uint32_t)l < 32) ? ((start >> (6 * (uint32_t)l)) & 63u) : 0u;
+      const uint64_t r = (w >> d) | (d ? (w << (64 - d)) : 0ull);
+      idx = (idx << 6) | (((uint32_t)__builtin_ctzll(r) + d) & 63u);
+    }
+    if (w != 0) {
+      const uint64_t take = take_from(w, want < (uint32_t)__popcll(w) ? want : (uint32_t)__popcll(w), start & 63u);
+      const uint64_t prev = lead_and(b.word(0, idx), ~take);
+      const uint64_t got = prev & take;
+      if (got && (prev & ~take) == 0 && b.nlevels > 1) bm_clear_from(b, 1, idx);
+      if (got) {
+        *word = idx;
+        return got;
+      }
+    } else if (load_u64(b.word(b.nlevels - 1, 0)) == 0) {
+      return 0;
+    }
+    start = hash32(start + 0x9e3779b9u + spins);
+  }
+  lead_flag(b.retry_flag);
+  return 0;
 }
 
 // ------------------------------------------------------------------ objects --
@@ -311,40 +357,106 @@ __device__ __forceinline__ F* field_ptr(const DevHeap& h, uint32_t obj, uint32_t
 }
 
 // Alg. 1 for all lanes of this wavefront that call it with the same `type`
-// (the caller guarantees a wave-uniform type).  Returns this lane's handle,
-// or kNull if the heap ran out of free blocks (sticky OOM flag set).
+// (the caller guarantees a wave-uniform type); lane i asks for k_i objects
+// (0 <= k_i < 256).  f(j, obj) is then called by lane i for j = 0 .. k_i - 1
+// with its j-th new handle, or kNull if the heap ran out of free blocks
+// (sticky OOM flag set).  f must not itself call wavefront heap operations.
 //
-// Request coalescing (Sec. 2.4): the n requesting lanes are served together.
-// Each round looks up an active block of the type; if none is found it takes
-// a free block (slow path: set the type, mark it allocated, and - unless this
-// round fills it - active).  Reservation is one atomic OR of the lowest free
-// bits the snapshot shows; the bits actually gained are take & ~prev.  The
-// round whose OR fills the block clears active[type] (Alg. 1, FULL case).
-// Lanes receive slots in rank order.
-__device__ inline uint32_t new_uniform(const DevHeap& h, uint32_t type) {
-  const uint64_t group = active_mask();
-  const uint32_t n = (uint32_t)__popcll(group);
-  const uint32_t rank = lanes_below(group);
+// Request coalescing (Sec. 2.4): the n = sum k_i requests of the wavefront
+// are served together, one leader lane issuing every atomic.  While at least
+// `capacity` requests remain, a round takes whole free blocks (full blocks
+// are dense by construction), several at once from one free-bitmap word.
+// Otherwise it looks up an active block of the type first (dense policy,
+// Sec. 2.2) and takes a free block only when none is found (slow path: set
+// the type, mark it allocated and, unless this round fills it, active).
+// Reservation in an active block is one atomic OR of the wanted number of
+// bits among those a snapshot shows free (after our own OR, the bits it left
+// free); the bits gained are take & ~prev, and a block that still has room is
+// used again without a new lookup.  The round
+// whose OR fills the block clears active[type] (Alg. 1, FULL).
+// Requests are numbered by lane order (exclusive prefix sums from bit-sliced
+// ballots, exact under any divergence) and handed out in that order.
+template <class F>
+__device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&& f) {
+  uint32_t prefix = 0, n = 0;
+#pragma unroll
+  for (uint32_t b = 0; b < 8; ++b) {
+    const uint64_t m = __ballot((k >> b) & 1u);
+    prefix += lanes_below(m) << b;
+    n += (uint32_t)__popcll(m) << b;
+  }
+  if (n == 0) return;
   const Bitmap active = active_bm(h, type);
-  uint32_t result = kNull;
-  uint32_t served = 0;
-  uint32_t start = bcast32(hash32((blockIdx.x << 4) ^ (threadIdx.x >> 6) ^ 0x5bd1e995u));
-  uint32_t retries = 0, slow = 0, fails = 0, oom_rounds = 0;
-  bool oom = false;
+  const uint32_t rot = bcast32(hash32((blockIdx.x << 5) ^ (threadIdx.x >> 6) ^ 0x5bd1e995u));
+  const uint32_t c = h.capacity;
+  uint32_t start = rot;
+  uint32_t served = 0, retries = 0, slow = 0, fails = 0, oom_rounds = 0;
+  bool oom = false, active_first = false;
+  int32_t cur = kFail;     // block of the last reservation, if it still had room
+  uint64_t cur_avail = 0;  // its free bits right after that reservation
   for (uint32_t it = 0; served < n; ++it) {
     if (it >= kSpinLimit) {
       lead_flag(h.ctrl + kCtlRetryLimit);
+      oom = true;  // hand NULL to the lanes still waiting
       break;
     }
-    int32_t bid = bm_try_find_set(active, start);
+    const uint32_t want = n - served;
+    if (want >= c && !active_first) {
+      // Whole free blocks, several from one free-bitmap word per atomic.
+      uint32_t word = 0;
+      const uint32_t nb = want / c < 64 ? want / c : 64;
+      const uint64_t blocks = bm_take_word(free_bm(h), start, nb, &word);
+      if (blocks == 0) {
+        active_first = true;  // no free block: use space left in active blocks
+        continue;
+      }
+      const uint32_t cnt_b = (uint32_t)__popcll(blocks);
+      // Type words and object bitmaps of the new blocks, spread over the
+      // active lanes; the blocks are ours alone until published.
+      const uint32_t me = lanes_below(active_mask()), nact = (uint32_t)__popcll(active_mask());
+      for (uint32_t j = me; j < cnt_b; j += nact) {
+        const uint32_t bid = word * 64 + nth_set_bit(blocks, j);
+        h.block_type[bid] = type;
+        __hip_atomic_store(h.obj_bitmap + bid, h.cap_mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      const Bitmap alloc = allocated_bm(h, type);
+      const uint64_t pa = lead_or(alloc.word(0, word), blocks);
+      if (pa == 0 && alloc.nlevels > 1) bm_set_from(alloc, 1, word);
+      slow += cnt_b;
+      const uint32_t span = cnt_b * c;
+      const uint32_t lo = prefix > served ? prefix : served;
+      const uint32_t hi = prefix + k < served + span ? prefix + k : served + span;
+      for (uint32_t r = lo; r < hi; ++r) {
+        const uint32_t q = r - served;
+        f(r - prefix, make_obj(word * 64 + nth_set_bit(blocks, q / c), q % c));
+      }
+      served += span;
+      continue;
+    }
+    int32_t bid = cur;
+    uint64_t avail = cur_avail;
     uint64_t got;
     if (bid == kFail) {
-      ++fails;
+      bid = bm_try_find_set(active, start);
+      if (bid == kFail) {
+        ++fails;
+      } else {
+        avail = ~load_u64(h.obj_bitmap + bid) & h.cap_mask;
+        if (avail == 0) {  // filled since the lookup; its filler clears the bit
+          ++retries;
+          start = hash32(start + it + 1);
+          continue;
+        }
+      }
+    }
+    cur = kFail;
+    if (bid == kFail) {
       bid = bm_find_clear(free_bm(h), start);
       if (bid == kFail) {
-        // No free block.  A block another wavefront is just opening may not
-        // be marked active yet; look again a few times before giving up.
+        // No free block.  A block another wavefront is opening may not be
+        // marked active yet: look again a few times before giving up.
         if (++oom_rounds <= kOomRetries) {
+          active_first = true;
           __builtin_amdgcn_s_sleep(8);
           start = hash32(start + it + 1);
           continue;
@@ -354,54 +466,59 @@ __device__ inline uint32_t new_uniform(const DevHeap& h, uint32_t type) {
       }
       ++slow;
       // Fresh block: nobody else can see it until it is marked active.
-      const uint32_t want = n - served;
-      got = want >= h.capacity ? h.cap_mask : ((1ull << want) - 1);
+      got = want >= c ? h.cap_mask : ((1ull << want) - 1);
       if (is_first_active()) {
         h.block_type[bid] = type;
-        __hip_atomic_fetch_or(h.obj_bitmap + bid, got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(h.obj_bitmap + bid, got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       bm_set(allocated_bm(h, type), (uint32_t)bid);
-      if (got != h.cap_mask) bm_set(active, (uint32_t)bid);
-    } else {
-      const uint64_t snap = load_u64(h.obj_bitmap + bid);
-      const uint64_t avail = ~snap & h.cap_mask;
-      if (avail == 0) {  // filled since the lookup; its filler clears the bit
-        ++retries;
-        start = hash32(start + it + 1);
-        continue;
+      if (got != h.cap_mask) {
+        bm_set(active, (uint32_t)bid);
+        cur = bid;
+        cur_avail = ~got & h.cap_mask;
       }
-      const uint64_t take = lowest_bits(avail, n - served);
+    } else {
+      const uint64_t take = take_from(avail, want < (uint32_t)__popcll(avail) ? want : (uint32_t)__popcll(avail),
+                                      rot & (c - 1));
       const uint64_t prev = lead_or(h.obj_bitmap + bid, take);
       got = take & ~prev;
-      if (got != take) ++retries;
       const uint64_t after = (prev | take) & h.cap_mask;
       if (after == h.cap_mask && (prev & h.cap_mask) != h.cap_mask) bm_clear(active, (uint32_t)bid);
+      if (after != h.cap_mask) {
+        cur = bid;  // still has room: the next round can use it without a lookup
+        cur_avail = ~after & h.cap_mask;
+      }
+      if (got != take) ++retries;
       if (got == 0) {
-        start = hash32(start + it + 1);
+        if (cur == kFail) start = hash32(start + it + 1);
         continue;
       }
     }
     const uint32_t cnt = (uint32_t)__popcll(got);
-    if (rank >= served && rank < served + cnt) result = make_obj((uint32_t)bid, nth_set_bit(got, rank - served));
+    const uint32_t lo = prefix > served ? prefix : served;
+    const uint32_t hi = prefix + k < served + cnt ? prefix + k : served + cnt;
+    for (uint32_t r = lo; r < hi; ++r) f(r - prefix, make_obj((uint32_t)bid, nth_set_bit(got, r - served)));
     served += cnt;
   }
-  if (oom) lead_flag(h.ctrl + kCtlOom);
+  if (oom) {
+    lead_flag(h.ctrl + kCtlOom);
+    for (uint32_t r = prefix > served ? prefix : served; r < prefix + k; ++r) f(r - prefix, kNull);
+  }
   uint64_t* sh = shard(h);
   if (served) lead_add(sh + kCntAllocs + type, served);
   if (retries) lead_add(sh + kCntReserveRetries, retries);
   if (slow) lead_add(sh + kCntSlowPaths, slow);
   if (fails) lead_add(sh + kCntFindFails, fails);
-  return result;
 }
 
-// Device `new`: lanes may pass different types; each distinct type is served
-// as one coalesced request.
+// Device `new`: every calling lane gets one object of `type`.  Lanes may pass
+// different types; each distinct type is served as one coalesced request.
 __device__ inline uint32_t dsoar_new(const DevHeap& h, uint32_t type) {
   uint32_t result = kNull;
   for (;;) {
     const uint32_t t0 = bcast32(type);
     if (type == t0) {
-      result = new_uniform(h, t0);
+      new_many(h, t0, 1u, [&](uint32_t, uint32_t o) { result = o; });
       break;
     }
   }

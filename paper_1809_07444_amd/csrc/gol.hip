@@ -54,32 +54,47 @@ __device__ __forceinline__ void for_neighbours(const World& w, uint32_t wid, uin
   f(rp + xm); f(rp + x); f(rp + xp);
 }
 
+// Global index of neighbour d (0..7: the row above, left and right, the row
+// below) of cell (x, y) of a world at offset `off` with side `side`.
+__device__ __forceinline__ uint32_t neighbour(uint32_t off, uint32_t side, uint32_t x, uint32_t y, uint32_t d) {
+  const uint32_t ddx = (0x9224u >> (2 * d)) & 3u;  // dx + 1 for d = 0..7: 0 1 2 0 2 0 1 2
+  const uint32_t ddy = (0xA940u >> (2 * d)) & 3u;  // dy + 1 for d = 0..7: 0 0 0 1 1 2 2 2
+  uint32_t nx = x + ddx, ny = y + ddy;              // shifted by +1, wrap below
+  nx = nx == 0 ? side - 1 : (nx - 1 == side ? 0 : nx - 1);
+  ny = ny == 0 ? side - 1 : (ny - 1 == side ? 0 : ny - 1);
+  return off + ny * side + nx;
+}
+
 struct AlivePrep {
   static constexpr uint32_t kKind = 30;
   using Args = World;
   static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& w) {
     const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
     const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
-    uint32_t live = 0;
-    for_neighbours(w, wid, g, [&](uint32_t n) {
-      const uint32_t hc = w.cells[n];
-      if (hc == kNull) return;  // only after an out-of-memory init
+    const uint32_t off = w.off[wid], side = w.side[wid];
+    const uint32_t local = g - off;
+    const uint32_t y = local / side, x = local - y * side;
+    uint32_t live = 0, claim = 0;
+#pragma unroll
+    for (uint32_t d = 0; d < 8; ++d) {
+      const uint32_t hc = w.cells[neighbour(off, side, x, y, d)];
+      if (hc == kNull) continue;  // only after an out-of-memory init
       const uint32_t alive = *field_ptr<uint32_t>(h, hc, kCell, kCAlive);
       live += alive;
-      bool create = false;
       if (!alive) {
+        // The lane that flips the dead cell's cand flag creates its Candidate.
         uint32_t* cand = field_ptr<uint32_t>(h, hc, kCell, kCCand);
-        if (__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-          create = atomicCAS(cand, 0u, 1u) == 0u;
+        if (__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 && atomicCAS(cand, 0u, 1u) == 0u)
+          claim |= 1u << d;
       }
-      if (create) {
-        const uint32_t o = dsoar_new(h, kCand);
-        if (o != kNull) {
-          *field_ptr<uint32_t>(h, o, kCand, kACell) = n;
-          *field_ptr<uint32_t>(h, o, kCand, kAWorld) = wid;
-          *field_ptr<uint32_t>(h, o, kCand, kAAction) = 0;
-        }
-      }
+    }
+    // One coalesced allocation for all of the wavefront's new Candidates.
+    new_many(h, kCand, (uint32_t)__popc(claim), [&](uint32_t j, uint32_t o) {
+      if (o == kNull) return;
+      const uint32_t n = neighbour(off, side, x, y, nth_set_bit(claim, j));
+      *field_ptr<uint32_t>(h, o, kCand, kACell) = n;
+      *field_ptr<uint32_t>(h, o, kCand, kAWorld) = wid;
+      *field_ptr<uint32_t>(h, o, kCand, kAAction) = 0;
     });
     *field_ptr<uint32_t>(h, self, type, kAAction) = (live == 2 || live == 3) ? 0u : 1u;
     return false;

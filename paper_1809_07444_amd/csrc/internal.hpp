@@ -14,7 +14,7 @@ namespace dsoar {
 // level-0 allocated[T] bitmap (64 blocks each); a workgroup of kEnumWaves
 // wavefronts is one tile of the decoupled look-back scan.
 constexpr uint32_t kEnumWaves = 8;
-constexpr uint32_t kEnumWordsPerWave = 4;
+constexpr uint32_t kEnumWordsPerWave = 1;
 constexpr uint32_t kEnumTileWords = kEnumWaves * kEnumWordsPerWave;
 
 // Per-type scan state: tile ticket, epoch (so the look-back flags never need
