@@ -31,13 +31,17 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="gol", choices=["gol", "micro", "micro_scaled"])
+    p.add_argument("--workload", default="gol", choices=["gol", "micro", "micro_scaled", "batched"])
+    p.add_argument("--tune", default="cache", choices=["cache", "full", "off"],
+                   help="batched: autotune (cached in paper_1809_07444_amd/tune_cache.json), full re-tune, or defaults")
+    p.add_argument("--no-plain", action="store_true", help="batched: skip the per-world plain baseline")
     p.add_argument("--seed", type=int, default=24301)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-graph", action="store_true")
     p.add_argument("--traffic-probe", action="store_true",
                    help="after the run, launch one elementwise kernel over 256 MiB (counter calibration)")
     p.add_argument("--scaled-blocks", type=int, default=1 << 22)
+    p.add_argument("--probe", action="store_true", help="also measure atomic and copy ceilings")
     return p.parse_args()
 
 
@@ -176,6 +180,78 @@ class MicroWorkload:
                 "sample": f"micro oracle, {n} objects x {inp.steps} steps, {dt:.3f} s"}
 
 
+class BatchedWorkload(GolWorkload):
+    name = "batched"
+
+    def __init__(self, args):
+        import torch
+        from paper_1809_07444_amd import _capi as C
+        from paper_1809_07444_amd import batch
+        from synth import workloads as W
+        self.C, self.batch, self.torch = C, batch, torch
+        self.gens = 100
+        self.inp = W.batch_inputs(256, self.gens, seed=args.seed)
+        cache = os.path.join(ROOT, "paper_1809_07444_amd", "tune_cache.json")
+        self.tune_table = None
+        if args.tune == "off":
+            cfg = batch.TuneConfig()
+        else:
+            if args.tune == "full" and os.path.exists(cache):
+                os.remove(cache)
+            log = lambda m: print(m, file=sys.stderr, flush=True)
+            cfg, self.tune_table = batch.autotune(self.inp.grids, 10, cache_path=cache, log=log)
+        self.cfg = cfg
+        self.b = batch.BatchedGol(self.inp.grids, cfg)
+        self.gol = self.b.gol
+        self.M = self.gol.heap.num_blocks
+        self.args = args
+        from dataclasses import asdict
+        self.config = {"workload": f"gol-batched-256worlds-loguniform64..1024-bernoulli0.1-{self.gens}gen",
+                       "worlds": 256, "cells": int(self.gol.total), "generations": self.gens,
+                       "heap_blocks": self.M, "tuned": asdict(cfg), "graph": True, "seed": args.seed}
+
+    def step(self):
+        self.b.run(self.gens)
+
+    def profiled_step(self):
+        self.gol.init()
+        self.gol.step(self.gens, self.C.DO_PERSISTENT)
+
+    def plain_baseline(self):
+        import torch
+        out = {}
+        for name, sync in (("plain", False), ("plain_sync", True)):
+            p = self.batch.PlainGol(self.inp.grids, capacity=64, sync=sync)
+            p.run(1)
+            p.synchronize()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p.run(self.gens)
+            p.synchronize()
+            out[name + "_ms"] = (time.perf_counter() - t0) * 1e3
+            del p
+            torch.cuda.empty_cache()
+        return out
+
+    def cpu_baseline(self):
+        import oracle
+        # Bounded sample: the first worlds in order until ~10 s of oracle work.
+        t0 = time.perf_counter()
+        ops = cells = 0
+        n = 0
+        for g in self.inp.grids:
+            _, c = oracle.gol_run(g, self.gens)
+            ops += int(2 * c[:, 0].sum() + c[:, 1].sum() + c[:, 2].sum())
+            cells += g.size
+            n += 1
+            if time.perf_counter() - t0 > 10:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": ops / dt, "unit": "allocs+frees/s", "cores": 1, "kind": "oracle",
+                "sample": f"dense B3/S23 oracle on the first {n} of 256 worlds ({cells} cells), {self.gens} "
+                          f"generations, {dt:.1f} s"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -187,6 +263,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "gol":
         wl = GolWorkload(args)
+    elif args.workload == "batched":
+        wl = BatchedWorkload(args)
     else:
         wl = MicroWorkload(args, scaled=args.workload == "micro_scaled")
 
@@ -234,6 +312,15 @@ def main():
     if not args.no_cpu_baseline:
         cpu = wl.cpu_baseline()
 
+    extra = {}
+    if args.probe:
+        from paper_1809_07444_amd import probe
+        extra["ceilings"] = dict(probe.atomics(), copy_gbs=probe.copy_bandwidth())
+    if args.workload == "batched" and not args.no_plain:
+        pb = wl.plain_baseline()
+        extra["batched_vs_plain"] = dict(pb, batched_ms=ms, speedup_vs_plain=pb["plain_ms"] / ms,
+                                         speedup_vs_plain_sync=pb["plain_sync_ms"] / ms)
+
     if args.traffic_probe:
         a = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
         b = torch.empty_like(a)
@@ -250,6 +337,7 @@ def main():
                      "find_fails": st1["find_fails"], "allocated_blocks_end": st1["allocated_blocks"]},
         "roofline": roof, "cpu_baseline": cpu, "kernels": kernels,
     }
+    out.update(extra)
     del st0
     print(json.dumps(out))
 

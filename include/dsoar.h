@@ -152,6 +152,13 @@ int dsoar_heap_get_layout(const dsoar_heap* heap, dsoar_heap_layout* out);
  * compute unit (1..64).  Defaults 256 and 8. */
 int dsoar_heap_set_launch(dsoar_heap* heap, uint32_t wg_threads, uint32_t wgs_per_cu);
 
+/* Allocation policy: a wavefront whose outstanding requests number at least
+ * bulk_min takes whole free blocks directly instead of first filling active
+ * blocks (whole blocks are fully dense; smaller remainders always go to
+ * active blocks first).  Values below the block capacity mean the capacity
+ * (the default); 0xFFFFFFFF always fills active blocks first. */
+int dsoar_heap_set_policy(dsoar_heap* heap, uint32_t bulk_min);
+
 /* Per-launch timing: when enabled, every enumeration and do-all launch of
  * this heap is bracketed by a pair of HIP events on its stream (at most 8192
  * launches are recorded between reports).  dsoar_heap_timing synchronises on
@@ -270,6 +277,18 @@ int dsoar_micro_init(dsoar_heap* heap, uint32_t type, uint32_t n, const float* x
 int dsoar_micro_step(dsoar_heap* heap, uint32_t type, uint32_t n_renew, const float* xs_dev,
                      const float* vs_dev, uint32_t flags, void* stream);
 
+/* ------------------------------------------------------------------ probes
+ * Ceilings the heap is measured against (AMD publishes no atomic peak).
+ * dsoar_probe_atomics: `waves` wavefronts, one lane each, do `iters` agent-
+ * scope 64-bit atomic ORs: mode 0 each on its own 64-byte line (throughput),
+ * 1 the same as a dependent chain (latency), 2 all on one word (contention);
+ * mode 3 is a chain of dependent agent-scope loads.  buf_dev: >= 16 words,
+ * 64-byte aligned, scratch (overwritten).  dsoar_probe_copy: a plain 16-byte
+ * vector copy kernel (bytes a multiple of 16). */
+int dsoar_probe_atomics(void* buf_dev, uint32_t words, uint32_t mode, uint32_t iters, uint32_t waves,
+                        void* stream);
+int dsoar_probe_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stream);
+
 /* ------------------------------------------------- Game of Life as objects
  * The paper's game-of-life application (Sec. 4, applications figure) on
  * square tori, one or many worlds in one heap.  The heap must declare, in
@@ -278,8 +297,9 @@ int dsoar_micro_step(dsoar_heap* heap, uint32_t type, uint32_t n_renew, const fl
  * generation is four do-alls (Alive, Candidate, Alive, Candidate); Candidate
  * and Alive objects are created and deleted with device new/delete. */
 typedef struct dsoar_gol dsoar_gol;
-#define DSOAR_GOL_GRAPH 0x100u /* capture one generation once into a HIP graph and
-                                  replay it (needs a non-default stream) */
+#define DSOAR_GRAPH 0x100u     /* capture one generation (step) once into a HIP graph
+                                  and replay it (needs a non-default stream) */
+#define DSOAR_GOL_GRAPH DSOAR_GRAPH
 /* Device bytes for the world table and the cell index (0 if invalid).  sides:
  * host array of num_worlds side lengths (1..65535, total cells < 2^32). */
 size_t dsoar_gol_bytes(uint32_t num_worlds, const uint32_t* sides);
@@ -299,6 +319,46 @@ int dsoar_gol_step(dsoar_gol* gol, uint32_t generations, uint32_t flags, void* s
 /* grid_dev[g] = 1 if cell g is alive, else 0 (uint8 per global cell). */
 int dsoar_gol_read(dsoar_gol* gol, uint8_t* grid_dev, void* stream);
 uint32_t dsoar_gol_total_cells(const dsoar_gol* gol);
+
+/* ------------------------------------------------- Sugarscape-style agents
+ * The paper's sugarscape application (Sec. 4, applications figure) with a
+ * synchronous, deterministic rule set on a side x side torus.  The heap's
+ * type 0 must be Agent {int32 sugar, metabolism, vision, age, pos, target}.
+ * One step: regrow (sugar = min(sugar + 1, cap)); choose the best visible
+ * cell (most sugar, then nearest, then lowest index, among the own cell and
+ * unoccupied cells up to `vision` along the four axes); move (the lowest
+ * requesting cell index wins a target); eat, metabolise, age, and die (delete)
+ * at sugar <= 0 or age >= max_age; fertile agents (fertile_min <= age <=
+ * fertile_max) with sugar >= repro_min request their lowest-index empty von
+ * Neumann neighbour, and the lowest requesting cell index creates a child
+ * there (new) with half of its sugar, metabolism U{1..4} and vision U{1..6}
+ * drawn from hash(seed, 10 or 11, step, cell), age 0. */
+typedef struct dsoar_sugar dsoar_sugar;
+typedef struct {
+  int32_t max_age, repro_min, fertile_min, fertile_max;
+  uint64_t seed;
+} dsoar_sugar_rules;
+/* Device bytes for the grids of a side x side world (0 if invalid). */
+size_t dsoar_sugar_bytes(uint32_t side);
+int dsoar_sugar_create(dsoar_heap* heap, uint32_t side, const dsoar_sugar_rules* rules, void* dev_mem,
+                       size_t dev_bytes, dsoar_sugar** out);
+int dsoar_sugar_destroy(dsoar_sugar* sugar);
+/* Initial state from per-cell device arrays (side*side each): sugar and cap
+ * (int32), occ (uint8, 1 = an agent starts here) and the agents' sugar,
+ * metabolism, vision and age (int32, read where occ).  step0 = index of the
+ * first step (it keys the random draws).  The heap should be freshly reset. */
+int dsoar_sugar_init(dsoar_sugar* sugar, const int32_t* sugar_dev, const int32_t* cap_dev,
+                     const uint8_t* occ_dev, const int32_t* a_sugar_dev, const int32_t* a_metab_dev,
+                     const int32_t* a_vision_dev, const int32_t* a_age_dev, uint32_t step0, void* stream);
+/* Advances `steps` steps.  flags: DSOAR_DO_PLAIN or DSOAR_DO_PERSISTENT,
+ * optionally | DSOAR_GRAPH (persistent only). */
+int dsoar_sugar_step(dsoar_sugar* sugar, uint32_t steps, uint32_t flags, void* stream);
+/* Canonical state per cell (device arrays, side*side each); agent fields are 0
+ * where no agent is.  *moves (host, optional) receives the moves made since
+ * init and synchronises the stream. */
+int dsoar_sugar_read(dsoar_sugar* sugar, int32_t* sugar_dev, uint8_t* occ_dev, int32_t* a_sugar_dev,
+                     int32_t* a_metab_dev, int32_t* a_vision_dev, int32_t* a_age_dev, uint32_t* moves,
+                     void* stream);
 
 #ifdef __cplusplus
 }

@@ -22,12 +22,13 @@ ERRORS = {
 ERR_OOM, ERR_RETRY_LIMIT, ERR_DOUBLE_FREE = -2, -3, -5
 
 DO_PERSISTENT, DO_PLAIN, DO_REUSE_ENUM = 0, 1, 2
-GOL_GRAPH = 0x100
+GRAPH = GOL_GRAPH = 0x100
 METHOD_VISIT_COUNT, METHOD_DELETE_IF_MOD, METHOD_MICRO_UPDATE, METHOD_MICRO_CULL, METHOD_FIELD_GATHER = 1, 2, 3, 4, 5
 BM_TRY_SET, BM_TRY_CLEAR, BM_SET, BM_CLEAR, BM_TRY_FIND_SET, BM_FIND_CLEAR = range(6)
 KIND_NAMES = {1: "enumerate", 10: "visit_count", 11: "delete_if_mod", 12: "gather", 20: "micro_update",
               21: "micro_cull", 30: "gol_alive_prep", 31: "gol_cand_prep", 32: "gol_alive_update",
-              33: "gol_cand_update"}
+              33: "gol_cand_update", 40: "sugar_choose", 41: "sugar_move", 42: "sugar_eat",
+              43: "sugar_request", 44: "sugar_birth"}
 INV_NAMES = ["bitmap_range", "allocated", "active", "active_implies_allocated", "free",
              "container", "live_count", "reserved"]
 
@@ -59,6 +60,11 @@ class Stats(ctypes.Structure):
                 ("retry_limit_hit", u32), ("double_free", u32), ("reserved", u32)]
 
 
+class SugarRules(ctypes.Structure):
+    _fields_ = [("max_age", i32), ("repro_min", i32), ("fertile_min", i32), ("fertile_max", i32),
+                ("seed", u64)]
+
+
 class VisitArgs(ctypes.Structure):
     _fields_ = [("counts_dev", vp)]
 
@@ -81,6 +87,7 @@ SIGNATURES = {
     "dsoar_heap_reset": (ctypes.c_int, [H, vp]),
     "dsoar_heap_get_layout": (ctypes.c_int, [H, ctypes.POINTER(HeapLayout)]),
     "dsoar_heap_set_launch": (ctypes.c_int, [H, u32, u32]),
+    "dsoar_heap_set_policy": (ctypes.c_int, [H, u32]),
     "dsoar_last_hip_error": (ctypes.c_int, [H]),
     "dsoar_heap_set_timing": (ctypes.c_int, [H, ctypes.c_int]),
     "dsoar_heap_timing": (ctypes.c_int, [H, vp, vp, vp, u32, ctypes.POINTER(u32)]),
@@ -102,6 +109,8 @@ SIGNATURES = {
     "dsoar_bitmap_run": (ctypes.c_int, [vp, u32, vp, u32, vp, vp, vp]),
     "dsoar_micro_init": (ctypes.c_int, [H, u32, u32, vp, vp, vp]),
     "dsoar_micro_step": (ctypes.c_int, [H, u32, u32, vp, vp, u32, vp]),
+    "dsoar_probe_atomics": (ctypes.c_int, [vp, u32, u32, u32, u32, vp]),
+    "dsoar_probe_copy": (ctypes.c_int, [vp, vp, sz, vp]),
     "dsoar_gol_bytes": (sz, [u32, vp]),
     "dsoar_gol_create": (ctypes.c_int, [H, u32, vp, vp, sz, vp, ctypes.POINTER(vp)]),
     "dsoar_gol_destroy": (ctypes.c_int, [vp]),
@@ -109,6 +118,12 @@ SIGNATURES = {
     "dsoar_gol_step": (ctypes.c_int, [vp, u32, u32, vp]),
     "dsoar_gol_read": (ctypes.c_int, [vp, vp, vp]),
     "dsoar_gol_total_cells": (u32, [vp]),
+    "dsoar_sugar_bytes": (sz, [u32]),
+    "dsoar_sugar_create": (ctypes.c_int, [H, u32, vp, vp, sz, ctypes.POINTER(vp)]),
+    "dsoar_sugar_destroy": (ctypes.c_int, [vp]),
+    "dsoar_sugar_init": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, u32, vp]),
+    "dsoar_sugar_step": (ctypes.c_int, [vp, u32, u32, vp]),
+    "dsoar_sugar_read": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(u32), vp]),
 }
 
 _lib = None

@@ -138,3 +138,80 @@ class GameOfLife:
 
     def synchronize(self):
         self.stream.synchronize()
+
+
+# -------------------------------------------------------------- sugarscape --
+
+SUGAR_TYPE = [(4, 4, 4, 4, 4, 4)]  # Agent {sugar, metabolism, vision, age, pos, target}
+
+
+@dataclass
+class SugarGpuState:
+    side: int
+    sugar: np.ndarray
+    occ: np.ndarray
+    a_sugar: np.ndarray
+    a_metab: np.ndarray
+    a_vision: np.ndarray
+    a_age: np.ndarray
+    moves: int
+    stats: dict
+
+
+class Sugarscape:
+    """The Sugarscape-style agent model of one world as objects in a device heap."""
+
+    def __init__(self, inp, rules: dict, capacity: int = 64, num_blocks: int | None = None, stream=None,
+                 device="cuda"):
+        self.side = inp.side
+        n = self.side * self.side
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        blocks = num_blocks or max(64, 1 << (max(1, -(-n // capacity)) - 1).bit_length())
+        self.heap = Heap(blocks, capacity, SUGAR_TYPE, device=device, stream=self.stream)
+        self.lib = self.heap.lib
+        nbytes = int(self.lib.dsoar_sugar_bytes(self.side))
+        if nbytes == 0:
+            raise ValueError("bad side")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.rules = C.SugarRules(rules["max_age"], rules["repro_min"], rules["fertile_min"],
+                                  rules["fertile_max"], int(inp.seed))
+        with torch.cuda.stream(self.stream):
+            self.inputs = [torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in
+                           (inp.sugar, inp.cap, inp.occ, inp.a_sugar, inp.a_metab, inp.a_vision, inp.a_age)]
+            self.out = [torch.empty(n, dtype=dt, device=device) for dt in
+                        (torch.int32, torch.uint8, torch.int32, torch.int32, torch.int32, torch.int32)]
+        s = ctypes.c_void_p()
+        C.check(self.lib.dsoar_sugar_create(self.heap.h, self.side, ctypes.byref(self.rules), self.buf.data_ptr(),
+                                            nbytes, ctypes.byref(s)), "dsoar_sugar_create")
+        self.s = s
+
+    def close(self):
+        if getattr(self, "s", None):
+            self.lib.dsoar_sugar_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, step0: int = 0):
+        self.heap.reset()
+        C.check(self.lib.dsoar_sugar_init(self.s, *[t.data_ptr() for t in self.inputs], step0, self.heap._s()),
+                "dsoar_sugar_init")
+
+    def step(self, steps: int, flags: int = C.DO_PERSISTENT):
+        C.check(self.lib.dsoar_sugar_step(self.s, steps, flags, self.heap._s()), "dsoar_sugar_step")
+
+    def read(self) -> SugarGpuState:
+        moves = ctypes.c_uint32()
+        C.check(self.lib.dsoar_sugar_read(self.s, *[t.data_ptr() for t in self.out], ctypes.byref(moves),
+                                          self.heap._s()), "dsoar_sugar_read")
+        self.stream.synchronize()
+        a = [t.cpu().numpy() for t in self.out]
+        return SugarGpuState(self.side, a[0], a[1], a[2], a[3], a[4], a[5], int(moves.value),
+                             self.heap.stats(raise_sticky=False))
+
+    def synchronize(self):
+        self.stream.synchronize()

@@ -63,6 +63,7 @@ struct DevHeap {
   uint32_t num_types;
   uint32_t nlevels;
   uint32_t bm_words;        // words per bitmap (all levels, padded)
+  uint32_t bulk_min;        // requests of at least this many take whole free blocks
   uint32_t field_off[kMaxTypes][kMaxFields];
   uint8_t field_shift[kMaxTypes][kMaxFields];  // log2(field width)
 };
@@ -276,20 +277,30 @@ __device__ inline bool bm_try_clear(const Bitmap& b, uint32_t pos) {
   return ok;
 }
 
+// The set bit of w (w != 0) that a 6-bit digit d selects: the
+// floor(d * popcount / 64)-th one, so digits spread evenly over the set bits
+// whatever their positions (a plain "first set bit at or after d" would send
+// every digit beyond the last set bit to the first one).
+__device__ __forceinline__ uint32_t pick_bit(uint64_t w, uint32_t d) {
+  return nth_set_bit(w, (d * (uint32_t)__popcll(w)) >> 6);
+}
+
+__device__ __forceinline__ uint32_t level_digit(uint32_t start, uint32_t l) {
+  return (start >> ((6 * l) % 30)) & 63u;
+}
+
 // try_find_set(): descend from the top word, one load per level (a
-// logarithmic number of accesses, Sec. 2.4).  At each level take the first
-// set bit at or after the matching base-64 digit of `start` (wrapping), which
-// spreads concurrent searches over the bitmap.  An empty word on the way down
-// means the summary is momentarily ahead of its container: FAIL.
+// logarithmic number of accesses, Sec. 2.4).  At each level the base-64 digit
+// of `start` for that level picks one of the word's set bits, so concurrent
+// searches with different starts spread over the whole bitmap.  An empty word
+// on the way down means the summary is momentarily ahead of its container:
+// FAIL.
 __device__ inline int32_t bm_try_find_set(const Bitmap& b, uint32_t start) {
   uint32_t idx = 0;
   for (int32_t l = (int32_t)b.nlevels - 1; l >= 0; --l) {
     const uint64_t w = load_u64(b.word((uint32_t)l, idx));
     if (w == 0) return kFail;
-    const uint32_t d = (6 * (uint32_t)l < 32) ? ((start >> (6 * (uint32_t)l)) & 63u) : 0u;
-    const uint64_t r = (w >> d) | (d ? (w << (64 - d)) : 0ull);
-    const uint32_t bit = ((uint32_t)__builtin_ctzll(r) + d) & 63u;
-    idx = (idx << 6) | bit;
+    idx = (idx << 6) | pick_bit(w, level_digit(start, (uint32_t)l));
   }
   return idx < b.nbits ? (int32_t)idx : kFail;
 }
@@ -322,9 +333,7 @@ __device__ inline uint64_t bm_take_word(const Bitmap& b, uint32_t start, uint32_
       w = load_u64(b.word((uint32_t)l, idx));
       if (w == 0) break;
       if (l == 0) break;
-      const uint32_t d = (6 * (uint32_t)l < 32) ? ((start >> (6 * (uint32_t)l)) & 63u) : 0u;
-      const uint64_t r = (w >> d) | (d ? (w << (64 - d)) : 0ull);
-      idx = (idx << 6) | (((uint32_t)__builtin_ctzll(r) + d) & 63u);
+      idx = (idx << 6) | pick_bit(w, level_digit(start, (uint32_t)l));
     }
     if (w != 0) {
       const uint64_t take = take_from(w, want < (uint32_t)__popcll(w) ? want : (uint32_t)__popcll(w), start & 63u);
@@ -401,7 +410,7 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
       break;
     }
     const uint32_t want = n - served;
-    if (want >= c && !active_first) {
+    if (want >= h.bulk_min && want >= c && !active_first) {
       // Whole free blocks, several from one free-bitmap word per atomic.
       uint32_t word = 0;
       const uint32_t nb = want / c < 64 ? want / c : 64;

@@ -213,7 +213,7 @@ struct dsoar_gol {
   uint32_t total;
   hipGraph_t graph;
   hipGraphExec_t exec;
-  uint32_t graph_flags;
+  uint32_t graph_epoch;  // heap config_epoch the graph was captured with
 };
 
 namespace {
@@ -307,6 +307,12 @@ int dsoar_gol_step(dsoar_gol* g, uint32_t generations, uint32_t flags, void* str
   dsoar_heap* h = g->heap;
   if (flags & DSOAR_GOL_GRAPH) {
     if (flags & DSOAR_DO_PLAIN) return DSOAR_ERR_INVALID_ARG;  // plain mode synchronises
+    if (g->exec && g->graph_epoch != h->config_epoch) {  // launch shape or policy changed
+      (void)hipGraphExecDestroy(g->exec);
+      (void)hipGraphDestroy(g->graph);
+      g->exec = nullptr;
+      g->graph = nullptr;
+    }
     if (!g->exec) {
       DSOAR_HIP(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       const int rc = gol_generation(g, 0, s);
@@ -319,6 +325,7 @@ int dsoar_gol_step(dsoar_gol* g, uint32_t generations, uint32_t flags, void* str
       if (e != hipSuccess) return hip_fail(h, e);
       g->graph = graph;
       DSOAR_HIP(h, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+      g->graph_epoch = h->config_epoch;
     }
     for (uint32_t i = 0; i < generations; ++i) DSOAR_HIP(h, hipGraphLaunch(g->exec, s));
     return DSOAR_OK;

@@ -53,6 +53,7 @@ struct Plan {
   uint64_t ctrl_off, stats_off;
   uint64_t R_off[kMaxTypes], S_off[kMaxTypes], scan_off[kMaxTypes];
   uint32_t num_tiles;
+  uint32_t enum_wpw;
 };
 
 Plan make_plan(const dsoar_heap_desc* d) {
@@ -90,7 +91,9 @@ Plan make_plan(const dsoar_heap_desc* d) {
   p.stats_off = off;
   off = align_up(off + sizeof(StatsOut), kAlign);
   const uint64_t W0 = (M + 63) / 64;
-  p.num_tiles = (uint32_t)((W0 + kEnumTileWords - 1) / kEnumTileWords);
+  p.enum_wpw = W0 > kEnumWideFrom ? kEnumWideWords : 1;
+  const uint64_t tile_words = (uint64_t)kEnumWaves * p.enum_wpw;
+  p.num_tiles = (uint32_t)((W0 + tile_words - 1) / tile_words);
   for (uint32_t t = 0; t < d->num_types; ++t) {
     p.R_off[t] = off;
     off = align_up(off + M * 4, kAlign);
@@ -190,13 +193,26 @@ __device__ inline void set_bits0(const Bitmap& b, uint32_t word, uint64_t m) {
 
 // Quiescent reclamation of the blocks in `rc` (a wave's lanes, word `word`),
 // all of type t and empty: they leave allocated[t] and active[t] and become
-// free again (the block-state figure's transition back to free).
+// free again (the block-state figure's transition back to free).  The three
+// level-0 updates are issued together; each does the nested update its
+// single-bit counterpart would (Alg. 2).
 __device__ inline void reclaim_word(const DevHeap& h, uint32_t t, uint32_t word, uint64_t rc) {
   if ((rc >> lane_id()) & 1ull) h.block_type[word * 64 + lane_id()] = kTypeNone;
-  clear_bits0(allocated_bm(h, t), word, rc);
-  const uint64_t act = load_u64(active_bm(h, t).word(0, word)) & rc;
-  if (act) clear_bits0(active_bm(h, t), word, act);
-  set_bits0(free_bm(h), word, rc);
+  const Bitmap al = allocated_bm(h, t), ac = active_bm(h, t), fr = free_bm(h);
+  uint64_t pa = 0, pc = 0, pf = 0;
+  if (is_first_active()) {
+    pa = __hip_atomic_fetch_and(al.word(0, word), ~rc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pc = __hip_atomic_fetch_and(ac.word(0, word), ~rc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pf = __hip_atomic_fetch_or(fr.word(0, word), rc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  pa = bcast64(pa);
+  pc = bcast64(pc);
+  pf = bcast64(pf);
+  if (al.nlevels > 1) {
+    if ((pa & rc) && (pa & ~rc) == 0) bm_clear_from(al, 1, word);
+    if ((pc & rc) && (pc & ~rc) == 0) bm_clear_from(ac, 1, word);
+    if (pf == 0) bm_set_from(fr, 1, word);
+  }
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -213,7 +229,10 @@ __device__ __forceinline__ uint64_t pack_flag(uint32_t epoch, uint64_t status, u
 // bits -> block ids), drop the empty blocks (reclaiming them) and compact the
 // rest into R with their object-bitmap snapshots (step 2, prefix sum).  One
 // pass: tile prefixes come from a decoupled look-back over per-tile flags,
-// tiles taken in launch order from a ticket counter.
+// tiles taken in launch order from a ticket counter.  Each wavefront covers
+// WPW level-0 words (64 blocks each); all their loads are issued before any
+// is used.  The heap is quiescent, so plain loads see the previous kernels.
+template <uint32_t WPW>
 __global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeap h, uint32_t type, EnumOut out) {
   __shared__ uint32_t s_tile, s_epoch, s_prefix;
   __shared__ uint32_t s_wave_total[kEnumWaves];
@@ -225,25 +244,25 @@ __global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeap h, u
   const uint32_t tile = s_tile, epoch = s_epoch;
   const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
   const uint32_t W0 = (h.num_blocks + 63) >> 6;
-  const Bitmap alloc = allocated_bm(h, type);
-  uint64_t live[kEnumWordsPerWave], snap[kEnumWordsPerWave];
+  const uint32_t word0 = (tile * kEnumWaves + wave) * WPW;
+  const uint64_t* alloc0 = allocated_bm(h, type).words;  // level 0 comes first
+  uint64_t w[WPW], live[WPW], snap[WPW];
+#pragma unroll
+  for (uint32_t j = 0; j < WPW; ++j) w[j] = word0 + j < W0 ? alloc0[word0 + j] : 0ull;
+#pragma unroll
+  for (uint32_t j = 0; j < WPW; ++j) {
+    const uint32_t b = (word0 + j) * 64 + lane;
+    const bool bit = ((w[j] >> lane) & 1ull) && b < h.num_blocks;
+    snap[j] = bit ? h.obj_bitmap[b] : 0ull;
+  }
   uint32_t wave_total = 0;
 #pragma unroll
-  for (uint32_t j = 0; j < kEnumWordsPerWave; ++j) {
-    const uint32_t word = tile * kEnumTileWords + wave * kEnumWordsPerWave + j;
-    live[j] = 0;
-    snap[j] = 0;
-    if (word < W0) {
-      const uint64_t w = load_u64(alloc.word(0, word));
-      const bool bit = ((w >> lane) & 1ull) && word * 64 + lane < h.num_blocks;
-      const uint64_t o = bit ? h.obj_bitmap[word * 64 + lane] : 0ull;
-      const uint64_t lv = __ballot(bit && o != 0);
-      const uint64_t rc = __ballot(bit && o == 0);
-      if (rc) reclaim_word(h, type, word, rc);
-      live[j] = lv;
-      snap[j] = o;
-      wave_total += (uint32_t)__popcll(lv);
-    }
+  for (uint32_t j = 0; j < WPW; ++j) {
+    const bool bit = (w[j] >> lane) & 1ull;
+    live[j] = __ballot(bit && snap[j] != 0);
+    const uint64_t rc = __ballot(bit && snap[j] == 0);
+    if (rc) reclaim_word(h, type, word0 + j, rc);
+    wave_total += (uint32_t)__popcll(live[j]);
   }
   if (lane == 0) s_wave_total[wave] = wave_total;
   __syncthreads();
@@ -294,11 +313,10 @@ __global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeap h, u
   __syncthreads();
   uint32_t base = s_prefix + wave_off;
 #pragma unroll
-  for (uint32_t j = 0; j < kEnumWordsPerWave; ++j) {
-    const uint32_t word = tile * kEnumTileWords + wave * kEnumWordsPerWave + j;
+  for (uint32_t j = 0; j < WPW; ++j) {
     if ((live[j] >> lane) & 1ull) {
       const uint32_t pos = base + lanes_below(live[j]);
-      out.R[pos] = word * 64 + lane;
+      out.R[pos] = (word0 + j) * 64 + lane;
       out.S[pos] = snap[j];
     }
     base += (uint32_t)__popcll(live[j]);
@@ -494,8 +512,12 @@ struct FieldGather {
 
 int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s) {
   const int rec = timing_begin(h, kKindEnumerate, s);
-  hipLaunchKernelGGL(enumerate_kernel, dim3(h->num_tiles), dim3(kEnumWaves * 64), 0, s, h->dev, type,
-                     h->enum_out[type]);
+  if (h->enum_wpw == kEnumWideWords)
+    hipLaunchKernelGGL(enumerate_kernel<kEnumWideWords>, dim3(h->num_tiles), dim3(kEnumWaves * 64), 0, s, h->dev,
+                       type, h->enum_out[type]);
+  else
+    hipLaunchKernelGGL(enumerate_kernel<1>, dim3(h->num_tiles), dim3(kEnumWaves * 64), 0, s, h->dev, type,
+                       h->enum_out[type]);
   timing_end(h, rec, s);
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
@@ -613,6 +635,7 @@ int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_byt
   h->base = (uint8_t*)dev_mem;
   h->bytes = dev_bytes;
   h->num_tiles = p.num_tiles;
+  h->enum_wpw = p.enum_wpw;
   DevHeap& d = h->dev;
   d.data = h->base + p.L.data_offset;
   d.obj_bitmap = (uint64_t*)(h->base + p.L.obj_bitmap_offset);
@@ -649,6 +672,7 @@ int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_byt
   h->num_cus = (uint32_t)prop.multiProcessorCount;
   h->doall_wg_threads = 256;
   h->doall_wgs_per_cu = 8;
+  d.bulk_min = desc->block_capacity;
   const int rc = init_device_state(h, (hipStream_t)stream);
   if (rc) {
     delete h;
@@ -744,6 +768,14 @@ int dsoar_heap_set_launch(dsoar_heap* h, uint32_t wg_threads, uint32_t wgs_per_c
     return DSOAR_ERR_INVALID_ARG;
   h->doall_wg_threads = wg_threads;
   h->doall_wgs_per_cu = wgs_per_cu;
+  h->config_epoch++;
+  return DSOAR_OK;
+}
+
+int dsoar_heap_set_policy(dsoar_heap* h, uint32_t bulk_min) {
+  if (!heap_ok(h)) return DSOAR_ERR_INVALID_ARG;
+  h->dev.bulk_min = bulk_min < h->desc.block_capacity ? h->desc.block_capacity : bulk_min;
+  h->config_epoch++;
   return DSOAR_OK;
 }
 

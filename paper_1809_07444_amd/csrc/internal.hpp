@@ -10,12 +10,13 @@
 
 namespace dsoar {
 
-// Enumeration tiling: one wavefront scans kEnumWordsPerWave words of the
-// level-0 allocated[T] bitmap (64 blocks each); a workgroup of kEnumWaves
-// wavefronts is one tile of the decoupled look-back scan.
+// Enumeration tiling: one wavefront scans 1 word of the level-0 allocated[T]
+// bitmap (64 blocks), or kEnumWideWords words when the bitmap has more than
+// kEnumWideFrom words; a workgroup of kEnumWaves wavefronts is one tile of
+// the decoupled look-back scan.
 constexpr uint32_t kEnumWaves = 8;
-constexpr uint32_t kEnumWordsPerWave = 1;
-constexpr uint32_t kEnumTileWords = kEnumWaves * kEnumWordsPerWave;
+constexpr uint32_t kEnumWideWords = 8;
+constexpr uint32_t kEnumWideFrom = 16384;
 
 // Per-type scan state: tile ticket, epoch (so the look-back flags never need
 // clearing between launches), the resulting count, then one flag per tile.
@@ -55,9 +56,11 @@ struct dsoar_heap {
   dsoar::EnumOut enum_out[dsoar::kMaxTypes];
   dsoar::StatsOut* stats_dev;
   uint32_t num_tiles;
+  uint32_t enum_wpw;           // level-0 words per enumeration wavefront
   uint32_t num_cus;
   uint32_t doall_wg_threads;   // workgroup size of do-all launches
   uint32_t doall_wgs_per_cu;   // persistent grid = num_cus * this
+  uint32_t config_epoch;       // bumped when launch shape or policy change
   hipError_t last_hip;
   // Optional per-launch timing with HIP events on the launch stream.
   int timing;

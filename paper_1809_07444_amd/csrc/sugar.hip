@@ -1,0 +1,403 @@
+// Sugarscape-style agents as objects on a square torus (the paper's
+// sugarscape application, Sec. 4; its rules are not in the paper, so this is
+// a synchronous, deterministic variant).  Agent {sugar, metabolism, vision,
+// age, pos, target}; the sugar, capacity, occupancy and request grids are
+// plain device arrays.  One step t:
+//   regrow (grid kernel): sugar = min(sugar + 1, cap)
+//   1 choose  (do-all): best of the own cell and the unoccupied cells up to
+//             `vision` away along the four axes: most sugar, then nearest,
+//             then lowest index; a move request is an atomicMin of the own
+//             cell index into req[target]
+//   2 move    (do-all): the lowest requesting cell index wins the target
+//   3 eat     (do-all): sugar += cell; cell = 0; sugar -= metabolism; age++;
+//             die (delete) if sugar <= 0 or age >= max_age
+//   4 request (do-all): fertile agents with enough sugar request their
+//             lowest-index empty von Neumann neighbour (atomicMin)
+//   5 birth   (do-all): the winner creates a child there with half its sugar
+//             and traits drawn from hash(seed, stream, t, cell)
+// Phases read occupancy only as it was when the phase started and change it
+// only where no other agent of the phase looks, so the result does not depend
+// on which lane or block runs first.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "internal.hpp"
+
+namespace dsoar {
+namespace {
+
+enum : uint32_t { kAgent = 0 };
+enum : uint32_t { kSugar = 0, kMetab = 1, kVision = 2, kAge = 3, kPos = 4, kTarget = 5 };
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+constexpr uint64_t kStreamChildMetab = 10, kStreamChildVision = 11;
+
+// SplitMix64 output finaliser (Steele, Lea, Flood, OOPSLA 2014) and the
+// workload hash h(seed, stream, a, b) = mix(mix(mix(seed ^ stream*golden) ^ a) ^ b).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
+}
+__device__ __forceinline__ uint64_t hash4(uint64_t seed, uint64_t stream, uint64_t a, uint64_t b) {
+  return mix64(mix64(mix64(seed ^ (stream * 0x9E3779B97F4A7C15ull)) ^ a) ^ b);
+}
+// U{lo..hi}: lo + floor(top32(h) * (hi - lo + 1) / 2^32).
+__device__ __forceinline__ int32_t uniform_int(uint64_t h, int32_t lo, int32_t hi) {
+  return lo + (int32_t)(((h >> 32) * (uint64_t)(hi - lo + 1)) >> 32);
+}
+
+struct Grid {
+  int32_t* sugar;
+  const int32_t* cap;
+  uint32_t* occ;    // agent handle or kNull
+  uint32_t* req;    // lowest requesting cell index or kInf
+  uint32_t* breq;
+  uint32_t* ctr;    // [0] step index; [2..3] moves (uint64)
+  uint32_t side;
+  int32_t max_age, repro_min, fertile_min, fertile_max;
+  uint64_t seed;
+};
+
+__device__ __forceinline__ uint32_t wrap_cell(int32_t side, int32_t x, int32_t y) {
+  x %= side;
+  if (x < 0) x += side;
+  y %= side;
+  if (y < 0) y += side;
+  return (uint32_t)y * (uint32_t)side + (uint32_t)x;
+}
+
+template <class F>
+__device__ __forceinline__ F& af(const DevHeap& h, uint32_t self, uint32_t field) {
+  return *field_ptr<F>(h, self, kAgent, field);
+}
+
+struct Choose {
+  static constexpr uint32_t kKind = 40;
+  using Args = Grid;
+  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
+    const uint32_t p = af<uint32_t>(h, self, kPos);
+    const int32_t vision = af<int32_t>(h, self, kVision);
+    const int32_t side = (int32_t)g.side;
+    const int32_t px = (int32_t)(p % g.side), py = (int32_t)(p / g.side);
+    uint32_t best = p;
+    int32_t best_sugar = g.sugar[p], best_dist = 0;
+    for (int32_t d = 0; d < 4; ++d) {
+      const int32_t dx = d == 0 ? 1 : (d == 1 ? -1 : 0);
+      const int32_t dy = d == 2 ? 1 : (d == 3 ? -1 : 0);
+      for (int32_t k = 1; k <= vision; ++k) {
+        const uint32_t q = wrap_cell(side, px + dx * k, py + dy * k);
+        if (g.occ[q] != kNull) continue;
+        const int32_t s = g.sugar[q];
+        if (s > best_sugar || (s == best_sugar && (k < best_dist || (k == best_dist && q < best)))) {
+          best = q;
+          best_sugar = s;
+          best_dist = k;
+        }
+      }
+    }
+    af<uint32_t>(h, self, kTarget) = best;
+    if (best != p) atomicMin(g.req + best, p);
+    return false;
+  }
+};
+
+struct Move {
+  static constexpr uint32_t kKind = 41;
+  using Args = Grid;
+  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
+    const uint32_t p = af<uint32_t>(h, self, kPos);
+    const uint32_t q = af<uint32_t>(h, self, kTarget);
+    const bool moves = q != p && __hip_atomic_load(g.req + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == p;
+    if (moves) {
+      g.occ[q] = self;
+      g.occ[p] = kNull;
+      af<uint32_t>(h, self, kPos) = q;
+      __hip_atomic_store(g.req + q, kInf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint64_t m = __ballot(moves);
+    if (m) lead_add(reinterpret_cast<uint64_t*>(g.ctr + 2), (uint64_t)__popcll(m));
+    return false;
+  }
+};
+
+struct Eat {
+  static constexpr uint32_t kKind = 42;
+  using Args = Grid;
+  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
+    const uint32_t p = af<uint32_t>(h, self, kPos);
+    const int32_t sugar = af<int32_t>(h, self, kSugar) + g.sugar[p] - af<int32_t>(h, self, kMetab);
+    const int32_t age = af<int32_t>(h, self, kAge) + 1;
+    g.sugar[p] = 0;
+    if (sugar <= 0 || age >= g.max_age) {
+      g.occ[p] = kNull;
+      return true;  // delete this; its fields are not written
+    }
+    af<int32_t>(h, self, kSugar) = sugar;
+    af<int32_t>(h, self, kAge) = age;
+    return false;
+  }
+};
+
+struct Request {
+  static constexpr uint32_t kKind = 43;
+  using Args = Grid;
+  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
+    const int32_t sugar = af<int32_t>(h, self, kSugar), age = af<int32_t>(h, self, kAge);
+    uint32_t best = kNull;
+    if (sugar >= g.repro_min && age >= g.fertile_min && age <= g.fertile_max) {
+      const uint32_t p = af<uint32_t>(h, self, kPos);
+      const int32_t side = (int32_t)g.side;
+      const int32_t px = (int32_t)(p % g.side), py = (int32_t)(p / g.side);
+      const uint32_t nb[4] = {wrap_cell(side, px + 1, py), wrap_cell(side, px - 1, py),
+                              wrap_cell(side, px, py + 1), wrap_cell(side, px, py - 1)};
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (g.occ[nb[d]] == kNull && nb[d] < best) best = nb[d];
+      if (best != kNull) atomicMin(g.breq + best, p);
+    }
+    af<uint32_t>(h, self, kTarget) = best;
+    return false;
+  }
+};
+
+struct Birth {
+  static constexpr uint32_t kKind = 44;
+  using Args = Grid;
+  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
+    const uint32_t n = af<uint32_t>(h, self, kTarget);
+    const uint32_t p = af<uint32_t>(h, self, kPos);
+    const bool wins = n != kNull && __hip_atomic_load(g.breq + n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == p;
+    int32_t give = 0;
+    if (wins) {
+      const int32_t sugar = af<int32_t>(h, self, kSugar);
+      give = sugar / 2;
+      af<int32_t>(h, self, kSugar) = sugar - give;
+      __hip_atomic_store(g.breq + n, kInf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint32_t t = __hip_atomic_load(g.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    new_many(h, kAgent, wins ? 1u : 0u, [&](uint32_t, uint32_t o) {
+      if (o == kNull) return;
+      af<int32_t>(h, o, kSugar) = give;
+      af<int32_t>(h, o, kMetab) = uniform_int(hash4(g.seed, kStreamChildMetab, t, n), 1, 4);
+      af<int32_t>(h, o, kVision) = uniform_int(hash4(g.seed, kStreamChildVision, t, n), 1, 6);
+      af<int32_t>(h, o, kAge) = 0;
+      af<uint32_t>(h, o, kPos) = n;
+      af<uint32_t>(h, o, kTarget) = kNull;
+      g.occ[n] = o;
+    });
+    return false;
+  }
+};
+
+// Regrow, and advance the step index (read by births of this step).
+__global__ void regrow_kernel(Grid g, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) g.ctr[0] += 1;
+  for (uint32_t c = i; c < n; c += gridDim.x * blockDim.x) {
+    const int32_t s = g.sugar[c] + 1, k = g.cap[c];
+    g.sugar[c] = s < k ? s : k;
+  }
+}
+
+__global__ void sugar_init_kernel(DevHeap h, Grid g, uint32_t n, const int32_t* sugar, const int32_t* cap,
+                                  const uint8_t* occ, const int32_t* as, const int32_t* am, const int32_t* av,
+                                  const int32_t* aa, uint32_t step0) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) {
+    g.ctr[0] = step0 - 1;  // the first regrow advances it to step0
+    g.ctr[2] = 0;
+    g.ctr[3] = 0;
+  }
+  if (c >= n) return;
+  g.sugar[c] = sugar[c];
+  const_cast<int32_t*>(g.cap)[c] = cap[c];
+  g.req[c] = kInf;
+  g.breq[c] = kInf;
+  g.occ[c] = kNull;
+  new_many(h, kAgent, occ[c] ? 1u : 0u, [&](uint32_t, uint32_t o) {
+    if (o == kNull) return;
+    af<int32_t>(h, o, kSugar) = as[c];
+    af<int32_t>(h, o, kMetab) = am[c];
+    af<int32_t>(h, o, kVision) = av[c];
+    af<int32_t>(h, o, kAge) = aa[c];
+    af<uint32_t>(h, o, kPos) = c;
+    af<uint32_t>(h, o, kTarget) = kNull;
+    g.occ[c] = o;
+  });
+}
+
+__global__ void sugar_read_kernel(DevHeap h, Grid g, uint32_t n, int32_t* sugar, uint8_t* occ, int32_t* as,
+                                  int32_t* am, int32_t* av, int32_t* aa) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  sugar[c] = g.sugar[c];
+  const uint32_t o = g.occ[c];
+  occ[c] = o != kNull;
+  as[c] = o != kNull ? af<int32_t>(h, o, kSugar) : 0;
+  am[c] = o != kNull ? af<int32_t>(h, o, kMetab) : 0;
+  av[c] = o != kNull ? af<int32_t>(h, o, kVision) : 0;
+  aa[c] = o != kNull ? af<int32_t>(h, o, kAge) : 0;
+}
+
+bool sugar_heap_ok(const dsoar_heap* h) {
+  const dsoar_type_layout& L = h->desc.types[0];
+  if (L.num_fields < 6) return false;
+  for (uint32_t f = 0; f < 6; ++f)
+    if (L.field_bytes[f] != 4) return false;
+  return true;
+}
+
+}  // namespace
+}  // namespace dsoar
+
+using namespace dsoar;
+
+struct dsoar_sugar {
+  dsoar_heap* heap;
+  Grid g;
+  uint32_t n;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  uint32_t graph_epoch;
+};
+
+namespace {
+
+int sugar_one_step(dsoar_sugar* s, uint32_t flags, hipStream_t st) {
+  dsoar_heap* h = s->heap;
+  const uint32_t base = flags & DSOAR_DO_PLAIN;
+  const uint32_t grid = std::min<uint32_t>((s->n + 255) / 256, h->num_cus * 16);
+  hipLaunchKernelGGL(regrow_kernel, dim3(grid), dim3(256), 0, st, s->g, s->n);
+  DSOAR_LAUNCHED(h);
+  int rc = launch_doall<Choose>(h, kAgent, s->g, base, st);
+  // choose and move create and delete nothing: move and eat reuse the list.
+  if (!rc) rc = launch_doall<Move>(h, kAgent, s->g, base | DSOAR_DO_REUSE_ENUM, st);
+  if (!rc) rc = launch_doall<Eat>(h, kAgent, s->g, base | DSOAR_DO_REUSE_ENUM, st);
+  // eat deletes: the request phase enumerates again; birth reuses that list.
+  if (!rc) rc = launch_doall<Request>(h, kAgent, s->g, base, st);
+  if (!rc) rc = launch_doall<Birth>(h, kAgent, s->g, base | DSOAR_DO_REUSE_ENUM, st);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dsoar_sugar_bytes(uint32_t side) {
+  if (side < 1 || side > 32768) return 0;
+  const uint64_t n = (uint64_t)side * side;
+  return (size_t)(256 + 5 * ((n * 4 + 255) / 256 * 256));
+}
+
+int dsoar_sugar_create(dsoar_heap* heap, uint32_t side, const dsoar_sugar_rules* rules, void* dev_mem,
+                       size_t dev_bytes, dsoar_sugar** out) {
+  if (!out) return DSOAR_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!heap_ok(heap) || !sugar_heap_ok(heap) || !rules || !dev_mem || ((uintptr_t)dev_mem & 255u))
+    return DSOAR_ERR_INVALID_ARG;
+  const size_t need = dsoar_sugar_bytes(side);
+  if (need == 0) return DSOAR_ERR_INVALID_ARG;
+  if (dev_bytes < need) return DSOAR_ERR_TOO_SMALL;
+  dsoar_sugar* s = new (std::nothrow) dsoar_sugar;
+  if (!s) return DSOAR_ERR_INVALID_ARG;
+  memset(s, 0, sizeof(*s));
+  s->heap = heap;
+  s->n = side * side;
+  const uint64_t plane = ((uint64_t)s->n * 4 + 255) / 256 * 256;
+  uint8_t* b = (uint8_t*)dev_mem;
+  s->g.ctr = (uint32_t*)b;
+  s->g.sugar = (int32_t*)(b + 256);
+  s->g.cap = (const int32_t*)(b + 256 + plane);
+  s->g.occ = (uint32_t*)(b + 256 + 2 * plane);
+  s->g.req = (uint32_t*)(b + 256 + 3 * plane);
+  s->g.breq = (uint32_t*)(b + 256 + 4 * plane);
+  s->g.side = side;
+  s->g.max_age = rules->max_age;
+  s->g.repro_min = rules->repro_min;
+  s->g.fertile_min = rules->fertile_min;
+  s->g.fertile_max = rules->fertile_max;
+  s->g.seed = rules->seed;
+  *out = s;
+  return DSOAR_OK;
+}
+
+int dsoar_sugar_destroy(dsoar_sugar* s) {
+  if (!s) return DSOAR_ERR_INVALID_ARG;
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  delete s;
+  return DSOAR_OK;
+}
+
+int dsoar_sugar_init(dsoar_sugar* s, const int32_t* sugar_dev, const int32_t* cap_dev, const uint8_t* occ_dev,
+                     const int32_t* a_sugar_dev, const int32_t* a_metab_dev, const int32_t* a_vision_dev,
+                     const int32_t* a_age_dev, uint32_t step0, void* stream) {
+  if (!s || !sugar_dev || !cap_dev || !occ_dev || !a_sugar_dev || !a_metab_dev || !a_vision_dev || !a_age_dev)
+    return DSOAR_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(sugar_init_kernel, dim3((s->n + 255) / 256), dim3(256), 0, (hipStream_t)stream, s->heap->dev,
+                     s->g, s->n, sugar_dev, cap_dev, occ_dev, a_sugar_dev, a_metab_dev, a_vision_dev, a_age_dev,
+                     step0);
+  DSOAR_LAUNCHED(s->heap);
+  return DSOAR_OK;
+}
+
+int dsoar_sugar_step(dsoar_sugar* s, uint32_t steps, uint32_t flags, void* stream) {
+  if (!s) return DSOAR_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  dsoar_heap* h = s->heap;
+  if (flags & DSOAR_GRAPH) {
+    if (flags & DSOAR_DO_PLAIN) return DSOAR_ERR_INVALID_ARG;
+    if (s->exec && s->graph_epoch != h->config_epoch) {
+      (void)hipGraphExecDestroy(s->exec);
+      (void)hipGraphDestroy(s->graph);
+      s->exec = nullptr;
+      s->graph = nullptr;
+    }
+    if (!s->exec) {
+      DSOAR_HIP(h, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      const int rc = sugar_one_step(s, 0, st);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(st, &graph);
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (e != hipSuccess) return hip_fail(h, e);
+      s->graph = graph;
+      DSOAR_HIP(h, hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+      s->graph_epoch = h->config_epoch;
+    }
+    for (uint32_t i = 0; i < steps; ++i) DSOAR_HIP(h, hipGraphLaunch(s->exec, st));
+    return DSOAR_OK;
+  }
+  for (uint32_t i = 0; i < steps; ++i) {
+    const int rc = sugar_one_step(s, flags, st);
+    if (rc) return rc;
+  }
+  return DSOAR_OK;
+}
+
+int dsoar_sugar_read(dsoar_sugar* s, int32_t* sugar_dev, uint8_t* occ_dev, int32_t* a_sugar_dev,
+                     int32_t* a_metab_dev, int32_t* a_vision_dev, int32_t* a_age_dev, uint32_t* moves,
+                     void* stream) {
+  if (!s || !sugar_dev || !occ_dev || !a_sugar_dev || !a_metab_dev || !a_vision_dev || !a_age_dev)
+    return DSOAR_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(sugar_read_kernel, dim3((s->n + 255) / 256), dim3(256), 0, st, s->heap->dev, s->g, s->n,
+                     sugar_dev, occ_dev, a_sugar_dev, a_metab_dev, a_vision_dev, a_age_dev);
+  DSOAR_LAUNCHED(s->heap);
+  if (moves) {
+    uint64_t m = 0;
+    DSOAR_HIP(s->heap, hipMemcpyAsync(&m, s->g.ctr + 2, 8, hipMemcpyDeviceToHost, st));
+    DSOAR_HIP(s->heap, hipStreamSynchronize(st));
+    *moves = (uint32_t)m;
+  }
+  return DSOAR_OK;
+}
+
+}  // extern "C"

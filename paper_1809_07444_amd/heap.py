@@ -78,6 +78,9 @@ class Heap:
     def set_launch(self, wg_threads: int, wgs_per_cu: int):
         C.check(self.lib.dsoar_heap_set_launch(self.h, wg_threads, wgs_per_cu), "dsoar_heap_set_launch")
 
+    def set_policy(self, bulk_min: int):
+        C.check(self.lib.dsoar_heap_set_policy(self.h, bulk_min), "dsoar_heap_set_policy")
+
     def set_timing(self, enable: bool):
         C.check(self.lib.dsoar_heap_set_timing(self.h, 1 if enable else 0), "dsoar_heap_set_timing")
 

@@ -1,0 +1,82 @@
+"""Writes the stored expected values of the large parity cases.
+
+Every value here comes from the oracle (oracle/) run on the seeded inputs of
+synth/; nothing is taken from the device path.  Usage:
+    python tests/golden/make_golden.py [batched|sugarscape|all]
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from synth import workloads as W  # noqa: E402
+
+
+def digest(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def batched(n_worlds=256, generations=100, seed=24301):
+    inp = W.batch_inputs(n_worlds, generations, seed=seed)
+    worlds = []
+    t0 = time.time()
+    for i, (side, g0) in enumerate(zip(inp.sides.tolist(), inp.grids)):
+        final, c = oracle.gol_run(g0, generations)
+        worlds.append({"side": side, "sha256": digest(final.astype(np.uint8)), "population": int(final.sum()),
+                       "initial_population": int(g0.sum()), "candidates": int(c[:, 0].sum()),
+                       "births": int(c[:, 1].sum()), "deaths": int(c[:, 2].sum())})
+    out = {"case": f"gol batched: {n_worlds} worlds, sides log-uniform 64..1024, Bernoulli(0.1), "
+                   f"{generations} generations, seed {seed}",
+           "source": "oracle.gol_run (dense B3/S23 torus) on synth.workloads.batch_inputs",
+           "n_worlds": n_worlds, "generations": generations, "seed": seed,
+           "total_cells": int(sum(w["side"] ** 2 for w in worlds)), "worlds": worlds,
+           "oracle_seconds": round(time.time() - t0, 1)}
+    path = os.path.join(HERE, f"gol_batched_{n_worlds}w_{generations}g_seed{seed}.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(path, out["oracle_seconds"], "s")
+
+
+def sugarscape(side=2048, n_agents=1 << 20, steps=500, seed=24301, every=100):
+    inp = W.sugar_inputs(side, n_agents, seed=seed)
+    rules = W.SUGAR_RULES
+    s = oracle.SugarState(side, inp.sugar, inp.cap, inp.occ, inp.a_sugar, inp.a_metab, inp.a_vision, inp.a_age)
+    checkpoints = []
+    t0 = time.time()
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        s = oracle.sugar_run(s, k, seed, rules, step0=done)
+        done += k
+        m = s.occ.astype(bool)
+        checkpoints.append({
+            "step": done, "agents": int(m.sum()), "births": s.births, "deaths": s.deaths, "moves": s.moves,
+            "sugar_grid_sha256": digest(s.sugar), "occ_sha256": digest(s.occ),
+            "agents_sha256": digest(np.stack([np.where(m, s.a_sugar, 0), np.where(m, s.a_metab, 0),
+                                              np.where(m, s.a_vision, 0), np.where(m, s.a_age, 0)]).astype(np.int32)),
+            "total_agent_sugar": int(s.a_sugar[m].sum()), "total_cell_sugar": int(s.sugar.sum())})
+        print(checkpoints[-1]["step"], checkpoints[-1]["agents"], round(time.time() - t0, 1), flush=True)
+    out = {"case": f"sugarscape: {side}x{side} torus, {n_agents} agents, {steps} steps, seed {seed}",
+           "source": "oracle.sugar_run on synth.workloads.sugar_inputs", "rules": rules, "side": side,
+           "n_agents": n_agents, "steps": steps, "seed": seed, "checkpoints": checkpoints,
+           "oracle_seconds": round(time.time() - t0, 1)}
+    path = os.path.join(HERE, f"sugarscape_{side}_{n_agents}a_{steps}s_seed{seed}.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(path, out["oracle_seconds"], "s")
+
+
+if __name__ == "__main__":
+    what = sys.argv[1] if len(sys.argv) > 1 else "all"
+    if what in ("batched", "all"):
+        batched()
+    if what in ("sugarscape", "all"):
+        sugarscape()
