@@ -320,10 +320,29 @@ int dsoar_gol_step(dsoar_gol* gol, uint32_t generations, uint32_t flags, void* s
 int dsoar_gol_read(dsoar_gol* gol, uint8_t* grid_dev, void* stream);
 uint32_t dsoar_gol_total_cells(const dsoar_gol* gol);
 
+/* World pool (continuous batching): max_worlds slots over a cell index of
+ * arena_cells cells.  Worlds are admitted into free slots and retired between
+ * generations; dsoar_gol_step advances every resident world by one
+ * generation per call (graph replay works across admissions).  A world's
+ * evolution depends only on its own cells, so it is the same alone or with
+ * others. */
+size_t dsoar_golpool_bytes(uint32_t max_worlds, uint32_t arena_cells);
+int dsoar_golpool_create(dsoar_heap* heap, uint32_t max_worlds, uint32_t arena_cells, void* dev_mem,
+                         size_t dev_bytes, void* stream, dsoar_gol** out);
+/* Admits a side x side world (grid_dev: uint8 per cell, row-major) into a free
+ * slot at cell index range [cell_offset, cell_offset + side^2), which must not
+ * overlap a resident world. */
+int dsoar_gol_admit(dsoar_gol* gol, uint32_t slot, uint32_t cell_offset, uint32_t side,
+                    const uint8_t* grid_dev, void* stream);
+/* Deletes the objects of the world in `slot` (between generations) and frees it. */
+int dsoar_gol_retire(dsoar_gol* gol, uint32_t slot, void* stream);
+/* grid_dev[i] = 1 if cell i of the world in `slot` is alive, else 0. */
+int dsoar_gol_read_world(dsoar_gol* gol, uint32_t slot, uint8_t* grid_dev, void* stream);
+
 /* ------------------------------------------------- Sugarscape-style agents
  * The paper's sugarscape application (Sec. 4, applications figure) with a
- * synchronous, deterministic rule set on a side x side torus.  The heap's
- * type 0 must be Agent {int32 sugar, metabolism, vision, age, pos, target}.
+ * synchronous, deterministic rule set on side x side tori.  The heap's type 0
+ * must be Agent {int32 sugar, metabolism, vision, age, pos, target, world}.
  * One step: regrow (sugar = min(sugar + 1, cap)); choose the best visible
  * cell (most sugar, then nearest, then lowest index, among the own cell and
  * unoccupied cells up to `vision` along the four axes); move (the lowest
@@ -336,9 +355,33 @@ uint32_t dsoar_gol_total_cells(const dsoar_gol* gol);
 typedef struct dsoar_sugar dsoar_sugar;
 typedef struct {
   int32_t max_age, repro_min, fertile_min, fertile_max;
-  uint64_t seed;
+  uint64_t seed; /* seed of the single-world interface */
 } dsoar_sugar_rules;
-/* Device bytes for the grids of a side x side world (0 if invalid). */
+
+/* World pool (continuous batching): up to max_worlds worlds, each in its own
+ * range of an arena of arena_cells cells, stepped together by
+ * dsoar_sugar_step.  A world's evolution depends only on its own state, seed
+ * and step index, so it is the same alone or with others. */
+size_t dsoar_sugarpool_bytes(uint32_t max_worlds, uint32_t arena_cells);
+int dsoar_sugarpool_create(dsoar_heap* heap, uint32_t max_worlds, uint32_t arena_cells,
+                           const dsoar_sugar_rules* rules, void* dev_mem, size_t dev_bytes,
+                           dsoar_sugar** out);
+/* Admits a side x side world into a free slot at arena cells [cell_offset,
+ * cell_offset + side^2) (must not overlap a resident world), from per-cell
+ * device arrays as in dsoar_sugar_init; seed and step0 key its random draws. */
+int dsoar_sugar_admit(dsoar_sugar* sugar, uint32_t slot, uint32_t cell_offset, uint32_t side, uint64_t seed,
+                      uint32_t step0, const int32_t* sugar_dev, const int32_t* cap_dev,
+                      const uint8_t* occ_dev, const int32_t* a_sugar_dev, const int32_t* a_metab_dev,
+                      const int32_t* a_vision_dev, const int32_t* a_age_dev, void* stream);
+/* Deletes every agent of the world in `slot` and frees the slot. */
+int dsoar_sugar_retire(dsoar_sugar* sugar, uint32_t slot, void* stream);
+/* Canonical state of one resident world (as dsoar_sugar_read). */
+int dsoar_sugar_read_world(dsoar_sugar* sugar, uint32_t slot, int32_t* sugar_dev, uint8_t* occ_dev,
+                           int32_t* a_sugar_dev, int32_t* a_metab_dev, int32_t* a_vision_dev,
+                           int32_t* a_age_dev, uint64_t* moves, void* stream);
+
+/* Single-world interface: a pool of one slot covering a side x side arena.
+ * Device bytes for it (0 if invalid). */
 size_t dsoar_sugar_bytes(uint32_t side);
 int dsoar_sugar_create(dsoar_heap* heap, uint32_t side, const dsoar_sugar_rules* rules, void* dev_mem,
                        size_t dev_bytes, dsoar_sugar** out);

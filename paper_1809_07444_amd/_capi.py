@@ -28,7 +28,7 @@ BM_TRY_SET, BM_TRY_CLEAR, BM_SET, BM_CLEAR, BM_TRY_FIND_SET, BM_FIND_CLEAR = ran
 KIND_NAMES = {1: "enumerate", 10: "visit_count", 11: "delete_if_mod", 12: "gather", 20: "micro_update",
               21: "micro_cull", 30: "gol_alive_prep", 31: "gol_cand_prep", 32: "gol_alive_update",
               33: "gol_cand_update", 40: "sugar_choose", 41: "sugar_move", 42: "sugar_eat",
-              43: "sugar_request", 44: "sugar_birth"}
+              43: "sugar_request", 44: "sugar_birth", 34: "gol_delete_world", 45: "sugar_delete_world"}
 INV_NAMES = ["bitmap_range", "allocated", "active", "active_implies_allocated", "free",
              "container", "live_count", "reserved"]
 
@@ -118,6 +118,16 @@ SIGNATURES = {
     "dsoar_gol_step": (ctypes.c_int, [vp, u32, u32, vp]),
     "dsoar_gol_read": (ctypes.c_int, [vp, vp, vp]),
     "dsoar_gol_total_cells": (u32, [vp]),
+    "dsoar_golpool_bytes": (sz, [u32, u32]),
+    "dsoar_golpool_create": (ctypes.c_int, [H, u32, u32, vp, sz, vp, ctypes.POINTER(vp)]),
+    "dsoar_gol_admit": (ctypes.c_int, [vp, u32, u32, u32, vp, vp]),
+    "dsoar_gol_retire": (ctypes.c_int, [vp, u32, vp]),
+    "dsoar_gol_read_world": (ctypes.c_int, [vp, u32, vp, vp]),
+    "dsoar_sugarpool_bytes": (sz, [u32, u32]),
+    "dsoar_sugarpool_create": (ctypes.c_int, [H, u32, u32, vp, vp, sz, ctypes.POINTER(vp)]),
+    "dsoar_sugar_admit": (ctypes.c_int, [vp, u32, u32, u32, u64, u32, vp, vp, vp, vp, vp, vp, vp, vp]),
+    "dsoar_sugar_retire": (ctypes.c_int, [vp, u32, vp]),
+    "dsoar_sugar_read_world": (ctypes.c_int, [vp, u32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(u64), vp]),
     "dsoar_sugar_bytes": (sz, [u32]),
     "dsoar_sugar_create": (ctypes.c_int, [H, u32, vp, vp, sz, ctypes.POINTER(vp)]),
     "dsoar_sugar_destroy": (ctypes.c_int, [vp]),

@@ -142,7 +142,7 @@ class GameOfLife:
 
 # -------------------------------------------------------------- sugarscape --
 
-SUGAR_TYPE = [(4, 4, 4, 4, 4, 4)]  # Agent {sugar, metabolism, vision, age, pos, target}
+SUGAR_TYPE = [(4, 4, 4, 4, 4, 4, 4)]  # Agent {sugar, metabolism, vision, age, pos, target, world}
 
 
 @dataclass

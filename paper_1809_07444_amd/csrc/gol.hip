@@ -176,12 +176,55 @@ __global__ void gol_init_kernel(DevHeap h, World w, uint32_t num_worlds, uint32_
   }
 }
 
-__global__ void gol_read_kernel(DevHeap h, World w, uint32_t total, uint8_t* out) {
-  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const uint32_t hc = w.cells[g];
-  out[g] = hc == kNull ? 0xFF : (uint8_t)*field_ptr<uint32_t>(h, hc, kCell, kCAlive);
+__global__ void gol_read_kernel(DevHeap h, World w, uint32_t off, uint32_t n, uint8_t* out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t hc = w.cells[off + i];
+  out[i] = hc == kNull ? 0xFF : (uint8_t)*field_ptr<uint32_t>(h, hc, kCell, kCAlive);
 }
+
+// Records world slot's cell range in the world table.
+__global__ void gol_set_slot_kernel(World w, uint32_t slot, uint32_t off, uint32_t side) {
+  const_cast<uint32_t*>(w.off)[slot] = off;
+  const_cast<uint32_t*>(w.side)[slot] = side;
+}
+
+// Creates the objects of one world admitted into slot `slot`.
+__global__ void gol_admit_kernel(DevHeap h, World w, uint32_t slot, uint32_t off, uint32_t n, const uint8_t* grid) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t g = off + i;
+  const uint32_t hc = dsoar_new(h, kCell);
+  const uint32_t alive = grid[i] ? 1u : 0u;
+  if (hc != kNull) {
+    *field_ptr<uint32_t>(h, hc, kCell, kCAlive) = alive;
+    *field_ptr<uint32_t>(h, hc, kCell, kCCand) = 0;
+  }
+  const_cast<uint32_t*>(w.cells)[g] = hc;
+  new_many(h, kAlive, alive, [&](uint32_t, uint32_t o) {
+    if (o == kNull) return;
+    *field_ptr<uint32_t>(h, o, kAlive, kACell) = g;
+    *field_ptr<uint32_t>(h, o, kAlive, kAWorld) = slot;
+    *field_ptr<uint32_t>(h, o, kAlive, kAAction) = 0;
+  });
+}
+
+// Deletes the Cells of one world (the Alive objects go with DeleteWorld).
+__global__ void gol_retire_cells_kernel(DevHeap h, World w, uint32_t off, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t* c = const_cast<uint32_t*>(w.cells) + off + i;
+  dsoar_delete(h, *c);
+  *c = kNull;
+}
+
+struct DeleteWorld {
+  static constexpr uint32_t kKind = 34;
+  struct Args { uint32_t slot; };
+  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& a) {
+    return *field_ptr<uint32_t>(h, self, type, kAWorld) == a.slot;
+  }
+};
 
 bool gol_heap_ok(const dsoar_heap* h) {
   if (h->desc.num_types < 3) return false;
@@ -209,8 +252,11 @@ using namespace dsoar;
 struct dsoar_gol {
   dsoar_heap* heap;
   World w;
-  uint32_t num_worlds;
-  uint32_t total;
+  uint32_t num_worlds;   // world slots
+  uint32_t total;        // cells of the cell index (the arena)
+  uint32_t* h_off;       // host copy of each slot's cell range (pool mode)
+  uint32_t* h_side;
+  uint8_t* live;         // slot holds a world (pool mode)
   hipGraph_t graph;
   hipGraphExec_t exec;
   uint32_t graph_epoch;  // heap config_epoch the graph was captured with
@@ -287,6 +333,9 @@ int dsoar_gol_create(dsoar_heap* heap, uint32_t num_worlds, const uint32_t* side
 
 int dsoar_gol_destroy(dsoar_gol* g) {
   if (!g) return DSOAR_ERR_INVALID_ARG;
+  free(g->h_off);
+  free(g->h_side);
+  free(g->live);
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
@@ -340,11 +389,92 @@ int dsoar_gol_step(dsoar_gol* g, uint32_t generations, uint32_t flags, void* str
 int dsoar_gol_read(dsoar_gol* g, uint8_t* grid_dev, void* stream) {
   if (!g || !grid_dev) return DSOAR_ERR_INVALID_ARG;
   hipLaunchKernelGGL(gol_read_kernel, dim3((g->total + 255) / 256), dim3(256), 0, (hipStream_t)stream, g->heap->dev,
-                     g->w, g->total, grid_dev);
+                     g->w, 0u, g->total, grid_dev);
   DSOAR_LAUNCHED(g->heap);
   return DSOAR_OK;
 }
 
 uint32_t dsoar_gol_total_cells(const dsoar_gol* g) { return g ? g->total : 0; }
+
+// ------------------------------------------------------------- world pool
+
+size_t dsoar_golpool_bytes(uint32_t max_worlds, uint32_t arena_cells) {
+  if (max_worlds == 0 || max_worlds > (1u << 20) || arena_cells == 0) return 0;
+  return (size_t)(((uint64_t)(2 * max_worlds + 1) * 4 + 255) / 256 * 256 + (uint64_t)arena_cells * 4);
+}
+
+int dsoar_golpool_create(dsoar_heap* heap, uint32_t max_worlds, uint32_t arena_cells, void* dev_mem,
+                         size_t dev_bytes, void* stream, dsoar_gol** out) {
+  (void)stream;
+  if (!out) return DSOAR_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!heap_ok(heap) || !gol_heap_ok(heap) || !dev_mem || ((uintptr_t)dev_mem & 255u)) return DSOAR_ERR_INVALID_ARG;
+  const size_t need = dsoar_golpool_bytes(max_worlds, arena_cells);
+  if (need == 0) return DSOAR_ERR_INVALID_ARG;
+  if (dev_bytes < need) return DSOAR_ERR_TOO_SMALL;
+  dsoar_gol* g = new (std::nothrow) dsoar_gol;
+  if (!g) return DSOAR_ERR_INVALID_ARG;
+  memset(g, 0, sizeof(*g));
+  g->heap = heap;
+  g->num_worlds = max_worlds;
+  g->total = arena_cells;
+  g->h_off = (uint32_t*)calloc(max_worlds, 4);
+  g->h_side = (uint32_t*)calloc(max_worlds, 4);
+  g->live = (uint8_t*)calloc(max_worlds, 1);
+  if (!g->h_off || !g->h_side || !g->live) {
+    dsoar_gol_destroy(g);
+    return DSOAR_ERR_INVALID_ARG;
+  }
+  uint32_t* tab = (uint32_t*)dev_mem;
+  const uint64_t head = ((uint64_t)(2 * max_worlds + 1) * 4 + 255) / 256 * 256;
+  g->w.off = tab;
+  g->w.side = tab + max_worlds + 1;
+  g->w.cells = (const uint32_t*)((uint8_t*)dev_mem + head);
+  *out = g;
+  return DSOAR_OK;
+}
+
+int dsoar_gol_admit(dsoar_gol* g, uint32_t slot, uint32_t cell_offset, uint32_t side, const uint8_t* grid_dev,
+                    void* stream) {
+  if (!g || !g->live || slot >= g->num_worlds || g->live[slot] || side == 0 || side > 65535 || !grid_dev)
+    return DSOAR_ERR_INVALID_ARG;
+  const uint64_t n = (uint64_t)side * side;
+  if ((uint64_t)cell_offset + n > g->total) return DSOAR_ERR_INVALID_ARG;
+  for (uint32_t k = 0; k < g->num_worlds; ++k)  // cell ranges of resident worlds must not overlap
+    if (g->live[k] && cell_offset < g->h_off[k] + g->h_side[k] * g->h_side[k] && g->h_off[k] < cell_offset + n)
+      return DSOAR_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(gol_set_slot_kernel, dim3(1), dim3(1), 0, s, g->w, slot, cell_offset, side);
+  DSOAR_LAUNCHED(g->heap);
+  hipLaunchKernelGGL(gol_admit_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, g->heap->dev, g->w, slot,
+                     cell_offset, (uint32_t)n, grid_dev);
+  DSOAR_LAUNCHED(g->heap);
+  g->h_off[slot] = cell_offset;
+  g->h_side[slot] = side;
+  g->live[slot] = 1;
+  return DSOAR_OK;
+}
+
+int dsoar_gol_retire(dsoar_gol* g, uint32_t slot, void* stream) {
+  if (!g || !g->live || slot >= g->num_worlds || !g->live[slot]) return DSOAR_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = launch_doall<DeleteWorld>(g->heap, kAlive, DeleteWorld::Args{slot}, 0, s);
+  if (rc) return rc;
+  const uint32_t n = g->h_side[slot] * g->h_side[slot];
+  hipLaunchKernelGGL(gol_retire_cells_kernel, dim3((n + 255) / 256), dim3(256), 0, s, g->heap->dev, g->w,
+                     g->h_off[slot], n);
+  DSOAR_LAUNCHED(g->heap);
+  g->live[slot] = 0;
+  return DSOAR_OK;
+}
+
+int dsoar_gol_read_world(dsoar_gol* g, uint32_t slot, uint8_t* grid_dev, void* stream) {
+  if (!g || !g->live || slot >= g->num_worlds || !g->live[slot] || !grid_dev) return DSOAR_ERR_INVALID_ARG;
+  const uint32_t n = g->h_side[slot] * g->h_side[slot];
+  hipLaunchKernelGGL(gol_read_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, g->heap->dev, g->w,
+                     g->h_off[slot], n, grid_dev);
+  DSOAR_LAUNCHED(g->heap);
+  return DSOAR_OK;
+}
 
 }  // extern "C"

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -134,7 +135,7 @@ __global__ void init_bitmap_kernel(uint64_t* bm, uint32_t nbits, uint32_t total_
         n = words;
       }
     }
-    bm[w] = v;
+    meta_store(bm + w, v);
   }
 }
 
@@ -142,10 +143,10 @@ __global__ void init_heap_kernel(DevHeap h, uint64_t ctrl_words) {
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nth = gridDim.x * blockDim.x;
   for (uint32_t b = tid; b < h.num_blocks; b += nth) {
-    h.obj_bitmap[b] = 0;
-    h.block_type[b] = kTypeNone;
+    meta_store(h.obj_bitmap + b, 0ull);
+    meta_store(h.block_type + b, kTypeNone);
   }
-  for (uint64_t w = tid; w < ctrl_words; w += nth) h.ctrl[w] = 0;
+  for (uint64_t w = tid; w < ctrl_words; w += nth) meta_store(h.ctrl + w, 0ull);
   // Bitmap 0 (free) all set, the others clear.
   const uint32_t L = h.nlevels;
   const uint64_t total = (uint64_t)(1 + 2 * h.num_types) * h.bm_words;
@@ -165,7 +166,7 @@ __global__ void init_heap_kernel(DevHeap h, uint64_t ctrl_words) {
         n = words;
       }
     }
-    h.bitmaps[w] = v;
+    meta_store(h.bitmaps + w, v);
   }
 }
 
@@ -197,7 +198,7 @@ __device__ inline void set_bits0(const Bitmap& b, uint32_t word, uint64_t m) {
 // level-0 updates are issued together; each does the nested update its
 // single-bit counterpart would (Alg. 2).
 __device__ inline void reclaim_word(const DevHeap& h, uint32_t t, uint32_t word, uint64_t rc) {
-  if ((rc >> lane_id()) & 1ull) h.block_type[word * 64 + lane_id()] = kTypeNone;
+  if ((rc >> lane_id()) & 1ull) meta_store(h.block_type + word * 64 + lane_id(), kTypeNone);
   const Bitmap al = allocated_bm(h, t), ac = active_bm(h, t), fr = free_bm(h);
   uint64_t pa = 0, pc = 0, pf = 0;
   if (is_first_active()) {
@@ -248,12 +249,12 @@ __global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeap h, u
   const uint64_t* alloc0 = allocated_bm(h, type).words;  // level 0 comes first
   uint64_t w[WPW], live[WPW], snap[WPW];
 #pragma unroll
-  for (uint32_t j = 0; j < WPW; ++j) w[j] = word0 + j < W0 ? alloc0[word0 + j] : 0ull;
+  for (uint32_t j = 0; j < WPW; ++j) w[j] = word0 + j < W0 ? load_u64(alloc0 + word0 + j) : 0ull;
 #pragma unroll
   for (uint32_t j = 0; j < WPW; ++j) {
     const uint32_t b = (word0 + j) * 64 + lane;
     const bool bit = ((w[j] >> lane) & 1ull) && b < h.num_blocks;
-    snap[j] = bit ? h.obj_bitmap[b] : 0ull;
+    snap[j] = bit ? meta_load(h.obj_bitmap + b) : 0ull;
   }
   uint32_t wave_total = 0;
 #pragma unroll
@@ -336,8 +337,8 @@ __global__ void reclaim_kernel(DevHeap h) {
   for (uint32_t word = blockIdx.x * wpb + (threadIdx.x >> 6); word < W0; word += gridDim.x * wpb) {
     const uint32_t b = word * 64 + lane;
     const bool in = b < h.num_blocks;
-    const uint32_t t = in ? h.block_type[b] : kTypeNone;
-    const bool empty = in && t != kTypeNone && h.obj_bitmap[b] == 0;
+    const uint32_t t = in ? meta_load(h.block_type + b) : kTypeNone;
+    const bool empty = in && t != kTypeNone && meta_load(h.obj_bitmap + b) == 0;
     uint64_t pending = __ballot(empty);
     while (pending) {
       const uint32_t t0 = __builtin_amdgcn_readlane(t, (uint32_t)__builtin_ctzll(pending));
@@ -358,10 +359,10 @@ __global__ void stats_kernel(DevHeap h, StatsOut* out, int check) {
   for (uint32_t word = gw; word < W0; word += nw) {
     const uint32_t b = word * 64 + lane;
     const bool in = b < h.num_blocks;
-    const uint32_t t = in ? h.block_type[b] : kTypeNone;
-    const uint64_t ob = in ? h.obj_bitmap[b] : 0;
+    const uint32_t t = in ? meta_load(h.block_type + b) : kTypeNone;
+    const uint64_t ob = in ? meta_load(h.obj_bitmap + b) : 0;
     const uint64_t obc = ob & h.cap_mask;
-    const bool fr = (free_bm(h).word(0, word)[0] >> lane) & 1ull;
+    const bool fr = (load_u64(free_bm(h).word(0, word)) >> lane) & 1ull;
     uint32_t v[DSOAR_INV_COUNT] = {0};
     if (in) {
       v[DSOAR_INV_BITMAP_RANGE] += (ob & ~h.cap_mask) != 0;
@@ -369,8 +370,8 @@ __global__ void stats_kernel(DevHeap h, StatsOut* out, int check) {
       if (t != kTypeNone && t >= h.num_types) v[DSOAR_INV_FREE] += 1;
     }
     for (uint32_t u = 0; u < h.num_types; ++u) {
-      const bool al = (allocated_bm(h, u).word(0, word)[0] >> lane) & 1ull;
-      const bool ac = (active_bm(h, u).word(0, word)[0] >> lane) & 1ull;
+      const bool al = (load_u64(allocated_bm(h, u).word(0, word)) >> lane) & 1ull;
+      const bool ac = (load_u64(active_bm(h, u).word(0, word)) >> lane) & 1ull;
       if (in) {
         v[DSOAR_INV_ALLOCATED] += al != (t == u && obc != 0);
         v[DSOAR_INV_ACTIVE] += ac != (al && obc != h.cap_mask);
@@ -410,10 +411,10 @@ __global__ void stats_kernel(DevHeap h, StatsOut* out, int check) {
     for (uint32_t l = 0; l < bm.nlevels; ++l) {
       const uint32_t words = ((n - 1) >> 6) + 1;
       for (uint32_t i = tid; i < words; i += nth) {
-        const uint64_t w = bm.word(l, i)[0];
+        const uint64_t w = meta_load(bm.word(l, i));
         uint32_t bad = (w & ~full_word(n, i)) != 0;
         if (l + 1 < bm.nlevels) {
-          const bool up = (bm.word(l + 1, i >> 6)[0] >> (i & 63)) & 1ull;
+          const bool up = (meta_load(bm.word(l + 1, i >> 6)) >> (i & 63)) & 1ull;
           bad += up != (w != 0);
         }
         if (bad) atomicAdd(&out->viol[DSOAR_INV_CONTAINER], bad);
@@ -574,7 +575,8 @@ int collect_stats(dsoar_heap* h, dsoar_stats* out, uint32_t* viol, int check, hi
   DSOAR_LAUNCHED(h);
   StatsOut so;
   const uint64_t ctrl_words = kCtlWords + kShards * kShardStride;
-  static thread_local uint64_t ctrl[kCtlWords + kShards * kShardStride];
+  std::vector<uint64_t> ctrl_buf(ctrl_words);
+  uint64_t* ctrl = ctrl_buf.data();
   DSOAR_HIP(h, hipMemcpyAsync(&so, h->stats_dev, sizeof(so), hipMemcpyDeviceToHost, s));
   DSOAR_HIP(h, hipMemcpyAsync(ctrl, h->dev.ctrl, ctrl_words * 8, hipMemcpyDeviceToHost, s));
   DSOAR_HIP(h, hipStreamSynchronize(s));

@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
   const uint32_t gw = blockIdx.x * wpb + (threadIdx.x >> 6);
   const uint32_t nw = gridDim.x * wpb;
   const uint32_t count = bcast32(*count_ptr);
-  uint32_t visits = 0;
+  uint32_t visits = 0, freed = 0;
   if (h.capacity == 64) {
     for (uint32_t e = gw; e < count; e += nw) {
       const uint32_t bid = R[e];
@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
       bool del = false;
       if ((snap >> lane) & 1ull) del = Method::run(h, type, make_obj(bid, lane), args);
       const uint64_t dm = __ballot(del);
-      if (dm) delete_mask(h, type, bid, dm);
+      if (dm) freed += delete_mask(h, type, bid, dm);
     }
   } else {
     const uint32_t half = lane >> 5, slot = lane & 31u;
@@ -144,11 +144,12 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
       bool del = false;
       if ((snap >> slot) & 1ull) del = Method::run(h, type, make_obj(bid, slot), args);
       const uint64_t dm = __ballot(del);
-      if (dm & 0xFFFFFFFFull) delete_mask(h, type, __builtin_amdgcn_readlane(bid, 0), dm & 0xFFFFFFFFull);
-      if (dm >> 32) delete_mask(h, type, __builtin_amdgcn_readlane(bid, 32), dm >> 32);
+      if (dm & 0xFFFFFFFFull) freed += delete_mask(h, type, __builtin_amdgcn_readlane(bid, 0), dm & 0xFFFFFFFFull);
+      if (dm >> 32) freed += delete_mask(h, type, __builtin_amdgcn_readlane(bid, 32), dm >> 32);
     }
   }
   if (visits) lead_add(shard(h) + kCntVisits + type, visits);
+  if (freed) lead_add(shard(h) + kCntFrees + type, freed);
 }
 
 // Enumerate (unless reusing) and launch the do-all of Method over `type`.

@@ -29,7 +29,7 @@ namespace dsoar {
 namespace {
 
 enum : uint32_t { kAgent = 0 };
-enum : uint32_t { kSugar = 0, kMetab = 1, kVision = 2, kAge = 3, kPos = 4, kTarget = 5 };
+enum : uint32_t { kSugar = 0, kMetab = 1, kVision = 2, kAge = 3, kPos = 4, kTarget = 5, kWorld = 6 };
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr uint64_t kStreamChildMetab = 10, kStreamChildVision = 11;
 
@@ -51,29 +51,50 @@ __device__ __forceinline__ int32_t uniform_int(uint64_t h, int32_t lo, int32_t h
   return lo + (int32_t)(((h >> 32) * (uint64_t)(hi - lo + 1)) >> 32);
 }
 
+// World table and grids.  Every world lives in its own range [off, off +
+// side^2) of the cell arena; pos and target are arena indices.  Each slot has
+// its own seed, step index and move count, so a world evolves exactly as it
+// would alone.
 struct Grid {
   int32_t* sugar;
   const int32_t* cap;
-  uint32_t* occ;    // agent handle or kNull
-  uint32_t* req;    // lowest requesting cell index or kInf
+  uint32_t* occ;      // agent handle or kNull
+  uint32_t* req;      // lowest requesting cell index or kInf
   uint32_t* breq;
-  uint32_t* ctr;    // [0] step index; [2..3] moves (uint64)
-  uint32_t side;
+  uint32_t* w_off;    // per slot
+  uint32_t* w_side;
+  uint64_t* w_seed;
+  uint32_t* w_step;   // index of the step in progress
+  uint64_t* w_moves;  // per slot, kMoveShards counters
+  uint32_t arena;
+  uint32_t max_worlds;
   int32_t max_age, repro_min, fertile_min, fertile_max;
-  uint64_t seed;
 };
 
-__device__ __forceinline__ uint32_t wrap_cell(int32_t side, int32_t x, int32_t y) {
+constexpr uint32_t kMoveShards = 64;
+
+__device__ __forceinline__ uint32_t wrap_cell(uint32_t off, int32_t side, int32_t x, int32_t y) {
   x %= side;
   if (x < 0) x += side;
   y %= side;
   if (y < 0) y += side;
-  return (uint32_t)y * (uint32_t)side + (uint32_t)x;
+  return off + (uint32_t)y * (uint32_t)side + (uint32_t)x;
 }
 
 template <class F>
 __device__ __forceinline__ F& af(const DevHeap& h, uint32_t self, uint32_t field) {
   return *field_ptr<F>(h, self, kAgent, field);
+}
+
+struct Where {
+  uint32_t off;
+  int32_t side, x, y;
+};
+
+__device__ __forceinline__ Where where(const Grid& g, uint32_t wid, uint32_t p) {
+  const uint32_t off = g.w_off[wid], side = g.w_side[wid];
+  const uint32_t local = p - off;
+  return Where{off, (int32_t)side, (int32_t)(local % side), (int32_t)(local / side)};
 }
 
 struct Choose {
@@ -82,15 +103,14 @@ struct Choose {
   static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
     const uint32_t p = af<uint32_t>(h, self, kPos);
     const int32_t vision = af<int32_t>(h, self, kVision);
-    const int32_t side = (int32_t)g.side;
-    const int32_t px = (int32_t)(p % g.side), py = (int32_t)(p / g.side);
+    const Where c = where(g, af<uint32_t>(h, self, kWorld), p);
     uint32_t best = p;
     int32_t best_sugar = g.sugar[p], best_dist = 0;
     for (int32_t d = 0; d < 4; ++d) {
       const int32_t dx = d == 0 ? 1 : (d == 1 ? -1 : 0);
       const int32_t dy = d == 2 ? 1 : (d == 3 ? -1 : 0);
       for (int32_t k = 1; k <= vision; ++k) {
-        const uint32_t q = wrap_cell(side, px + dx * k, py + dy * k);
+        const uint32_t q = wrap_cell(c.off, c.side, c.x + dx * k, c.y + dy * k);
         if (g.occ[q] != kNull) continue;
         const int32_t s = g.sugar[q];
         if (s > best_sugar || (s == best_sugar && (k < best_dist || (k == best_dist && q < best)))) {
@@ -112,6 +132,7 @@ struct Move {
   static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
     const uint32_t p = af<uint32_t>(h, self, kPos);
     const uint32_t q = af<uint32_t>(h, self, kTarget);
+    const uint32_t wid = af<uint32_t>(h, self, kWorld);
     const bool moves = q != p && __hip_atomic_load(g.req + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == p;
     if (moves) {
       g.occ[q] = self;
@@ -119,8 +140,15 @@ struct Move {
       af<uint32_t>(h, self, kPos) = q;
       __hip_atomic_store(g.req + q, kInf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    const uint64_t m = __ballot(moves);
-    if (m) lead_add(reinterpret_cast<uint64_t*>(g.ctr + 2), (uint64_t)__popcll(m));
+    // Count moves per world: one sharded atomic per world present in the wavefront.
+    uint64_t pending = __ballot(moves);
+    const uint32_t sh = (blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) & (kMoveShards - 1);
+    while (pending) {
+      const uint32_t w0 = __builtin_amdgcn_readlane(wid, (uint32_t)__builtin_ctzll(pending));
+      const uint64_t mine = __ballot(moves && wid == w0);
+      lead_add(g.w_moves + (uint64_t)w0 * kMoveShards + sh, (uint64_t)__popcll(mine));
+      pending &= ~mine;
+    }
     return false;
   }
 };
@@ -151,10 +179,9 @@ struct Request {
     uint32_t best = kNull;
     if (sugar >= g.repro_min && age >= g.fertile_min && age <= g.fertile_max) {
       const uint32_t p = af<uint32_t>(h, self, kPos);
-      const int32_t side = (int32_t)g.side;
-      const int32_t px = (int32_t)(p % g.side), py = (int32_t)(p / g.side);
-      const uint32_t nb[4] = {wrap_cell(side, px + 1, py), wrap_cell(side, px - 1, py),
-                              wrap_cell(side, px, py + 1), wrap_cell(side, px, py - 1)};
+      const Where c = where(g, af<uint32_t>(h, self, kWorld), p);
+      const uint32_t nb[4] = {wrap_cell(c.off, c.side, c.x + 1, c.y), wrap_cell(c.off, c.side, c.x - 1, c.y),
+                              wrap_cell(c.off, c.side, c.x, c.y + 1), wrap_cell(c.off, c.side, c.x, c.y - 1)};
 #pragma unroll
       for (int d = 0; d < 4; ++d)
         if (g.occ[nb[d]] == kNull && nb[d] < best) best = nb[d];
@@ -171,6 +198,7 @@ struct Birth {
   static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
     const uint32_t n = af<uint32_t>(h, self, kTarget);
     const uint32_t p = af<uint32_t>(h, self, kPos);
+    const uint32_t wid = af<uint32_t>(h, self, kWorld);
     const bool wins = n != kNull && __hip_atomic_load(g.breq + n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == p;
     int32_t give = 0;
     if (wins) {
@@ -179,64 +207,85 @@ struct Birth {
       af<int32_t>(h, self, kSugar) = sugar - give;
       __hip_atomic_store(g.breq + n, kInf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    const uint32_t t = __hip_atomic_load(g.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     new_many(h, kAgent, wins ? 1u : 0u, [&](uint32_t, uint32_t o) {
       if (o == kNull) return;
+      const uint64_t seed = g.w_seed[wid];
+      const uint32_t t = g.w_step[wid], local = n - g.w_off[wid];
       af<int32_t>(h, o, kSugar) = give;
-      af<int32_t>(h, o, kMetab) = uniform_int(hash4(g.seed, kStreamChildMetab, t, n), 1, 4);
-      af<int32_t>(h, o, kVision) = uniform_int(hash4(g.seed, kStreamChildVision, t, n), 1, 6);
+      af<int32_t>(h, o, kMetab) = uniform_int(hash4(seed, kStreamChildMetab, t, local), 1, 4);
+      af<int32_t>(h, o, kVision) = uniform_int(hash4(seed, kStreamChildVision, t, local), 1, 6);
       af<int32_t>(h, o, kAge) = 0;
       af<uint32_t>(h, o, kPos) = n;
       af<uint32_t>(h, o, kTarget) = kNull;
+      af<uint32_t>(h, o, kWorld) = wid;
       g.occ[n] = o;
     });
     return false;
   }
 };
 
-// Regrow, and advance the step index (read by births of this step).
-__global__ void regrow_kernel(Grid g, uint32_t n) {
+struct DeleteWorld {
+  static constexpr uint32_t kKind = 45;
+  struct Args { uint32_t slot; };
+  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+    return af<uint32_t>(h, self, kWorld) == a.slot;
+  }
+};
+
+// Regrow every arena cell, and advance every slot's step index (read by the
+// births of this step).  Cells outside resident worlds are rewritten at
+// admission, so regrowing them is harmless.
+__global__ void regrow_kernel(Grid g) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) g.ctr[0] += 1;
-  for (uint32_t c = i; c < n; c += gridDim.x * blockDim.x) {
+  if (i < g.max_worlds) g.w_step[i] += 1;
+  for (uint32_t c = i; c < g.arena; c += gridDim.x * blockDim.x) {
     const int32_t s = g.sugar[c] + 1, k = g.cap[c];
     g.sugar[c] = s < k ? s : k;
   }
 }
 
-__global__ void sugar_init_kernel(DevHeap h, Grid g, uint32_t n, const int32_t* sugar, const int32_t* cap,
-                                  const uint8_t* occ, const int32_t* as, const int32_t* am, const int32_t* av,
-                                  const int32_t* aa, uint32_t step0) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c == 0) {
-    g.ctr[0] = step0 - 1;  // the first regrow advances it to step0
-    g.ctr[2] = 0;
-    g.ctr[3] = 0;
+__global__ void set_world_kernel(Grid g, uint32_t slot, uint32_t off, uint32_t side, uint64_t seed, uint32_t step0) {
+  const uint32_t i = threadIdx.x;
+  if (i == 0) {
+    g.w_off[slot] = off;
+    g.w_side[slot] = side;
+    g.w_seed[slot] = seed;
+    g.w_step[slot] = step0 - 1;  // the first regrow advances it to step0
   }
+  if (i < kMoveShards) g.w_moves[(uint64_t)slot * kMoveShards + i] = 0;
+}
+
+__global__ void sugar_admit_kernel(DevHeap h, Grid g, uint32_t slot, uint32_t off, uint32_t n, const int32_t* sugar,
+                                   const int32_t* cap, const uint8_t* occ, const int32_t* as, const int32_t* am,
+                                   const int32_t* av, const int32_t* aa) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  g.sugar[c] = sugar[c];
-  const_cast<int32_t*>(g.cap)[c] = cap[c];
-  g.req[c] = kInf;
-  g.breq[c] = kInf;
-  g.occ[c] = kNull;
+  const uint32_t q = off + c;
+  g.sugar[q] = sugar[c];
+  const_cast<int32_t*>(g.cap)[q] = cap[c];
+  g.req[q] = kInf;
+  g.breq[q] = kInf;
+  g.occ[q] = kNull;
   new_many(h, kAgent, occ[c] ? 1u : 0u, [&](uint32_t, uint32_t o) {
     if (o == kNull) return;
     af<int32_t>(h, o, kSugar) = as[c];
     af<int32_t>(h, o, kMetab) = am[c];
     af<int32_t>(h, o, kVision) = av[c];
     af<int32_t>(h, o, kAge) = aa[c];
-    af<uint32_t>(h, o, kPos) = c;
+    af<uint32_t>(h, o, kPos) = q;
     af<uint32_t>(h, o, kTarget) = kNull;
-    g.occ[c] = o;
+    af<uint32_t>(h, o, kWorld) = slot;
+    g.occ[q] = o;
   });
 }
 
-__global__ void sugar_read_kernel(DevHeap h, Grid g, uint32_t n, int32_t* sugar, uint8_t* occ, int32_t* as,
-                                  int32_t* am, int32_t* av, int32_t* aa) {
+__global__ void sugar_read_kernel(DevHeap h, Grid g, uint32_t off, uint32_t n, int32_t* sugar, uint8_t* occ,
+                                  int32_t* as, int32_t* am, int32_t* av, int32_t* aa) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  sugar[c] = g.sugar[c];
-  const uint32_t o = g.occ[c];
+  const uint32_t q = off + c;
+  sugar[c] = g.sugar[q];
+  const uint32_t o = g.occ[q];
   occ[c] = o != kNull;
   as[c] = o != kNull ? af<int32_t>(h, o, kSugar) : 0;
   am[c] = o != kNull ? af<int32_t>(h, o, kMetab) : 0;
@@ -246,8 +295,8 @@ __global__ void sugar_read_kernel(DevHeap h, Grid g, uint32_t n, int32_t* sugar,
 
 bool sugar_heap_ok(const dsoar_heap* h) {
   const dsoar_type_layout& L = h->desc.types[0];
-  if (L.num_fields < 6) return false;
-  for (uint32_t f = 0; f < 6; ++f)
+  if (L.num_fields < 7) return false;
+  for (uint32_t f = 0; f < 7; ++f)
     if (L.field_bytes[f] != 4) return false;
   return true;
 }
@@ -260,7 +309,10 @@ using namespace dsoar;
 struct dsoar_sugar {
   dsoar_heap* heap;
   Grid g;
-  uint32_t n;
+  uint64_t default_seed;
+  uint32_t* h_off;
+  uint32_t* h_side;
+  uint8_t* live;
   hipGraph_t graph;
   hipGraphExec_t exec;
   uint32_t graph_epoch;
@@ -271,8 +323,9 @@ namespace {
 int sugar_one_step(dsoar_sugar* s, uint32_t flags, hipStream_t st) {
   dsoar_heap* h = s->heap;
   const uint32_t base = flags & DSOAR_DO_PLAIN;
-  const uint32_t grid = std::min<uint32_t>((s->n + 255) / 256, h->num_cus * 16);
-  hipLaunchKernelGGL(regrow_kernel, dim3(grid), dim3(256), 0, st, s->g, s->n);
+  const uint32_t grid = std::min<uint32_t>(std::max<uint32_t>((s->g.arena + 255) / 256, (s->g.max_worlds + 255) / 256),
+                                           std::max<uint32_t>(h->num_cus * 16, (s->g.max_worlds + 255) / 256));
+  hipLaunchKernelGGL(regrow_kernel, dim3(grid), dim3(256), 0, st, s->g);
   DSOAR_LAUNCHED(h);
   int rc = launch_doall<Choose>(h, kAgent, s->g, base, st);
   // choose and move create and delete nothing: move and eat reuse the list.
@@ -284,52 +337,144 @@ int sugar_one_step(dsoar_sugar* s, uint32_t flags, hipStream_t st) {
   return rc;
 }
 
+size_t plane_bytes(uint64_t cells) { return (size_t)((cells * 4 + 255) / 256 * 256); }
+
+size_t table_bytes(uint32_t max_worlds) {
+  return (size_t)(((uint64_t)max_worlds * (4 + 4 + 8 + 4) + 255) / 256 * 256 +
+                  (uint64_t)max_worlds * kMoveShards * 8);
+}
+
 }  // namespace
 
 extern "C" {
 
-size_t dsoar_sugar_bytes(uint32_t side) {
-  if (side < 1 || side > 32768) return 0;
-  const uint64_t n = (uint64_t)side * side;
-  return (size_t)(256 + 5 * ((n * 4 + 255) / 256 * 256));
+size_t dsoar_sugarpool_bytes(uint32_t max_worlds, uint32_t arena_cells) {
+  if (max_worlds == 0 || max_worlds > (1u << 16) || arena_cells == 0 || arena_cells > (1u << 30)) return 0;
+  return table_bytes(max_worlds) + 5 * plane_bytes(arena_cells);
 }
 
-int dsoar_sugar_create(dsoar_heap* heap, uint32_t side, const dsoar_sugar_rules* rules, void* dev_mem,
-                       size_t dev_bytes, dsoar_sugar** out) {
+int dsoar_sugarpool_create(dsoar_heap* heap, uint32_t max_worlds, uint32_t arena_cells,
+                           const dsoar_sugar_rules* rules, void* dev_mem, size_t dev_bytes, dsoar_sugar** out) {
   if (!out) return DSOAR_ERR_INVALID_ARG;
   *out = nullptr;
   if (!heap_ok(heap) || !sugar_heap_ok(heap) || !rules || !dev_mem || ((uintptr_t)dev_mem & 255u))
     return DSOAR_ERR_INVALID_ARG;
-  const size_t need = dsoar_sugar_bytes(side);
+  const size_t need = dsoar_sugarpool_bytes(max_worlds, arena_cells);
   if (need == 0) return DSOAR_ERR_INVALID_ARG;
   if (dev_bytes < need) return DSOAR_ERR_TOO_SMALL;
   dsoar_sugar* s = new (std::nothrow) dsoar_sugar;
   if (!s) return DSOAR_ERR_INVALID_ARG;
   memset(s, 0, sizeof(*s));
   s->heap = heap;
-  s->n = side * side;
-  const uint64_t plane = ((uint64_t)s->n * 4 + 255) / 256 * 256;
+  s->default_seed = rules->seed;
+  s->h_off = (uint32_t*)calloc(max_worlds, 4);
+  s->h_side = (uint32_t*)calloc(max_worlds, 4);
+  s->live = (uint8_t*)calloc(max_worlds, 1);
+  if (!s->h_off || !s->h_side || !s->live) {
+    free(s->h_off);
+    free(s->h_side);
+    free(s->live);
+    delete s;
+    return DSOAR_ERR_INVALID_ARG;
+  }
   uint8_t* b = (uint8_t*)dev_mem;
-  s->g.ctr = (uint32_t*)b;
-  s->g.sugar = (int32_t*)(b + 256);
-  s->g.cap = (const int32_t*)(b + 256 + plane);
-  s->g.occ = (uint32_t*)(b + 256 + 2 * plane);
-  s->g.req = (uint32_t*)(b + 256 + 3 * plane);
-  s->g.breq = (uint32_t*)(b + 256 + 4 * plane);
-  s->g.side = side;
-  s->g.max_age = rules->max_age;
-  s->g.repro_min = rules->repro_min;
-  s->g.fertile_min = rules->fertile_min;
-  s->g.fertile_max = rules->fertile_max;
-  s->g.seed = rules->seed;
+  Grid& g = s->g;
+  g.w_seed = (uint64_t*)b;                                   // 8-byte entries first
+  g.w_off = (uint32_t*)(b + (uint64_t)max_worlds * 8);
+  g.w_side = g.w_off + max_worlds;
+  g.w_step = g.w_side + max_worlds;
+  g.w_moves = (uint64_t*)(b + ((uint64_t)max_worlds * 20 + 255) / 256 * 256);
+  uint8_t* planes = b + table_bytes(max_worlds);
+  const uint64_t plane = plane_bytes(arena_cells);
+  g.sugar = (int32_t*)planes;
+  g.cap = (const int32_t*)(planes + plane);
+  g.occ = (uint32_t*)(planes + 2 * plane);
+  g.req = (uint32_t*)(planes + 3 * plane);
+  g.breq = (uint32_t*)(planes + 4 * plane);
+  g.arena = arena_cells;
+  g.max_worlds = max_worlds;
+  g.max_age = rules->max_age;
+  g.repro_min = rules->repro_min;
+  g.fertile_min = rules->fertile_min;
+  g.fertile_max = rules->fertile_max;
   *out = s;
   return DSOAR_OK;
+}
+
+int dsoar_sugar_admit(dsoar_sugar* s, uint32_t slot, uint32_t cell_offset, uint32_t side, uint64_t seed,
+                      uint32_t step0, const int32_t* sugar_dev, const int32_t* cap_dev, const uint8_t* occ_dev,
+                      const int32_t* a_sugar_dev, const int32_t* a_metab_dev, const int32_t* a_vision_dev,
+                      const int32_t* a_age_dev, void* stream) {
+  if (!s || slot >= s->g.max_worlds || s->live[slot] || side == 0 || side > 32768 || !sugar_dev || !cap_dev ||
+      !occ_dev || !a_sugar_dev || !a_metab_dev || !a_vision_dev || !a_age_dev)
+    return DSOAR_ERR_INVALID_ARG;
+  const uint64_t n = (uint64_t)side * side;
+  if ((uint64_t)cell_offset + n > s->g.arena) return DSOAR_ERR_INVALID_ARG;
+  for (uint32_t k = 0; k < s->g.max_worlds; ++k)
+    if (s->live[k] && cell_offset < s->h_off[k] + (uint64_t)s->h_side[k] * s->h_side[k] && s->h_off[k] < cell_offset + n)
+      return DSOAR_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(set_world_kernel, dim3(1), dim3(kMoveShards), 0, st, s->g, slot, cell_offset, side, seed, step0);
+  DSOAR_LAUNCHED(s->heap);
+  hipLaunchKernelGGL(sugar_admit_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, s->heap->dev, s->g, slot,
+                     cell_offset, (uint32_t)n, sugar_dev, cap_dev, occ_dev, a_sugar_dev, a_metab_dev, a_vision_dev,
+                     a_age_dev);
+  DSOAR_LAUNCHED(s->heap);
+  s->h_off[slot] = cell_offset;
+  s->h_side[slot] = side;
+  s->live[slot] = 1;
+  return DSOAR_OK;
+}
+
+int dsoar_sugar_retire(dsoar_sugar* s, uint32_t slot, void* stream) {
+  if (!s || slot >= s->g.max_worlds || !s->live[slot]) return DSOAR_ERR_INVALID_ARG;
+  const int rc = launch_doall<DeleteWorld>(s->heap, kAgent, DeleteWorld::Args{slot}, 0, (hipStream_t)stream);
+  if (rc) return rc;
+  s->live[slot] = 0;
+  return DSOAR_OK;
+}
+
+int dsoar_sugar_read_world(dsoar_sugar* s, uint32_t slot, int32_t* sugar_dev, uint8_t* occ_dev, int32_t* a_sugar_dev,
+                           int32_t* a_metab_dev, int32_t* a_vision_dev, int32_t* a_age_dev, uint64_t* moves,
+                           void* stream) {
+  if (!s || slot >= s->g.max_worlds || !s->live[slot] || !sugar_dev || !occ_dev || !a_sugar_dev || !a_metab_dev ||
+      !a_vision_dev || !a_age_dev)
+    return DSOAR_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t n = s->h_side[slot] * s->h_side[slot];
+  hipLaunchKernelGGL(sugar_read_kernel, dim3((n + 255) / 256), dim3(256), 0, st, s->heap->dev, s->g, s->h_off[slot], n,
+                     sugar_dev, occ_dev, a_sugar_dev, a_metab_dev, a_vision_dev, a_age_dev);
+  DSOAR_LAUNCHED(s->heap);
+  if (moves) {
+    uint64_t m[kMoveShards];
+    DSOAR_HIP(s->heap, hipMemcpyAsync(m, s->g.w_moves + (uint64_t)slot * kMoveShards, sizeof(m), hipMemcpyDeviceToHost, st));
+    DSOAR_HIP(s->heap, hipStreamSynchronize(st));
+    uint64_t t = 0;
+    for (uint32_t i = 0; i < kMoveShards; ++i) t += m[i];
+    *moves = t;
+  }
+  return DSOAR_OK;
+}
+
+// Single-world interface: a pool of one slot covering the whole arena.
+size_t dsoar_sugar_bytes(uint32_t side) {
+  if (side < 1 || side > 32768) return 0;
+  return dsoar_sugarpool_bytes(1, side * side);
+}
+
+int dsoar_sugar_create(dsoar_heap* heap, uint32_t side, const dsoar_sugar_rules* rules, void* dev_mem,
+                       size_t dev_bytes, dsoar_sugar** out) {
+  if (side < 1 || side > 32768) return DSOAR_ERR_INVALID_ARG;
+  return dsoar_sugarpool_create(heap, 1, side * side, rules, dev_mem, dev_bytes, out);
 }
 
 int dsoar_sugar_destroy(dsoar_sugar* s) {
   if (!s) return DSOAR_ERR_INVALID_ARG;
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->graph) (void)hipGraphDestroy(s->graph);
+  free(s->h_off);
+  free(s->h_side);
+  free(s->live);
   delete s;
   return DSOAR_OK;
 }
@@ -337,13 +482,13 @@ int dsoar_sugar_destroy(dsoar_sugar* s) {
 int dsoar_sugar_init(dsoar_sugar* s, const int32_t* sugar_dev, const int32_t* cap_dev, const uint8_t* occ_dev,
                      const int32_t* a_sugar_dev, const int32_t* a_metab_dev, const int32_t* a_vision_dev,
                      const int32_t* a_age_dev, uint32_t step0, void* stream) {
-  if (!s || !sugar_dev || !cap_dev || !occ_dev || !a_sugar_dev || !a_metab_dev || !a_vision_dev || !a_age_dev)
-    return DSOAR_ERR_INVALID_ARG;
-  hipLaunchKernelGGL(sugar_init_kernel, dim3((s->n + 255) / 256), dim3(256), 0, (hipStream_t)stream, s->heap->dev,
-                     s->g, s->n, sugar_dev, cap_dev, occ_dev, a_sugar_dev, a_metab_dev, a_vision_dev, a_age_dev,
-                     step0);
-  DSOAR_LAUNCHED(s->heap);
-  return DSOAR_OK;
+  if (!s) return DSOAR_ERR_INVALID_ARG;
+  uint32_t side = 1;
+  while ((uint64_t)side * side < s->g.arena) ++side;
+  if ((uint64_t)side * side != s->g.arena) return DSOAR_ERR_INVALID_ARG;
+  s->live[0] = 0;  // the heap is reset by the caller: slot 0 starts afresh
+  return dsoar_sugar_admit(s, 0, 0, side, s->default_seed, step0, sugar_dev, cap_dev, occ_dev, a_sugar_dev,
+                           a_metab_dev, a_vision_dev, a_age_dev, stream);
 }
 
 int dsoar_sugar_step(dsoar_sugar* s, uint32_t steps, uint32_t flags, void* stream) {
@@ -382,22 +527,13 @@ int dsoar_sugar_step(dsoar_sugar* s, uint32_t steps, uint32_t flags, void* strea
   return DSOAR_OK;
 }
 
-int dsoar_sugar_read(dsoar_sugar* s, int32_t* sugar_dev, uint8_t* occ_dev, int32_t* a_sugar_dev,
-                     int32_t* a_metab_dev, int32_t* a_vision_dev, int32_t* a_age_dev, uint32_t* moves,
-                     void* stream) {
-  if (!s || !sugar_dev || !occ_dev || !a_sugar_dev || !a_metab_dev || !a_vision_dev || !a_age_dev)
-    return DSOAR_ERR_INVALID_ARG;
-  hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(sugar_read_kernel, dim3((s->n + 255) / 256), dim3(256), 0, st, s->heap->dev, s->g, s->n,
-                     sugar_dev, occ_dev, a_sugar_dev, a_metab_dev, a_vision_dev, a_age_dev);
-  DSOAR_LAUNCHED(s->heap);
-  if (moves) {
-    uint64_t m = 0;
-    DSOAR_HIP(s->heap, hipMemcpyAsync(&m, s->g.ctr + 2, 8, hipMemcpyDeviceToHost, st));
-    DSOAR_HIP(s->heap, hipStreamSynchronize(st));
-    *moves = (uint32_t)m;
-  }
-  return DSOAR_OK;
+int dsoar_sugar_read(dsoar_sugar* s, int32_t* sugar_dev, uint8_t* occ_dev, int32_t* a_sugar_dev, int32_t* a_metab_dev,
+                     int32_t* a_vision_dev, int32_t* a_age_dev, uint32_t* moves, void* stream) {
+  uint64_t m = 0;
+  const int rc = dsoar_sugar_read_world(s, 0, sugar_dev, occ_dev, a_sugar_dev, a_metab_dev, a_vision_dev, a_age_dev,
+                                        moves ? &m : nullptr, stream);
+  if (!rc && moves) *moves = (uint32_t)m;
+  return rc;
 }
 
 }  // extern "C"

@@ -125,3 +125,54 @@ def sugar_inputs(side: int = 2048, n_agents: int = 1 << 20, seed: int = rng.DEFA
     return SugarInputs(side, n_agents, seed, cap.copy(), cap, occ,
                        trait(rng.S_SUGAR_SUGAR, 5, 25), trait(rng.S_SUGAR_METAB, 1, 4),
                        trait(rng.S_SUGAR_VISION, 1, 6), trait(rng.S_SUGAR_AGE, 0, max_age - 1))
+
+
+# ---------------------------------------------------------------- serving ---
+
+
+@dataclass
+class EpisodeSpec:
+    eid: int
+    kind: str          # "gol" or "sugar"
+    side: int
+    length: int        # generations (gol) or steps (sugar)
+    seed: int
+    agents: int        # sugar only
+    arrival: float     # seconds after the start of the run
+
+
+def serving_episodes(n: int, rate: float, seed: int = rng.DEFAULT_SEED, gol_frac: float = 0.7,
+                     gol_sides=(128, 2048), gol_lengths=(50, 300), sugar_sides=(256, 1024),
+                     sugar_agents=(10_000, 200_000), sugar_steps: int = 100) -> list:
+    """Episodes with Poisson arrivals (rate per second; inf = all at time 0):
+    70% Game of Life (side log-uniform, generations uniform), 30% Sugarscape
+    (side log-uniform, agents uniform, capped at a quarter of the cells)."""
+    e = np.arange(n, dtype=np.uint64)
+    h = lambda k: rng.hash4(seed, rng.S_EPISODE, k, e)
+    kind = rng.uniform01_f32(h(0)) < gol_frac
+    u = rng.uniform01_f32(h(1)).astype(np.float64)
+    gl = rng.uniform_int(h(2), *gol_lengths)
+    ag = rng.uniform_int(h(3), *sugar_agents)
+    ia = rng.uniform01_f32(h(4)).astype(np.float64)
+    seeds = h(5)
+    out, t = [], 0.0
+    for i in range(n):
+        if np.isfinite(rate):
+            t += -np.log(1.0 - ia[i]) / rate
+        if kind[i]:
+            lo, hi = gol_sides
+            side = int(np.rint(lo * (hi / lo) ** u[i]))
+            out.append(EpisodeSpec(i, "gol", side, int(gl[i]), int(seeds[i]), 0, t))
+        else:
+            lo, hi = sugar_sides
+            side = int(np.rint(lo * (hi / lo) ** u[i]))
+            out.append(EpisodeSpec(i, "sugar", side, sugar_steps, int(seeds[i]),
+                                   min(int(ag[i]), side * side // 4), t))
+    return out
+
+
+def episode_inputs(ep: EpisodeSpec):
+    """Initial state of an episode (a GoL grid or Sugarscape inputs)."""
+    if ep.kind == "gol":
+        return gol_grid(ep.side, ep.side, seed=ep.seed)
+    return sugar_inputs(ep.side, ep.agents, seed=ep.seed)
