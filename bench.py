@@ -31,7 +31,11 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="gol", choices=["gol", "micro", "micro_scaled", "batched"])
+    p.add_argument("--workload", default="gol",
+                   choices=["gol", "micro", "micro_scaled", "batched", "sugarscape", "serve"])
+    p.add_argument("--episodes", type=int, default=200, help="serve: episodes per arrival rate")
+    p.add_argument("--rates", default="0.25,0.5,0.75,0.9,1.1",
+                   help="serve: arrival rates as fractions of the measured capacity")
     p.add_argument("--tune", default="cache", choices=["cache", "full", "off"],
                    help="batched: autotune (cached in paper_1809_07444_amd/tune_cache.json), full re-tune, or defaults")
     p.add_argument("--no-plain", action="store_true", help="batched: skip the per-world plain baseline")
@@ -252,6 +256,104 @@ class BatchedWorkload(GolWorkload):
                           f"generations, {dt:.1f} s"}
 
 
+class SugarWorkload(GolWorkload):
+    name = "sugarscape"
+
+    def __init__(self, args):
+        import torch
+        from paper_1809_07444_amd import _capi as C
+        from paper_1809_07444_amd import apps
+        from synth import workloads as W
+        self.C, self.torch = C, torch
+        self.side, self.agents, self.steps = 2048, 1 << 20, 500
+        self.inp = W.sugar_inputs(self.side, self.agents, seed=args.seed)
+        self.sim = apps.Sugarscape(self.inp, W.SUGAR_RULES)
+        self.flags = C.DO_PERSISTENT | (0 if args.no_graph else C.GRAPH)
+        self.M = self.sim.heap.num_blocks
+        self.config = {"workload": f"sugarscape-{self.side}x{self.side}-{self.agents}agents-{self.steps}steps",
+                       "cells": self.side ** 2, "agents": self.agents, "steps": self.steps,
+                       "heap_blocks": self.M, "block_capacity": 64, "graph": not args.no_graph, "seed": args.seed,
+                       "rules": W.SUGAR_RULES}
+
+    def step(self):
+        self.sim.init()
+        self.sim.step(self.steps, self.flags)
+
+    def profiled_step(self):
+        self.sim.init()
+        self.sim.step(self.steps, self.C.DO_PERSISTENT)
+
+    def stats(self):
+        return self.sim.heap.stats()
+
+    def heap(self):
+        return self.sim.heap
+
+    def kernel_bytes(self, kind, launches, st):
+        # this-fields (read 24 B, write <= 12 B) + 5 * (4*vision+1) grid reads are counted for choose;
+        # each phase's own fields otherwise.  Per agent visit of the phase:
+        v = st["visits"][0] / 5  # five do-alls per step
+        per = {"sugar_choose": 12 + 4 + 25 * 8, "sugar_move": 12 + 8, "sugar_eat": 16 + 8 + 8,
+               "sugar_request": 16 + 16 + 4, "sugar_birth": 12 + 4}
+        if kind in per:
+            return v * per[kind]
+        if kind == "enumerate":
+            return launches * (self.M / 8) + (2 * v / 64) * 20
+        return None
+
+    def cpu_baseline(self):
+        import oracle
+        from synth import workloads as W
+        st = oracle.SugarState(self.side, self.inp.sugar, self.inp.cap, self.inp.occ, self.inp.a_sugar,
+                               self.inp.a_metab, self.inp.a_vision, self.inp.a_age)
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < 10 and n < self.steps:
+            st = oracle.sugar_run(st, 5, self.inp.seed, W.SUGAR_RULES, step0=n)
+            n += 5
+        dt = time.perf_counter() - t0
+        ops = st.births + st.deaths
+        return {"value": ops / dt, "unit": "allocs+frees/s", "cores": 1, "kind": "oracle",
+                "sample": f"sequential rules oracle, full {self.side}x{self.side} world, first {n} of "
+                          f"{self.steps} steps, {dt:.1f} s; births+deaths / oracle time"}
+
+
+def serve_bench(args):
+    import torch
+    from paper_1809_07444_amd import serve
+    from synth import workloads as W
+    torch.cuda.set_device(0)
+    n = args.episodes
+
+    def run(specs):
+        inputs = {s.eid: W.episode_inputs(s) for s in specs}      # requests carry their data
+        srv = serve.Server()
+        try:
+            recs, _, st = srv.run(specs, lambda s: inputs[s.eid], keep_results=False)
+        finally:
+            srv.close()
+        return serve.summarize(recs, st["wall_s"]), st
+
+    warm, _ = run(W.serving_episodes(16, float("inf"), seed=args.seed + 1))
+    cap_sum, cap_st = run(W.serving_episodes(n, float("inf"), seed=args.seed))
+    capacity = cap_sum["episodes_per_s"]
+    sweep = []
+    for f in [float(x) for x in args.rates.split(",")]:
+        specs = W.serving_episodes(n, f * capacity, seed=args.seed)
+        s, st = run(specs)
+        sweep.append(dict(s, rate_fraction=f, rate_episodes_per_s=f * capacity, server_steps=st["server_steps"]))
+        print(json.dumps({"progress": "serve", "rate_fraction": f, **s}), file=sys.stderr, flush=True)
+    best = max(sweep, key=lambda r: r["episodes_per_s"])
+    out = {"metric": METRIC, "value": best["episodes_per_s"], "unit": "episodes/s", "n_gpus": 1,
+           "steps": len(sweep), "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32/u64", "data": "synthetic",
+           "config": {"workload": f"serve-poisson-{n}episodes-70%gol128..2048-30%sugar256..1024",
+                      "episodes_per_rate": n, "seed": args.seed},
+           "capacity_episodes_per_s": capacity, "capacity_run": dict(cap_sum, **cap_st), "sweep": sweep,
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -261,10 +363,14 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "serve":
+        return serve_bench(args)
     if args.workload == "gol":
         wl = GolWorkload(args)
     elif args.workload == "batched":
         wl = BatchedWorkload(args)
+    elif args.workload == "sugarscape":
+        wl = SugarWorkload(args)
     else:
         wl = MicroWorkload(args, scaled=args.workload == "micro_scaled")
 

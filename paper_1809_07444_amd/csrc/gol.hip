@@ -209,7 +209,7 @@ __global__ void gol_admit_kernel(DevHeap h, World w, uint32_t slot, uint32_t off
   });
 }
 
-// Deletes the Cells of one world (the Alive objects go with DeleteWorld).
+// Deletes the Cells of one world (the Alive objects go with GolDeleteWorld).
 __global__ void gol_retire_cells_kernel(DevHeap h, World w, uint32_t off, uint32_t n) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -218,7 +218,7 @@ __global__ void gol_retire_cells_kernel(DevHeap h, World w, uint32_t off, uint32
   *c = kNull;
 }
 
-struct DeleteWorld {
+struct GolDeleteWorld {
   static constexpr uint32_t kKind = 34;
   struct Args { uint32_t slot; };
   static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& a) {
@@ -458,7 +458,7 @@ int dsoar_gol_admit(dsoar_gol* g, uint32_t slot, uint32_t cell_offset, uint32_t 
 int dsoar_gol_retire(dsoar_gol* g, uint32_t slot, void* stream) {
   if (!g || !g->live || slot >= g->num_worlds || !g->live[slot]) return DSOAR_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  int rc = launch_doall<DeleteWorld>(g->heap, kAlive, DeleteWorld::Args{slot}, 0, s);
+  int rc = launch_doall<GolDeleteWorld>(g->heap, kAlive, GolDeleteWorld::Args{slot}, 0, s);
   if (rc) return rc;
   const uint32_t n = g->h_side[slot] * g->h_side[slot];
   hipLaunchKernelGGL(gol_retire_cells_kernel, dim3((n + 255) / 256), dim3(256), 0, s, g->heap->dev, g->w,

@@ -224,7 +224,7 @@ struct Birth {
   }
 };
 
-struct DeleteWorld {
+struct SugarDeleteWorld {
   static constexpr uint32_t kKind = 45;
   struct Args { uint32_t slot; };
   static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
@@ -428,7 +428,7 @@ int dsoar_sugar_admit(dsoar_sugar* s, uint32_t slot, uint32_t cell_offset, uint3
 
 int dsoar_sugar_retire(dsoar_sugar* s, uint32_t slot, void* stream) {
   if (!s || slot >= s->g.max_worlds || !s->live[slot]) return DSOAR_ERR_INVALID_ARG;
-  const int rc = launch_doall<DeleteWorld>(s->heap, kAgent, DeleteWorld::Args{slot}, 0, (hipStream_t)stream);
+  const int rc = launch_doall<SugarDeleteWorld>(s->heap, kAgent, SugarDeleteWorld::Args{slot}, 0, (hipStream_t)stream);
   if (rc) return rc;
   s->live[slot] = 0;
   return DSOAR_OK;
