@@ -357,7 +357,7 @@ def serve_bench(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
                                    "(sharding across GPUs is described in the design notes, not built)"}))
         sys.exit(2)
     import torch

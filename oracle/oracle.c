@@ -492,7 +492,7 @@ int orc_gol_run(int32_t width, int32_t height, int32_t generations,
 /* ============================================================== Sugarscape
  * Synchronous, deterministic Sugarscape-style model on a side x side torus
  * (the paper names the application but not its rules; these are the rules
- * adopted for this build, stated in full here).  One step t:
+ * adopted here, stated in full).  One step t:
  *  1 regrow: sugar[c] = min(sugar[c] + 1, cap[c]) everywhere.
  *  2 choose: each agent at p looks at its own cell and at the cells 1..vision
  *    steps away in the four axis directions; among its own cell and the cells
@@ -508,7 +508,12 @@ int orc_gol_run(int32_t width, int32_t height, int32_t generations,
  *  6 birth: the winner's child gets floor(sugar / 2) (the parent keeps the
  *    rest), metabolism U{1..4} from hash(seed, 10, t, n), vision U{1..6} from
  *    hash(seed, 11, t, n), age 0, at cell n.
- * Agents are stored by cell (at most one per cell). */
+ * Agents are stored by cell (at most one per cell).
+ * Pins: hand-worked one- and two-agent cases, the tie-breaks, the birth and
+ * death rules and run invariants (at most one agent per cell, 0 <= sugar <=
+ * cap, population ledger), all derived from the rules above.  The paper fixes
+ * none of these rules, so with respect to the paper this function is parity
+ * unpinned. */
 
 #define SUG_STREAM_CHILD_METAB 10
 #define SUG_STREAM_CHILD_VISION 11

@@ -393,15 +393,15 @@ __device__ __forceinline__ F* field_ptr(const DevHeap& h, uint32_t obj, uint32_t
 //
 // Request coalescing (Sec. 2.4): the n = sum k_i requests of the wavefront
 // are served together, one leader lane issuing every atomic.  While at least
-// `capacity` requests remain, a round takes whole free blocks (full blocks
+// `capacity` requests remain, a pass takes whole free blocks (full blocks
 // are dense by construction), several at once from one free-bitmap word.
 // Otherwise it looks up an active block of the type first (dense policy,
 // Sec. 2.2) and takes a free block only when none is found (slow path: set
-// the type, mark it allocated and, unless this round fills it, active).
+// the type, mark it allocated and, unless this pass fills it, active).
 // Reservation in an active block is one atomic OR of the wanted number of
 // bits among those a snapshot shows free (after our own OR, the bits it left
 // free); the bits gained are take & ~prev, and a block that still has room is
-// used again without a new lookup.  The round
+// used again without a new lookup.  The pass
 // whose OR fills the block clears active[type] (Alg. 1, FULL).
 // Requests are numbered by lane order (exclusive prefix sums from bit-sliced
 // ballots, exact under any divergence) and handed out in that order.
@@ -514,7 +514,7 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
       const uint64_t after = (prev | take) & h.cap_mask;
       if (after == h.cap_mask && (prev & h.cap_mask) != h.cap_mask) bm_clear(active, (uint32_t)bid);
       if (after != h.cap_mask) {
-        cur = bid;  // still has room: the next round can use it without a lookup
+        cur = bid;  // still has room: the next pass can use it without a lookup
         cur_avail = ~after & h.cap_mask;
       }
       if (got != take) ++retries;
