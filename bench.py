@@ -414,6 +414,13 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": best,
                 "avg_launch_us": round(kernels[best]["avg_us"], 2)}
 
+    # Atomic read-modify-writes the methods issue themselves (claim flags,
+    # move requests): for the GoL the dominant kernel's compare-and-swaps.
+    if roof is not None and best == "gol_alive_prep":
+        n_at = stp["method_atomics"]
+        roof["method_atomics_per_launch"] = n_at / kern[best][0]
+        roof["method_atomics_per_s"] = n_at / (kern[best][1] / 1e3)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = wl.cpu_baseline()
@@ -440,7 +447,8 @@ def main():
         "doall_objects_per_s": per_step_visits / (ms / 1e3),
         "per_step": {"allocs": st1["allocs"], "frees": st1["frees"], "doall_visits": st1["visits"],
                      "reserve_retries": st1["reserve_retries"], "slow_paths": st1["slow_paths"],
-                     "find_fails": st1["find_fails"], "allocated_blocks_end": st1["allocated_blocks"]},
+                     "find_fails": st1["find_fails"], "method_atomics": st1["method_atomics"],
+                     "allocated_blocks_end": st1["allocated_blocks"]},
         "roofline": roof, "cpu_baseline": cpu, "kernels": kernels,
     }
     out.update(extra)

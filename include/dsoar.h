@@ -106,6 +106,7 @@ typedef struct {
   uint64_t reserve_retries;               /* reservations that gained fewer bits than tried */
   uint64_t slow_paths;                    /* free blocks taken (Alg. 1 slow path) */
   uint64_t find_fails;                    /* try_find_set FAILs on active[T] */
+  uint64_t method_atomics;                /* atomic RMWs do-all methods issued on their own data */
   uint32_t free_blocks;
   uint32_t num_blocks;
   uint32_t oom;                           /* sticky flags */
@@ -158,6 +159,14 @@ int dsoar_heap_set_launch(dsoar_heap* heap, uint32_t wg_threads, uint32_t wgs_pe
  * active blocks first).  Values below the block capacity mean the capacity
  * (the default); 0xFFFFFFFF always fills active blocks first. */
 int dsoar_heap_set_policy(dsoar_heap* heap, uint32_t bulk_min);
+
+/* Blocks per wavefront pass for do-all methods that split into a load phase
+ * and an apply phase (at block capacity 64): 1, 2, 4 (the default) or 8.  The
+ * loads of all blocks of a pass are issued before any is used, which keeps
+ * more memory traffic in flight (Sec. 2.3: the do-all is bound by memory
+ * access).  Used only when every wavefront of the launch gets that many
+ * blocks; results do not depend on it.  Other values: DSOAR_ERR_INVALID_ARG. */
+int dsoar_heap_set_unroll(dsoar_heap* heap, uint32_t blocks_per_pass);
 
 /* Per-launch timing: when enabled, every enumeration and do-all launch of
  * this heap is bracketed by a pair of HIP events on its stream (at most 8192

@@ -50,8 +50,11 @@ enum : uint32_t {
   kCntSlowPaths = 2 * kMaxTypes + 1,
   kCntFindFails = 2 * kMaxTypes + 2,
   kCntVisits = 2 * kMaxTypes + 3,  // + type: objects visited by do-alls
+  kCntMethodAtomics = 3 * kMaxTypes + 3,  // atomic RMWs methods issue on their own data
   kShardStride = 32,
 };
+static_assert(kCntMethodAtomics < kShardStride, "counter slots exceed a shard");
+
 
 struct DevHeap {
   uint8_t* data;            // M * block_stride bytes of SOA segments
@@ -67,8 +70,11 @@ struct DevHeap {
   uint32_t nlevels;
   uint32_t bm_words;        // words per bitmap (all levels, padded)
   uint32_t bulk_min;        // requests of at least this many take whole free blocks
-  uint32_t field_off[kMaxTypes][kMaxFields];
-  uint8_t field_shift[kMaxTypes][kMaxFields];  // log2(field width)
+  uint32_t doall_unroll;    // blocks per wavefront pass of split do-alls (1, 2, 4, 8)
+  // Field f of type t: byte offset of its array in a block (low 24 bits)
+  // and log2 of its width (high 8 bits), in one dword so that a kernel reads
+  // it with one scalar load.
+  uint32_t field_loc[kMaxTypes][kMaxFields];
 };
 
 // ------------------------------------------------------------ wave helpers --
@@ -186,6 +192,16 @@ __device__ __forceinline__ uint64_t* shard(const DevHeap& h) {
   return h.ctrl + kCtlWords + (uint64_t)(wave & (kShards - 1)) * kShardStride;
 }
 
+// Adds the active lanes' counts (each below 256) to counter `slot` of this
+// wavefront's shard with one atomic; exact under divergence (bit-sliced
+// ballots).  For methods that report their own atomic operations.
+__device__ inline void wave_count(const DevHeap& h, uint32_t slot, uint32_t k) {
+  uint32_t n = 0;
+#pragma unroll
+  for (uint32_t b = 0; b < 8; ++b) n += (uint32_t)__popcll(__ballot((k >> b) & 1u)) << b;
+  if (n) lead_add(shard(h) + slot, n);
+}
+
 // ------------------------------------------------------ hierarchical bitmap --
 // Bitmap k of the heap: k = 0 free, 1 + 2t allocated[t], 2 + 2t active[t].
 // Level l + 1 holds one bit per word of level l; the top level is one word.
@@ -276,6 +292,20 @@ __device__ inline bool bm_clear_from(const Bitmap& b, uint32_t level, uint32_t p
 
 __device__ __forceinline__ bool bm_set(const Bitmap& b, uint32_t pos) { return bm_set_from(b, 0, pos); }
 __device__ __forceinline__ bool bm_clear(const Bitmap& b, uint32_t pos) { return bm_clear_from(b, 0, pos); }
+
+// set(pos) for every bit of m in level-0 word `word`, with one atomic OR when
+// no other operation holds any of them: bits that were already set are set
+// again one by one with set's retry, so each still pairs with the clear that
+// is about to take it away.  The nested bit is set when the word was empty.
+__device__ inline void bm_set_bits0(const Bitmap& b, uint32_t word, uint64_t m) {
+  const uint64_t prev = lead_or(b.word(0, word), m);
+  if (prev == 0 && b.nlevels > 1) bm_set_from(b, 1, word);
+  uint64_t busy = prev & m;
+  while (busy) {
+    bm_set(b, word * 64 + (uint32_t)__builtin_ctzll(busy));
+    busy &= busy - 1;
+  }
+}
 
 // try_set(pos): one atomic OR; on success from an empty container, set the
 // nested bit (retrying).
@@ -379,10 +409,16 @@ __device__ __forceinline__ uint32_t obj_block(uint32_t obj) { return obj >> 6; }
 __device__ __forceinline__ uint32_t obj_slot(uint32_t obj) { return obj & 63u; }
 __device__ __forceinline__ uint32_t make_obj(uint32_t block, uint32_t slot) { return (block << 6) | slot; }
 
+// Address of field `field` of object `obj` of type `type` (SOA: the field's
+// array inside the object's block, indexed by slot).  type and field must be
+// wave-uniform; they are read into scalar registers so that the layout table
+// is fetched with scalar loads, which never wait on the vector loads in flight.
 template <class F>
 __device__ __forceinline__ F* field_ptr(const DevHeap& h, uint32_t obj, uint32_t type, uint32_t field) {
-  return reinterpret_cast<F*>(h.data + (uint64_t)obj_block(obj) * h.block_stride + h.field_off[type][field] +
-                              ((uint64_t)obj_slot(obj) << h.field_shift[type][field]));
+  const uint32_t t = __builtin_amdgcn_readfirstlane(type), f = __builtin_amdgcn_readfirstlane(field);
+  const uint32_t loc = h.field_loc[t][f];
+  return reinterpret_cast<F*>(h.data + (uint64_t)obj_block(obj) * h.block_stride + (loc & 0xFFFFFFu) +
+                              ((uint64_t)obj_slot(obj) << (loc >> 24)));
 }
 
 // Alg. 1 for all lanes of this wavefront that call it with the same `type`
@@ -588,7 +624,7 @@ __device__ inline void dsoar_delete(const DevHeap& h, uint32_t obj) {
   uint64_t pending = __ballot(mine);
   while (pending) {
     const uint32_t leader = (uint32_t)__ffsll((unsigned long long)pending) - 1;
-    const uint32_t b0 = __builtin_amdgcn_readlane(obj, leader) >> 6;
+    const uint32_t b0 = (uint32_t)__builtin_amdgcn_readlane(obj, leader) >> 6;
     const bool in = mine && (obj >> 6) == b0 && ((pending >> lane_id()) & 1);
     const uint64_t grp = __ballot(in);
     const uint64_t m = slots_of(grp, obj_slot(obj));

@@ -74,7 +74,7 @@ struct AlivePrep {
     const uint32_t off = w.off[wid], side = w.side[wid];
     const uint32_t local = g - off;
     const uint32_t y = local / side, x = local - y * side;
-    uint32_t live = 0, claim = 0;
+    uint32_t live = 0, claim = 0, cas = 0;
 #pragma unroll
     for (uint32_t d = 0; d < 8; ++d) {
       const uint32_t hc = w.cells[neighbour(off, side, x, y, d)];
@@ -83,11 +83,17 @@ struct AlivePrep {
       live += alive;
       if (!alive) {
         // The lane that flips the dead cell's cand flag creates its Candidate.
+        // The pre-check may read a stale 0 (workgroup scope: served by this
+        // XCD's L2); the compare-and-swap then decides.  It never reads a
+        // stale 1: the flag only goes 0 -> 1 during this phase.
         uint32_t* cand = field_ptr<uint32_t>(h, hc, kCell, kCCand);
-        if (__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 && atomicCAS(cand, 0u, 1u) == 0u)
-          claim |= 1u << d;
+        if (__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+          ++cas;
+          if (atomicCAS(cand, 0u, 1u) == 0u) claim |= 1u << d;
+        }
       }
     }
+    wave_count(h, kCntMethodAtomics, cas);
     // One coalesced allocation for all of the wavefront's new Candidates.
     new_many(h, kCand, (uint32_t)__popc(claim), [&](uint32_t j, uint32_t o) {
       if (o == kNull) return;

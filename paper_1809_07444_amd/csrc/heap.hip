@@ -479,7 +479,9 @@ __global__ void field_rw_kernel(DevHeap h, uint32_t type, uint32_t field, const 
 struct VisitCount {
   static constexpr uint32_t kKind = 10;
   struct Args { uint32_t* counts; };
-  static __device__ bool run(const DevHeap&, uint32_t, uint32_t self, const Args& a) {
+  struct Pre {};
+  static __device__ Pre load(const DevHeap&, uint32_t, uint32_t, const Args&) { return {}; }
+  static __device__ bool apply(const DevHeap&, uint32_t, uint32_t self, const Args& a, const Pre&) {
     atomicAdd(a.counts + self, 1u);
     return false;
   }
@@ -488,9 +490,12 @@ struct VisitCount {
 struct DeleteIfMod {
   static constexpr uint32_t kKind = 11;
   struct Args { uint32_t field; int32_t modulus; int32_t residue; };
-  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& a) {
-    const int32_t v = *field_ptr<int32_t>(h, self, type, a.field);
-    return (v % a.modulus) == a.residue;
+  struct Pre { int32_t v; };
+  static __device__ Pre load(const DevHeap& h, uint32_t type, uint32_t self, const Args& a) {
+    return {*field_ptr<int32_t>(h, self, type, a.field)};
+  }
+  static __device__ bool apply(const DevHeap&, uint32_t, uint32_t, const Args& a, const Pre& p) {
+    return (p.v % a.modulus) == a.residue;
   }
 };
 
@@ -592,6 +597,7 @@ int collect_stats(dsoar_heap* h, dsoar_stats* out, uint32_t* viol, int check, hi
     st.reserve_retries += c[kCntReserveRetries];
     st.slow_paths += c[kCntSlowPaths];
     st.find_fails += c[kCntFindFails];
+    st.method_atomics += c[kCntMethodAtomics];
   }
   for (uint32_t t = 0; t < kMaxTypes; ++t) {
     st.live_objects[t] = so.live[t];
@@ -653,8 +659,7 @@ int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_byt
   d.bm_words = (uint32_t)(p.L.bitmap_stride / 8);
   for (uint32_t t = 0; t < desc->num_types; ++t)
     for (uint32_t f = 0; f < desc->types[t].num_fields; ++f) {
-      d.field_off[t][f] = p.L.field_offset[t][f];
-      d.field_shift[t][f] = desc->types[t].field_bytes[f] == 8 ? 3 : 2;
+      d.field_loc[t][f] = p.L.field_offset[t][f] | ((desc->types[t].field_bytes[f] == 8 ? 3u : 2u) << 24);
     }
   h->stats_dev = (StatsOut*)(h->base + p.stats_off);
   for (uint32_t t = 0; t < desc->num_types; ++t) {
@@ -675,6 +680,7 @@ int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_byt
   h->doall_wg_threads = 256;
   h->doall_wgs_per_cu = 8;
   d.bulk_min = desc->block_capacity;
+  d.doall_unroll = 4;
   const int rc = init_device_state(h, (hipStream_t)stream);
   if (rc) {
     delete h;
@@ -777,6 +783,14 @@ int dsoar_heap_set_launch(dsoar_heap* h, uint32_t wg_threads, uint32_t wgs_per_c
 int dsoar_heap_set_policy(dsoar_heap* h, uint32_t bulk_min) {
   if (!heap_ok(h)) return DSOAR_ERR_INVALID_ARG;
   h->dev.bulk_min = bulk_min < h->desc.block_capacity ? h->desc.block_capacity : bulk_min;
+  h->config_epoch++;
+  return DSOAR_OK;
+}
+
+int dsoar_heap_set_unroll(dsoar_heap* h, uint32_t blocks_per_pass) {
+  if (!heap_ok(h) || (blocks_per_pass != 1 && blocks_per_pass != 2 && blocks_per_pass != 4 && blocks_per_pass != 8))
+    return DSOAR_ERR_INVALID_ARG;
+  h->dev.doall_unroll = blocks_per_pass;
   h->config_epoch++;
   return DSOAR_OK;
 }

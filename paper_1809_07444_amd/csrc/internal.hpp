@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/dsoar.h"
 #include "dsoar_device.hpp"
 
@@ -103,6 +105,173 @@ inline void timing_end(dsoar_heap* h, int r, hipStream_t s) {
 int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s);
 int read_count(dsoar_heap* h, uint32_t type, hipStream_t s, uint32_t* count);
 
+// A method may split into a load phase and an apply phase:
+//   struct Pre { ... };                      // values the load phase reads
+//   static __device__ Pre load(const DevHeap&, uint32_t type, uint32_t self, const Args&);
+//   static __device__ bool apply(const DevHeap&, uint32_t type, uint32_t self, const Args&, const Pre&);
+// load must not write memory and may read only fields of `self` (it also runs
+// for the empty slots of a listed block, whose values it must not use); apply
+// may write only the fields of `self` (besides creating objects).  The do-all then issues the loads of U blocks
+// before it applies the method to any of them, so a wavefront keeps U times
+// more bytes in flight; this is what lets a do-all over a heap larger than
+// the caches approach the HBM bandwidth.
+template <class M, class = void>
+struct HasSplit : std::false_type {};
+template <class M>
+struct HasSplit<M, std::void_t<typename M::Pre>> : std::true_type {};
+
+template <class Method>
+__device__ __forceinline__ bool run_method(const DevHeap& h, uint32_t type, uint32_t self,
+                                           const typename Method::Args& a) {
+  if constexpr (HasSplit<Method>::value)
+    return Method::apply(h, type, self, a, Method::load(h, type, self, a));
+  else
+    return Method::run(h, type, self, a);
+}
+
+// Makes the value's registers an input of an empty asm statement: the
+// compiler then waits for the loads that produce it at this point (and not
+// later, at a conditional use).  No instruction is emitted.
+template <class T>
+__device__ __forceinline__ void ready(const T& v) {
+  if constexpr (sizeof(T) % 4 == 0) {
+    uint32_t w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (uint32_t i = 0; i < sizeof(T) / 4; ++i) __asm__ volatile("" ::"v"(w[i]));
+  }
+}
+
+// One pass of the split do-all: U list entries, their snapshots and the
+// values the load phase read for them.
+template <class Method, uint32_t U>
+struct SplitPass {
+  uint32_t bid[U];
+  uint64_t snap[U];
+  typename Method::Pre pre[U];
+};
+
+// Capacity 64, U blocks per wavefront pass, software-pipelined over two
+// passes: the list entries of pass k+2 and the field loads of pass k+1 are
+// issued before pass k is applied, so neither the list reads nor the stores
+// of pass k wait for each other.  List entries [e, e + U) are read by lane
+// groups (index clamped to the list, so the loads are unconditional) and
+// broadcast with readlane.  Every lane runs the load phase, live slot or not
+// (all slots of a listed block are addressable): the loads are straight-line
+// code.  The two pass buffers alternate so that no loaded value is copied
+// between registers before it is used.
+template <class Method, uint32_t U>
+__device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, const uint32_t* __restrict__ R,
+                                              const uint64_t* __restrict__ S, uint32_t count, uint32_t gw,
+                                              uint32_t nw, const typename Method::Args& args, uint32_t& visits,
+                                              uint32_t& freed) {
+  const uint32_t lane = lane_id();
+  const uint32_t stride = nw * U;
+  uint32_t rl;
+  uint64_t sl;
+  auto fetch = [&](uint32_t e) {
+    const uint32_t ei = min(e + (lane & (U - 1)), count - 1);
+    rl = R[ei];
+    sl = S[ei];
+  };
+  auto take = [&](SplitPass<Method, U>& p, uint32_t e) {
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+      p.bid[u] = (uint32_t)__builtin_amdgcn_readlane(rl, u);
+      // readlane returns int: widen through uint32_t, never sign-extend.
+      const uint64_t sn = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(sl >> 32), u) << 32) |
+                          (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)sl, u);
+      p.snap[u] = e + u < count ? sn : 0ull;
+    }
+  };
+  auto issue = [&](SplitPass<Method, U>& p) {
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) p.pre[u] = Method::load(h, type, make_obj(p.bid[u], lane), args);
+    // Compiler barrier (no instruction): keeps the loads here instead of
+    // letting them sink to their conditional uses after the next pass.
+    __asm__ volatile("" ::: "memory");
+  };
+  auto finish = [&](SplitPass<Method, U>& p) {
+    // Take delivery of every value of the pass here, unconditionally: the
+    // applies below run under per-lane conditions, and a load whose value a
+    // skipped apply never used would otherwise make the compiler wait
+    // before reusing its register in the next pass.
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) ready(p.pre[u]);
+    uint64_t dm[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+      visits += (uint32_t)__popcll(p.snap[u]);
+      bool del = false;
+      if ((p.snap[u] >> lane) & 1ull) del = Method::apply(h, type, make_obj(p.bid[u], lane), args, p.pre[u]);
+      dm[u] = __ballot(del);
+    }
+    // Deferred deletes of the pass: the leader issues every object-bitmap
+    // AND before it waits for any result; the blocks that were full go back
+    // to active[type] with one OR per level-0 word (the pass's blocks are
+    // consecutive in the ascending list, so they mostly share one word).
+    uint64_t any = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) any |= dm[u];
+    if (any) {
+      uint64_t prev[U];
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        prev[u] = 0;
+        if (dm[u] && is_first_active())
+          prev[u] = __hip_atomic_fetch_and(h.obj_bitmap + p.bid[u], ~dm[u], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+      const Bitmap act = active_bm(h, type);
+      uint32_t act_word = 0xFFFFFFFFu;
+      uint64_t act_bits = 0;
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        if (!dm[u]) continue;
+        const uint64_t pv = bcast64(prev[u]);
+        if ((pv & dm[u]) != dm[u]) lead_flag(h.ctrl + kCtlDoubleFree);
+        const uint64_t removed = pv & dm[u];
+        freed += (uint32_t)__popcll(removed);
+        if (removed && (pv & h.cap_mask) == h.cap_mask) {
+          const uint32_t w = p.bid[u] >> 6;
+          if (w != act_word) {
+            if (act_bits) bm_set_bits0(act, act_word, act_bits);
+            act_word = w;
+            act_bits = 0;
+          }
+          act_bits |= 1ull << (p.bid[u] & 63u);
+        }
+      }
+      if (act_bits) bm_set_bits0(act, act_word, act_bits);
+    }
+  };
+  uint32_t e = gw * U;
+  if (e >= count) return;
+  SplitPass<Method, U> A, B;
+  fetch(e);
+  take(A, e);
+  fetch(e + stride);
+  issue(A);
+  // The next pass is issued unconditionally (past the end of the list its
+  // snapshots are empty), so the compiler's wait counts never have to allow
+  // for a skipped batch of loads.
+  for (;;) {
+    const uint32_t e1 = e + stride;
+    take(B, e1);
+    fetch(e1 + stride);
+    issue(B);
+    finish(A);
+    if (e1 >= count) break;
+    const uint32_t e2 = e1 + stride;
+    take(A, e2);
+    fetch(e2 + stride);
+    issue(A);
+    finish(B);
+    if (e2 >= count) break;
+    e = e2;
+  }
+}
+
 // The do-all kernel (Sec. 2.3).  Entry e of the compacted list R is handled
 // by capacity consecutive lanes: with capacity 64 one wavefront per block,
 // with 32 two blocks per wavefront.  Lane slot s runs the method when bit s of
@@ -110,26 +279,40 @@ int read_count(dsoar_heap* h, uint32_t type, hipStream_t s, uint32_t* count);
 // applied as one atomic AND per block when the wavefront finishes the block.
 //
 // Method: struct with `struct Args`, a `static constexpr uint32_t kKind`
-// (an id for per-kernel timing) and
+// (an id for per-kernel timing) and either
 //   static __device__ bool run(const DevHeap&, uint32_t type, uint32_t self, const Args&)
-// returning true to delete self.
+// returning true to delete self, or the load / apply pair described above.
 template <class Method>
 __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, const uint32_t* __restrict__ R,
                                                       const uint64_t* __restrict__ S, const uint32_t* count_ptr,
                                                       typename Method::Args args) {
   const uint32_t lane = lane_id();
   const uint32_t wpb = blockDim.x >> 6;
-  const uint32_t gw = blockIdx.x * wpb + (threadIdx.x >> 6);
+  const uint32_t gw = blockIdx.x * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const uint32_t nw = gridDim.x * wpb;
   const uint32_t count = bcast32(*count_ptr);
   uint32_t visits = 0, freed = 0;
-  if (h.capacity == 64) {
+  bool done = false;
+  if constexpr (HasSplit<Method>::value) {
+    // Several blocks per pass only when every wavefront gets that many.
+    if (h.capacity == 64 && h.doall_unroll > 1 && count >= nw * h.doall_unroll) {
+      if (h.doall_unroll >= 8)
+        doall_split64<Method, 8>(h, type, R, S, count, gw, nw, args, visits, freed);
+      else if (h.doall_unroll >= 4)
+        doall_split64<Method, 4>(h, type, R, S, count, gw, nw, args, visits, freed);
+      else
+        doall_split64<Method, 2>(h, type, R, S, count, gw, nw, args, visits, freed);
+      done = true;
+    }
+  }
+  if (done) {
+  } else if (h.capacity == 64) {
     for (uint32_t e = gw; e < count; e += nw) {
       const uint32_t bid = R[e];
       const uint64_t snap = S[e];
       visits += (uint32_t)__popcll(snap);
       bool del = false;
-      if ((snap >> lane) & 1ull) del = Method::run(h, type, make_obj(bid, lane), args);
+      if ((snap >> lane) & 1ull) del = run_method<Method>(h, type, make_obj(bid, lane), args);
       const uint64_t dm = __ballot(del);
       if (dm) freed += delete_mask(h, type, bid, dm);
     }
@@ -142,7 +325,7 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
       const uint64_t snap = valid ? S[e] : 0ull;
       visits += (uint32_t)__popcll(__ballot((snap >> slot) & 1ull));
       bool del = false;
-      if ((snap >> slot) & 1ull) del = Method::run(h, type, make_obj(bid, slot), args);
+      if ((snap >> slot) & 1ull) del = run_method<Method>(h, type, make_obj(bid, slot), args);
       const uint64_t dm = __ballot(del);
       if (dm & 0xFFFFFFFFull) freed += delete_mask(h, type, __builtin_amdgcn_readlane(bid, 0), dm & 0xFFFFFFFFull);
       if (dm >> 32) freed += delete_mask(h, type, __builtin_amdgcn_readlane(bid, 32), dm >> 32);

@@ -12,10 +12,12 @@ enum : uint32_t { kId = 0, kX = 1, kV = 2 };
 struct MicroUpdate {
   static constexpr uint32_t kKind = 20;
   struct Args { uint32_t unused; };
-  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args&) {
-    float* x = field_ptr<float>(h, self, type, kX);
-    const float v = *field_ptr<float>(h, self, type, kV);
-    *x = __builtin_fmaf(0.01f, v, *x);  // one rounding
+  struct Pre { float x, v; };
+  static __device__ Pre load(const DevHeap& h, uint32_t type, uint32_t self, const Args&) {
+    return {*field_ptr<float>(h, self, type, kX), *field_ptr<float>(h, self, type, kV)};
+  }
+  static __device__ bool apply(const DevHeap& h, uint32_t type, uint32_t self, const Args&, const Pre& p) {
+    *field_ptr<float>(h, self, type, kX) = __builtin_fmaf(0.01f, p.v, p.x);  // one rounding
     return false;
   }
 };
@@ -23,8 +25,12 @@ struct MicroUpdate {
 struct MicroCull {
   static constexpr uint32_t kKind = 21;
   struct Args { uint32_t unused; };
-  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args&) {
-    return (*field_ptr<int32_t>(h, self, type, kId) % 3) == 0;
+  struct Pre { int32_t id; };
+  static __device__ Pre load(const DevHeap& h, uint32_t type, uint32_t self, const Args&) {
+    return {*field_ptr<int32_t>(h, self, type, kId)};
+  }
+  static __device__ bool apply(const DevHeap&, uint32_t, uint32_t, const Args&, const Pre& p) {
+    return p.id % 3 == 0;
   }
 };
 

@@ -122,6 +122,7 @@ struct Choose {
     }
     af<uint32_t>(h, self, kTarget) = best;
     if (best != p) atomicMin(g.req + best, p);
+    wave_count(h, kCntMethodAtomics, best != p ? 1u : 0u);
     return false;
   }
 };
@@ -188,6 +189,7 @@ struct Request {
       if (best != kNull) atomicMin(g.breq + best, p);
     }
     af<uint32_t>(h, self, kTarget) = best;
+    wave_count(h, kCntMethodAtomics, best != kNull ? 1u : 0u);
     return false;
   }
 };

@@ -81,6 +81,10 @@ class Heap:
     def set_policy(self, bulk_min: int):
         C.check(self.lib.dsoar_heap_set_policy(self.h, bulk_min), "dsoar_heap_set_policy")
 
+    def set_unroll(self, blocks_per_pass: int):
+        """Blocks per wavefront pass of split do-all methods (1, 2, 4, 8)."""
+        C.check(self.lib.dsoar_heap_set_unroll(self.h, blocks_per_pass), "dsoar_heap_set_unroll")
+
     def set_timing(self, enable: bool):
         C.check(self.lib.dsoar_heap_set_timing(self.h, 1 if enable else 0), "dsoar_heap_set_timing")
 
@@ -112,7 +116,8 @@ class Heap:
             visits=list(st.visits[:nt]),
             allocated_blocks=list(st.allocated_blocks[:nt]), active_blocks=list(st.active_blocks[:nt]),
             typed_blocks=list(st.typed_blocks[:nt]), reserve_retries=st.reserve_retries,
-            slow_paths=st.slow_paths, find_fails=st.find_fails, free_blocks=st.free_blocks,
+            slow_paths=st.slow_paths, find_fails=st.find_fails, method_atomics=st.method_atomics,
+            free_blocks=st.free_blocks,
             num_blocks=st.num_blocks, oom=st.oom, retry_limit_hit=st.retry_limit_hit,
             double_free=st.double_free, status=rc)
 
