@@ -46,6 +46,10 @@ def parse():
                    help="after the run, launch one elementwise kernel over 256 MiB (counter calibration)")
     p.add_argument("--scaled-blocks", type=int, default=1 << 22)
     p.add_argument("--probe", action="store_true", help="also measure atomic and copy ceilings")
+    p.add_argument("--bulk-min", type=lambda v: 0xFFFFFFFF if v == "never" else int(v), default=None,
+                   help="allocation policy: requests of at least this many take whole free blocks first "
+                        "('never' = the dense default)")
+    p.add_argument("--unroll", type=int, default=None, help="blocks per wavefront pass of split do-alls")
     return p.parse_args()
 
 
@@ -146,6 +150,7 @@ class MicroWorkload:
         from synth import workloads as W
         self.C = C
         if scaled:
+            self.name = "micro_scaled"
             self.M = args.scaled_blocks
             n, steps = 16 * self.M, 2
         else:
@@ -374,6 +379,13 @@ def main():
     else:
         wl = MicroWorkload(args, scaled=args.workload == "micro_scaled")
 
+    if args.bulk_min is not None:
+        wl.heap().set_policy(args.bulk_min)
+        wl.config["bulk_min"] = args.bulk_min
+    if args.unroll is not None:
+        wl.heap().set_unroll(args.unroll)
+        wl.config["unroll"] = args.unroll
+
     for _ in range(args.warmup):
         wl.step()
     torch.cuda.synchronize()
@@ -413,6 +425,15 @@ def main():
         roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": best,
                 "avg_launch_us": round(kernels[best]["avg_us"], 2)}
+
+    # Bytes beyond L2 per launch of the dominant kernel, from the committed
+    # rocprofv3 counter summary of this workload, while the device sources
+    # still hash as they did when the counters were taken (else null).
+    if roof is not None:
+        from paper_1809_07444_amd import profiling
+        summ = profiling.read_summary(os.path.join(ROOT, "profiles", f"traffic_{wl.name}.txt"))
+        if summ and summ["source_hash"] == profiling.source_hash() and best in summ["kernels"]:
+            roof["traffic"] = summ["kernels"][best]
 
     # Atomic read-modify-writes the methods issue themselves (claim flags,
     # move requests): for the GoL the dominant kernel's compare-and-swaps.

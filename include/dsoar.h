@@ -153,11 +153,13 @@ int dsoar_heap_get_layout(const dsoar_heap* heap, dsoar_heap_layout* out);
  * compute unit (1..64).  Defaults 256 and 8. */
 int dsoar_heap_set_launch(dsoar_heap* heap, uint32_t wg_threads, uint32_t wgs_per_cu);
 
-/* Allocation policy: a wavefront whose outstanding requests number at least
- * bulk_min takes whole free blocks directly instead of first filling active
- * blocks (whole blocks are fully dense; smaller remainders always go to
- * active blocks first).  Values below the block capacity mean the capacity
- * (the default); 0xFFFFFFFF always fills active blocks first. */
+/* Allocation policy.  By default (bulk_min = 0xFFFFFFFF) a wavefront fills
+ * active blocks of the type first (Sec. 2.2) and takes free blocks only when
+ * it finds none, whole ones while it still needs at least a block's worth.
+ * A wavefront whose outstanding requests number at least bulk_min instead
+ * takes whole free blocks directly, without the active lookup (fewer atomics,
+ * more partially filled blocks).  Values below the block capacity mean the
+ * capacity. */
 int dsoar_heap_set_policy(dsoar_heap* heap, uint32_t bulk_min);
 
 /* Blocks per wavefront pass for do-all methods that split into a load phase
@@ -397,7 +399,8 @@ int dsoar_sugar_create(dsoar_heap* heap, uint32_t side, const dsoar_sugar_rules*
 int dsoar_sugar_destroy(dsoar_sugar* sugar);
 /* Initial state from per-cell device arrays (side*side each): sugar and cap
  * (int32), occ (uint8, 1 = an agent starts here) and the agents' sugar,
- * metabolism, vision and age (int32, read where occ).  step0 = index of the
+ * metabolism, vision and age (int32, read where occ).  Vision is 1..6 (the
+ * choose phase looks at most 6 cells along each axis).  step0 = index of the
  * first step (it keys the random draws).  The heap should be freshly reset. */
 int dsoar_sugar_init(dsoar_sugar* sugar, const int32_t* sugar_dev, const int32_t* cap_dev,
                      const uint8_t* occ_dev, const int32_t* a_sugar_dev, const int32_t* a_metab_dev,

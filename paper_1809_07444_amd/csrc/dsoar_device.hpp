@@ -35,6 +35,7 @@ constexpr uint32_t kTypeNone = 0xFFFFFFFFu;
 constexpr int32_t kFail = -1;
 constexpr uint32_t kSpinLimit = 1u << 20;  // bound of every retry loop
 constexpr uint32_t kShards = 1024;         // counter shards (spread atomics)
+constexpr uint32_t kMultiBlocks = 8;  // active blocks one lookup may reserve in
 constexpr uint32_t kOomRetries = 4;        // active lookups retried before OOM
 
 // Control words (uint64 array at DevHeap::ctrl).
@@ -121,6 +122,19 @@ __device__ __forceinline__ uint64_t lowest_bits(uint64_t m, uint32_t n) {
   if (n == 0) return 0;
   uint32_t p = nth_set_bit(m, n);  // first bit not taken
   return m & ((1ull << p) - 1);
+}
+
+// OR of (1 << slot) over the lanes in `lanes` (all of them active); reads
+// each lane with readlane, so inactive lanes of a divergent caller are never
+// touched.
+__device__ __forceinline__ uint64_t slots_of(uint64_t lanes, uint32_t slot) {
+  uint64_t m = 0;
+  while (lanes) {
+    const uint32_t l = (uint32_t)__builtin_ctzll(lanes);
+    m |= 1ull << (__builtin_amdgcn_readlane(slot, l) & 63u);
+    lanes &= lanes - 1;
+  }
+  return m;
 }
 
 // The n set bits of m found by scanning upwards from bit r and wrapping
@@ -307,6 +321,38 @@ __device__ inline void bm_set_bits0(const Bitmap& b, uint32_t word, uint64_t m) 
   }
 }
 
+// bm_set_bits0 in two halves, so that the wait for the OR's result can be
+// put off: _issue returns the previous word in the leader lane only (call
+// both halves with the same lanes active), _settle finishes the operation.
+__device__ __forceinline__ uint64_t bm_set_bits0_issue(const Bitmap& b, uint32_t word, uint64_t m) {
+  uint64_t r = 0;
+  if (is_first_active()) r = __hip_atomic_fetch_or(b.word(0, word), m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return r;
+}
+__device__ inline void bm_set_bits0_settle(const Bitmap& b, uint32_t word, uint64_t m, uint64_t leader_prev) {
+  const uint64_t prev = bcast64(leader_prev);
+  if (prev == 0 && b.nlevels > 1) bm_set_from(b, 1, word);
+  uint64_t busy = prev & m;
+  while (busy) {
+    bm_set(b, word * 64 + (uint32_t)__builtin_ctzll(busy));
+    busy &= busy - 1;
+  }
+}
+
+// clear(pos) for every bit of m in level-0 word `word`: one atomic AND; bits
+// that were not set yet (their set is still on its way) are cleared one by
+// one with clear's retry.  The nested bit is cleared when this AND emptied
+// the word (Alg. 2 for several bits at once).
+__device__ inline void bm_clear_bits0(const Bitmap& b, uint32_t word, uint64_t m) {
+  const uint64_t prev = lead_and(b.word(0, word), ~m);
+  if ((prev & m) && (prev & ~m) == 0 && b.nlevels > 1) bm_clear_from(b, 1, word);
+  uint64_t busy = m & ~prev;
+  while (busy) {
+    bm_clear(b, word * 64 + (uint32_t)__builtin_ctzll(busy));
+    busy &= busy - 1;
+  }
+}
+
 // try_set(pos): one atomic OR; on success from an empty container, set the
 // nested bit (retrying).
 __device__ inline bool bm_try_set(const Bitmap& b, uint32_t pos) {
@@ -353,6 +399,21 @@ __device__ inline int32_t bm_try_find_set(const Bitmap& b, uint32_t start) {
     idx = (idx << 6) | pick_bit(w, level_digit(start, (uint32_t)l));
   }
   return idx < b.nbits ? (int32_t)idx : kFail;
+}
+
+// try_find_set() stopped one level early: the index of a non-empty level-0
+// word (chosen as try_find_set chooses) and its bits, or FAIL.
+__device__ inline int32_t bm_find_word(const Bitmap& b, uint32_t start, uint64_t* bits) {
+  uint32_t idx = 0;
+  for (int32_t l = (int32_t)b.nlevels - 1; l >= 1; --l) {
+    const uint64_t w = load_u64(b.word((uint32_t)l, idx));
+    if (w == 0) return kFail;
+    idx = (idx << 6) | pick_bit(w, level_digit(start, (uint32_t)l));
+  }
+  const uint64_t w = load_u64(b.word(0, idx));
+  if (w == 0) return kFail;
+  *bits = w;
+  return (int32_t)idx;
 }
 
 // clear() of Sec. 2.1: find a set bit and clear it, repeating until this
@@ -428,12 +489,14 @@ __device__ __forceinline__ F* field_ptr(const DevHeap& h, uint32_t obj, uint32_t
 // (sticky OOM flag set).  f must not itself call wavefront heap operations.
 //
 // Request coalescing (Sec. 2.4): the n = sum k_i requests of the wavefront
-// are served together, one leader lane issuing every atomic.  While at least
-// `capacity` requests remain, a pass takes whole free blocks (full blocks
-// are dense by construction), several at once from one free-bitmap word.
-// Otherwise it looks up an active block of the type first (dense policy,
-// Sec. 2.2) and takes a free block only when none is found (slow path: set
-// the type, mark it allocated and, unless this pass fills it, active).
+// are served together, one leader lane issuing every atomic.  A pass looks
+// up an active block of the type first (dense policy, Sec. 2.2) and takes a
+// free block only when none is found (slow path: set the type, mark it
+// allocated and, unless this pass fills it, active).  Once no active block
+// was found, and while at least `capacity` requests remain, a pass takes
+// whole free blocks, several at once from one free-bitmap word (full blocks
+// are dense by construction).  With bulk_min set, requests of at least that
+// many skip the active lookup and take whole free blocks directly.
 // Reservation in an active block is one atomic OR of the wanted number of
 // bits among those a snapshot shows free (after our own OR, the bits it left
 // free); the bits gained are take & ~prev, and a block that still has room is
@@ -456,7 +519,7 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
   const uint32_t c = h.capacity;
   uint32_t start = rot;
   uint32_t served = 0, retries = 0, slow = 0, fails = 0, oom_rounds = 0;
-  bool oom = false, active_first = false;
+  bool oom = false, active_first = false, none_active = false;
   int32_t cur = kFail;     // block of the last reservation, if it still had room
   uint64_t cur_avail = 0;  // its free bits right after that reservation
   for (uint32_t it = 0; served < n; ++it) {
@@ -466,7 +529,7 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
       break;
     }
     const uint32_t want = n - served;
-    if (want >= h.bulk_min && want >= c && !active_first) {
+    if (want >= c && (want >= h.bulk_min || none_active) && !active_first) {
       // Whole free blocks, several from one free-bitmap word per atomic.
       uint32_t word = 0;
       const uint32_t nb = want / c < 64 ? want / c : 64;
@@ -502,16 +565,72 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
     uint64_t avail = cur_avail;
     uint64_t got;
     if (bid == kFail) {
-      bid = bm_try_find_set(active, start);
-      if (bid == kFail) {
+      uint64_t wbits = 0;
+      const int32_t aw = bm_find_word(active, start, &wbits);
+      if (aw == kFail) {
         ++fails;
+        // No active block: whole free blocks for the rest while it fills them.
+        none_active = true;
+        if (want >= c && !active_first) continue;
       } else {
-        avail = ~load_u64(h.obj_bitmap + bid) & h.cap_mask;
-        if (avail == 0) {  // filled since the lookup; its filler clears the bit
-          ++retries;
-          start = hash32(start + it + 1);
-          continue;
+        // Up to kMultiBlocks active blocks of this word, one active lane per
+        // block: their object bitmaps are read and reserved in parallel, so a
+        // request larger than one block's room costs one lookup, not one per
+        // block.  Requests are spread over the blocks in rank order.
+        const uint64_t am = active_mask();
+        const uint32_t me = lanes_below(am), nact = (uint32_t)__popcll(am);
+        uint32_t nb = (uint32_t)__popcll(wbits);
+        nb = nb < kMultiBlocks ? nb : kMultiBlocks;
+        nb = nb < nact ? nb : nact;
+        const uint64_t sel = take_from(wbits, nb, start & 63u);
+        uint32_t my_bid = 0;
+        uint64_t my_av = 0;
+        if (me < nb) {
+          my_bid = (uint32_t)aw * 64 + nth_set_bit(sel, me);
+          if (my_bid < h.num_blocks) my_av = ~load_u64(h.obj_bitmap + my_bid) & h.cap_mask;
         }
+        const uint32_t cnt = (uint32_t)__popcll(my_av);
+        uint32_t excl = 0;
+#pragma unroll
+        for (uint32_t b = 0; b < 7; ++b) excl += lanes_below(__ballot((cnt >> b) & 1u)) << b;
+        const uint32_t my_t = want > excl ? (cnt < want - excl ? cnt : want - excl) : 0u;
+        const uint64_t my_take = my_t ? take_from(my_av, my_t, rot & (c - 1)) : 0ull;
+        uint64_t my_prev = 0;
+        if (my_take)
+          my_prev = __hip_atomic_fetch_or(h.obj_bitmap + my_bid, my_take, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t my_got = my_take & ~my_prev;
+        const uint64_t my_after = (my_prev | my_take) & h.cap_mask;
+        // The reservation that set a block's last free bit takes it out of active.
+        const uint64_t fill_lanes = __ballot(my_take && my_after == h.cap_mask && (my_prev & h.cap_mask) != h.cap_mask);
+        if (fill_lanes) bm_clear_bits0(active, (uint32_t)aw, slots_of(fill_lanes, my_bid & 63u));
+        if (__ballot(my_got != my_take)) ++retries;
+        const uint64_t room_lanes = __ballot(my_take && my_after != h.cap_mask);
+        if (room_lanes) {
+          const uint32_t l = 63u - (uint32_t)__builtin_clzll(room_lanes);
+          cur = (int32_t)__builtin_amdgcn_readlane(my_bid, l);
+          cur_avail = ~(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(my_after >> 32), l) << 32) |
+                        (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)my_after, l)) &
+                      h.cap_mask;
+        }
+        // Hand the gained slots out, block by block in rank order.
+        uint64_t lanes = __ballot(me < nb);
+        uint32_t gained = 0;
+        while (lanes) {
+          const uint32_t l = (uint32_t)__builtin_ctzll(lanes);
+          lanes &= lanes - 1;
+          const uint64_t g = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(my_got >> 32), l) << 32) |
+                             (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)my_got, l);
+          if (!g) continue;
+          const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane(my_bid, l);
+          const uint32_t gc = (uint32_t)__popcll(g);
+          const uint32_t lo = prefix > served ? prefix : served;
+          const uint32_t hi = prefix + k < served + gc ? prefix + k : served + gc;
+          for (uint32_t r = lo; r < hi; ++r) f(r - prefix, make_obj(gb, nth_set_bit(g, r - served)));
+          served += gc;
+          gained += gc;
+        }
+        if (gained == 0 && cur == kFail) start = hash32(start + it + 1);
+        continue;
       }
     }
     cur = kFail;
@@ -600,19 +719,6 @@ __device__ inline uint32_t delete_mask(const DevHeap& h, uint32_t type, uint32_t
   const uint64_t removed = prev & mask;
   if (removed && (prev & h.cap_mask) == h.cap_mask) bm_set(active_bm(h, type), bid);
   return (uint32_t)__popcll(removed);
-}
-
-// OR of (1 << slot) over the lanes in `lanes` (all of them active); reads
-// each lane with readlane, so inactive lanes of a divergent caller are never
-// touched.
-__device__ __forceinline__ uint64_t slots_of(uint64_t lanes, uint32_t slot) {
-  uint64_t m = 0;
-  while (lanes) {
-    const uint32_t l = (uint32_t)__builtin_ctzll(lanes);
-    m |= 1ull << (__builtin_amdgcn_readlane(slot, l) & 63u);
-    lanes &= lanes - 1;
-  }
-  return m;
 }
 
 // Device `delete` of arbitrary objects: lanes are grouped by block; each group

@@ -679,7 +679,7 @@ int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_byt
   h->num_cus = (uint32_t)prop.multiProcessorCount;
   h->doall_wg_threads = 256;
   h->doall_wgs_per_cu = 8;
-  d.bulk_min = desc->block_capacity;
+  d.bulk_min = 0xFFFFFFFFu;  // dense policy: active blocks first
   d.doall_unroll = 4;
   const int rc = init_device_state(h, (hipStream_t)stream);
   if (rc) {

@@ -191,6 +191,15 @@ __device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, c
     // letting them sink to their conditional uses after the next pass.
     __asm__ volatile("" ::: "memory");
   };
+  // The active-bitmap OR of the last pass, settled (its result used) one
+  // pass later, when it has long returned.
+  const Bitmap act = active_bm(h, type);
+  uint32_t pend_word = 0;
+  uint64_t pend_bits = 0, pend_prev = 0;
+  auto settle = [&]() {
+    if (pend_bits) bm_set_bits0_settle(act, pend_word, pend_bits, pend_prev);
+    pend_bits = 0;
+  };
   auto finish = [&](SplitPass<Method, U>& p) {
     // Take delivery of every value of the pass here, unconditionally: the
     // applies below run under per-lane conditions, and a load whose value a
@@ -210,25 +219,35 @@ __device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, c
     // AND before it waits for any result; the blocks that were full go back
     // to active[type] with one OR per level-0 word (the pass's blocks are
     // consecutive in the ascending list, so they mostly share one word).
+    // A block whose snapshot is full is still exactly full here: during a
+    // do-all only the wavefront visiting a block removes its objects
+    // (methods delete only `this`), and a full block is not active, so no
+    // allocation adds to it.  Its AND needs no result and is not waited for.
     uint64_t any = 0;
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) any |= dm[u];
     if (any) {
+      const bool leader = is_first_active();
+      // Two separate loops, so the compiler keeps the first kind of AND
+      // without a return value instead of merging it with the second.
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u)
+        if (dm[u] && p.snap[u] == h.cap_mask && leader)
+          __hip_atomic_fetch_and(h.obj_bitmap + p.bid[u], ~dm[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       uint64_t prev[U];
 #pragma unroll
       for (uint32_t u = 0; u < U; ++u) {
         prev[u] = 0;
-        if (dm[u] && is_first_active())
+        if (dm[u] && p.snap[u] != h.cap_mask && leader)
           prev[u] = __hip_atomic_fetch_and(h.obj_bitmap + p.bid[u], ~dm[u], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
       }
-      const Bitmap act = active_bm(h, type);
       uint32_t act_word = 0xFFFFFFFFu;
       uint64_t act_bits = 0;
 #pragma unroll
       for (uint32_t u = 0; u < U; ++u) {
         if (!dm[u]) continue;
-        const uint64_t pv = bcast64(prev[u]);
+        const uint64_t pv = p.snap[u] == h.cap_mask ? h.cap_mask : bcast64(prev[u]);
         if ((pv & dm[u]) != dm[u]) lead_flag(h.ctrl + kCtlDoubleFree);
         const uint64_t removed = pv & dm[u];
         freed += (uint32_t)__popcll(removed);
@@ -242,7 +261,12 @@ __device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, c
           act_bits |= 1ull << (p.bid[u] & 63u);
         }
       }
-      if (act_bits) bm_set_bits0(act, act_word, act_bits);
+      if (act_bits) {
+        settle();
+        pend_word = act_word;
+        pend_bits = act_bits;
+        pend_prev = bm_set_bits0_issue(act, act_word, act_bits);
+      }
     }
   };
   uint32_t e = gw * U;
@@ -270,6 +294,7 @@ __device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, c
     if (e2 >= count) break;
     e = e2;
   }
+  settle();
 }
 
 // The do-all kernel (Sec. 2.3).  Entry e of the compacted list R is handled

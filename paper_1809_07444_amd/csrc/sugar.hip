@@ -97,6 +97,15 @@ __device__ __forceinline__ Where where(const Grid& g, uint32_t wid, uint32_t p) 
   return Where{off, (int32_t)side, (int32_t)(local % side), (int32_t)(local / side)};
 }
 
+// Cell at offset (dx*k, dy*k) from (x, y) on a torus of side `side`.
+__device__ __forceinline__ uint32_t step_cell(const Where& c, int32_t dx, int32_t dy, int32_t k) {
+  int32_t x = c.x + dx * k, y = c.y + dy * k;
+  if (x < 0 || x >= c.side || y < 0 || y >= c.side) return wrap_cell(c.off, c.side, x, y);
+  return c.off + (uint32_t)y * (uint32_t)c.side + (uint32_t)x;
+}
+
+constexpr int32_t kMaxVision = 6;
+
 struct Choose {
   static constexpr uint32_t kKind = 40;
   using Args = Grid;
@@ -104,17 +113,37 @@ struct Choose {
     const uint32_t p = af<uint32_t>(h, self, kPos);
     const int32_t vision = af<int32_t>(h, self, kVision);
     const Where c = where(g, af<uint32_t>(h, self, kWorld), p);
+    // The cells in sight along two axis directions at a time (beyond
+    // `vision` the own cell stands in, so that the loads of a half are all
+    // issued together, unconditionally), then the choice: most sugar, then
+    // nearest, then lowest index.  The order in which the candidates are
+    // compared does not matter for that total order.
     uint32_t best = p;
     int32_t best_sugar = g.sugar[p], best_dist = 0;
-    for (int32_t d = 0; d < 4; ++d) {
-      const int32_t dx = d == 0 ? 1 : (d == 1 ? -1 : 0);
-      const int32_t dy = d == 2 ? 1 : (d == 3 ? -1 : 0);
-      for (int32_t k = 1; k <= vision; ++k) {
-        const uint32_t q = wrap_cell(c.off, c.side, c.x + dx * k, c.y + dy * k);
-        if (g.occ[q] != kNull) continue;
-        const int32_t s = g.sugar[q];
-        if (s > best_sugar || (s == best_sugar && (k < best_dist || (k == best_dist && q < best)))) {
-          best = q;
+#pragma unroll
+    for (int32_t half = 0; half < 2; ++half) {
+      uint32_t q[2 * kMaxVision], o[2 * kMaxVision];
+      int32_t sg[2 * kMaxVision];
+#pragma unroll
+      for (int32_t j = 0; j < 2; ++j)
+#pragma unroll
+        for (int32_t k = 1; k <= kMaxVision; ++k) {
+          const int32_t d = 2 * half + j;
+          const int32_t dx = d == 0 ? 1 : (d == 1 ? -1 : 0);
+          const int32_t dy = d == 2 ? 1 : (d == 3 ? -1 : 0);
+          q[j * kMaxVision + k - 1] = k <= vision ? step_cell(c, dx, dy, k) : p;
+        }
+#pragma unroll
+      for (int32_t i = 0; i < 2 * kMaxVision; ++i) o[i] = g.occ[q[i]];
+#pragma unroll
+      for (int32_t i = 0; i < 2 * kMaxVision; ++i) sg[i] = g.sugar[q[i]];
+#pragma unroll
+      for (int32_t i = 0; i < 2 * kMaxVision; ++i) {
+        const int32_t k = i % kMaxVision + 1;
+        if (k > vision || o[i] != kNull) continue;
+        const int32_t s = sg[i];
+        if (s > best_sugar || (s == best_sugar && (k < best_dist || (k == best_dist && q[i] < best)))) {
+          best = q[i];
           best_sugar = s;
           best_dist = k;
         }

@@ -17,7 +17,7 @@ import numpy as np
 import torch
 
 from . import _capi as C
-from .apps import GOL_TYPES, SUGAR_TYPE
+from .apps import GOL_TYPES, SUGAR_TYPE, GameOfLife
 from .heap import Heap
 
 
@@ -79,6 +79,8 @@ class Pool:
         self.stream = torch.cuda.Stream(device=device)
         types = GOL_TYPES if kind == "gol" else SUGAR_TYPE
         self.heap = Heap(blocks, 64, types, device=device, stream=self.stream)
+        if kind == "gol":
+            self.heap.set_policy(GameOfLife.BULK_MIN)  # as the single-pool GoL driver
         self.lib = self.heap.lib
         self.blocks = blocks
         self.budget = blocks
