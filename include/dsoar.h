@@ -64,10 +64,13 @@ typedef struct {
 } dsoar_type_layout;
 
 /* Heap geometry.  num_blocks = M (1 .. 2^26).  block_capacity = slots per
- * block, 64 (one wavefront per block, the paper's capacity for the smallest
- * type) or 32 (two blocks per wavefront; Sec. 2 notes capacities of at least
- * 32 keep 4-byte SOA arrays at 128 bytes).  All types are declared up front
- * (Sec. 2, footnote on pre-declared types). */
+ * block of every type, 64 (one wavefront per block, the paper's capacity for
+ * the smallest type) or 32 (two blocks per wavefront; Sec. 2 notes capacities
+ * of at least 32 keep 4-byte SOA arrays at 128 bytes), or 0 for the byte-size
+ * rule of Sec. 2: the smallest type has 64 slots and fixes the block size (64
+ * of its objects), every other type the largest power of two of slots that
+ * fits a block (64 / c blocks per wavefront in a do-all).  All types are
+ * declared up front (Sec. 2, footnote on pre-declared types). */
 typedef struct {
   uint32_t num_blocks;
   uint32_t block_capacity;
@@ -92,6 +95,7 @@ typedef struct {
   uint32_t level_word_offset[8];
   uint32_t level_words[8];
   uint32_t field_offset[DSOAR_MAX_TYPES][DSOAR_MAX_FIELDS];
+  uint32_t type_capacity[DSOAR_MAX_TYPES]; /* slots per block of each type */
 } dsoar_heap_layout;
 
 /* Quiescent statistics, filled by dsoar_heap_stats. */

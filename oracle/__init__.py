@@ -70,6 +70,8 @@ def lib() -> ctypes.CDLL:
         L.orc_bm_trace.argtypes = [vp, vp, i64]
         L.orc_bm_op.restype = ctypes.c_int
         L.orc_bm_op.argtypes = [vp, ctypes.c_int, i64, ctypes.POINTER(i64)]
+        L.orc_type_capacity.restype = i32
+        L.orc_type_capacity.argtypes = [vp, i32, i32]
         L.orc_heap_new.restype = vp
         L.orc_heap_new.argtypes = [i32, i32, i32]
         L.orc_heap_delete.argtypes = [vp]
@@ -93,6 +95,12 @@ def lib() -> ctypes.CDLL:
         L.orc_sugar_run.argtypes = [i32, i32, i32, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
+
+
+def type_capacity(sizes, t: int) -> int:
+    """Slots per block of type t (Sec. 2 byte-size rule) among types of the given byte sizes."""
+    a = np.ascontiguousarray(sizes, dtype=np.int32)
+    return int(lib().orc_type_capacity(a.ctypes.data_as(ctypes.c_void_p), len(a), t))
 
 
 def _p(a: np.ndarray):

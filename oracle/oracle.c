@@ -221,6 +221,23 @@ int orc_bm_op(void *b, int op, int64_t pos, int64_t *result) {
   }
 }
 
+/* ======================================================== block capacities
+ * Sec. 2 ("Blocks of the smallest type always have a capacity of 64 ... other
+ * types may have a smaller capacity"): the block holds 64 objects of the
+ * smallest type; a type gets the largest power-of-two number of its objects
+ * whose bytes do not exceed that (powers of two keep a block's slots one
+ * aligned group of a 64-bit object bitmap), and never fewer than one. */
+int32_t orc_type_capacity(const int32_t *sizes, int32_t ntypes, int32_t t) {
+  int64_t smallest = sizes[0];
+  for (int32_t i = 1; i < ntypes; i++)
+    if (sizes[i] < smallest) smallest = sizes[i];
+  const int64_t block_bytes = 64 * smallest;
+  int32_t best = 1;
+  for (int32_t c = 1; c <= 64; c *= 2)
+    if ((int64_t)c * sizes[t] <= block_bytes) best = c;
+  return best;
+}
+
 /* ================================================================ heap model
  * Sec. 2: M blocks of `capacity` object slots, each holding objects of one
  * type; a 64-bit object allocation bitmap per block; block states free,

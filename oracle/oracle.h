@@ -66,6 +66,13 @@ void orc_bm_words(void *b, int level, uint64_t *out);
 int64_t orc_bm_trace(void *b, int64_t *out, int64_t cap);
 int orc_bm_op(void *b, int op, int64_t pos, int64_t *result);
 
+/* --------------------------------------------------- block capacities --- */
+/* Sec. 2: slots per block of type t among ntypes types of sizes[] bytes.  The
+ * smallest type has 64 and fixes the block size (64 of its objects); another
+ * type gets the largest power of two of its objects that fits in that size,
+ * at least 1. */
+int32_t orc_type_capacity(const int32_t *sizes, int32_t ntypes, int32_t t);
+
 /* ---------------------------------------------------------- heap model --- */
 void *orc_heap_new(int32_t num_blocks, int32_t capacity, int32_t num_types);
 void orc_heap_delete(void *h);

@@ -48,7 +48,8 @@ class HeapLayout(ctypes.Structure):
     _fields_ = [("total_bytes", u64), ("data_offset", u64), ("block_stride", u64),
                 ("obj_bitmap_offset", u64), ("block_type_offset", u64), ("bitmaps_offset", u64),
                 ("bitmap_stride", u64), ("num_levels", u32), ("level_word_offset", u32 * 8),
-                ("level_words", u32 * 8), ("field_offset", (u32 * MAX_FIELDS) * MAX_TYPES)]
+                ("level_words", u32 * 8), ("field_offset", (u32 * MAX_FIELDS) * MAX_TYPES),
+                ("type_capacity", u32 * MAX_TYPES)]
 
 
 class Stats(ctypes.Structure):

@@ -77,8 +77,12 @@ def gol_blocks_for(total_cells: int, capacity: int = 64) -> int:
     """Heap size for a Game of Life state: one block per `capacity` cells for
     the Cells and twice as many again for Alive and Candidate objects (at most
     one of them per cell, plus partly filled blocks), rounded up to a power of
-    two."""
-    need = max(64, 3 * -(-total_cells // capacity))
+    two.  Capacity 0 (per-type capacities by object size): Cells {2 x 4 B}
+    have 64 slots, Alive and Candidate {3 x 4 B} 32."""
+    if capacity == 0:
+        need = max(64, -(-total_cells // 64) + 2 * -(-total_cells // 32))
+    else:
+        need = max(64, 3 * -(-total_cells // capacity))
     return 1 << (need - 1).bit_length()
 
 
@@ -173,7 +177,7 @@ class Sugarscape:
         self.side = inp.side
         n = self.side * self.side
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
-        blocks = num_blocks or max(64, 1 << (max(1, -(-n // capacity)) - 1).bit_length())
+        blocks = num_blocks or max(64, 1 << (max(1, -(-n // (capacity or 64))) - 1).bit_length())
         self.heap = Heap(blocks, capacity, SUGAR_TYPE, device=device, stream=self.stream)
         self.lib = self.heap.lib
         nbytes = int(self.lib.dsoar_sugar_bytes(self.side))

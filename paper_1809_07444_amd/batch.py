@@ -24,10 +24,10 @@ NEVER = 0xFFFFFFFF
 
 @dataclass(frozen=True)
 class TuneConfig:
-    capacity: int = 64
+    capacity: int = 64         # slots per block; 0 = per type by object size
     wg_threads: int = 256
     wgs_per_cu: int = 8
-    bulk_min: int = 0          # 0 = block capacity (default policy); NEVER = always active blocks first
+    bulk_min: int = 0          # 0 = whole free blocks first; NEVER = active blocks first (dense)
 
     def apply(self, heap):
         heap.set_launch(self.wg_threads, self.wgs_per_cu)
@@ -35,7 +35,7 @@ class TuneConfig:
 
 
 DEFAULT_SPACE = {
-    "capacity": [64, 32],
+    "capacity": [64, 32, 0],
     "wg_threads": [256, 1024],
     "wgs_per_cu": [2, 4, 8, 16],
     "bulk_min": [0, NEVER],

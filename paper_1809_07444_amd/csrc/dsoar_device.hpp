@@ -64,9 +64,9 @@ struct DevHeap {
   uint64_t* bitmaps;        // (1 + 2T) hierarchical bitmaps, bm_words apart
   uint64_t* ctrl;           // flags + counter shards
   uint64_t block_stride;
-  uint64_t cap_mask;        // low `capacity` bits
+  uint64_t cap_mask[kMaxTypes];  // per type: low `capacity` bits
+  uint32_t capacity[kMaxTypes];  // per type: slots per block, a power of two <= 64
   uint32_t num_blocks;
-  uint32_t capacity;        // 32 or 64
   uint32_t num_types;
   uint32_t nlevels;
   uint32_t bm_words;        // words per bitmap (all levels, padded)
@@ -470,6 +470,15 @@ __device__ __forceinline__ uint32_t obj_block(uint32_t obj) { return obj >> 6; }
 __device__ __forceinline__ uint32_t obj_slot(uint32_t obj) { return obj & 63u; }
 __device__ __forceinline__ uint32_t make_obj(uint32_t block, uint32_t slot) { return (block << 6) | slot; }
 
+// Slots per block and the mask of valid object-bitmap bits of a type (the
+// type must be wave-uniform: read with scalar loads).
+__device__ __forceinline__ uint32_t cap_of(const DevHeap& h, uint32_t type) {
+  return h.capacity[__builtin_amdgcn_readfirstlane(type)];
+}
+__device__ __forceinline__ uint64_t capmask_of(const DevHeap& h, uint32_t type) {
+  return h.cap_mask[__builtin_amdgcn_readfirstlane(type)];
+}
+
 // Address of field `field` of object `obj` of type `type` (SOA: the field's
 // array inside the object's block, indexed by slot).  type and field must be
 // wave-uniform; they are read into scalar registers so that the layout table
@@ -516,7 +525,8 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
   if (n == 0) return;
   const Bitmap active = active_bm(h, type);
   const uint32_t rot = bcast32(hash32((blockIdx.x << 5) ^ (threadIdx.x >> 6) ^ 0x5bd1e995u));
-  const uint32_t c = h.capacity;
+  const uint32_t c = cap_of(h, type);
+  const uint64_t cap = capmask_of(h, type);
   uint32_t start = rot;
   uint32_t served = 0, retries = 0, slow = 0, fails = 0, oom_rounds = 0;
   bool oom = false, active_first = false, none_active = false;
@@ -545,7 +555,7 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
       for (uint32_t j = me; j < cnt_b; j += nact) {
         const uint32_t bid = word * 64 + nth_set_bit(blocks, j);
         meta_store(h.block_type + bid, type);
-        meta_store(h.obj_bitmap + bid, h.cap_mask);
+        meta_store(h.obj_bitmap + bid, cap);
       }
       const Bitmap alloc = allocated_bm(h, type);
       const uint64_t pa = lead_or(alloc.word(0, word), blocks);
@@ -587,7 +597,7 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
         uint64_t my_av = 0;
         if (me < nb) {
           my_bid = (uint32_t)aw * 64 + nth_set_bit(sel, me);
-          if (my_bid < h.num_blocks) my_av = ~load_u64(h.obj_bitmap + my_bid) & h.cap_mask;
+          if (my_bid < h.num_blocks) my_av = ~load_u64(h.obj_bitmap + my_bid) & cap;
         }
         const uint32_t cnt = (uint32_t)__popcll(my_av);
         uint32_t excl = 0;
@@ -599,18 +609,18 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
         if (my_take)
           my_prev = __hip_atomic_fetch_or(h.obj_bitmap + my_bid, my_take, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t my_got = my_take & ~my_prev;
-        const uint64_t my_after = (my_prev | my_take) & h.cap_mask;
+        const uint64_t my_after = (my_prev | my_take) & cap;
         // The reservation that set a block's last free bit takes it out of active.
-        const uint64_t fill_lanes = __ballot(my_take && my_after == h.cap_mask && (my_prev & h.cap_mask) != h.cap_mask);
+        const uint64_t fill_lanes = __ballot(my_take && my_after == cap && (my_prev & cap) != cap);
         if (fill_lanes) bm_clear_bits0(active, (uint32_t)aw, slots_of(fill_lanes, my_bid & 63u));
         if (__ballot(my_got != my_take)) ++retries;
-        const uint64_t room_lanes = __ballot(my_take && my_after != h.cap_mask);
+        const uint64_t room_lanes = __ballot(my_take && my_after != cap);
         if (room_lanes) {
           const uint32_t l = 63u - (uint32_t)__builtin_clzll(room_lanes);
           cur = (int32_t)__builtin_amdgcn_readlane(my_bid, l);
           cur_avail = ~(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(my_after >> 32), l) << 32) |
                         (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)my_after, l)) &
-                      h.cap_mask;
+                      cap;
         }
         // Hand the gained slots out, block by block in rank order.
         uint64_t lanes = __ballot(me < nb);
@@ -650,27 +660,27 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
       }
       ++slow;
       // Fresh block: nobody else can see it until it is marked active.
-      got = want >= c ? h.cap_mask : ((1ull << want) - 1);
+      got = want >= c ? cap : ((1ull << want) - 1);
       if (is_first_active()) {
         meta_store(h.block_type + bid, type);
         meta_store(h.obj_bitmap + bid, got);
       }
       bm_set(allocated_bm(h, type), (uint32_t)bid);
-      if (got != h.cap_mask) {
+      if (got != cap) {
         bm_set(active, (uint32_t)bid);
         cur = bid;
-        cur_avail = ~got & h.cap_mask;
+        cur_avail = ~got & cap;
       }
     } else {
       const uint64_t take = take_from(avail, want < (uint32_t)__popcll(avail) ? want : (uint32_t)__popcll(avail),
                                       rot & (c - 1));
       const uint64_t prev = lead_or(h.obj_bitmap + bid, take);
       got = take & ~prev;
-      const uint64_t after = (prev | take) & h.cap_mask;
-      if (after == h.cap_mask && (prev & h.cap_mask) != h.cap_mask) bm_clear(active, (uint32_t)bid);
-      if (after != h.cap_mask) {
+      const uint64_t after = (prev | take) & cap;
+      if (after == cap && (prev & cap) != cap) bm_clear(active, (uint32_t)bid);
+      if (after != cap) {
         cur = bid;  // still has room: the next pass can use it without a lookup
-        cur_avail = ~after & h.cap_mask;
+        cur_avail = ~after & cap;
       }
       if (got != take) ++retries;
       if (got == 0) {
@@ -717,7 +727,8 @@ __device__ inline uint32_t delete_mask(const DevHeap& h, uint32_t type, uint32_t
   const uint64_t prev = lead_and(h.obj_bitmap + bid, ~mask);
   if ((prev & mask) != mask) lead_flag(h.ctrl + kCtlDoubleFree);
   const uint64_t removed = prev & mask;
-  if (removed && (prev & h.cap_mask) == h.cap_mask) bm_set(active_bm(h, type), bid);
+  const uint64_t cap = capmask_of(h, type);
+  if (removed && (prev & cap) == cap) bm_set(active_bm(h, type), bid);
   return (uint32_t)__popcll(removed);
 }
 

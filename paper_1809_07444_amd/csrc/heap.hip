@@ -34,7 +34,7 @@ uint32_t level_word_offset_host(uint32_t nbits, uint32_t l) {
 bool desc_valid(const dsoar_heap_desc* d) {
   if (!d || d->reserved != 0) return false;
   if (d->num_blocks < 1 || d->num_blocks > (1u << 26)) return false;
-  if (d->block_capacity != 32 && d->block_capacity != 64) return false;
+  if (d->block_capacity != 0 && d->block_capacity != 32 && d->block_capacity != 64) return false;
   if (d->num_types < 1 || d->num_types > DSOAR_MAX_TYPES) return false;
   for (uint32_t t = 0; t < d->num_types; ++t) {
     const dsoar_type_layout& L = d->types[t];
@@ -45,10 +45,34 @@ bool desc_valid(const dsoar_heap_desc* d) {
   return true;
 }
 
+// Slots per block of each type.  A fixed block capacity (32 or 64) applies to
+// every type.  Capacity 0 asks for the byte-size rule of Sec. 2: the smallest
+// type has 64 slots and fixes the block size, 64 times its object size; a
+// larger type gets the largest power of two of slots that fits that size.
+void type_capacities(const dsoar_heap_desc* d, uint32_t* cap) {
+  uint64_t smin = ~0ull, size[DSOAR_MAX_TYPES] = {0};
+  for (uint32_t t = 0; t < d->num_types; ++t) {
+    for (uint32_t f = 0; f < d->types[t].num_fields; ++f) size[t] += d->types[t].field_bytes[f];
+    smin = std::min(smin, size[t]);
+  }
+  for (uint32_t t = 0; t < d->num_types; ++t) {
+    if (d->block_capacity) {
+      cap[t] = d->block_capacity;
+      continue;
+    }
+    uint32_t c = 64;
+    while (c > 1 && (uint64_t)c * size[t] > 64 * smin) c >>= 1;
+    cap[t] = c;
+  }
+}
+
 // Computes the layout of a heap in one caller buffer.  Block b's data segment
-// holds, for its type, one SOA array per field (Sec. 2), each array padded to
-// 128 bytes (Sec. 2 "Coalesced Access"); every block has the size of the
-// widest type's segment so all blocks are equal in bytes.
+// holds, for its type, one SOA array per field (Sec. 2).  With a fixed
+// capacity each array is padded to 128 bytes (Sec. 2 "Coalesced Access") and
+// every block has the size of the widest type's segment.  With per-type
+// capacities the arrays of a type are packed largest first (their sizes are
+// powers of two, so each stays aligned to its own size, or to 128 bytes) and
+// the block size is that of the smallest type's 64 objects.
 struct Plan {
   dsoar_heap_layout L;
   uint64_t ctrl_off, stats_off;
@@ -60,13 +84,25 @@ struct Plan {
 Plan make_plan(const dsoar_heap_desc* d) {
   Plan p;
   memset(&p, 0, sizeof(p));
-  const uint64_t M = d->num_blocks, c = d->block_capacity;
+  const uint64_t M = d->num_blocks;
+  type_capacities(d, p.L.type_capacity);
   uint64_t stride = 0;
   for (uint32_t t = 0; t < d->num_types; ++t) {
+    const uint64_t c = p.L.type_capacity[t];
+    const uint32_t nf = d->types[t].num_fields;
     uint64_t off = 0;
-    for (uint32_t f = 0; f < d->types[t].num_fields; ++f) {
-      p.L.field_offset[t][f] = (uint32_t)off;
-      off += align_up(c * d->types[t].field_bytes[f], 128);
+    if (d->block_capacity) {
+      for (uint32_t f = 0; f < nf; ++f) {
+        p.L.field_offset[t][f] = (uint32_t)off;
+        off += align_up(c * d->types[t].field_bytes[f], 128);
+      }
+    } else {
+      for (uint32_t w = 8; w >= 4; w -= 4)  // 8-byte fields first, then 4-byte ones
+        for (uint32_t f = 0; f < nf; ++f)
+          if (d->types[t].field_bytes[f] == w) {
+            p.L.field_offset[t][f] = (uint32_t)off;
+            off += c * w;
+          }
     }
     stride = std::max(stride, off);
   }
@@ -361,11 +397,12 @@ __global__ void stats_kernel(DevHeap h, StatsOut* out, int check) {
     const bool in = b < h.num_blocks;
     const uint32_t t = in ? meta_load(h.block_type + b) : kTypeNone;
     const uint64_t ob = in ? meta_load(h.obj_bitmap + b) : 0;
-    const uint64_t obc = ob & h.cap_mask;
+    const uint64_t cm = t < h.num_types ? h.cap_mask[t] : ~0ull;  // this block's type's slots
+    const uint64_t obc = ob & cm;
     const bool fr = (load_u64(free_bm(h).word(0, word)) >> lane) & 1ull;
     uint32_t v[DSOAR_INV_COUNT] = {0};
     if (in) {
-      v[DSOAR_INV_BITMAP_RANGE] += (ob & ~h.cap_mask) != 0;
+      v[DSOAR_INV_BITMAP_RANGE] += (ob & ~cm) != 0;
       v[DSOAR_INV_FREE] += fr != (t == kTypeNone && obc == 0);
       if (t != kTypeNone && t >= h.num_types) v[DSOAR_INV_FREE] += 1;
     }
@@ -374,7 +411,7 @@ __global__ void stats_kernel(DevHeap h, StatsOut* out, int check) {
       const bool ac = (load_u64(active_bm(h, u).word(0, word)) >> lane) & 1ull;
       if (in) {
         v[DSOAR_INV_ALLOCATED] += al != (t == u && obc != 0);
-        v[DSOAR_INV_ACTIVE] += ac != (al && obc != h.cap_mask);
+        v[DSOAR_INV_ACTIVE] += ac != (al && obc != cm);
         v[DSOAR_INV_ACTIVE_IMPLIES_ALLOCATED] += ac && !al;
         v[DSOAR_INV_FREE] += (al || ac) && fr;
       } else {
@@ -651,8 +688,11 @@ int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_byt
   d.bitmaps = (uint64_t*)(h->base + p.L.bitmaps_offset);
   d.ctrl = (uint64_t*)(h->base + p.ctrl_off);
   d.block_stride = p.L.block_stride;
-  d.capacity = desc->block_capacity;
-  d.cap_mask = desc->block_capacity == 64 ? ~0ull : ((1ull << desc->block_capacity) - 1);
+  for (uint32_t t = 0; t < kMaxTypes; ++t) {
+    const uint32_t c = t < desc->num_types ? p.L.type_capacity[t] : 64u;
+    d.capacity[t] = c;
+    d.cap_mask[t] = c == 64 ? ~0ull : ((1ull << c) - 1);
+  }
   d.num_blocks = desc->num_blocks;
   d.num_types = desc->num_types;
   d.nlevels = p.L.num_levels;
@@ -782,7 +822,7 @@ int dsoar_heap_set_launch(dsoar_heap* h, uint32_t wg_threads, uint32_t wgs_per_c
 
 int dsoar_heap_set_policy(dsoar_heap* h, uint32_t bulk_min) {
   if (!heap_ok(h)) return DSOAR_ERR_INVALID_ARG;
-  h->dev.bulk_min = bulk_min < h->desc.block_capacity ? h->desc.block_capacity : bulk_min;
+  h->dev.bulk_min = bulk_min;  // below a type's capacity it acts as that capacity
   h->config_epoch++;
   return DSOAR_OK;
 }

@@ -167,6 +167,7 @@ __device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, c
                                               uint32_t& freed) {
   const uint32_t lane = lane_id();
   const uint32_t stride = nw * U;
+  constexpr uint64_t kFull64 = ~0ull;  // capacity 64: every bit is a slot
   uint32_t rl;
   uint64_t sl;
   auto fetch = [&](uint32_t e) {
@@ -232,13 +233,13 @@ __device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, c
       // without a return value instead of merging it with the second.
 #pragma unroll
       for (uint32_t u = 0; u < U; ++u)
-        if (dm[u] && p.snap[u] == h.cap_mask && leader)
+        if (dm[u] && p.snap[u] == kFull64 && leader)
           __hip_atomic_fetch_and(h.obj_bitmap + p.bid[u], ~dm[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       uint64_t prev[U];
 #pragma unroll
       for (uint32_t u = 0; u < U; ++u) {
         prev[u] = 0;
-        if (dm[u] && p.snap[u] != h.cap_mask && leader)
+        if (dm[u] && p.snap[u] != kFull64 && leader)
           prev[u] = __hip_atomic_fetch_and(h.obj_bitmap + p.bid[u], ~dm[u], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -247,11 +248,11 @@ __device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, c
 #pragma unroll
       for (uint32_t u = 0; u < U; ++u) {
         if (!dm[u]) continue;
-        const uint64_t pv = p.snap[u] == h.cap_mask ? h.cap_mask : bcast64(prev[u]);
+        const uint64_t pv = p.snap[u] == kFull64 ? kFull64 : bcast64(prev[u]);
         if ((pv & dm[u]) != dm[u]) lead_flag(h.ctrl + kCtlDoubleFree);
         const uint64_t removed = pv & dm[u];
         freed += (uint32_t)__popcll(removed);
-        if (removed && (pv & h.cap_mask) == h.cap_mask) {
+        if (removed && (pv & kFull64) == kFull64) {
           const uint32_t w = p.bid[u] >> 6;
           if (w != act_word) {
             if (act_bits) bm_set_bits0(act, act_word, act_bits);
@@ -318,9 +319,10 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
   const uint32_t count = bcast32(*count_ptr);
   uint32_t visits = 0, freed = 0;
   bool done = false;
+  const uint32_t c = cap_of(h, type);
   if constexpr (HasSplit<Method>::value) {
     // Several blocks per pass only when every wavefront gets that many.
-    if (h.capacity == 64 && h.doall_unroll > 1 && count >= nw * h.doall_unroll) {
+    if (c == 64 && h.doall_unroll > 1 && count >= nw * h.doall_unroll) {
       if (h.doall_unroll >= 8)
         doall_split64<Method, 8>(h, type, R, S, count, gw, nw, args, visits, freed);
       else if (h.doall_unroll >= 4)
@@ -331,7 +333,7 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
     }
   }
   if (done) {
-  } else if (h.capacity == 64) {
+  } else if (c == 64) {
     for (uint32_t e = gw; e < count; e += nw) {
       const uint32_t bid = R[e];
       const uint64_t snap = S[e];
@@ -342,9 +344,13 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
       if (dm) freed += delete_mask(h, type, bid, dm);
     }
   } else {
-    const uint32_t half = lane >> 5, slot = lane & 31u;
-    for (uint32_t e0 = 2 * gw; e0 < count; e0 += 2 * nw) {
-      const uint32_t e = e0 + half;
+    // 64 / c blocks per wavefront: lane l handles slot l % c of entry
+    // e0 + l / c (Fig. 4 with blocks smaller than a wavefront).
+    const uint32_t bpw = 64u / c, sh = (uint32_t)__builtin_ctz(c);
+    const uint32_t sub = lane >> sh, slot = lane & (c - 1u);
+    const uint64_t group = c == 64 ? ~0ull : ((1ull << c) - 1ull);
+    for (uint32_t e0 = bpw * gw; e0 < count; e0 += bpw * nw) {
+      const uint32_t e = e0 + sub;
       const bool valid = e < count;
       const uint32_t bid = valid ? R[e] : 0u;
       const uint64_t snap = valid ? S[e] : 0ull;
@@ -352,8 +358,10 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
       bool del = false;
       if ((snap >> slot) & 1ull) del = run_method<Method>(h, type, make_obj(bid, slot), args);
       const uint64_t dm = __ballot(del);
-      if (dm & 0xFFFFFFFFull) freed += delete_mask(h, type, __builtin_amdgcn_readlane(bid, 0), dm & 0xFFFFFFFFull);
-      if (dm >> 32) freed += delete_mask(h, type, __builtin_amdgcn_readlane(bid, 32), dm >> 32);
+      for (uint32_t k = 0; k < bpw && dm; ++k) {
+        const uint64_t part = (dm >> (k * c)) & group;
+        if (part) freed += delete_mask(h, type, (uint32_t)__builtin_amdgcn_readlane(bid, k * c), part);
+      }
     }
   }
   if (visits) lead_add(shard(h) + kCntVisits + type, visits);
@@ -377,7 +385,7 @@ int launch_doall(dsoar_heap* h, uint32_t type, const typename Method::Args& args
     int rc = read_count(h, type, s, &count);
     if (rc) return rc;
     if (count == 0) return DSOAR_OK;
-    const uint32_t per_wave = 64 / h->desc.block_capacity;
+    const uint32_t per_wave = 64 / h->dev.capacity[type];
     const uint64_t waves = (count + per_wave - 1) / per_wave;
     grid = (uint32_t)((waves * 64 + threads - 1) / threads);
   } else {

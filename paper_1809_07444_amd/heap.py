@@ -100,6 +100,12 @@ class Heap:
         return {C.KIND_NAMES.get(int(kinds[i]), str(int(kinds[i]))): (int(counts[i]), float(ms[i]))
                 for i in range(n.value)}
 
+    @property
+    def type_capacity(self) -> list:
+        """Slots per block of each type (the byte-size rule when capacity is 0)."""
+        L = self.layout()
+        return list(L.type_capacity[:len(self.types)])
+
     def layout(self) -> C.HeapLayout:
         L = C.HeapLayout()
         C.check(self.lib.dsoar_heap_get_layout(self.h, ctypes.byref(L)), "dsoar_heap_get_layout")
