@@ -93,6 +93,8 @@ def lib() -> ctypes.CDLL:
         L.orc_gol_run.argtypes = [i32, i32, i32, vp, vp]
         L.orc_sugar_run.restype = ctypes.c_int
         L.orc_sugar_run.argtypes = [i32, i32, i32, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_traffic_run.restype = ctypes.c_int
+        L.orc_traffic_run.argtypes = [i32, i32, i32, i32, u64, i32, ctypes.c_uint32, ctypes.c_uint32, vp, vp]
         _lib = L
     return _lib
 
@@ -315,3 +317,23 @@ def sugar_run(state: SugarState, steps: int, seed: int, rules: dict, step0: int 
         raise ValueError("sugar_run: bad arguments")
     s.births, s.deaths, s.moves = (int(c) for c in counts)
     return s
+
+
+@dataclass
+class TrafficResult:
+    vel: np.ndarray      # int32 [roads, length], -1 = empty
+    entries: int
+    exits: int
+
+
+def traffic_run(vel: np.ndarray, steps: int, seed: int, rules: dict, step0: int = 0) -> TrafficResult:
+    """Nagel-Schreckenberg traffic (open roads) from the speed grid `vel`."""
+    v = np.ascontiguousarray(vel, dtype=np.int32).copy()
+    counts = np.zeros(2, dtype=np.int64)
+    roads, length = v.shape
+    rc = lib().orc_traffic_run(roads, length, steps, step0, seed, rules["vmax"], rules["p_slow24"],
+                               rules["p_in24"], _p(v), _p(counts))
+    if rc != 0:
+        raise ValueError("orc_traffic_run failed")
+    return TrafficResult(v, int(counts[0]), int(counts[1]))
+

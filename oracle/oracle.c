@@ -645,3 +645,61 @@ int orc_sugar_run(int32_t side, int32_t steps, int32_t step0, uint64_t seed,
   free(snap);
   return 0;
 }
+
+/* =============================================================== traffic
+ * Nagel-Schreckenberg cellular traffic (the paper's "traffic" application
+ * names the model; its rules are the published ones), on open single-lane
+ * roads.  One step t, for every car at cell i of road r with speed v, all
+ * decisions taken on the state at the start of the step:
+ *  1 accelerate: v = min(v + 1, vmax);
+ *  2 brake: v = min(v, gap), gap = the empty cells directly ahead of the car
+ *    (cells past the road's end count as empty: the exit);
+ *  3 dawdle: if v > 0 and Bernoulli(p_slow) from hash(seed, 32, r*length + i, t),
+ *    v = v - 1;
+ *  4 move: the car advances v cells; one that passes the last cell leaves.
+ * Then on every road whose first cell is empty, a car enters there at speed 0
+ * when Bernoulli(p_in) from hash(seed, 33, r, t).
+ * Moves never collide: a car ends before the old cell of the car ahead. */
+
+#define TRAFFIC_STREAM_SLOW 32
+#define TRAFFIC_STREAM_IN 33
+
+int orc_traffic_run(int32_t roads, int32_t length, int32_t steps, int32_t step0, uint64_t seed,
+                    int32_t vmax, uint32_t p_slow24, uint32_t p_in24, int32_t *vel, int64_t *counts) {
+  if (roads < 1 || length < 1 || steps < 0 || vmax < 1) return -1;
+  const int64_t n = (int64_t)roads * length;
+  int32_t *next = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  if (!next) return -1;
+  for (int32_t s = 0; s < steps; s++) {
+    const uint64_t t = (uint64_t)(step0 + s);
+    for (int64_t c = 0; c < n; c++) next[c] = -1;
+    for (int32_t r = 0; r < roads; r++) {
+      const int32_t *road = vel + (int64_t)r * length;
+      for (int32_t i = 0; i < length; i++) {
+        if (road[i] < 0) continue;
+        int32_t v = road[i] + 1 < vmax ? road[i] + 1 : vmax;
+        int32_t gap = 0;
+        while (gap < v && (i + gap + 1 >= length || road[i + gap + 1] < 0)) gap++;
+        if (gap < v) v = gap;
+        const uint64_t h = orc_hash(seed, TRAFFIC_STREAM_SLOW, (uint64_t)r * (uint64_t)length + (uint64_t)i, t);
+        if (v > 0 && (uint32_t)(h >> 40) < p_slow24) v--;
+        if (i + v >= length) {
+          counts[1]++;
+        } else {
+          next[(int64_t)r * length + i + v] = v;
+        }
+      }
+    }
+    for (int32_t r = 0; r < roads; r++) {
+      const uint64_t h = orc_hash(seed, TRAFFIC_STREAM_IN, (uint64_t)r, t);
+      if (next[(int64_t)r * length] < 0 && (uint32_t)(h >> 40) < p_in24) {
+        next[(int64_t)r * length] = 0;
+        counts[0]++;
+      }
+    }
+    memcpy(vel, next, (size_t)n * sizeof(int32_t));
+  }
+  free(next);
+  return 0;
+}
+

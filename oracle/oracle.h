@@ -114,4 +114,13 @@ int orc_sugar_run(int32_t side, int32_t steps, int32_t step0, uint64_t seed,
 #ifdef __cplusplus
 }
 #endif
+
+/* ----------------------------------------------------------- traffic ----- */
+/* Nagel-Schreckenberg traffic on `roads` open roads of `length` cells, for
+ * `steps` steps starting at step index step0.  vel[r*length + i] is the speed
+ * of the car in cell i of road r, or -1 for an empty cell (updated in place).
+ * counts[0] += cars that entered, counts[1] += cars that left. */
+int orc_traffic_run(int32_t roads, int32_t length, int32_t steps, int32_t step0, uint64_t seed,
+                    int32_t vmax, uint32_t p_slow24, uint32_t p_in24, int32_t *vel, int64_t *counts);
+
 #endif

@@ -46,6 +46,10 @@ S_WORLD_SEED = 13
 S_WORLD_KIND = 14
 S_EPISODE = 15
 S_MICRO_V0 = 16  # 16..27: the twelve Irwin-Hall sub-streams
+S_TRAFFIC_OCC = 30
+S_TRAFFIC_V0 = 31
+S_TRAFFIC_SLOW = 32   # drawn by the method itself, each step (both sides implement hash)
+S_TRAFFIC_IN = 33     # idem
 
 DEFAULT_SEED = 24301
 BERNOULLI_0_1 = 1677721  # floor(0.1 * 2**24)

@@ -176,3 +176,31 @@ def episode_inputs(ep: EpisodeSpec):
     if ep.kind == "gol":
         return gol_grid(ep.side, ep.side, seed=ep.seed)
     return sugar_inputs(ep.side, ep.agents, seed=ep.seed)
+
+
+# ---------------------------------------------------------------- traffic --
+
+# Nagel-Schreckenberg constants: top speed, slowdown and entry probabilities
+# as 24-bit Bernoulli thresholds.
+TRAFFIC_RULES = dict(vmax=5, p_slow24=1 << 22, p_in24=1 << 23)  # p_slow 0.25, p_in 0.5
+TRAFFIC_DENSITY24 = 2516582  # floor(0.15 * 2**24)
+
+
+@dataclass
+class TrafficInputs:
+    roads: int
+    length: int
+    seed: int
+    vel: np.ndarray   # int32 [roads, length]: a car's speed, -1 = empty cell
+
+
+def traffic_inputs(roads: int = 1024, length: int = 1024, seed: int = rng.DEFAULT_SEED,
+                   density24: int = TRAFFIC_DENSITY24, vmax: int = 5) -> TrafficInputs:
+    """Roads of `length` cells; cell (r, i) holds a car with probability
+    density24 / 2**24 and the car's speed is U{0..vmax}."""
+    r = np.arange(roads, dtype=np.uint64)[:, None]
+    i = np.arange(length, dtype=np.uint64)[None, :]
+    occ = rng.bernoulli(rng.hash4(seed, rng.S_TRAFFIC_OCC, r, i), density24)
+    v0 = rng.uniform_int(rng.hash4(seed, rng.S_TRAFFIC_V0, r, i), 0, vmax)
+    vel = np.where(occ, v0, -1).astype(np.int32)
+    return TrafficInputs(roads, length, seed, np.ascontiguousarray(vel))
