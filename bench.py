@@ -32,7 +32,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="gol",
-                   choices=["gol", "micro", "micro_scaled", "batched", "sugarscape", "serve"])
+                   choices=["gol", "micro", "micro_scaled", "batched", "sugarscape", "traffic", "serve"])
     p.add_argument("--episodes", type=int, default=200, help="serve: episodes per arrival rate")
     p.add_argument("--rates", default="0.25,0.5,0.75,0.9,1.1",
                    help="serve: arrival rates as fractions of the measured capacity")
@@ -323,6 +323,63 @@ class SugarWorkload(GolWorkload):
                           f"{self.steps} steps, {dt:.1f} s; births+deaths / oracle time"}
 
 
+class TrafficWorkload(GolWorkload):
+    name = "traffic"
+
+    def __init__(self, args):
+        import torch
+        from paper_1809_07444_amd import _capi as C
+        from paper_1809_07444_amd import apps
+        from synth import workloads as W
+        self.C, self.torch = C, torch
+        self.roads, self.length, self.steps = 1024, 1024, 500
+        self.inp = W.traffic_inputs(self.roads, self.length, seed=args.seed)
+        self.rules = W.TRAFFIC_RULES
+        self.sim = apps.Traffic(self.inp, self.rules)
+        self.flags = C.DO_PERSISTENT | (0 if args.no_graph else C.GRAPH)
+        self.M = self.sim.heap.num_blocks
+        self.config = {"workload": f"traffic-{self.roads}roads-{self.length}cells-density0.15-{self.steps}steps",
+                       "roads": self.roads, "cells": self.roads * self.length, "steps": self.steps,
+                       "heap_blocks": self.M, "block_capacity": 64, "graph": not args.no_graph, "seed": args.seed,
+                       "rules": self.rules}
+
+    def step(self):
+        self.sim.init()
+        self.sim.step(self.steps, self.flags)
+
+    def profiled_step(self):
+        self.sim.init()
+        self.sim.step(self.steps, self.C.DO_PERSISTENT)
+
+    def stats(self):
+        return self.sim.heap.stats()
+
+    def heap(self):
+        return self.sim.heap
+
+    def kernel_bytes(self, kind, launches, st):
+        v = st["visits"][0] / 2  # two do-alls per step visit every car
+        # Decide: cell, speed read, next speed written, up to vmax cells ahead
+        # read; Drive: next speed and cell read, speed and cell written, two
+        # road cells written.
+        per = {"traffic_decide": 12 + 4 * self.rules["vmax"], "traffic_drive": 8 + 8 + 8}
+        if kind in per:
+            return v * per[kind] + v / 64 * 12
+        if kind == "enumerate":
+            return launches * (self.M / 8) + v / 64 * 20
+        return None
+
+    def cpu_baseline(self):
+        import oracle
+        t0 = time.perf_counter()
+        r = oracle.traffic_run(self.inp.vel, self.steps, self.inp.seed, self.rules)
+        dt = time.perf_counter() - t0
+        ops = int((self.inp.vel >= 0).sum()) + r.entries + r.exits
+        return {"value": ops / dt, "unit": "allocs+frees/s", "cores": 1, "kind": "oracle",
+                "sample": f"sequential Nagel-Schreckenberg oracle, full {self.roads}x{self.length} roads, "
+                          f"{self.steps} steps, {dt:.2f} s; initial cars + entries + exits / oracle time"}
+
+
 def serve_bench(args):
     import torch
     from paper_1809_07444_amd import serve
@@ -376,6 +433,8 @@ def main():
         wl = BatchedWorkload(args)
     elif args.workload == "sugarscape":
         wl = SugarWorkload(args)
+    elif args.workload == "traffic":
+        wl = TrafficWorkload(args)
     else:
         wl = MicroWorkload(args, scaled=args.workload == "micro_scaled")
 

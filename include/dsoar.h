@@ -419,6 +419,40 @@ int dsoar_sugar_read(dsoar_sugar* sugar, int32_t* sugar_dev, uint8_t* occ_dev, i
                      int32_t* a_metab_dev, int32_t* a_vision_dev, int32_t* a_age_dev, uint32_t* moves,
                      void* stream);
 
+/* ------------------------------------------------------------------ traffic
+ * Nagel-Schreckenberg traffic (the paper's "traffic" application, Fig. 6) on
+ * `roads` open single-lane roads of `length` cells: Car objects {cell, speed,
+ * next speed} (type 0 of the heap: at least three 4-byte fields) advance by
+ * the model's rules; cars enter at a road's first cell and are deleted when
+ * they pass its last cell.  Per step: a do-all decides every car's speed
+ * (accelerate, brake to the empty cells ahead, dawdle with probability
+ * p_slow24 / 2^24 from hash(seed, 32, cell, t)), a second do-all moves the
+ * cars, then a car enters each empty first cell with probability p_in24 /
+ * 2^24 from hash(seed, 33, road, t) (the hash of the workload generator). */
+typedef struct dsoar_traffic dsoar_traffic;
+typedef struct {
+  int32_t vmax;      /* top speed, 1 .. 8 */
+  uint32_t p_slow24; /* dawdling probability * 2^24 (<= 2^24) */
+  uint32_t p_in24;   /* entry probability * 2^24 (<= 2^24) */
+  uint32_t reserved;
+  uint64_t seed;
+} dsoar_traffic_rules;
+/* Device bytes for the road state (0 if roads * length is 0 or above 2^30). */
+size_t dsoar_traffic_bytes(uint32_t roads, uint32_t length);
+/* dev_mem: caller-owned, 256-byte aligned, at least dsoar_traffic_bytes. */
+int dsoar_traffic_create(dsoar_heap* heap, uint32_t roads, uint32_t length, const dsoar_traffic_rules* rules,
+                         void* dev_mem, size_t dev_bytes, dsoar_traffic** out);
+int dsoar_traffic_destroy(dsoar_traffic* traffic);
+/* Initial state: vel_dev[r*length + i] (int32, device) is the speed (0 ..
+ * vmax) of the car in cell i of road r, or -1 for an empty cell.  step0 keys
+ * the random draws of the first step.  The heap should be freshly reset. */
+int dsoar_traffic_init(dsoar_traffic* traffic, const int32_t* vel_dev, uint32_t step0, void* stream);
+/* Advances `steps` steps.  flags: DSOAR_DO_PLAIN or DSOAR_DO_PERSISTENT,
+ * optionally | DSOAR_GRAPH (persistent only). */
+int dsoar_traffic_step(dsoar_traffic* traffic, uint32_t steps, uint32_t flags, void* stream);
+/* Speed per cell (-1 = empty) into vel_dev (int32, roads*length, device). */
+int dsoar_traffic_read(dsoar_traffic* traffic, int32_t* vel_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -226,3 +226,61 @@ class Sugarscape:
 
     def synchronize(self):
         self.stream.synchronize()
+
+
+# ---------------------------------------------------------------- traffic --
+
+TRAFFIC_TYPE = [(4, 4, 4)]  # Car {cell, speed, next speed}
+
+
+class Traffic:
+    """Nagel-Schreckenberg traffic on open roads, Car objects in a device heap."""
+
+    def __init__(self, inp, rules: dict, capacity: int = 64, num_blocks: int | None = None, stream=None,
+                 device="cuda"):
+        self.roads, self.length = inp.roads, inp.length
+        n = self.roads * self.length
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        # At most one car per cell, plus partly filled blocks.
+        blocks = num_blocks or max(64, 1 << (2 * -(-n // (capacity or 64)) - 1).bit_length())
+        self.heap = Heap(blocks, capacity, TRAFFIC_TYPE, device=device, stream=self.stream)
+        self.lib = self.heap.lib
+        nbytes = int(self.lib.dsoar_traffic_bytes(self.roads, self.length))
+        if nbytes == 0:
+            raise ValueError("bad road size")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.rules = C.TrafficRules(rules["vmax"], rules["p_slow24"], rules["p_in24"], 0, int(inp.seed))
+        with torch.cuda.stream(self.stream):
+            self.vel0 = torch.from_numpy(np.ascontiguousarray(inp.vel, dtype=np.int32).ravel()).to(device)
+            self.out = torch.empty(n, dtype=torch.int32, device=device)
+        t = ctypes.c_void_p()
+        C.check(self.lib.dsoar_traffic_create(self.heap.h, self.roads, self.length, ctypes.byref(self.rules),
+                                              self.buf.data_ptr(), nbytes, ctypes.byref(t)), "dsoar_traffic_create")
+        self.t = t
+
+    def close(self):
+        if getattr(self, "t", None):
+            self.lib.dsoar_traffic_destroy(self.t)
+            self.t = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, step0: int = 0):
+        self.heap.reset()
+        C.check(self.lib.dsoar_traffic_init(self.t, self.vel0.data_ptr(), step0, self.heap._s()),
+                "dsoar_traffic_init")
+
+    def step(self, steps: int, flags: int = C.DO_PERSISTENT):
+        C.check(self.lib.dsoar_traffic_step(self.t, steps, flags, self.heap._s()), "dsoar_traffic_step")
+
+    def read(self) -> np.ndarray:
+        C.check(self.lib.dsoar_traffic_read(self.t, self.out.data_ptr(), self.heap._s()), "dsoar_traffic_read")
+        self.stream.synchronize()
+        return self.out.cpu().numpy().reshape(self.roads, self.length)
+
+    def synchronize(self):
+        self.stream.synchronize()
