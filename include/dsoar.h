@@ -87,7 +87,8 @@ typedef struct {
                                  b*block_stride + field_offset[t][f] + slot*width */
   uint64_t block_stride;
   uint64_t obj_bitmap_offset; /* uint64 per block: bit s = slot s allocated */
-  uint64_t block_type_offset; /* uint32 per block: type, 0xFFFFFFFF = none */
+  uint64_t block_type_offset; /* uint32 per block: type in the low 8 bits (0xFF =
+                                 free), times the block was freed above them */
   uint64_t bitmaps_offset;    /* (1 + 2*num_types) hierarchical bitmaps:
                                  0 = free, 1+2t = allocated[t], 2+2t = active[t] */
   uint64_t bitmap_stride;     /* bytes between consecutive bitmaps */
@@ -111,6 +112,7 @@ typedef struct {
   uint64_t slow_paths;                    /* free blocks taken (Alg. 1 slow path) */
   uint64_t find_fails;                    /* try_find_set FAILs on active[T] */
   uint64_t method_atomics;                /* atomic RMWs do-all methods issued on their own data */
+  uint64_t online_releases;               /* blocks freed by the delete that emptied them */
   uint32_t free_blocks;
   uint32_t num_blocks;
   uint32_t oom;                           /* sticky flags */
@@ -165,6 +167,15 @@ int dsoar_heap_set_launch(dsoar_heap* heap, uint32_t wg_threads, uint32_t wgs_pe
  * more partially filled blocks).  Values below the block capacity mean the
  * capacity. */
 int dsoar_heap_set_policy(dsoar_heap* heap, uint32_t bulk_min);
+
+/* Block reclamation.  By default (online = 0) a block emptied by deletes
+ * stays allocated to its type until the next enumeration of that type or
+ * dsoar_reclaim returns it to the free bitmap, at a point where no kernel of
+ * the heap runs.  With online = 1 the delete that empties a block frees it at
+ * once (Sec. 2 block states: free = holds no object), so other types can take
+ * it within the same kernel; allocations then pin a block while reserving in
+ * it (two more atomics per reservation).  Results do not depend on it. */
+int dsoar_heap_set_reclaim(dsoar_heap* heap, int online);
 
 /* Blocks per wavefront pass for do-all methods that split into a load phase
  * and an apply phase (at block capacity 64): 1, 2, 4 (the default) or 8.  The
@@ -254,6 +265,16 @@ int dsoar_heap_check(dsoar_heap* heap, uint32_t* violations, void* stream);
  * objs_dev[i] (DSOAR_NULL entries are skipped). */
 int dsoar_alloc_n(dsoar_heap* heap, uint32_t type, uint32_t n, dsoar_obj* out_dev, void* stream);
 int dsoar_free_n(dsoar_heap* heap, const dsoar_obj* objs_dev, uint32_t n, void* stream);
+
+/* Concurrency stress of new/delete (tests): n lanes run `rounds` rounds; in
+ * round r each wavefront creates one object per lane of type (spread *
+ * wavefront + r) mod num_types, writes the handle into the object's field 0 (4 bytes in
+ * every type), and deletes it at once unless a hash of (seed, lane, round)
+ * is 0 mod keep; kept handles go to out_dev[lane * rounds + r] (DSOAR_NULL
+ * otherwise).  errors_dev[0] (device, zeroed by the caller) counts fields
+ * found overwritten, i.e. slots handed out twice. */
+int dsoar_stress_churn(dsoar_heap* heap, uint32_t n, uint32_t rounds, uint32_t keep, uint32_t spread,
+                       uint32_t seed, dsoar_obj* out_dev, uint32_t* errors_dev, void* stream);
 
 /* Copies a 4-byte field of n objects to/from a dense device array. */
 int dsoar_field_read(dsoar_heap* heap, uint32_t type, uint32_t field, const dsoar_obj* objs_dev,

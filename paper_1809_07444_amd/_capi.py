@@ -58,7 +58,7 @@ class Stats(ctypes.Structure):
                 ("visits", u64 * MAX_TYPES),
                 ("allocated_blocks", u32 * MAX_TYPES), ("active_blocks", u32 * MAX_TYPES),
                 ("typed_blocks", u32 * MAX_TYPES), ("reserve_retries", u64), ("slow_paths", u64),
-                ("find_fails", u64), ("method_atomics", u64), ("free_blocks", u32), ("num_blocks", u32), ("oom", u32),
+                ("find_fails", u64), ("method_atomics", u64), ("online_releases", u64), ("free_blocks", u32), ("num_blocks", u32), ("oom", u32),
                 ("retry_limit_hit", u32), ("double_free", u32), ("reserved", u32)]
 
 
@@ -95,6 +95,8 @@ SIGNATURES = {
     "dsoar_heap_set_launch": (ctypes.c_int, [H, u32, u32]),
     "dsoar_heap_set_policy": (ctypes.c_int, [H, u32]),
     "dsoar_heap_set_unroll": (ctypes.c_int, [H, u32]),
+    "dsoar_heap_set_reclaim": (ctypes.c_int, [H, ctypes.c_int]),
+    "dsoar_stress_churn": (ctypes.c_int, [H, u32, u32, u32, u32, u32, vp, vp, vp]),
     "dsoar_last_hip_error": (ctypes.c_int, [H]),
     "dsoar_heap_set_timing": (ctypes.c_int, [H, ctypes.c_int]),
     "dsoar_heap_timing": (ctypes.c_int, [H, vp, vp, vp, u32, ctypes.POINTER(u32)]),

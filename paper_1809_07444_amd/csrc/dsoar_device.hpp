@@ -31,7 +31,9 @@ constexpr uint32_t kMaxTypes = 8;
 constexpr uint32_t kMaxFields = 8;
 constexpr uint32_t kMaxLevels = 8;
 constexpr uint32_t kNull = 0xFFFFFFFFu;
-constexpr uint32_t kTypeNone = 0xFFFFFFFFu;
+// Block type word: the type in the low 8 bits (kTypeNone for a free block),
+// above them the number of times the block was freed (its version).
+constexpr uint32_t kTypeNone = 0xFFu;
 constexpr int32_t kFail = -1;
 constexpr uint32_t kSpinLimit = 1u << 20;  // bound of every retry loop
 constexpr uint32_t kShards = 1024;         // counter shards (spread atomics)
@@ -52,15 +54,17 @@ enum : uint32_t {
   kCntFindFails = 2 * kMaxTypes + 2,
   kCntVisits = 2 * kMaxTypes + 3,  // + type: objects visited by do-alls
   kCntMethodAtomics = 3 * kMaxTypes + 3,  // atomic RMWs methods issue on their own data
+  kCntReleases = 3 * kMaxTypes + 4,       // blocks freed online by the delete that emptied them
   kShardStride = 32,
 };
-static_assert(kCntMethodAtomics < kShardStride, "counter slots exceed a shard");
+static_assert(kCntReleases < kShardStride, "counter slots exceed a shard");
 
 
 struct DevHeap {
   uint8_t* data;            // M * block_stride bytes of SOA segments
   uint64_t* obj_bitmap;     // M words: bit s = slot s holds an object
-  uint32_t* block_type;     // M words: type of the block, kTypeNone if free
+  uint32_t* block_type;     // M words: version << 8 | type (kTypeNone if free)
+  uint32_t* pins;           // M words: reservations in progress (online reclamation only)
   uint64_t* bitmaps;        // (1 + 2T) hierarchical bitmaps, bm_words apart
   uint64_t* ctrl;           // flags + counter shards
   uint64_t block_stride;
@@ -72,6 +76,7 @@ struct DevHeap {
   uint32_t bm_words;        // words per bitmap (all levels, padded)
   uint32_t bulk_min;        // requests of at least this many take whole free blocks
   uint32_t doall_unroll;    // blocks per wavefront pass of split do-alls (1, 2, 4, 8)
+  uint32_t online_reclaim;  // 1: the delete that empties a block frees it at once
   // Field f of type t: byte offset of its array in a block (low 24 bits)
   // and log2 of its width (high 8 bits), in one dword so that a kernel reads
   // it with one scalar load.
@@ -177,6 +182,10 @@ __device__ __forceinline__ void meta_store(uint32_t* p, uint32_t v) {
 __device__ __forceinline__ void meta_store(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+__device__ __forceinline__ uint32_t tw_type(uint32_t w) { return w & 0xFFu; }
+__device__ __forceinline__ uint32_t tw_with(uint32_t w, uint32_t type) { return (w & ~0xFFu) | type; }
+__device__ __forceinline__ uint32_t tw_freed(uint32_t w) { return (w & ~0xFFu) + 0x100u + kTypeNone; }
 
 // Leader-issued RMWs; all calling lanes receive the previous value.
 __device__ __forceinline__ uint64_t lead_or(uint64_t* p, uint64_t v) {
@@ -491,6 +500,29 @@ __device__ __forceinline__ F* field_ptr(const DevHeap& h, uint32_t obj, uint32_t
                               ((uint64_t)obj_slot(obj) << (loc >> 24)));
 }
 
+// Reservation side of online reclamation: pin block `bid` (per lane) if its
+// type word still reads `w`; false (and no pin held) otherwise.
+__device__ __forceinline__ bool pin_block(const DevHeap& h, uint32_t bid, uint32_t w) {
+  __hip_atomic_fetch_add(h.pins + bid, 1u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+  if (__hip_atomic_load(h.block_type + bid, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT) == w) return true;
+  __hip_atomic_fetch_sub(h.pins + bid, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  return false;
+}
+__device__ __forceinline__ void unpin_block(const DevHeap& h, uint32_t bid) {
+  __hip_atomic_fetch_sub(h.pins + bid, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A block just taken from the free bitmap: its object bitmap first, then its
+// type word (release), so that a reservation that reads the new type word
+// also reads the initialised bitmap.  Per lane.
+__device__ __forceinline__ uint32_t publish_block(const DevHeap& h, uint32_t bid, uint32_t type, uint64_t bits) {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const uint32_t w = tw_with(__hip_atomic_load(h.block_type + bid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), type);
+  __hip_atomic_store(h.obj_bitmap + bid, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(h.block_type + bid, w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  return w;
+}
+
 // Alg. 1 for all lanes of this wavefront that call it with the same `type`
 // (the caller guarantees a wave-uniform type); lane i asks for k_i objects
 // (0 <= k_i < 256).  f(j, obj) is then called by lane i for j = 0 .. k_i - 1
@@ -532,6 +564,7 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
   bool oom = false, active_first = false, none_active = false;
   int32_t cur = kFail;     // block of the last reservation, if it still had room
   uint64_t cur_avail = 0;  // its free bits right after that reservation
+  uint32_t cur_tw = 0;     // its type word then (online reclamation: checked on reuse)
   for (uint32_t it = 0; served < n; ++it) {
     if (it >= kSpinLimit) {
       lead_flag(h.ctrl + kCtlRetryLimit);
@@ -552,11 +585,7 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
       // Type words and object bitmaps of the new blocks, spread over the
       // active lanes; the blocks are ours alone until published.
       const uint32_t me = lanes_below(active_mask()), nact = (uint32_t)__popcll(active_mask());
-      for (uint32_t j = me; j < cnt_b; j += nact) {
-        const uint32_t bid = word * 64 + nth_set_bit(blocks, j);
-        meta_store(h.block_type + bid, type);
-        meta_store(h.obj_bitmap + bid, cap);
-      }
+      for (uint32_t j = me; j < cnt_b; j += nact) publish_block(h, word * 64 + nth_set_bit(blocks, j), type, cap);
       const Bitmap alloc = allocated_bm(h, type);
       const uint64_t pa = lead_or(alloc.word(0, word), blocks);
       if (pa == 0 && alloc.nlevels > 1) bm_set_from(alloc, 1, word);
@@ -593,11 +622,20 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
         nb = nb < kMultiBlocks ? nb : kMultiBlocks;
         nb = nb < nact ? nb : nact;
         const uint64_t sel = take_from(wbits, nb, start & 63u);
-        uint32_t my_bid = 0;
+        uint32_t my_bid = 0, my_tw = 0;
         uint64_t my_av = 0;
+        bool my_pin = false;
         if (me < nb) {
           my_bid = (uint32_t)aw * 64 + nth_set_bit(sel, me);
-          if (my_bid < h.num_blocks) my_av = ~load_u64(h.obj_bitmap + my_bid) & cap;
+          bool ok = my_bid < h.num_blocks;
+          if (ok && h.online_reclaim) {
+            // The block may have been freed and reused since the lookup:
+            // reserve only while pinned to the type word read now.
+            my_tw = meta_load(h.block_type + my_bid);
+            ok = tw_type(my_tw) == type && pin_block(h, my_bid, my_tw);
+            my_pin = ok;
+          }
+          if (ok) my_av = ~meta_load(h.obj_bitmap + my_bid) & cap;
         }
         const uint32_t cnt = (uint32_t)__popcll(my_av);
         uint32_t excl = 0;
@@ -608,6 +646,7 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
         uint64_t my_prev = 0;
         if (my_take)
           my_prev = __hip_atomic_fetch_or(h.obj_bitmap + my_bid, my_take, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (my_pin) unpin_block(h, my_bid);
         const uint64_t my_got = my_take & ~my_prev;
         const uint64_t my_after = (my_prev | my_take) & cap;
         // The reservation that set a block's last free bit takes it out of active.
@@ -618,6 +657,7 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
         if (room_lanes) {
           const uint32_t l = 63u - (uint32_t)__builtin_clzll(room_lanes);
           cur = (int32_t)__builtin_amdgcn_readlane(my_bid, l);
+          cur_tw = (uint32_t)__builtin_amdgcn_readlane(my_tw, l);
           cur_avail = ~(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(my_after >> 32), l) << 32) |
                         (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)my_after, l)) &
                       cap;
@@ -661,20 +701,25 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
       ++slow;
       // Fresh block: nobody else can see it until it is marked active.
       got = want >= c ? cap : ((1ull << want) - 1);
-      if (is_first_active()) {
-        meta_store(h.block_type + bid, type);
-        meta_store(h.obj_bitmap + bid, got);
-      }
+      uint32_t w = 0;
+      if (is_first_active()) w = publish_block(h, (uint32_t)bid, type, got);
       bm_set(allocated_bm(h, type), (uint32_t)bid);
       if (got != cap) {
         bm_set(active, (uint32_t)bid);
         cur = bid;
         cur_avail = ~got & cap;
+        cur_tw = bcast32(w);
       }
     } else {
+      if (h.online_reclaim) {
+        uint32_t pinned = 0;
+        if (is_first_active()) pinned = pin_block(h, (uint32_t)bid, cur_tw) ? 1u : 0u;
+        if (!bcast32(pinned)) continue;  // freed since: look up another block
+      }
       const uint64_t take = take_from(avail, want < (uint32_t)__popcll(avail) ? want : (uint32_t)__popcll(avail),
                                       rot & (c - 1));
       const uint64_t prev = lead_or(h.obj_bitmap + bid, take);
+      if (h.online_reclaim && is_first_active()) unpin_block(h, (uint32_t)bid);
       got = take & ~prev;
       const uint64_t after = (prev | take) & cap;
       if (after == cap && (prev & cap) != cap) bm_clear(active, (uint32_t)bid);
@@ -719,6 +764,55 @@ __device__ inline uint32_t dsoar_new(const DevHeap& h, uint32_t type) {
   return result;
 }
 
+// Online reclamation: the wavefront whose delete left block `bid` of `type`
+// empty frees it at once (the block-state figure's return to free, inside a
+// kernel).  Used when the heap's online_reclaim is set.
+//  1 Invalidate: compare-and-swap the object bitmap from 0 to all ones.  If
+//    that fails an allocation got in first and the block stays.  All ones
+//    reads as full, so no reservation can gain a slot from here on.
+//  2 Bump the version in the type word and mark it free, then wait until no
+//    reservation holds the block.  A reservation pins the block and then
+//    re-reads the type word (both sequentially consistent), so either it
+//    sees the change and withdraws, or this wait sees its pin.
+//  3 Leave active[type] and allocated[type] (clear with retry: each pairs
+//    with the set of the transition that made the bit true).
+//  4 Reset the object bitmap, then set the free bit, in release order: an
+//    allocator that takes the block from the free bitmap sees the reset
+//    bitmap and the new type word.
+// Returns whether the block was freed (wave-uniform).
+__device__ inline bool try_release(const DevHeap& h, uint32_t type, uint32_t bid) {
+  uint32_t ok = 0;
+  if (is_first_active()) {
+    uint64_t expected = 0;
+    ok = __hip_atomic_compare_exchange_strong(h.obj_bitmap + bid, &expected, ~0ull, __ATOMIC_ACQ_REL,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+             ? 1u
+             : 0u;
+    if (ok) {
+      const uint32_t w = __hip_atomic_load(h.block_type + bid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(h.block_type + bid, tw_freed(w), __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (!bcast32(ok)) return false;
+  for (uint32_t spins = 0;; ++spins) {
+    uint32_t p = 0;
+    if (is_first_active()) p = __hip_atomic_load(h.pins + bid, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+    if (bcast32(p) == 0) break;
+    if (spins >= kSpinLimit) {
+      lead_flag(h.ctrl + kCtlRetryLimit);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  bm_clear(active_bm(h, type), bid);
+  bm_clear(allocated_bm(h, type), bid);
+  if (is_first_active()) __hip_atomic_store(h.obj_bitmap + bid, 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  bm_set(free_bm(h), bid);
+  lead_add(shard(h) + kCntReleases, 1);
+  return true;
+}
+
 // Delete a set of slots of one block (a wavefront's lanes, coalesced): one
 // atomic AND on the object bitmap.  A block that was full becomes active
 // again.  Blocks that become empty stay allocated until quiescent reclaim.
@@ -729,6 +823,7 @@ __device__ inline uint32_t delete_mask(const DevHeap& h, uint32_t type, uint32_t
   const uint64_t removed = prev & mask;
   const uint64_t cap = capmask_of(h, type);
   if (removed && (prev & cap) == cap) bm_set(active_bm(h, type), bid);
+  if (h.online_reclaim && removed && ((prev & ~mask) & cap) == 0) try_release(h, type, bid);
   return (uint32_t)__popcll(removed);
 }
 
@@ -745,7 +840,8 @@ __device__ inline void dsoar_delete(const DevHeap& h, uint32_t obj) {
     const bool in = mine && (obj >> 6) == b0 && ((pending >> lane_id()) & 1);
     const uint64_t grp = __ballot(in);
     const uint64_t m = slots_of(grp, obj_slot(obj));
-    const uint32_t type = bcast32(__hip_atomic_load(h.block_type + b0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint32_t type =
+        tw_type(bcast32(__hip_atomic_load(h.block_type + b0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
     if (type < h.num_types) {
       const uint32_t freed = delete_mask(h, type, b0, m);
       if (freed) lead_add(shard(h) + kCntFrees + type, freed);

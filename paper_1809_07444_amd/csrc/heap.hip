@@ -75,7 +75,7 @@ void type_capacities(const dsoar_heap_desc* d, uint32_t* cap) {
 // the block size is that of the smallest type's 64 objects.
 struct Plan {
   dsoar_heap_layout L;
-  uint64_t ctrl_off, stats_off;
+  uint64_t ctrl_off, stats_off, pins_off;
   uint64_t R_off[kMaxTypes], S_off[kMaxTypes], scan_off[kMaxTypes];
   uint32_t num_tiles;
   uint32_t enum_wpw;
@@ -113,6 +113,8 @@ Plan make_plan(const dsoar_heap_desc* d) {
   p.L.obj_bitmap_offset = off;
   off = align_up(off + M * 8, kAlign);
   p.L.block_type_offset = off;
+  off = align_up(off + M * 4, kAlign);
+  p.pins_off = off;
   off = align_up(off + M * 4, kAlign);
   p.L.bitmaps_offset = off;
   const uint32_t bm_words = bitmap_words((uint32_t)M);
@@ -181,6 +183,7 @@ __global__ void init_heap_kernel(DevHeap h, uint64_t ctrl_words) {
   for (uint32_t b = tid; b < h.num_blocks; b += nth) {
     meta_store(h.obj_bitmap + b, 0ull);
     meta_store(h.block_type + b, kTypeNone);
+    meta_store(h.pins + b, 0u);
   }
   for (uint64_t w = tid; w < ctrl_words; w += nth) meta_store(h.ctrl + w, 0ull);
   // Bitmap 0 (free) all set, the others clear.
@@ -234,7 +237,10 @@ __device__ inline void set_bits0(const Bitmap& b, uint32_t word, uint64_t m) {
 // level-0 updates are issued together; each does the nested update its
 // single-bit counterpart would (Alg. 2).
 __device__ inline void reclaim_word(const DevHeap& h, uint32_t t, uint32_t word, uint64_t rc) {
-  if ((rc >> lane_id()) & 1ull) meta_store(h.block_type + word * 64 + lane_id(), kTypeNone);
+  if ((rc >> lane_id()) & 1ull) {
+    uint32_t* tw = h.block_type + word * 64 + lane_id();
+    meta_store(tw, tw_freed(meta_load(tw)));
+  }
   const Bitmap al = allocated_bm(h, t), ac = active_bm(h, t), fr = free_bm(h);
   uint64_t pa = 0, pc = 0, pf = 0;
   if (is_first_active()) {
@@ -373,7 +379,7 @@ __global__ void reclaim_kernel(DevHeap h) {
   for (uint32_t word = blockIdx.x * wpb + (threadIdx.x >> 6); word < W0; word += gridDim.x * wpb) {
     const uint32_t b = word * 64 + lane;
     const bool in = b < h.num_blocks;
-    const uint32_t t = in ? meta_load(h.block_type + b) : kTypeNone;
+    const uint32_t t = in ? tw_type(meta_load(h.block_type + b)) : kTypeNone;
     const bool empty = in && t != kTypeNone && meta_load(h.obj_bitmap + b) == 0;
     uint64_t pending = __ballot(empty);
     while (pending) {
@@ -395,7 +401,7 @@ __global__ void stats_kernel(DevHeap h, StatsOut* out, int check) {
   for (uint32_t word = gw; word < W0; word += nw) {
     const uint32_t b = word * 64 + lane;
     const bool in = b < h.num_blocks;
-    const uint32_t t = in ? meta_load(h.block_type + b) : kTypeNone;
+    const uint32_t t = in ? tw_type(meta_load(h.block_type + b)) : kTypeNone;
     const uint64_t ob = in ? meta_load(h.obj_bitmap + b) : 0;
     const uint64_t cm = t < h.num_types ? h.cap_mask[t] : ~0ull;  // this block's type's slots
     const uint64_t obc = ob & cm;
@@ -499,6 +505,42 @@ __global__ void free_n_kernel(DevHeap h, const uint32_t* objs, uint32_t n) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   dsoar_delete(h, objs[i]);
+}
+
+// Allocation/deletion stress: lane i runs `rounds` rounds; in round r its
+// wavefront creates objects of type (spread * wave + r) mod num_types, one per lane,
+// each lane writes its handle into field 0 of its object and, unless the
+// round's draw keeps it, checks the field still holds the handle and deletes
+// the object at once.  Kept handles go to out[i * rounds + r] (DSOAR_NULL
+// otherwise).  A field found overwritten (a slot handed out twice) counts in
+// errors[0].  Every lane of a wavefront runs every round (the heap calls are
+// wavefront operations).
+__global__ void churn_kernel(DevHeap h, uint32_t n, uint32_t rounds, uint32_t keep, uint32_t spread, uint32_t seed,
+                             uint32_t* out, uint32_t* errors) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i < n;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(i >> 6);
+  for (uint32_t r = 0; r < rounds; ++r) {
+    const uint32_t t = (spread * wave + r) % h.num_types;
+    uint32_t o = kNull;
+    new_many(h, t, in ? 1u : 0u, [&](uint32_t, uint32_t obj) { o = obj; });
+    uint32_t del = kNull;
+    if (o != kNull) {
+      uint32_t* f0 = field_ptr<uint32_t>(h, o, t, 0);
+      *f0 = o;
+      const bool kept = hash32(seed ^ (i * 0x9E3779B1u) ^ (r * 0x85EBCA77u)) % keep == 0;
+      if (kept) {
+        out[(uint64_t)i * rounds + r] = o;
+      } else {
+        if (*f0 != o) atomicAdd(errors, 1u);
+        del = o;
+        out[(uint64_t)i * rounds + r] = kNull;
+      }
+    } else if (in) {
+      out[(uint64_t)i * rounds + r] = kNull;
+    }
+    dsoar_delete(h, del);
+  }
 }
 
 __global__ void field_rw_kernel(DevHeap h, uint32_t type, uint32_t field, const uint32_t* objs, uint32_t n,
@@ -635,6 +677,7 @@ int collect_stats(dsoar_heap* h, dsoar_stats* out, uint32_t* viol, int check, hi
     st.slow_paths += c[kCntSlowPaths];
     st.find_fails += c[kCntFindFails];
     st.method_atomics += c[kCntMethodAtomics];
+    st.online_releases += c[kCntReleases];
   }
   for (uint32_t t = 0; t < kMaxTypes; ++t) {
     st.live_objects[t] = so.live[t];
@@ -685,6 +728,7 @@ int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_byt
   d.data = h->base + p.L.data_offset;
   d.obj_bitmap = (uint64_t*)(h->base + p.L.obj_bitmap_offset);
   d.block_type = (uint32_t*)(h->base + p.L.block_type_offset);
+  d.pins = (uint32_t*)(h->base + p.pins_off);
   d.bitmaps = (uint64_t*)(h->base + p.L.bitmaps_offset);
   d.ctrl = (uint64_t*)(h->base + p.ctrl_off);
   d.block_stride = p.L.block_stride;
@@ -827,6 +871,13 @@ int dsoar_heap_set_policy(dsoar_heap* h, uint32_t bulk_min) {
   return DSOAR_OK;
 }
 
+int dsoar_heap_set_reclaim(dsoar_heap* h, int online) {
+  if (!heap_ok(h)) return DSOAR_ERR_INVALID_ARG;
+  h->dev.online_reclaim = online ? 1u : 0u;
+  h->config_epoch++;
+  return DSOAR_OK;
+}
+
 int dsoar_heap_set_unroll(dsoar_heap* h, uint32_t blocks_per_pass) {
   if (!heap_ok(h) || (blocks_per_pass != 1 && blocks_per_pass != 2 && blocks_per_pass != 4 && blocks_per_pass != 8))
     return DSOAR_ERR_INVALID_ARG;
@@ -916,6 +967,18 @@ int dsoar_alloc_n(dsoar_heap* h, uint32_t type, uint32_t n, dsoar_obj* out_dev, 
   if (n == 0) return DSOAR_OK;
   hipLaunchKernelGGL(alloc_n_kernel, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, (hipStream_t)stream, h->dev,
                      type, n, out_dev);
+  DSOAR_LAUNCHED(h);
+  return DSOAR_OK;
+}
+
+int dsoar_stress_churn(dsoar_heap* h, uint32_t n, uint32_t rounds, uint32_t keep, uint32_t spread, uint32_t seed,
+                       dsoar_obj* out_dev, uint32_t* errors_dev, void* stream) {
+  if (!heap_ok(h) || n == 0 || rounds == 0 || keep == 0 || !out_dev || !errors_dev || (uint64_t)n * rounds > (1ull << 32))
+    return DSOAR_ERR_INVALID_ARG;
+  for (uint32_t t = 0; t < h->desc.num_types; ++t)
+    if (h->desc.types[t].field_bytes[0] != 4) return DSOAR_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(churn_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, h->dev, n, rounds, keep,
+                     spread, seed, out_dev, errors_dev);
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }

@@ -245,6 +245,7 @@ __device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, c
       }
       uint32_t act_word = 0xFFFFFFFFu;
       uint64_t act_bits = 0;
+      uint32_t emptied = 0;  // bit u: this pass's deletes left block u empty
 #pragma unroll
       for (uint32_t u = 0; u < U; ++u) {
         if (!dm[u]) continue;
@@ -252,6 +253,7 @@ __device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, c
         if ((pv & dm[u]) != dm[u]) lead_flag(h.ctrl + kCtlDoubleFree);
         const uint64_t removed = pv & dm[u];
         freed += (uint32_t)__popcll(removed);
+        if (removed && (pv & ~dm[u]) == 0) emptied |= 1u << u;
         if (removed && (pv & kFull64) == kFull64) {
           const uint32_t w = p.bid[u] >> 6;
           if (w != act_word) {
@@ -263,10 +265,19 @@ __device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, c
         }
       }
       if (act_bits) {
-        settle();
-        pend_word = act_word;
-        pend_bits = act_bits;
-        pend_prev = bm_set_bits0_issue(act, act_word, act_bits);
+        if (h.online_reclaim) {
+          bm_set_bits0(act, act_word, act_bits);  // settled before the releases below
+        } else {
+          settle();
+          pend_word = act_word;
+          pend_bits = act_bits;
+          pend_prev = bm_set_bits0_issue(act, act_word, act_bits);
+        }
+      }
+      if (h.online_reclaim && emptied) {
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+          if ((emptied >> u) & 1u) try_release(h, type, p.bid[u]);
       }
     }
   };

@@ -81,6 +81,10 @@ class Heap:
     def set_policy(self, bulk_min: int):
         C.check(self.lib.dsoar_heap_set_policy(self.h, bulk_min), "dsoar_heap_set_policy")
 
+    def set_reclaim(self, online: bool):
+        """Free emptied blocks at the delete that empties them (online) or at enumeration."""
+        C.check(self.lib.dsoar_heap_set_reclaim(self.h, 1 if online else 0), "dsoar_heap_set_reclaim")
+
     def set_unroll(self, blocks_per_pass: int):
         """Blocks per wavefront pass of split do-all methods (1, 2, 4, 8)."""
         C.check(self.lib.dsoar_heap_set_unroll(self.h, blocks_per_pass), "dsoar_heap_set_unroll")
@@ -123,6 +127,7 @@ class Heap:
             allocated_blocks=list(st.allocated_blocks[:nt]), active_blocks=list(st.active_blocks[:nt]),
             typed_blocks=list(st.typed_blocks[:nt]), reserve_retries=st.reserve_retries,
             slow_paths=st.slow_paths, find_fails=st.find_fails, method_atomics=st.method_atomics,
+            online_releases=st.online_releases,
             free_blocks=st.free_blocks,
             num_blocks=st.num_blocks, oom=st.oom, retry_limit_hit=st.retry_limit_hit,
             double_free=st.double_free, status=rc)
@@ -187,6 +192,17 @@ class Heap:
         C.check(self.lib.dsoar_alloc_n(self.h, t, n, out.data_ptr(), self._s()), "dsoar_alloc_n")
         return out[:n]
 
+    def stress_churn(self, n: int, rounds: int, keep: int, seed: int = 1, spread: int = 1):
+        """Runs the new/delete stress kernel; returns (kept handles [n, rounds], error count)."""
+        out = torch.empty(n * rounds, dtype=torch.int32, device=self.buffer.device)
+        err = torch.zeros(1, dtype=torch.int32, device=self.buffer.device)
+        torch.cuda.synchronize()
+        C.check(self.lib.dsoar_stress_churn(self.h, n, rounds, keep, spread, seed, out.data_ptr(), err.data_ptr(),
+                                            self._s()),
+                "dsoar_stress_churn")
+        torch.cuda.synchronize()
+        return out.view(n, rounds), int(err.item())
+
     def free_n(self, objs: torch.Tensor):
         objs = objs.to(torch.int32).contiguous()
         C.check(self.lib.dsoar_free_n(self.h, objs.data_ptr(), objs.numel(), self._s()), "dsoar_free_n")
@@ -212,7 +228,9 @@ class Heap:
         M = self.num_blocks
         b = self.buffer
         ob = b[L.obj_bitmap_offset: L.obj_bitmap_offset + 8 * M].view(torch.int64)
-        bt = b[L.block_type_offset: L.block_type_offset + 4 * M].view(torch.int32)
+        tw = b[L.block_type_offset: L.block_type_offset + 4 * M].view(torch.int32)
+        t8 = tw & 0xFF
+        bt = torch.where(t8 == 0xFF, torch.full_like(t8, -1), t8)  # type, -1 = free
         nbm = 1 + 2 * len(self.types)
         bms = b[L.bitmaps_offset: L.bitmaps_offset + nbm * L.bitmap_stride].view(torch.int64)
         bms = bms.view(nbm, L.bitmap_stride // 8)
