@@ -93,6 +93,8 @@ def lib() -> ctypes.CDLL:
         L.orc_gol_run.argtypes = [i32, i32, i32, vp, vp]
         L.orc_sugar_run.restype = ctypes.c_int
         L.orc_sugar_run.argtypes = [i32, i32, i32, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_collide_run.restype = ctypes.c_int
+        L.orc_collide_run.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.orc_traffic_run.restype = ctypes.c_int
         L.orc_traffic_run.argtypes = [i32, i32, i32, i32, u64, i32, ctypes.c_uint32, ctypes.c_uint32, vp, vp]
         _lib = L
@@ -336,4 +338,29 @@ def traffic_run(vel: np.ndarray, steps: int, seed: int, rules: dict, step0: int 
     if rc != 0:
         raise ValueError("orc_traffic_run failed")
     return TrafficResult(v, int(counts[0]), int(counts[1]))
+
+
+class _CollideParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_float), ("eps2", ctypes.c_float), ("r2_merge", ctypes.c_float)]
+
+
+@dataclass
+class CollideState:
+    x: np.ndarray
+    y: np.ndarray
+    vx: np.ndarray
+    vy: np.ndarray
+    m: np.ndarray      # 0 = merged away
+    merges: int = 0
+
+
+def collide_run(state: CollideState, steps: int, params: dict) -> CollideState:
+    """Merging-bodies particle system (float32, every operation rounded once)."""
+    a = [np.ascontiguousarray(v, dtype=np.float32).copy() for v in (state.x, state.y, state.vx, state.vy, state.m)]
+    counts = np.zeros(1, dtype=np.int64)
+    pr = _CollideParams(params["dt"], params["eps2"], params["r2_merge"])
+    rc = lib().orc_collide_run(len(a[0]), steps, ctypes.byref(pr), *[_p(v) for v in a], _p(counts))
+    if rc != 0:
+        raise ValueError("orc_collide_run failed")
+    return CollideState(*a, merges=state.merges + int(counts[0]))
 

@@ -703,3 +703,110 @@ int orc_traffic_run(int32_t roads, int32_t length, int32_t steps, int32_t step0,
   return 0;
 }
 
+/* ============================================================ collisions
+ * Bodies in the plane under mutual attraction, merging when they come close
+ * (the paper names the application; the rules here are the ones adopted,
+ * written out in full).  G is folded into the masses.  One step:
+ *  1 acceleration of every live body i, summed over all ids j in increasing
+ *    order (j = i and merged bodies contribute exactly 0):
+ *      dx = x_j - x_i, dy = y_j - y_i, r2 = fma(dx, dx, fma(dy, dy, eps2)),
+ *      s = m_j / (r2 * sqrt(r2)), ax = fma(s, dx, ax), ay = fma(s, dy, ay)
+ *  2 move: vx = fma(dt, ax, vx), x = fma(dt, vx, x) (and y)
+ *  3 roots: a live body is a root if no live body of lower id lies within
+ *    the merge radius: d2 = fma(dx, dx, dy * dy) < r2_merge
+ *  4 targets: a live non-root body merges into the lowest-id root within the
+ *    merge radius, if there is one
+ *  5 merge: a root that absorbs bodies takes, in increasing id order of the
+ *    absorbed, M = M + m_i, P = fma(m_i, v_i, P) and C = fma(m_i, x_i, C),
+ *    starting from M = m_j, P = m_j * v_j, C = m_j * x_j; then v = P / M,
+ *    x = C / M, m = M.  Roots that absorb nothing are unchanged.
+ *  6 the absorbed bodies are removed (m = 0).
+ * Every operation is IEEE single precision with one rounding; fma and sqrt
+ * are correctly rounded. */
+
+int orc_collide_run(int32_t n, int32_t steps, const orc_collide_params *p, float *x, float *y, float *vx,
+                    float *vy, float *m, int64_t *counts) {
+  if (n < 1 || steps < 0) return -1;
+  float *ax = (float *)malloc((size_t)n * sizeof(float));
+  float *ay = (float *)malloc((size_t)n * sizeof(float));
+  int32_t *target = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  uint8_t *root = (uint8_t *)malloc((size_t)n);
+  if (!ax || !ay || !target || !root) {
+    free(ax); free(ay); free(target); free(root);
+    return -1;
+  }
+  for (int32_t s = 0; s < steps; s++) {
+    for (int32_t i = 0; i < n; i++) {
+      float sx = 0.0f, sy = 0.0f;
+      if (m[i] > 0.0f) {
+        for (int32_t j = 0; j < n; j++) {
+          const float dx = x[j] - x[i], dy = y[j] - y[i];
+          const float r2 = fmaf(dx, dx, fmaf(dy, dy, p->eps2));
+          const float sc = m[j] / (r2 * sqrtf(r2));
+          sx = fmaf(sc, dx, sx);
+          sy = fmaf(sc, dy, sy);
+        }
+      }
+      ax[i] = sx;
+      ay[i] = sy;
+    }
+    for (int32_t i = 0; i < n; i++) {
+      if (!(m[i] > 0.0f)) continue;
+      vx[i] = fmaf(p->dt, ax[i], vx[i]);
+      vy[i] = fmaf(p->dt, ay[i], vy[i]);
+      x[i] = fmaf(p->dt, vx[i], x[i]);
+      y[i] = fmaf(p->dt, vy[i], y[i]);
+    }
+    for (int32_t i = 0; i < n; i++) {
+      root[i] = 0;
+      if (!(m[i] > 0.0f)) continue;
+      int near_lower = 0;
+      for (int32_t j = 0; j < i && !near_lower; j++) {
+        if (!(m[j] > 0.0f)) continue;
+        const float dx = x[j] - x[i], dy = y[j] - y[i];
+        if (fmaf(dx, dx, dy * dy) < p->r2_merge) near_lower = 1;
+      }
+      root[i] = (uint8_t)!near_lower;
+    }
+    for (int32_t i = 0; i < n; i++) {
+      target[i] = -1;
+      if (!(m[i] > 0.0f) || root[i]) continue;
+      for (int32_t j = 0; j < n; j++) {
+        if (!root[j]) continue;
+        const float dx = x[j] - x[i], dy = y[j] - y[i];
+        if (fmaf(dx, dx, dy * dy) < p->r2_merge) {
+          target[i] = j;
+          break;
+        }
+      }
+    }
+    for (int32_t j = 0; j < n; j++) {
+      if (!root[j]) continue;
+      float M = m[j], px = m[j] * vx[j], py = m[j] * vy[j], cx = m[j] * x[j], cy = m[j] * y[j];
+      int absorbed = 0;
+      for (int32_t i = 0; i < n; i++) {
+        if (target[i] != j) continue;
+        M = M + m[i];
+        px = fmaf(m[i], vx[i], px);
+        py = fmaf(m[i], vy[i], py);
+        cx = fmaf(m[i], x[i], cx);
+        cy = fmaf(m[i], y[i], cy);
+        absorbed++;
+      }
+      if (!absorbed) continue;
+      vx[j] = px / M;
+      vy[j] = py / M;
+      x[j] = cx / M;
+      y[j] = cy / M;
+      m[j] = M;
+    }
+    for (int32_t i = 0; i < n; i++)
+      if (target[i] >= 0) {
+        m[i] = 0.0f;
+        counts[0]++;
+      }
+  }
+  free(ax); free(ay); free(target); free(root);
+  return 0;
+}
+

@@ -123,4 +123,16 @@ int orc_sugar_run(int32_t side, int32_t steps, int32_t step0, uint64_t seed,
 int orc_traffic_run(int32_t roads, int32_t length, int32_t steps, int32_t step0, uint64_t seed,
                     int32_t vmax, uint32_t p_slow24, uint32_t p_in24, int32_t *vel, int64_t *counts);
 
+
+/* --------------------------------------------------------- collisions ---- */
+/* Particle system with merging bodies in the plane (the paper's "collisions"
+ * application, Fig. 6b).  Bodies are indexed by id; m[id] == 0 marks a body
+ * that merged into another (its other entries keep their last values).
+ * Updates x, y, vx, vy, m in place for `steps` steps; counts[0] += merges. */
+typedef struct {
+  float dt, eps2, r2_merge;
+} orc_collide_params;
+int orc_collide_run(int32_t n, int32_t steps, const orc_collide_params *p, float *x, float *y, float *vx,
+                    float *vy, float *m, int64_t *counts);
+
 #endif

@@ -50,6 +50,11 @@ S_TRAFFIC_OCC = 30
 S_TRAFFIC_V0 = 31
 S_TRAFFIC_SLOW = 32   # drawn by the method itself, each step (both sides implement hash)
 S_TRAFFIC_IN = 33     # idem
+S_BODY_X = 34
+S_BODY_Y = 35
+S_BODY_VX = 36
+S_BODY_VY = 37
+S_BODY_M = 38
 
 DEFAULT_SEED = 24301
 BERNOULLI_0_1 = 1677721  # floor(0.1 * 2**24)

@@ -204,3 +204,34 @@ def traffic_inputs(roads: int = 1024, length: int = 1024, seed: int = rng.DEFAUL
     v0 = rng.uniform_int(rng.hash4(seed, rng.S_TRAFFIC_V0, r, i), 0, vmax)
     vel = np.where(occ, v0, -1).astype(np.int32)
     return TrafficInputs(roads, length, seed, np.ascontiguousarray(vel))
+
+
+# ------------------------------------------------------------- collisions --
+
+# Time step, softening and merge radius squared (float32 values).
+COLLIDE_PARAMS = dict(dt=0.01, eps2=0.01, r2_merge=0.0001)
+
+
+@dataclass
+class CollideInputs:
+    n: int
+    seed: int
+    x: np.ndarray
+    y: np.ndarray
+    vx: np.ndarray
+    vy: np.ndarray
+    m: np.ndarray
+
+
+def collide_inputs(n: int = 4096, seed: int = rng.DEFAULT_SEED, box: float = 8.0) -> CollideInputs:
+    """n bodies uniform in [0, box)^2, velocities uniform in [-0.5, 0.5)^2,
+    masses U{1..4} / 1024 (all values exact in float32)."""
+    i = np.arange(n, dtype=np.uint64)
+    x = (rng.uniform01_f32(rng.hash4(seed, rng.S_BODY_X, 0, i)) * np.float32(box)).astype(np.float32)
+    y = (rng.uniform01_f32(rng.hash4(seed, rng.S_BODY_Y, 0, i)) * np.float32(box)).astype(np.float32)
+    vx = (rng.uniform01_f32(rng.hash4(seed, rng.S_BODY_VX, 0, i)) - np.float32(0.5)).astype(np.float32)
+    vy = (rng.uniform01_f32(rng.hash4(seed, rng.S_BODY_VY, 0, i)) - np.float32(0.5)).astype(np.float32)
+    m = (rng.uniform_int(rng.hash4(seed, rng.S_BODY_M, 0, i), 1, 4).astype(np.float32) *
+         np.float32(1.0 / 1024)).astype(np.float32)
+    return CollideInputs(n, seed, x, y, vx, vy, m)
+

@@ -28,12 +28,15 @@ def churn(online, M, n=65536, rounds=12, keep=5, seed=3, capacity=64, spread=1):
     return heap, out.cpu().numpy().view(np.uint32), errors
 
 
-@pytest.mark.parametrize("online,M,seed,capacity", [(False, 8192, 3, 64), (True, 8192, 3, 64),
-                                                    (True, 2560, 5, 64), (True, 4096, 7, 32), (True, 1800, 9, 64)])
-def test_churn_hands_every_slot_out_once(online, M, seed, capacity):
-    # The smaller heaps keep the free bitmap nearly empty, so blocks are freed
-    # and taken again by other types as fast as the wavefronts run.
-    heap, out, errors = churn(online, M=M, seed=seed, capacity=capacity)
+@pytest.mark.parametrize("online,M,seed,capacity,rounds", [
+    (False, 8192, 3, 64, 12), (True, 8192, 3, 64, 12), (True, 3072, 5, 64, 6), (True, 6144, 7, 32, 6),
+    (True, 2600, 9, 64, 4)])
+def test_churn_hands_every_slot_out_once(online, M, seed, capacity, rounds):
+    # One fifth of the objects are kept (65,536 lanes x rounds / 5) and every
+    # wavefront holds a block's worth more while it churns: the smaller heaps
+    # leave a few hundred blocks spare, so blocks are freed and taken again by
+    # other types as fast as the wavefronts run.
+    heap, out, errors = churn(online, M=M, seed=seed, capacity=capacity, rounds=rounds)
     assert errors == 0
     st = heap.stats(raise_sticky=False)
     assert st["oom"] == 0 and st["retry_limit_hit"] == 0 and st["double_free"] == 0
