@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -24,6 +25,7 @@ if ROOT not in sys.path:
 
 METRIC = "allocs+frees/sec and do-all objects/sec (HBM GB/s % peak); batched vs plain"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32
 
 
 def parse():
@@ -32,7 +34,8 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="gol",
-                   choices=["gol", "micro", "micro_scaled", "batched", "sugarscape", "traffic", "serve"])
+                   choices=["gol", "micro", "micro_scaled", "batched", "sugarscape", "traffic", "collisions",
+                            "serve"])
     p.add_argument("--episodes", type=int, default=200, help="serve: episodes per arrival rate")
     p.add_argument("--rates", default="0.25,0.5,0.75,0.9,1.1",
                    help="serve: arrival rates as fractions of the measured capacity")
@@ -50,6 +53,8 @@ def parse():
                    help="allocation policy: requests of at least this many take whole free blocks first "
                         "('never' = the dense default)")
     p.add_argument("--unroll", type=int, default=None, help="blocks per wavefront pass of split do-alls")
+    p.add_argument("--bodies", type=int, default=65536,
+                   help="collisions: number of bodies (the box side grows with sqrt(bodies), fixed density)")
     return p.parse_args()
 
 
@@ -380,6 +385,77 @@ class TrafficWorkload(GolWorkload):
                           f"{self.steps} steps, {dt:.2f} s; initial cars + entries + exits / oracle time"}
 
 
+class CollideWorkload(GolWorkload):
+    name = "collisions"
+    # Per body pair in the force do-all: 2 subtractions, 2 fma (4 flops) for
+    # r2, square root, multiplication, division, 2 fma (4 flops) = 13.
+    FLOPS_PER_PAIR = 13
+
+    def __init__(self, args):
+        import torch
+        from paper_1809_07444_amd import _capi as C
+        from paper_1809_07444_amd import apps
+        from synth import workloads as W
+        self.C, self.torch = C, torch
+        # 16384 bodies in a 16 x 16 box; other counts keep that density.
+        self.n, self.steps = args.bodies, 20
+        self.box = float(16.0 * math.sqrt(self.n / 16384))
+        self.inp = W.collide_inputs(self.n, seed=args.seed, box=self.box)
+        self.params = W.COLLIDE_PARAMS
+        self.sim = apps.Collisions(self.inp, self.params)
+        self.flags = C.DO_PERSISTENT | (0 if args.no_graph else C.GRAPH)
+        self.M = self.sim.heap.num_blocks
+        self.config = {"workload": f"collisions-{self.n}bodies-box{self.box:g}-{self.steps}steps",
+                       "bodies": self.n, "steps": self.steps, "heap_blocks": self.M, "block_capacity": 64,
+                       "graph": not args.no_graph, "seed": args.seed, "params": self.params}
+
+    def step(self):
+        self.sim.init()
+        self.sim.step(self.steps, self.flags)
+
+    def profiled_step(self):
+        self.sim.init()
+        self.sim.step(self.steps, self.C.DO_PERSISTENT)
+
+    def stats(self):
+        return self.sim.heap.stats()
+
+    def heap(self):
+        return self.sim.heap
+
+    def kernel_flops(self, kind, launches, st):
+        if kind != "collide_force":
+            return None
+        v = st["visits"][0] / 6  # six do-alls per step visit every live body
+        return v * self.n * self.FLOPS_PER_PAIR
+
+    def kernel_bytes(self, kind, launches, st):
+        v = st["visits"][0] / 6
+        per = {"collide_force": 12 + 8 + 16 * 0, "collide_move": 32 + 24, "collide_root": 12 + 4,
+               "collide_target": 16 + 4, "collide_merge": 24 + 4, "collide_remove": 8}
+        if kind in per:
+            return v * per[kind] + v / 64 * 12
+        if kind == "enumerate":
+            return launches * (self.M / 8) + v / 64 * 20
+        return None
+
+    def cpu_baseline(self):
+        import oracle
+        st = oracle.CollideState(self.inp.x, self.inp.y, self.inp.vx, self.inp.vy, self.inp.m)
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < 10 and k < self.steps:
+            st = oracle.collide_run(st, 1, self.params)
+            k += 1
+        dt = time.perf_counter() - t0
+        pairs = self.n * self.n * k
+        ops = int((self.inp.m > 0).sum()) + st.merges
+        return {"value": ops / dt, "unit": "allocs+frees/s", "cores": 1, "kind": "oracle",
+                "force_tflops": pairs * self.FLOPS_PER_PAIR / dt / 1e12,
+                "sample": f"sequential collisions oracle, all {self.n} bodies, first {k} of {self.steps} steps, "
+                          f"{dt:.1f} s; initial bodies + merges / oracle time"}
+
+
 def serve_bench(args):
     import torch
     from paper_1809_07444_amd import serve
@@ -435,6 +511,8 @@ def main():
         wl = SugarWorkload(args)
     elif args.workload == "traffic":
         wl = TrafficWorkload(args)
+    elif args.workload == "collisions":
+        wl = CollideWorkload(args)
     else:
         wl = MicroWorkload(args, scaled=args.workload == "micro_scaled")
 
@@ -479,7 +557,15 @@ def main():
         if best is None or tot_ms > kern[best][1]:
             best = kind
     roof = None
-    if best is not None and kernels[best]["gbs"] is not None:
+    flops = getattr(wl, "kernel_flops", lambda *a: None)(best, kern[best][0], stp) if best else None
+    if flops is not None:
+        # An arithmetic-bound kernel: algorithmic float32 operations per second
+        # against the chip's vector FP32 peak.
+        ach = flops / (kern[best][1] / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / FP32_PEAK_TFLOPS, 5), "traffic": None, "kernel": best,
+                "avg_launch_us": round(kernels[best]["avg_us"], 2)}
+    elif best is not None and kernels[best]["gbs"] is not None:
         ach = kernels[best]["gbs"]
         roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": best,

@@ -474,6 +474,40 @@ int dsoar_traffic_step(dsoar_traffic* traffic, uint32_t steps, uint32_t flags, v
 /* Speed per cell (-1 = empty) into vel_dev (int32, roads*length, device). */
 int dsoar_traffic_read(dsoar_traffic* traffic, int32_t* vel_dev, void* stream);
 
+/* --------------------------------------------------------------- collisions
+ * Merging bodies in the plane (the paper's "collisions" application, Fig.
+ * 6b): Body objects {x, y, vx, vy, ax, ay, m, id} (type 0 of the heap: at
+ * least eight 4-byte fields).  Per step six do-alls: accelerations summed
+ * over all ids in increasing order (m_j (p_j - p) / (r2 sqrt(r2)), r2 = |p_j -
+ * p|^2 + eps2), Euler move (v += dt a, p += dt v), roots (no live body of
+ * lower id within the merge radius), targets (a non-root merges into the
+ * lowest-id root within the radius), merges (mass, momentum and mass-weighted
+ * position added in increasing id order), removal of the merged bodies
+ * (delete).  Single-precision operations, one rounding each, in that order. */
+typedef struct dsoar_collide dsoar_collide;
+typedef struct {
+  float dt;       /* time step */
+  float eps2;     /* softening, > 0 */
+  float r2_merge; /* merge radius squared, >= 0 */
+  uint32_t reserved;
+} dsoar_collide_params;
+/* Device bytes for n body ids (0 if n is 0 or above 2^24). */
+size_t dsoar_collide_bytes(uint32_t n);
+int dsoar_collide_create(dsoar_heap* heap, uint32_t n, const dsoar_collide_params* params, void* dev_mem,
+                         size_t dev_bytes, dsoar_collide** out);
+int dsoar_collide_destroy(dsoar_collide* collide);
+/* Bodies by id from device float arrays of n entries; a body exists where
+ * m_dev[id] > 0.  The heap should be freshly reset. */
+int dsoar_collide_init(dsoar_collide* collide, const float* x_dev, const float* y_dev, const float* vx_dev,
+                       const float* vy_dev, const float* m_dev, void* stream);
+/* Advances `steps` steps.  flags: DSOAR_DO_PLAIN or DSOAR_DO_PERSISTENT,
+ * optionally | DSOAR_GRAPH (persistent only). */
+int dsoar_collide_step(dsoar_collide* collide, uint32_t steps, uint32_t flags, void* stream);
+/* State by id into device float arrays of n entries; m = 0 for a body that
+ * merged away (its other entries keep their last values). */
+int dsoar_collide_read(dsoar_collide* collide, float* x_dev, float* y_dev, float* vx_dev, float* vy_dev,
+                       float* m_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

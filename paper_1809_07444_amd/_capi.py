@@ -29,7 +29,8 @@ KIND_NAMES = {1: "enumerate", 10: "visit_count", 11: "delete_if_mod", 12: "gathe
               21: "micro_cull", 30: "gol_alive_prep", 31: "gol_cand_prep", 32: "gol_alive_update",
               33: "gol_cand_update", 40: "sugar_choose", 41: "sugar_move", 42: "sugar_eat",
               43: "sugar_request", 44: "sugar_birth", 34: "gol_delete_world", 45: "sugar_delete_world",
-              50: "traffic_decide", 51: "traffic_drive"}
+              50: "traffic_decide", 51: "traffic_drive", 60: "collide_force", 61: "collide_move",
+              62: "collide_root", 63: "collide_target", 64: "collide_merge", 65: "collide_remove"}
 INV_NAMES = ["bitmap_range", "allocated", "active", "active_implies_allocated", "free",
              "container", "live_count", "reserved"]
 
@@ -60,6 +61,10 @@ class Stats(ctypes.Structure):
                 ("typed_blocks", u32 * MAX_TYPES), ("reserve_retries", u64), ("slow_paths", u64),
                 ("find_fails", u64), ("method_atomics", u64), ("online_releases", u64), ("free_blocks", u32), ("num_blocks", u32), ("oom", u32),
                 ("retry_limit_hit", u32), ("double_free", u32), ("reserved", u32)]
+
+
+class CollideParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_float), ("eps2", ctypes.c_float), ("r2_merge", ctypes.c_float), ("reserved", u32)]
 
 
 class TrafficRules(ctypes.Structure):
@@ -143,6 +148,12 @@ SIGNATURES = {
     "dsoar_sugar_init": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, u32, vp]),
     "dsoar_sugar_step": (ctypes.c_int, [vp, u32, u32, vp]),
     "dsoar_sugar_read": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(u32), vp]),
+    "dsoar_collide_bytes": (sz, [u32]),
+    "dsoar_collide_create": (ctypes.c_int, [H, u32, vp, vp, sz, ctypes.POINTER(vp)]),
+    "dsoar_collide_destroy": (ctypes.c_int, [vp]),
+    "dsoar_collide_init": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+    "dsoar_collide_step": (ctypes.c_int, [vp, u32, u32, vp]),
+    "dsoar_collide_read": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
     "dsoar_traffic_bytes": (sz, [u32, u32]),
     "dsoar_traffic_create": (ctypes.c_int, [H, u32, u32, vp, vp, sz, ctypes.POINTER(vp)]),
     "dsoar_traffic_destroy": (ctypes.c_int, [vp]),

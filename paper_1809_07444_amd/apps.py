@@ -284,3 +284,72 @@ class Traffic:
 
     def synchronize(self):
         self.stream.synchronize()
+
+
+# ------------------------------------------------------------- collisions --
+
+BODY_TYPE = [(4,) * 8]  # Body {x, y, vx, vy, ax, ay, m, id}
+
+
+@dataclass
+class CollideGpuState:
+    x: np.ndarray
+    y: np.ndarray
+    vx: np.ndarray
+    vy: np.ndarray
+    m: np.ndarray
+    stats: dict
+
+
+class Collisions:
+    """Merging bodies in the plane, Body objects in a device heap."""
+
+    def __init__(self, inp, params: dict, capacity: int = 64, num_blocks: int | None = None, stream=None,
+                 device="cuda"):
+        self.n = inp.n
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        blocks = num_blocks or max(64, 1 << (2 * -(-self.n // (capacity or 64)) - 1).bit_length())
+        self.heap = Heap(blocks, capacity, BODY_TYPE, device=device, stream=self.stream)
+        self.lib = self.heap.lib
+        nbytes = int(self.lib.dsoar_collide_bytes(self.n))
+        if nbytes == 0:
+            raise ValueError("bad body count")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.params = C.CollideParams(params["dt"], params["eps2"], params["r2_merge"], 0)
+        with torch.cuda.stream(self.stream):
+            self.inputs = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+                           for a in (inp.x, inp.y, inp.vx, inp.vy, inp.m)]
+            self.out = [torch.empty(self.n, dtype=torch.float32, device=device) for _ in range(5)]
+        c = ctypes.c_void_p()
+        C.check(self.lib.dsoar_collide_create(self.heap.h, self.n, ctypes.byref(self.params), self.buf.data_ptr(),
+                                              nbytes, ctypes.byref(c)), "dsoar_collide_create")
+        self.c = c
+
+    def close(self):
+        if getattr(self, "c", None):
+            self.lib.dsoar_collide_destroy(self.c)
+            self.c = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self):
+        self.heap.reset()
+        C.check(self.lib.dsoar_collide_init(self.c, *[t.data_ptr() for t in self.inputs], self.heap._s()),
+                "dsoar_collide_init")
+
+    def step(self, steps: int, flags: int = C.DO_PERSISTENT):
+        C.check(self.lib.dsoar_collide_step(self.c, steps, flags, self.heap._s()), "dsoar_collide_step")
+
+    def read(self) -> CollideGpuState:
+        C.check(self.lib.dsoar_collide_read(self.c, *[t.data_ptr() for t in self.out], self.heap._s()),
+                "dsoar_collide_read")
+        self.stream.synchronize()
+        a = [t.cpu().numpy() for t in self.out]
+        return CollideGpuState(*a, stats=self.heap.stats(raise_sticky=False))
+
+    def synchronize(self):
+        self.stream.synchronize()

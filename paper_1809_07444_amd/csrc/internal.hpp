@@ -120,6 +120,21 @@ struct HasSplit : std::false_type {};
 template <class M>
 struct HasSplit<M, std::void_t<typename M::Pre>> : std::true_type {};
 
+// Or a method may take the whole wavefront:
+//   static __device__ bool run_wave(const DevHeap&, uint32_t type, uint32_t self, bool live, const Args&);
+// The do-all calls it with every lane active; `live` tells whether `self` is
+// an allocated object of the do-all.  The other lanes carry an empty slot of
+// a listed block (or of block 0 past the end of the list): their field reads
+// stay inside the heap but return nothing meaningful, and they must write
+// nothing.  With all lanes active, a wavefront can load a chunk of a shared
+// array with one coalesced access and hand its entries around with
+// cross-lane reads, where a per-lane loop would wait on one load per entry.
+// Only a live lane's true return deletes its object.
+template <class M, class = void>
+struct HasWave : std::false_type {};
+template <class M>
+struct HasWave<M, std::void_t<decltype(&M::run_wave)>> : std::true_type {};
+
 template <class Method>
 __device__ __forceinline__ bool run_method(const DevHeap& h, uint32_t type, uint32_t self,
                                            const typename Method::Args& a) {
@@ -127,6 +142,21 @@ __device__ __forceinline__ bool run_method(const DevHeap& h, uint32_t type, uint
     return Method::apply(h, type, self, a, Method::load(h, type, self, a));
   else
     return Method::run(h, type, self, a);
+}
+
+// The method on one lane's slot: every lane enters for a wavefront method,
+// only live lanes otherwise.
+template <class Method>
+__device__ __forceinline__ bool run_slot(const DevHeap& h, uint32_t type, uint32_t self, bool live,
+                                         const typename Method::Args& a) {
+  if constexpr (HasWave<Method>::value) {
+    const bool del = Method::run_wave(h, type, self, live, a);
+    return live && del;
+  } else {
+    bool del = false;
+    if (live) del = run_method<Method>(h, type, self, a);
+    return del;
+  }
 }
 
 // Makes the value's registers an input of an empty asm statement: the
@@ -349,8 +379,7 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
       const uint32_t bid = R[e];
       const uint64_t snap = S[e];
       visits += (uint32_t)__popcll(snap);
-      bool del = false;
-      if ((snap >> lane) & 1ull) del = run_method<Method>(h, type, make_obj(bid, lane), args);
+      const bool del = run_slot<Method>(h, type, make_obj(bid, lane), (snap >> lane) & 1ull, args);
       const uint64_t dm = __ballot(del);
       if (dm) freed += delete_mask(h, type, bid, dm);
     }
@@ -366,8 +395,7 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
       const uint32_t bid = valid ? R[e] : 0u;
       const uint64_t snap = valid ? S[e] : 0ull;
       visits += (uint32_t)__popcll(__ballot((snap >> slot) & 1ull));
-      bool del = false;
-      if ((snap >> slot) & 1ull) del = run_method<Method>(h, type, make_obj(bid, slot), args);
+      const bool del = run_slot<Method>(h, type, make_obj(bid, slot), (snap >> slot) & 1ull, args);
       const uint64_t dm = __ballot(del);
       for (uint32_t k = 0; k < bpw && dm; ++k) {
         const uint64_t part = (dm >> (k * c)) & group;
