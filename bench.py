@@ -67,7 +67,8 @@ def gol_kernel_bytes(kind, launches, st, M):
     A, K = 1, 2  # Alive, Candidate type ids
     va, vk = st["visits"][A] / 2, st["visits"][K] / 2     # each type is visited by two do-alls
     if kind == "gol_alive_prep":
-        return va * (12 + 64) + st["allocs"][K] * 16 + va / 64 * 12
+        # handles and live flags of the 24 cells around (5 x 5 neighbourhood)
+        return va * (12 + 192) + st["allocs"][K] * 16 + va / 64 * 12
     if kind == "gol_cand_prep":
         return vk * (12 + 64) + vk / 64 * 12
     if kind == "gol_alive_update":
@@ -579,13 +580,6 @@ def main():
         summ = profiling.read_summary(os.path.join(ROOT, "profiles", f"traffic_{wl.name}.txt"))
         if summ and summ["source_hash"] == profiling.source_hash() and best in summ["kernels"]:
             roof["traffic"] = summ["kernels"][best]
-
-    # Atomic read-modify-writes the methods issue themselves (claim flags,
-    # move requests): for the GoL the dominant kernel's compare-and-swaps.
-    if roof is not None and best == "gol_alive_prep":
-        n_at = stp["method_atomics"]
-        roof["method_atomics_per_launch"] = n_at / kern[best][0]
-        roof["method_atomics_per_s"] = n_at / (kern[best][1] / 1e3)
 
     cpu = None
     if not args.no_cpu_baseline:

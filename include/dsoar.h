@@ -328,8 +328,8 @@ int dsoar_probe_copy(const void* src_dev, void* dst_dev, size_t bytes, void* str
 /* ------------------------------------------------- Game of Life as objects
  * The paper's game-of-life application (Sec. 4, applications figure) on
  * square tori, one or many worlds in one heap.  The heap must declare, in
- * this order, Cell {int32 alive, int32 cand}, Alive {int32 cell, int32 world,
- * int32 action} and Candidate {int32 cell, int32 world, int32 action}.  One
+ * this order, Cell {int32 alive}, Alive {int32 cell, int32 world, int32
+ * action} and Candidate {int32 cell, int32 world, int32 action}.  One
  * generation is four do-alls (Alive, Candidate, Alive, Candidate); Candidate
  * and Alive objects are created and deleted with device new/delete. */
 typedef struct dsoar_gol dsoar_gol;

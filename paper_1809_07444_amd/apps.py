@@ -69,7 +69,7 @@ def micro_run(inp, num_blocks: int = 4096, capacity: int = 64, flags: int = C.DO
 
 # ------------------------------------------------------------ game of life --
 
-GOL_TYPES = [(4, 4), (4, 4, 4), (4, 4, 4)]  # Cell, Alive, Candidate
+GOL_TYPES = [(4,), (4, 4, 4), (4, 4, 4)]  # Cell, Alive, Candidate
 GOL_CELL, GOL_ALIVE, GOL_CAND = 0, 1, 2
 
 
@@ -77,10 +77,10 @@ def gol_blocks_for(total_cells: int, capacity: int = 64) -> int:
     """Heap size for a Game of Life state: one block per `capacity` cells for
     the Cells and twice as many again for Alive and Candidate objects (at most
     one of them per cell, plus partly filled blocks), rounded up to a power of
-    two.  Capacity 0 (per-type capacities by object size): Cells {2 x 4 B}
-    have 64 slots, Alive and Candidate {3 x 4 B} 32."""
+    two.  Capacity 0 (per-type capacities by object size): Cells {4 B} have
+    64 slots, Alive and Candidate {3 x 4 B} 16."""
     if capacity == 0:
-        need = max(64, -(-total_cells // 64) + 2 * -(-total_cells // 32))
+        need = max(64, -(-total_cells // 64) + 2 * -(-total_cells // 16))
     else:
         need = max(64, 3 * -(-total_cells // capacity))
     return 1 << (need - 1).bit_length()

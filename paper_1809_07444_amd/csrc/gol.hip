@@ -1,17 +1,18 @@
 // Game of Life as objects (B3/S23 on square tori), for one world or many
 // worlds sharing one heap.
 //
-// Types: Cell {alive, cand} is created once per grid position and found
-// through a position -> handle index; Alive {cell, world, action} exists for
-// every live cell; Candidate {cell, world, action} exists during a generation
-// for every dead cell next to a live one.  One generation is four do-alls:
-//   1 Alive:     count live neighbours -> action (die unless 2 or 3); for each
-//                dead neighbour, the lane that flips the Cell's cand flag from
-//                0 to 1 creates that cell's Candidate.
+// Types: Cell {alive} is created once per grid position and found through a
+// position -> handle index; Alive {cell, world, action} exists for every live
+// cell; Candidate {cell, world, action} exists during a generation for every
+// dead cell next to a live one.  One generation is four do-alls:
+//   1 Alive:     count live neighbours -> action (die unless 2 or 3); create
+//                the Candidate of each dead neighbour whose first live
+//                neighbour (in a fixed direction order) is this cell, so
+//                that every such cell gets exactly one, without atomics.
 //   2 Candidate: action = born iff exactly 3 live neighbours.
 //   3 Alive:     dying ones clear their Cell's alive flag and delete themselves.
-//   4 Candidate: clear the Cell's cand flag; born ones set alive and create an
-//                Alive; every Candidate deletes itself.
+//   4 Candidate: born ones set their Cell's alive flag and create an Alive;
+//                every Candidate deletes itself.
 // Live flags are only read in phases 1-2 and only written in 3-4, so the
 // kernel boundaries make the update synchronous.
 #include <string.h>
@@ -24,7 +25,7 @@ namespace dsoar {
 namespace {
 
 enum : uint32_t { kCell = 0, kAlive = 1, kCand = 2 };
-enum : uint32_t { kCAlive = 0, kCCand = 1 };
+enum : uint32_t { kCAlive = 0 };
 enum : uint32_t { kACell = 0, kAWorld = 1, kAAction = 2 };
 
 struct World {
@@ -65,6 +66,42 @@ __device__ __forceinline__ uint32_t neighbour(uint32_t off, uint32_t side, uint3
   return off + ny * side + nx;
 }
 
+// The 5 x 5 neighbourhood of a cell: bit (dy + 2) * 5 + (dx + 2) for the
+// cell at offset (dx, dy).  Directions d = 0..7 in the order of neighbour();
+// direction 7 - d is the opposite of direction d.
+constexpr int kDirX[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
+constexpr int kDirY[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
+constexpr uint32_t nb_bit(int dx, int dy) { return (uint32_t)((dy + 2) * 5 + dx + 2); }
+
+// A dead cell's Candidate is created by the first of its live neighbours in
+// direction order.  The dead neighbour in direction d sees this cell in
+// direction 7 - d, so this cell creates it iff none of the dead cell's
+// neighbours in the directions before 7 - d is alive; owner_mask(d) holds
+// those cells.  On a torus smaller than 5 x 5 several offsets name one cell:
+// each offset is loaded from the cell it names, so the rule still picks one
+// creator per dead cell.
+constexpr uint32_t owner_mask(uint32_t d) {
+  uint32_t m = 0;
+  for (uint32_t e = 0; e + d < 7; ++e) m |= 1u << nb_bit(kDirX[d] + kDirX[e], kDirY[d] + kDirY[e]);
+  return m;
+}
+constexpr uint32_t ring_mask() {
+  uint32_t m = 0;
+  for (uint32_t d = 0; d < 8; ++d) m |= 1u << nb_bit(kDirX[d], kDirY[d]);
+  return m;
+}
+
+// x + dx on a torus of side `side`, dx in -2..2 (any side >= 1).
+__device__ __forceinline__ uint32_t torus_add(uint32_t x, int dx, uint32_t side) {
+  int v = (int)x + dx;
+  const int s = (int)side;
+  v = v < 0 ? v + s : v;
+  v = v < 0 ? v + s : v;
+  v = v >= s ? v - s : v;
+  v = v >= s ? v - s : v;
+  return (uint32_t)v;
+}
+
 struct AlivePrep {
   static constexpr uint32_t kKind = 30;
   using Args = World;
@@ -74,26 +111,33 @@ struct AlivePrep {
     const uint32_t off = w.off[wid], side = w.side[wid];
     const uint32_t local = g - off;
     const uint32_t y = local / side, x = local - y * side;
-    uint32_t live = 0, claim = 0, cas = 0;
+    uint32_t row[5], col[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      row[i] = off + torus_add(y, i - 2, side) * side;
+      col[i] = torus_add(x, i - 2, side);
+    }
+    // Live flags of the 24 surrounding cells; all loads are independent.
+    uint32_t hc[25];
+#pragma unroll
+    for (uint32_t b = 0; b < 25; ++b) hc[b] = b == 12 ? kNull : w.cells[row[b / 5] + col[b % 5]];
+    uint32_t alive = 0, present = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < 25; ++b) {
+      if (b == 12) continue;
+      const bool here = hc[b] != kNull;  // missing only after an out-of-memory init
+      const uint32_t v = *field_ptr<uint32_t>(h, here ? hc[b] : 0u, kCell, kCAlive);  // 0: any in-heap Cell slot
+      present |= (uint32_t)here << b;
+      alive |= (uint32_t)(here && v != 0) << b;
+    }
+    uint32_t claim = 0;
 #pragma unroll
     for (uint32_t d = 0; d < 8; ++d) {
-      const uint32_t hc = w.cells[neighbour(off, side, x, y, d)];
-      if (hc == kNull) continue;  // only after an out-of-memory init
-      const uint32_t alive = *field_ptr<uint32_t>(h, hc, kCell, kCAlive);
-      live += alive;
-      if (!alive) {
-        // The lane that flips the dead cell's cand flag creates its Candidate.
-        // The pre-check may read a stale 0 (workgroup scope: served by this
-        // XCD's L2); the compare-and-swap then decides.  It never reads a
-        // stale 1: the flag only goes 0 -> 1 during this phase.
-        uint32_t* cand = field_ptr<uint32_t>(h, hc, kCell, kCCand);
-        if (__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
-          ++cas;
-          if (atomicCAS(cand, 0u, 1u) == 0u) claim |= 1u << d;
-        }
-      }
+      const uint32_t b = nb_bit(kDirX[d], kDirY[d]);
+      const bool dead = ((present & ~alive) >> b) & 1u;
+      if (dead && !(alive & owner_mask(d))) claim |= 1u << d;
     }
-    wave_count(h, kCntMethodAtomics, cas);
+    const uint32_t live = (uint32_t)__popc(alive & ring_mask());
     // One coalesced allocation for all of the wavefront's new Candidates.
     new_many(h, kCand, (uint32_t)__popc(claim), [&](uint32_t j, uint32_t o) {
       if (o == kNull) return;
@@ -137,7 +181,6 @@ struct CandUpdate {
     const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
     const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
     const bool born = *field_ptr<uint32_t>(h, self, type, kAAction) != 0;
-    *cell_field(h, w, g, kCCand) = 0;
     if (born) {
       *cell_field(h, w, g, kCAlive) = 1;
       const uint32_t o = dsoar_new(h, kAlive);
@@ -167,10 +210,7 @@ __global__ void gol_init_kernel(DevHeap h, World w, uint32_t num_worlds, uint32_
   if (g >= total) return;
   const uint32_t hc = dsoar_new(h, kCell);
   const uint32_t alive = grid[g] ? 1u : 0u;
-  if (hc != kNull) {
-    *field_ptr<uint32_t>(h, hc, kCell, kCAlive) = alive;
-    *field_ptr<uint32_t>(h, hc, kCell, kCCand) = 0;
-  }
+  if (hc != kNull) *field_ptr<uint32_t>(h, hc, kCell, kCAlive) = alive;
   const_cast<uint32_t*>(w.cells)[g] = hc;
   if (alive) {
     const uint32_t o = dsoar_new(h, kAlive);
@@ -202,10 +242,7 @@ __global__ void gol_admit_kernel(DevHeap h, World w, uint32_t slot, uint32_t off
   const uint32_t g = off + i;
   const uint32_t hc = dsoar_new(h, kCell);
   const uint32_t alive = grid[i] ? 1u : 0u;
-  if (hc != kNull) {
-    *field_ptr<uint32_t>(h, hc, kCell, kCAlive) = alive;
-    *field_ptr<uint32_t>(h, hc, kCell, kCCand) = 0;
-  }
+  if (hc != kNull) *field_ptr<uint32_t>(h, hc, kCell, kCAlive) = alive;
   const_cast<uint32_t*>(w.cells)[g] = hc;
   new_many(h, kAlive, alive, [&](uint32_t, uint32_t o) {
     if (o == kNull) return;
@@ -234,7 +271,7 @@ struct GolDeleteWorld {
 
 bool gol_heap_ok(const dsoar_heap* h) {
   if (h->desc.num_types < 3) return false;
-  const uint32_t want[3] = {2, 3, 3};
+  const uint32_t want[3] = {1, 3, 3};
   for (uint32_t t = 0; t < 3; ++t) {
     const dsoar_type_layout& L = h->desc.types[t];
     if (L.num_fields < want[t]) return false;

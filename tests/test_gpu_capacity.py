@@ -2,7 +2,7 @@
 layout's capacities equal the oracle's; mixed-capacity heaps keep every
 invariant under churn and the do-all (64 / c blocks per wavefront) visits each
 live object exactly once; Game of Life with Cells at 64 and Alive/Candidate at
-32 slots equals the oracle."""
+16 slots equals the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -73,7 +73,7 @@ def test_gol_per_type_capacity_equals_oracle(seed):
     sides = rng.integers(3, 90, size=5)
     grids = [W.gol_grid(int(s), int(s), seed=seed * 100 + i) for i, s in enumerate(sides)]
     gol = apps.GameOfLife(grids, capacity=0)
-    assert gol.heap.type_capacity == [64, 32, 32]
+    assert gol.heap.type_capacity == [64, 16, 16]
     gol.init()
     gol.step(40, C.DO_PERSISTENT | C.GOL_GRAPH)
     for got, g in zip(gol.read(), grids):
