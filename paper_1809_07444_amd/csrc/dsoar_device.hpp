@@ -514,9 +514,12 @@ __device__ __forceinline__ void unpin_block(const DevHeap& h, uint32_t bid) {
 
 // A block just taken from the free bitmap: its object bitmap first, then its
 // type word (release), so that a reservation that reads the new type word
-// also reads the initialised bitmap.  Per lane.
+// also reads the initialised bitmap.  Per lane.  With online reclamation the
+// block may have been freed during this kernel: the acquire fence orders the
+// type-word read after the free-bitmap update that handed the block over.
+// Quiescent reclamation frees blocks only in earlier kernels.
 __device__ __forceinline__ uint32_t publish_block(const DevHeap& h, uint32_t bid, uint32_t type, uint64_t bits) {
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (h.online_reclaim) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const uint32_t w = tw_with(__hip_atomic_load(h.block_type + bid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), type);
   __hip_atomic_store(h.obj_bitmap + bid, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(h.block_type + bid, w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -703,9 +706,16 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
       got = want >= c ? cap : ((1ull << want) - 1);
       uint32_t w = 0;
       if (is_first_active()) w = publish_block(h, (uint32_t)bid, type, got);
-      bm_set(allocated_bm(h, type), (uint32_t)bid);
+      // allocated[type] and, unless full, active[type]: both ORs are issued
+      // before either result is used (each keeps set's retry and cascade).
+      const Bitmap alloc = allocated_bm(h, type);
+      const uint32_t bw = (uint32_t)bid >> 6;
+      const uint64_t bm = 1ull << ((uint32_t)bid & 63u);
+      const uint64_t pa = bm_set_bits0_issue(alloc, bw, bm);
+      const uint64_t pc = got != cap ? bm_set_bits0_issue(active, bw, bm) : 0ull;
+      bm_set_bits0_settle(alloc, bw, bm, pa);
       if (got != cap) {
-        bm_set(active, (uint32_t)bid);
+        bm_set_bits0_settle(active, bw, bm, pc);
         cur = bid;
         cur_avail = ~got & cap;
         cur_tw = bcast32(w);
