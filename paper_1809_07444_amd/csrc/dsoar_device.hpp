@@ -394,35 +394,63 @@ __device__ __forceinline__ uint32_t level_digit(uint32_t start, uint32_t l) {
   return (start >> ((6 * l) % 30)) & 63u;
 }
 
-// try_find_set(): descend from the top word, one load per level (a
-// logarithmic number of accesses, Sec. 2.4).  At each level the base-64 digit
-// of `start` for that level picks one of the word's set bits, so concurrent
-// searches with different starts spread over the whole bitmap.  An empty word
-// on the way down means the summary is momentarily ahead of its container:
-// FAIL.
-__device__ inline int32_t bm_try_find_set(const Bitmap& b, uint32_t start) {
-  uint32_t idx = 0;
-  for (int32_t l = (int32_t)b.nlevels - 1; l >= 0; --l) {
-    const uint64_t w = load_u64(b.word((uint32_t)l, idx));
-    if (w == 0) return kFail;
-    idx = (idx << 6) | pick_bit(w, level_digit(start, (uint32_t)l));
+// First word of a descent.  With three or more levels the search starts one
+// level below the top, at the word that `start`'s top digit names among that
+// level's words, and reads the top word only if that word is empty: the top
+// word is the bitmap's most contended one, and a bitmap with set bits
+// usually has few empty words one level down.  Either way the descent goes
+// on from a non-empty word, so it still finds a set bit when there is one.
+// False: the whole bitmap is empty.
+__device__ inline bool bm_descend_start(const Bitmap& b, uint32_t start, uint32_t* level, uint32_t* idx,
+                                        uint64_t* w) {
+  const uint32_t top = b.nlevels - 1;
+  if (top >= 2) {
+    const uint32_t nw = ((b.nbits - 1) >> (6 * top)) + 1;  // words one level below the top
+    const uint32_t i = (level_digit(start, top) * nw) >> 6;
+    const uint64_t v = load_u64(b.word(top - 1, i));
+    if (v != 0) {
+      *level = top - 1;
+      *idx = i;
+      *w = v;
+      return true;
+    }
   }
-  return idx < b.nbits ? (int32_t)idx : kFail;
+  const uint64_t v = load_u64(b.word(top, 0));
+  *level = top;
+  *idx = 0;
+  *w = v;
+  return v != 0;
 }
 
 // try_find_set() stopped one level early: the index of a non-empty level-0
-// word (chosen as try_find_set chooses) and its bits, or FAIL.
+// word (chosen as try_find_set chooses) and its bits, or FAIL.  One load per
+// level (a logarithmic number of accesses, Sec. 2.4); at each level the
+// base-64 digit of `start` for that level picks one of the word's set bits,
+// so concurrent searches with different starts spread over the whole bitmap.
+// An empty word on the way down means the summary is momentarily ahead of its
+// container: FAIL.
 __device__ inline int32_t bm_find_word(const Bitmap& b, uint32_t start, uint64_t* bits) {
-  uint32_t idx = 0;
-  for (int32_t l = (int32_t)b.nlevels - 1; l >= 1; --l) {
-    const uint64_t w = load_u64(b.word((uint32_t)l, idx));
+  uint32_t l, idx;
+  uint64_t w;
+  if (!bm_descend_start(b, start, &l, &idx, &w)) return kFail;
+  while (l > 0) {
+    idx = (idx << 6) | pick_bit(w, level_digit(start, l));
+    --l;
+    w = load_u64(b.word(l, idx));
     if (w == 0) return kFail;
-    idx = (idx << 6) | pick_bit(w, level_digit(start, (uint32_t)l));
   }
-  const uint64_t w = load_u64(b.word(0, idx));
-  if (w == 0) return kFail;
   *bits = w;
   return (int32_t)idx;
+}
+
+// try_find_set(): descend to a non-empty level-0 word and pick one of its set
+// bits with the digit of `start` for level 0.
+__device__ inline int32_t bm_try_find_set(const Bitmap& b, uint32_t start) {
+  uint64_t w = 0;
+  const int32_t word = bm_find_word(b, start, &w);
+  if (word == kFail) return kFail;
+  const uint32_t idx = ((uint32_t)word << 6) | pick_bit(w, level_digit(start, 0));
+  return idx < b.nbits ? (int32_t)idx : kFail;
 }
 
 // clear() of Sec. 2.1: find a set bit and clear it, repeating until this
@@ -447,15 +475,10 @@ __device__ inline int32_t bm_find_clear(const Bitmap& b, uint32_t start) {
 // Returns the bits gained (0 = the bitmap is empty) and the word in *word.
 __device__ inline uint64_t bm_take_word(const Bitmap& b, uint32_t start, uint32_t want, uint32_t* word) {
   for (uint32_t spins = 0; spins < kSpinLimit; ++spins) {
-    uint32_t idx = 0;
     uint64_t w = 0;
-    for (int32_t l = (int32_t)b.nlevels - 1; l >= 0; --l) {
-      w = load_u64(b.word((uint32_t)l, idx));
-      if (w == 0) break;
-      if (l == 0) break;
-      idx = (idx << 6) | pick_bit(w, level_digit(start, (uint32_t)l));
-    }
-    if (w != 0) {
+    const int32_t found = bm_find_word(b, start, &w);
+    const uint32_t idx = found == kFail ? 0u : (uint32_t)found;
+    if (found != kFail) {
       const uint64_t take = take_from(w, want < (uint32_t)__popcll(w) ? want : (uint32_t)__popcll(w), start & 63u);
       const uint64_t prev = lead_and(b.word(0, idx), ~take);
       const uint64_t got = prev & take;
