@@ -269,10 +269,11 @@ __device__ __forceinline__ uint64_t pack_flag(uint32_t epoch, uint64_t status, u
 }
 
 // Parallel enumeration (Sec. 2.3): scan allocated[type] level 0 (step 1, set
-// bits -> block ids), drop the empty blocks (reclaiming them) and compact the
-// rest into R with their object-bitmap snapshots (step 2, prefix sum).  One
-// pass: tile prefixes come from a decoupled look-back over per-tile flags,
-// tiles taken in launch order from a ticket counter.  Each wavefront covers
+// bits -> block ids), drop the empty blocks (reclaiming them once the tile's
+// entries are out) and compact the rest into R with their object-bitmap
+// snapshots (step 2, prefix sum).  One pass: tile prefixes come from a
+// decoupled look-back over per-tile flags, tiles taken in launch order from a
+// ticket counter.  Each wavefront covers
 // WPW level-0 words (64 blocks each); all their loads are issued before any
 // is used.  The heap is quiescent, so plain loads see the previous kernels.
 template <uint32_t WPW>
@@ -299,12 +300,12 @@ __global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeap h, u
     snap[j] = bit ? meta_load(h.obj_bitmap + b) : 0ull;
   }
   uint32_t wave_total = 0;
+  uint64_t empty[WPW];  // allocated blocks without objects: reclaimed at the end
 #pragma unroll
   for (uint32_t j = 0; j < WPW; ++j) {
     const bool bit = (w[j] >> lane) & 1ull;
     live[j] = __ballot(bit && snap[j] != 0);
-    const uint64_t rc = __ballot(bit && snap[j] == 0);
-    if (rc) reclaim_word(h, type, word0 + j, rc);
+    empty[j] = __ballot(bit && snap[j] == 0);
     wave_total += (uint32_t)__popcll(live[j]);
   }
   if (lane == 0) s_wave_total[wave] = wave_total;
@@ -364,6 +365,12 @@ __global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeap h, u
     }
     base += (uint32_t)__popcll(live[j]);
   }
+  // Reclamation does not change the list, so it comes after the tile's
+  // prefix is published and its entries are written: later tiles' look-back
+  // never waits for these atomics.
+#pragma unroll
+  for (uint32_t j = 0; j < WPW; ++j)
+    if (empty[j]) reclaim_word(h, type, word0 + j, empty[j]);
   if (tile == out.num_tiles - 1 && threadIdx.x == 0) {
     __hip_atomic_store(&out.st->count, s_prefix + tile_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&out.st->tile_counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
