@@ -32,6 +32,9 @@ METHOD_KIND = {
     "Choose": "sugar_choose", "Move": "sugar_move", "Eat": "sugar_eat", "Request": "sugar_request",
     "Birth": "sugar_birth", "VisitCount": "visit_count", "DeleteIfMod": "delete_if_mod",
     "FieldGather": "gather", "GolDeleteWorld": "gol_delete_world", "SugarDeleteWorld": "sugar_delete_world",
+    "Decide": "traffic_decide", "Drive": "traffic_drive", "BodyForce": "collide_force", "BodyMove": "collide_move",
+    "BodyRoot": "collide_root", "BodyTarget": "collide_target", "BodyMerge": "collide_merge",
+    "BodyRemove": "collide_remove",
 }
 
 
