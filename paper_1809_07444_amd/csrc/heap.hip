@@ -603,14 +603,12 @@ struct FieldGather {
 // ------------------------------------------------------ shared host helpers
 
 int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s) {
-  const int rec = timing_begin(h, kKindEnumerate, s);
   if (h->enum_wpw == kEnumWideWords)
-    hipLaunchKernelGGL(enumerate_kernel<kEnumWideWords>, dim3(h->num_tiles), dim3(kEnumWaves * 64), 0, s, h->dev,
-                       type, h->enum_out[type]);
+    launch_timed(h, kKindEnumerate, enumerate_kernel<kEnumWideWords>, dim3(h->num_tiles), dim3(kEnumWaves * 64),
+                 s, h->dev, type, h->enum_out[type]);
   else
-    hipLaunchKernelGGL(enumerate_kernel<1>, dim3(h->num_tiles), dim3(kEnumWaves * 64), 0, s, h->dev, type,
-                       h->enum_out[type]);
-  timing_end(h, rec, s);
+    launch_timed(h, kKindEnumerate, enumerate_kernel<1>, dim3(h->num_tiles), dim3(kEnumWaves * 64), s, h->dev,
+                 type, h->enum_out[type]);
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }

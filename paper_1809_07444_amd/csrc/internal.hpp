@@ -2,6 +2,7 @@
 // translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -89,17 +90,20 @@ inline int hip_fail(dsoar_heap* h, hipError_t e) {
 constexpr uint32_t kTimingCap = 8192;
 constexpr uint32_t kKindEnumerate = 1;
 
-// Brackets one launch with a pair of events when timing is on.  Returns the
-// record index (or -1 when off or full).
-inline int timing_begin(dsoar_heap* h, uint32_t kind, hipStream_t s) {
-  if (!h->timing || h->rec_used >= kTimingCap) return -1;
-  const int r = (int)h->rec_used++;
-  h->rec_kind[r] = kind;
-  (void)hipEventRecord(h->ev_pool[2 * r], s);
-  return r;
-}
-inline void timing_end(dsoar_heap* h, int r, hipStream_t s) {
-  if (r >= 0) (void)hipEventRecord(h->ev_pool[2 * r + 1], s);
+// Launches `kernel` on stream s.  With timing on (and room in the record), the
+// launch itself carries a start and a stop event (hipExtLaunchKernel): they
+// take the dispatch's own begin and end timestamps, so the recorded time is
+// the kernel's execution without the gaps around it.
+template <class K, class... A>
+inline void launch_timed(dsoar_heap* h, uint32_t kind, K kernel, dim3 grid, dim3 block, hipStream_t s,
+                         A... args) {
+  if (h->timing && h->rec_used < kTimingCap) {
+    const uint32_t r = h->rec_used++;
+    h->rec_kind[r] = kind;
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, h->ev_pool[2 * r], h->ev_pool[2 * r + 1], 0u, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+  }
 }
 
 int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s);
@@ -430,10 +434,8 @@ int launch_doall(dsoar_heap* h, uint32_t type, const typename Method::Args& args
   } else {
     grid = h->num_cus * h->doall_wgs_per_cu;
   }
-  const int rec = timing_begin(h, Method::kKind, s);
-  hipLaunchKernelGGL(doall_kernel<Method>, dim3(grid), dim3(threads), 0, s, h->dev, type, eo.R, eo.S,
-                     &eo.st->count, args);
-  timing_end(h, rec, s);
+  launch_timed(h, Method::kKind, doall_kernel<Method>, dim3(grid), dim3(threads), s, h->dev, type,
+               (const uint32_t*)eo.R, (const uint64_t*)eo.S, (const uint32_t*)&eo.st->count, args);
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }
