@@ -97,6 +97,8 @@ def lib() -> ctypes.CDLL:
         L.orc_collide_run.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.orc_traffic_run.restype = ctypes.c_int
         L.orc_traffic_run.argtypes = [i32, i32, i32, i32, u64, i32, ctypes.c_uint32, ctypes.c_uint32, vp, vp]
+        L.orc_wator_run.restype = ctypes.c_int
+        L.orc_wator_run.argtypes = [i32, i32, i32, u64, i32, i32, i32, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -364,3 +366,37 @@ def collide_run(state: CollideState, steps: int, params: dict) -> CollideState:
         raise ValueError("orc_collide_run failed")
     return CollideState(*a, merges=state.merges + int(counts[0]))
 
+
+
+@dataclass
+class WatorState:
+    kind: np.ndarray     # int32 [side, side]: 0 empty, 1 fish, 2 shark
+    age: np.ndarray      # int32 [side, side]
+    energy: np.ndarray   # int32 [side, side], sharks
+    fish_born: int = 0
+    sharks_born: int = 0
+    fish_eaten: int = 0
+    sharks_starved: int = 0
+
+    def copy(self) -> "WatorState":
+        return WatorState(self.kind.copy(), self.age.copy(), self.energy.copy(), self.fish_born,
+                          self.sharks_born, self.fish_eaten, self.sharks_starved)
+
+
+def wator_run(state: WatorState, steps: int, seed: int, rules: dict, step0: int = 0) -> WatorState:
+    """Wa-Tor (fish and sharks) for `steps` steps from step index step0; counts accumulate."""
+    s = state.copy()
+    s.kind = np.ascontiguousarray(s.kind, dtype=np.int32)
+    s.age = np.ascontiguousarray(s.age, dtype=np.int32)
+    s.energy = np.ascontiguousarray(s.energy, dtype=np.int32)
+    counts = np.zeros(4, dtype=np.int64)
+    side = s.kind.shape[0]
+    rc = lib().orc_wator_run(side, steps, step0, seed, rules["fish_breed"], rules["shark_breed"], rules["starve"],
+                             _p(s.kind), _p(s.age), _p(s.energy), _p(counts))
+    if rc != 0:
+        raise ValueError("orc_wator_run failed")
+    s.fish_born += int(counts[0])
+    s.sharks_born += int(counts[1])
+    s.fish_eaten += int(counts[2])
+    s.sharks_starved += int(counts[3])
+    return s

@@ -810,3 +810,148 @@ int orc_collide_run(int32_t n, int32_t steps, const orc_collide_params *p, float
   return 0;
 }
 
+
+/* ================================================================= wa-tor
+ * Fish and sharks on a square torus (the paper names the application; the
+ * rules are Dewdney's published ones in a synchronous reading, written out in
+ * full).  kind[c]: 0 empty, 1 fish, 2 shark; age[c] for both, energy[c] for
+ * sharks.  Neighbours of a cell in the order up, right, down, left (torus).
+ * One step t:
+ *  Fish: on the grid at the start of the phase, a fish picks one of its empty
+ *    neighbours, the k-th in neighbour order with k = U{0..n-1} from
+ *    hash(seed, 40, c, t), n = number of empty neighbours.  A target cell
+ *    requested by several fish goes to the lowest requesting cell.  Every
+ *    fish ages by one; a fish that moves with age >= fish_breed leaves a
+ *    newborn fish (age 0) in the cell it left and its own age becomes 0.
+ *  Sharks: on the grid after the fish phase, a shark picks one of its fish
+ *    neighbours (k from hash(seed, 41, c, t) over them) or, if it has none
+ *    and its energy is above 1, one of its empty neighbours (same draw).  The
+ *    lowest requesting cell wins a target.  A shark that moves onto a fish
+ *    eats it and its energy becomes `starve`; any other shark loses one unit
+ *    and dies where it stands when it reaches 0.  Sharks age and breed as
+ *    fish do (shark_breed; a newborn shark has energy `starve`).
+ * counts[0..3] += fish born, sharks born, fish eaten, sharks starved. */
+
+#define WATOR_STREAM_FISH 40
+#define WATOR_STREAM_SHARK 41
+
+static int64_t wator_nb(int32_t side, int64_t c, int d) {
+  const int64_t x = c % side, y = c / side;
+  int64_t nx = x, ny = y;
+  if (d == 0) ny = y == 0 ? side - 1 : y - 1;
+  if (d == 1) nx = x + 1 == side ? 0 : x + 1;
+  if (d == 2) ny = y + 1 == side ? 0 : y + 1;
+  if (d == 3) nx = x == 0 ? side - 1 : x - 1;
+  return ny * side + nx;
+}
+
+/* Lowest requesting cell per target: win[target] = min over requesters. */
+static void wator_resolve(int64_t n, const int64_t *target, int64_t *win) {
+  for (int64_t c = 0; c < n; c++) win[c] = -1;
+  for (int64_t c = 0; c < n; c++) {
+    const int64_t t = target[c];
+    if (t >= 0 && (win[t] < 0 || c < win[t])) win[t] = c;
+  }
+}
+
+int orc_wator_run(int32_t side, int32_t steps, int32_t step0, uint64_t seed, int32_t fish_breed,
+                  int32_t shark_breed, int32_t starve, int32_t *kind, int32_t *age, int32_t *energy,
+                  int64_t *counts) {
+  if (side < 1 || steps < 0 || fish_breed < 1 || shark_breed < 1 || starve < 1) return -1;
+  const int64_t n = (int64_t)side * side;
+  int64_t *target = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+  int64_t *win = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+  int32_t *k0 = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  if (!target || !win || !k0) {
+    free(target);
+    free(win);
+    free(k0);
+    return -1;
+  }
+  for (int32_t s = 0; s < steps; s++) {
+    const uint64_t t = (uint64_t)(step0 + s);
+    /* fish phase */
+    memcpy(k0, kind, (size_t)n * sizeof(int32_t));
+    for (int64_t c = 0; c < n; c++) {
+      target[c] = -1;
+      if (k0[c] != 1) continue;
+      int64_t opt[4];
+      int m = 0;
+      for (int d = 0; d < 4; d++) {
+        const int64_t q = wator_nb(side, c, d);
+        if (k0[q] == 0) opt[m++] = q;
+      }
+      if (m > 0) target[c] = opt[orc_uniform_int(orc_hash(seed, WATOR_STREAM_FISH, (uint64_t)c, t), 0, m - 1)];
+    }
+    wator_resolve(n, target, win);
+    for (int64_t c = 0; c < n; c++) {
+      if (k0[c] != 1) continue;
+      const int32_t a = age[c] + 1;
+      const int64_t q = target[c];
+      if (q >= 0 && win[q] == c) {
+        kind[q] = 1;
+        if (a >= fish_breed) {
+          age[q] = 0;
+          age[c] = 0; /* the newborn stays in the old cell */
+          counts[0]++;
+        } else {
+          age[q] = a;
+          kind[c] = 0;
+        }
+      } else {
+        age[c] = a;
+      }
+    }
+    /* shark phase */
+    memcpy(k0, kind, (size_t)n * sizeof(int32_t));
+    for (int64_t c = 0; c < n; c++) {
+      target[c] = -1;
+      if (k0[c] != 2) continue;
+      int64_t fish[4], empty[4];
+      int nf = 0, ne = 0;
+      for (int d = 0; d < 4; d++) {
+        const int64_t q = wator_nb(side, c, d);
+        if (k0[q] == 1) fish[nf++] = q;
+        if (k0[q] == 0) empty[ne++] = q;
+      }
+      const uint64_t h = orc_hash(seed, WATOR_STREAM_SHARK, (uint64_t)c, t);
+      if (nf > 0)
+        target[c] = fish[orc_uniform_int(h, 0, nf - 1)];
+      else if (ne > 0 && energy[c] > 1)
+        target[c] = empty[orc_uniform_int(h, 0, ne - 1)];
+    }
+    wator_resolve(n, target, win);
+    for (int64_t c = 0; c < n; c++) {
+      if (k0[c] != 2) continue;
+      const int64_t q = target[c];
+      const int won = q >= 0 && win[q] == c;
+      const int ate = won && k0[q] == 1;
+      const int32_t e = ate ? starve : energy[c] - 1;
+      const int32_t a = age[c] + 1;
+      if (e <= 0) {
+        kind[c] = 0;
+        counts[3]++;
+      } else if (won) {
+        if (ate) counts[2]++;
+        kind[q] = 2;
+        energy[q] = e;
+        if (a >= shark_breed) {
+          age[q] = 0;
+          age[c] = 0;
+          energy[c] = starve;
+          counts[1]++;
+        } else {
+          age[q] = a;
+          kind[c] = 0;
+        }
+      } else {
+        energy[c] = e;
+        age[c] = a;
+      }
+    }
+  }
+  free(target);
+  free(win);
+  free(k0);
+  return 0;
+}

@@ -135,4 +135,14 @@ typedef struct {
 int orc_collide_run(int32_t n, int32_t steps, const orc_collide_params *p, float *x, float *y, float *vx,
                     float *vy, float *m, int64_t *counts);
 
+/* ------------------------------------------------------------ wa-tor ---- */
+/* Fish and sharks on a side x side torus (the paper's "wator" application,
+ * Fig. 6h; Dewdney's rules in a synchronous reading).  kind[c] 0 empty, 1
+ * fish, 2 shark; age[c]; energy[c] (sharks).  Updated in place for `steps`
+ * steps from step index step0; counts[0..3] += fish born, sharks born, fish
+ * eaten, sharks starved. */
+int orc_wator_run(int32_t side, int32_t steps, int32_t step0, uint64_t seed, int32_t fish_breed,
+                  int32_t shark_breed, int32_t starve, int32_t *kind, int32_t *age, int32_t *energy,
+                  int64_t *counts);
+
 #endif

@@ -55,6 +55,12 @@ S_BODY_Y = 35
 S_BODY_VX = 36
 S_BODY_VY = 37
 S_BODY_M = 38
+S_WATOR_FISH = 40    # drawn by the method itself, each step (both sides implement hash)
+S_WATOR_SHARK = 41   # idem
+S_WATOR_KIND = 42
+S_WATOR_FISH_AGE = 43
+S_WATOR_SHARK_AGE = 44
+S_WATOR_ENERGY = 45
 
 DEFAULT_SEED = 24301
 BERNOULLI_0_1 = 1677721  # floor(0.1 * 2**24)

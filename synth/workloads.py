@@ -235,3 +235,37 @@ def collide_inputs(n: int = 4096, seed: int = rng.DEFAULT_SEED, box: float = 8.0
          np.float32(1.0 / 1024)).astype(np.float32)
     return CollideInputs(n, seed, x, y, vx, vy, m)
 
+
+
+# ------------------------------------------------------------------ wa-tor --
+
+WATOR_RULES = dict(fish_breed=3, shark_breed=10, starve=3)
+WATOR_FISH24 = 5033164   # floor(0.30 * 2**24)
+WATOR_SHARK24 = 838860   # floor(0.05 * 2**24)
+
+
+@dataclass
+class WatorInputs:
+    side: int
+    seed: int
+    kind: np.ndarray     # int32 [side, side]: 0 empty, 1 fish, 2 shark
+    age: np.ndarray      # int32 [side, side]
+    energy: np.ndarray   # int32 [side, side]
+
+
+def wator_inputs(side: int = 1024, seed: int = rng.DEFAULT_SEED, rules: dict = WATOR_RULES,
+                 fish24: int = WATOR_FISH24, shark24: int = WATOR_SHARK24) -> WatorInputs:
+    """Each cell holds a fish with probability fish24 / 2**24, else a shark
+    with probability shark24 / 2**24 (one 24-bit draw); fish ages
+    U{0..fish_breed-1}, shark ages U{0..shark_breed-1}, shark energies
+    U{1..starve}."""
+    c = np.arange(side * side, dtype=np.uint64).reshape(side, side)
+    u = (rng.hash4(seed, rng.S_WATOR_KIND, 0, c) >> np.uint64(40)).astype(np.int64)
+    kind = np.where(u < fish24, 1, np.where(u < fish24 + shark24, 2, 0)).astype(np.int32)
+    fa = rng.uniform_int(rng.hash4(seed, rng.S_WATOR_FISH_AGE, 0, c), 0, rules["fish_breed"] - 1)
+    sa = rng.uniform_int(rng.hash4(seed, rng.S_WATOR_SHARK_AGE, 0, c), 0, rules["shark_breed"] - 1)
+    se = rng.uniform_int(rng.hash4(seed, rng.S_WATOR_ENERGY, 0, c), 1, rules["starve"])
+    age = np.where(kind == 1, fa, np.where(kind == 2, sa, 0)).astype(np.int32)
+    energy = np.where(kind == 2, se, 0).astype(np.int32)
+    return WatorInputs(side, seed, np.ascontiguousarray(kind), np.ascontiguousarray(age),
+                       np.ascontiguousarray(energy))

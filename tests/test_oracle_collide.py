@@ -65,3 +65,14 @@ def test_split_runs_equal_one_run():
     for f in ("x", "y", "vx", "vy", "m"):
         assert np.array_equal(getattr(a, f), getattr(b, f))
     assert a.merges == b.merges
+
+
+def test_zero_merge_radius_never_merges():
+    # The same dense bodies merge with the default radius and never with 0.
+    inp = W.collide_inputs(512, seed=7, box=1.0)
+    st = oracle.CollideState(inp.x, inp.y, inp.vx, inp.vy, inp.m)
+    merged = oracle.collide_run(st, 3, W.COLLIDE_PARAMS)
+    assert merged.merges > 0
+    kept = oracle.collide_run(st, 3, dict(W.COLLIDE_PARAMS, r2_merge=0.0))
+    assert kept.merges == 0
+    assert np.array_equal(kept.m, inp.m)
