@@ -830,6 +830,7 @@ int orc_collide_run(int32_t n, int32_t steps, const orc_collide_params *p, float
  *    eats it and its energy becomes `starve`; any other shark loses one unit
  *    and dies where it stands when it reaches 0.  Sharks age and breed as
  *    fish do (shark_breed; a newborn shark has energy `starve`).
+ * After each step empty cells hold age 0 and energy 0, and fish energy 0.
  * counts[0..3] += fish born, sharks born, fish eaten, sharks starved. */
 
 #define WATOR_STREAM_FISH 40
@@ -948,6 +949,11 @@ int orc_wator_run(int32_t side, int32_t steps, int32_t step0, uint64_t seed, int
         energy[c] = e;
         age[c] = a;
       }
+    }
+    /* Canonical sea: empty cells carry age 0 and energy 0, fish energy 0. */
+    for (int64_t c = 0; c < n; c++) {
+      if (kind[c] == 0) age[c] = 0;
+      if (kind[c] != 2) energy[c] = 0;
     }
   }
   free(target);
