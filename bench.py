@@ -34,7 +34,8 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="gol",
-                   choices=["gol", "micro", "micro_scaled", "batched", "sugarscape", "traffic", "collisions",
+                   choices=["gol", "micro", "micro_scaled", "batched", "sugarscape", "traffic", "collisions", "nbody",
+                            "wator",
                             "serve"])
     p.add_argument("--episodes", type=int, default=200, help="serve: episodes per arrival rate")
     p.add_argument("--rates", default="0.25,0.5,0.75,0.9,1.1",
@@ -386,6 +387,73 @@ class TrafficWorkload(GolWorkload):
                           f"{self.steps} steps, {dt:.2f} s; initial cars + entries + exits / oracle time"}
 
 
+class WatorWorkload(GolWorkload):
+    name = "wator"
+
+    def __init__(self, args):
+        import torch
+        from paper_1809_07444_amd import _capi as C
+        from paper_1809_07444_amd import apps
+        from synth import workloads as W
+        self.C, self.torch = C, torch
+        self.side, self.steps = 2048, 200
+        self.inp = W.wator_inputs(self.side, seed=args.seed)
+        self.rules = W.WATOR_RULES
+        self.sim = apps.Wator(self.inp, self.rules)
+        self.flags = C.DO_PERSISTENT | (0 if args.no_graph else C.GRAPH)
+        self.M = self.sim.heap.num_blocks
+        self.config = {"workload": f"wator-{self.side}x{self.side}-fish0.30-sharks0.05-{self.steps}steps",
+                       "cells": self.side * self.side, "steps": self.steps, "heap_blocks": self.M,
+                       "block_capacity": 64, "graph": not args.no_graph, "seed": args.seed, "rules": self.rules}
+
+    def step(self):
+        self.sim.init()
+        self.sim.step(self.steps, self.flags)
+
+    def profiled_step(self):
+        self.sim.init()
+        self.sim.step(self.steps, self.C.DO_PERSISTENT)
+
+    def stats(self):
+        return self.sim.heap.stats()
+
+    def heap(self):
+        return self.sim.heap
+
+    def kernel_bytes(self, kind, launches, st):
+        vf, vs = st["visits"][0] / 3, st["visits"][1] / 2  # three fish do-alls, two shark do-alls per step
+        # Fields read and written, the four neighbours' kinds, the request
+        # word (an atomic in Decide, a read in Move), the sea cells written,
+        # and the newborns' fields.
+        per_f = {"wator_fish_decide": 8 + 16 + 8, "wator_fish_move": 12 + 8 + 16, "wator_fish_eaten": 8}
+        per_s = {"wator_shark_decide": 12 + 16 + 8, "wator_shark_move": 16 + 12 + 20}
+        if kind in per_f:
+            extra = st["allocs"][0] * 12 if kind == "wator_fish_move" else 0
+            return vf * per_f[kind] + vf / 64 * 12 + extra
+        if kind in per_s:
+            extra = st["allocs"][1] * 16 if kind == "wator_shark_move" else 0
+            return vs * per_s[kind] + vs / 64 * 12 + extra
+        if kind == "enumerate":
+            return launches * (self.M / 8) + (vf + vs) / 64 * 20
+        return None
+
+    def cpu_baseline(self):
+        import oracle
+        st = oracle.WatorState(self.inp.kind, self.inp.age, self.inp.energy)
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < 10 and k < self.steps:
+            st = oracle.wator_run(st, 1, self.inp.seed, self.rules, step0=k)
+            k += 1
+        dt = time.perf_counter() - t0
+        ops = int((self.inp.kind > 0).sum()) * k / self.steps + st.fish_born + st.sharks_born + \
+            st.fish_eaten + st.sharks_starved
+        return {"value": ops / dt, "unit": "allocs+frees/s", "cores": 1, "kind": "oracle",
+                "sample": f"sequential Wa-Tor oracle, full {self.side}x{self.side} sea, first {k} of {self.steps} "
+                          f"steps, {dt:.1f} s; births + meals + starvations (+ the initial animals pro rata) "
+                          f"/ oracle time"}
+
+
 class CollideWorkload(GolWorkload):
     name = "collisions"
     # Per body pair in the force do-all: 2 subtractions, 2 fma (4 flops) for
@@ -402,11 +470,15 @@ class CollideWorkload(GolWorkload):
         self.n, self.steps = args.bodies, 20
         self.box = float(16.0 * math.sqrt(self.n / 16384))
         self.inp = W.collide_inputs(self.n, seed=args.seed, box=self.box)
-        self.params = W.COLLIDE_PARAMS
+        self.params = dict(W.COLLIDE_PARAMS, r2_merge=0.0) if args.workload == "nbody" else W.COLLIDE_PARAMS
+        self.doalls = 6  # do-alls per step, each visiting every live body
+        if args.workload == "nbody":
+            self.name = "nbody"  # merge radius 0: force and move only
+            self.doalls = 2
         self.sim = apps.Collisions(self.inp, self.params)
         self.flags = C.DO_PERSISTENT | (0 if args.no_graph else C.GRAPH)
         self.M = self.sim.heap.num_blocks
-        self.config = {"workload": f"collisions-{self.n}bodies-box{self.box:g}-{self.steps}steps",
+        self.config = {"workload": f"{self.name}-{self.n}bodies-box{self.box:g}-{self.steps}steps",
                        "bodies": self.n, "steps": self.steps, "heap_blocks": self.M, "block_capacity": 64,
                        "graph": not args.no_graph, "seed": args.seed, "params": self.params}
 
@@ -427,11 +499,11 @@ class CollideWorkload(GolWorkload):
     def kernel_flops(self, kind, launches, st):
         if kind != "collide_force":
             return None
-        v = st["visits"][0] / 6  # six do-alls per step visit every live body
+        v = st["visits"][0] / self.doalls
         return v * self.n * self.FLOPS_PER_PAIR
 
     def kernel_bytes(self, kind, launches, st):
-        v = st["visits"][0] / 6
+        v = st["visits"][0] / self.doalls
         per = {"collide_force": 12 + 8 + 16 * 0, "collide_move": 32 + 24, "collide_root": 12 + 4,
                "collide_target": 16 + 4, "collide_merge": 24 + 4, "collide_remove": 8}
         if kind in per:
@@ -453,7 +525,7 @@ class CollideWorkload(GolWorkload):
         ops = int((self.inp.m > 0).sum()) + st.merges
         return {"value": ops / dt, "unit": "allocs+frees/s", "cores": 1, "kind": "oracle",
                 "force_tflops": pairs * self.FLOPS_PER_PAIR / dt / 1e12,
-                "sample": f"sequential collisions oracle, all {self.n} bodies, first {k} of {self.steps} steps, "
+                "sample": f"sequential {self.name} oracle, all {self.n} bodies, first {k} of {self.steps} steps, "
                           f"{dt:.1f} s; initial bodies + merges / oracle time"}
 
 
@@ -512,8 +584,10 @@ def main():
         wl = SugarWorkload(args)
     elif args.workload == "traffic":
         wl = TrafficWorkload(args)
-    elif args.workload == "collisions":
+    elif args.workload in ("collisions", "nbody"):
         wl = CollideWorkload(args)
+    elif args.workload == "wator":
+        wl = WatorWorkload(args)
     else:
         wl = MicroWorkload(args, scaled=args.workload == "micro_scaled")
 

@@ -483,7 +483,9 @@ int dsoar_traffic_read(dsoar_traffic* traffic, int32_t* vel_dev, void* stream);
  * lower id within the merge radius), targets (a non-root merges into the
  * lowest-id root within the radius), merges (mass, momentum and mass-weighted
  * position added in increasing id order), removal of the merged bodies
- * (delete).  Single-precision operations, one rounding each, in that order. */
+ * (delete).  Single-precision operations, one rounding each, in that order.
+ * With r2_merge = 0 no body ever merges and a step is the first two do-alls
+ * only: the paper's "nbody" application (Fig. 6d). */
 typedef struct dsoar_collide dsoar_collide;
 typedef struct {
   float dt;       /* time step */
@@ -507,6 +509,45 @@ int dsoar_collide_step(dsoar_collide* collide, uint32_t steps, uint32_t flags, v
  * merged away (its other entries keep their last values). */
 int dsoar_collide_read(dsoar_collide* collide, float* x_dev, float* y_dev, float* vx_dev, float* vy_dev,
                        float* m_dev, void* stream);
+
+/* ------------------------------------------------------------------- wa-tor
+ * Fish and sharks on a side x side torus (the paper's "wator" application,
+ * Fig. 6h; Dewdney's rules as a synchronous step).  The heap must declare
+ * Fish {int32 pos, int32 age, int32 target} as type 0 and Shark {int32 pos,
+ * int32 age, int32 energy, int32 target} as type 1.  One step: fish pick an
+ * empty neighbour (up, right, down, left; the k-th, k = U{0..n-1} from
+ * hash(seed, 40, cell, t)), the lowest requesting cell wins, movers of age >=
+ * fish_breed leave a newborn fish (new); sharks pick a neighbouring fish, or
+ * with none and energy above 1 an empty neighbour (hash(seed, 41, cell, t)),
+ * the lowest requesting cell wins, a shark landing on a fish eats it (energy
+ * = starve) and any other loses one unit and deletes itself at 0, breeding as
+ * fish do; eaten fish delete themselves.  The step index lives on the device
+ * (a captured step replays correctly). */
+typedef struct dsoar_wator dsoar_wator;
+typedef struct {
+  int32_t fish_breed;  /* >= 1 */
+  int32_t shark_breed; /* >= 1 */
+  int32_t starve;      /* a shark's full energy, >= 1 */
+  uint32_t reserved;
+  uint64_t seed;
+} dsoar_wator_rules;
+/* Device bytes for the sea (0 if side is 0 or side^2 above 2^30). */
+size_t dsoar_wator_bytes(uint32_t side);
+/* dev_mem: caller-owned, 256-byte aligned, at least dsoar_wator_bytes. */
+int dsoar_wator_create(dsoar_heap* heap, uint32_t side, const dsoar_wator_rules* rules, void* dev_mem,
+                       size_t dev_bytes, dsoar_wator** out);
+int dsoar_wator_destroy(dsoar_wator* wator);
+/* Initial sea from device int32 arrays of side^2 cells (row-major): kind (0
+ * empty, 1 fish, 2 shark), age, energy (sharks, 1 .. starve).  step0 keys the
+ * draws of the first step.  The heap should be freshly reset. */
+int dsoar_wator_init(dsoar_wator* wator, const int32_t* kind_dev, const int32_t* age_dev, const int32_t* energy_dev,
+                     uint32_t step0, void* stream);
+/* Advances `steps` steps.  flags: DSOAR_DO_PLAIN or DSOAR_DO_PERSISTENT,
+ * optionally | DSOAR_GRAPH (persistent only). */
+int dsoar_wator_step(dsoar_wator* wator, uint32_t steps, uint32_t flags, void* stream);
+/* The sea into device int32 arrays of side^2 cells: kind, age (0 where empty)
+ * and energy (0 except for sharks). */
+int dsoar_wator_read(dsoar_wator* wator, int32_t* kind_dev, int32_t* age_dev, int32_t* energy_dev, void* stream);
 
 #ifdef __cplusplus
 }

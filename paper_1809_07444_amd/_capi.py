@@ -30,7 +30,9 @@ KIND_NAMES = {1: "enumerate", 10: "visit_count", 11: "delete_if_mod", 12: "gathe
               33: "gol_cand_update", 40: "sugar_choose", 41: "sugar_move", 42: "sugar_eat",
               43: "sugar_request", 44: "sugar_birth", 34: "gol_delete_world", 45: "sugar_delete_world",
               50: "traffic_decide", 51: "traffic_drive", 60: "collide_force", 61: "collide_move",
-              62: "collide_root", 63: "collide_target", 64: "collide_merge", 65: "collide_remove"}
+              62: "collide_root", 63: "collide_target", 64: "collide_merge", 65: "collide_remove",
+              70: "wator_fish_decide", 71: "wator_fish_move", 72: "wator_shark_decide",
+              73: "wator_shark_move", 74: "wator_fish_eaten", 75: "wator_fish_read", 76: "wator_shark_read"}
 INV_NAMES = ["bitmap_range", "allocated", "active", "active_implies_allocated", "free",
              "container", "live_count", "reserved"]
 
@@ -69,6 +71,10 @@ class CollideParams(ctypes.Structure):
 
 class TrafficRules(ctypes.Structure):
     _fields_ = [("vmax", i32), ("p_slow24", u32), ("p_in24", u32), ("reserved", u32), ("seed", u64)]
+
+
+class WatorRules(ctypes.Structure):
+    _fields_ = [("fish_breed", i32), ("shark_breed", i32), ("starve", i32), ("reserved", u32), ("seed", u64)]
 
 
 class SugarRules(ctypes.Structure):
@@ -160,6 +166,12 @@ SIGNATURES = {
     "dsoar_traffic_init": (ctypes.c_int, [vp, vp, u32, vp]),
     "dsoar_traffic_step": (ctypes.c_int, [vp, u32, u32, vp]),
     "dsoar_traffic_read": (ctypes.c_int, [vp, vp, vp]),
+    "dsoar_wator_bytes": (sz, [u32]),
+    "dsoar_wator_create": (ctypes.c_int, [H, u32, vp, vp, sz, ctypes.POINTER(vp)]),
+    "dsoar_wator_destroy": (ctypes.c_int, [vp]),
+    "dsoar_wator_init": (ctypes.c_int, [vp, vp, vp, vp, u32, vp]),
+    "dsoar_wator_step": (ctypes.c_int, [vp, u32, u32, vp]),
+    "dsoar_wator_read": (ctypes.c_int, [vp, vp, vp, vp, vp]),
 }
 
 _lib = None

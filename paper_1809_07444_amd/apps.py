@@ -353,3 +353,75 @@ class Collisions:
 
     def synchronize(self):
         self.stream.synchronize()
+
+
+# ------------------------------------------------------------------ wa-tor --
+
+WATOR_TYPES = [(4, 4, 4), (4, 4, 4, 4)]  # Fish {pos, age, target}, Shark {pos, age, energy, target}
+
+
+@dataclass
+class WatorGpuState:
+    kind: np.ndarray     # int32 [side, side]
+    age: np.ndarray
+    energy: np.ndarray
+    stats: dict
+
+
+class Wator:
+    """Wa-Tor fish and sharks on a torus, Fish and Shark objects in a device heap."""
+
+    def __init__(self, inp, rules: dict, capacity: int = 64, num_blocks: int | None = None, stream=None,
+                 device="cuda"):
+        self.side = inp.side
+        n = self.side * self.side
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        # At most one animal per cell; room for both types' partly filled blocks.
+        blocks = num_blocks or max(64, 1 << (4 * -(-n // (capacity or 64)) - 1).bit_length())
+        self.heap = Heap(blocks, capacity, WATOR_TYPES, device=device, stream=self.stream)
+        self.lib = self.heap.lib
+        nbytes = int(self.lib.dsoar_wator_bytes(self.side))
+        if nbytes == 0:
+            raise ValueError("bad sea size")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.rules = C.WatorRules(rules["fish_breed"], rules["shark_breed"], rules["starve"], 0, int(inp.seed))
+        with torch.cuda.stream(self.stream):
+            self.inputs = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32).ravel()).to(device)
+                           for a in (inp.kind, inp.age, inp.energy)]
+            self.out = [torch.empty(n, dtype=torch.int32, device=device) for _ in range(3)]
+        w = ctypes.c_void_p()
+        C.check(self.lib.dsoar_wator_create(self.heap.h, self.side, ctypes.byref(self.rules), self.buf.data_ptr(),
+                                            nbytes, ctypes.byref(w)), "dsoar_wator_create")
+        self.w = w
+
+    def close(self):
+        if getattr(self, "w", None):
+            self.lib.dsoar_wator_destroy(self.w)
+            self.w = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, step0: int = 0):
+        self.heap.reset()
+        k, a, e = self.inputs
+        C.check(self.lib.dsoar_wator_init(self.w, k.data_ptr(), a.data_ptr(), e.data_ptr(), step0, self.heap._s()),
+                "dsoar_wator_init")
+
+    def step(self, steps: int, flags: int = C.DO_PERSISTENT):
+        C.check(self.lib.dsoar_wator_step(self.w, steps, flags, self.heap._s()), "dsoar_wator_step")
+
+    def read(self) -> WatorGpuState:
+        k, a, e = self.out
+        C.check(self.lib.dsoar_wator_read(self.w, k.data_ptr(), a.data_ptr(), e.data_ptr(), self.heap._s()),
+                "dsoar_wator_read")
+        self.stream.synchronize()
+        shape = (self.side, self.side)
+        return WatorGpuState(k.cpu().numpy().reshape(shape), a.cpu().numpy().reshape(shape),
+                             e.cpu().numpy().reshape(shape), self.heap.stats())
+
+    def synchronize(self):
+        self.stream.synchronize()

@@ -317,6 +317,10 @@ int collide_one_step(dsoar_collide* c, uint32_t flags, hipStream_t st) {
   const uint32_t base = flags & DSOAR_DO_PLAIN, reuse = base | DSOAR_DO_REUSE_ENUM;
   int rc = launch_doall<BodyForce>(h, kBody, c->a, base, st);
   if (!rc) rc = launch_doall<BodyMove>(h, kBody, c->a, reuse, st);
+  // No squared distance is below a merge radius of 0: the bodies then never
+  // merge (the paper's nbody application), and the merge phases would change
+  // nothing.
+  if (!(c->a.r2_merge > 0.0f)) return rc;
   if (!rc) rc = launch_doall<BodyRoot>(h, kBody, c->a, reuse, st);
   if (!rc) rc = launch_doall<BodyTarget>(h, kBody, c->a, reuse, st);
   if (!rc) rc = launch_doall<BodyMerge>(h, kBody, c->a, reuse, st);

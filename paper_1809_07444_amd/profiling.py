@@ -34,7 +34,9 @@ METHOD_KIND = {
     "FieldGather": "gather", "GolDeleteWorld": "gol_delete_world", "SugarDeleteWorld": "sugar_delete_world",
     "Decide": "traffic_decide", "Drive": "traffic_drive", "BodyForce": "collide_force", "BodyMove": "collide_move",
     "BodyRoot": "collide_root", "BodyTarget": "collide_target", "BodyMerge": "collide_merge",
-    "BodyRemove": "collide_remove",
+    "BodyRemove": "collide_remove", "FishDecide": "wator_fish_decide", "FishMove": "wator_fish_move",
+    "SharkDecide": "wator_shark_decide", "SharkMove": "wator_shark_move", "FishEaten": "wator_fish_eaten",
+    "FishRead": "wator_fish_read", "SharkRead": "wator_shark_read",
 }
 
 

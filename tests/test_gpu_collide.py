@@ -77,3 +77,14 @@ def test_full_config_4096_bodies_50_steps():
     inp = W.collide_inputs(4096)
     r = check(inp, W.COLLIDE_PARAMS, [25, 25], flags=GRAPH)
     assert r.merges > 100
+
+
+def test_nbody_mode_no_merge_radius():
+    # Merge radius 0: no body ever merges (the nbody application); a step is
+    # the force and move do-alls only.  Dense bodies that would merge with a
+    # positive radius.
+    inp = W.collide_inputs(2048, seed=7, box=2.0)
+    params = dict(W.COLLIDE_PARAMS, r2_merge=0.0)
+    ref = check(inp, params, [7, 13])
+    assert ref.merges == 0
+    assert int((ref.m > 0).sum()) == 2048
