@@ -74,3 +74,29 @@ def test_bitmap_bytes():
     assert lib.dsoar_bitmap_bytes(0) == 0
     assert lib.dsoar_bitmap_bytes(64) == 256 + 256
     assert lib.dsoar_bitmap_bytes(1 << 30) > (1 << 27)
+
+
+def test_application_entry_points_validate_without_a_gpu():
+    lib = C.load()
+    out = ctypes.c_void_p()
+    # Sizes: 0 or too large is invalid; otherwise the documented layout.
+    assert lib.dsoar_wator_bytes(0) == 0 and lib.dsoar_wator_bytes(1 << 16) == 0
+    assert lib.dsoar_wator_bytes(64) == 256 + 64 * 64 * 4 + 64 * 64 * 8
+    assert lib.dsoar_collide_bytes(0) == 0 and lib.dsoar_collide_bytes((1 << 24) + 1) == 0
+    assert lib.dsoar_collide_bytes(100) == 1792 + 1024 + 512
+    assert lib.dsoar_traffic_bytes(0, 8) == 0 and lib.dsoar_traffic_bytes(8, 0) == 0
+    # A missing heap, handle or rules is an argument error, before any device work.
+    wr = C.WatorRules(3, 10, 3, 0, 1)
+    assert lib.dsoar_wator_create(None, 64, ctypes.byref(wr), 256, 1 << 20, ctypes.byref(out)) == -1
+    assert lib.dsoar_wator_create(None, 64, None, 256, 1 << 20, None) == -1
+    cp = C.CollideParams(0.01, 0.01, 0.0, 0)
+    assert lib.dsoar_collide_create(None, 16, ctypes.byref(cp), 256, 1 << 20, ctypes.byref(out)) == -1
+    tr = C.TrafficRules(5, 0, 0, 0, 1)
+    assert lib.dsoar_traffic_create(None, 4, 4, ctypes.byref(tr), 256, 1 << 20, ctypes.byref(out)) == -1
+    for fn in ("dsoar_wator_destroy", "dsoar_collide_destroy", "dsoar_traffic_destroy"):
+        assert getattr(lib, fn)(None) == -1
+    assert lib.dsoar_wator_step(None, 1, 0, None) == -1
+    assert lib.dsoar_collide_step(None, 1, 0, None) == -1
+    assert lib.dsoar_traffic_step(None, 1, 0, None) == -1
+    assert lib.dsoar_wator_read(None, None, None, None, None) == -1
+    assert lib.dsoar_wator_init(None, None, None, None, 0, None) == -1
