@@ -55,8 +55,13 @@ __device__ __forceinline__ int32_t uniform_int(uint64_t h, int32_t lo, int32_t h
 // side^2) of the cell arena; pos and target are arena indices.  Each slot has
 // its own seed, step index and move count, so a world evolves exactly as it
 // would alone.
+// A cell's sugar word also carries its occupancy (kOccupied), so that the
+// cells an agent looks at take one load each; occ keeps the agent handle.
+constexpr int32_t kOccupied = 1 << 30;
+__device__ __forceinline__ int32_t sugar_of(int32_t w) { return w & ~kOccupied; }
+
 struct Grid {
-  int32_t* sugar;
+  int32_t* sugar;     // sugar | kOccupied when an agent stands there
   const int32_t* cap;
   uint32_t* occ;      // agent handle or kNull
   uint32_t* req;      // lowest requesting cell index or kInf
@@ -119,10 +124,10 @@ struct Choose {
     // nearest, then lowest index.  The order in which the candidates are
     // compared does not matter for that total order.
     uint32_t best = p;
-    int32_t best_sugar = g.sugar[p], best_dist = 0;
+    int32_t best_sugar = sugar_of(g.sugar[p]), best_dist = 0;
 #pragma unroll
     for (int32_t half = 0; half < 2; ++half) {
-      uint32_t q[2 * kMaxVision], o[2 * kMaxVision];
+      uint32_t q[2 * kMaxVision];
       int32_t sg[2 * kMaxVision];
 #pragma unroll
       for (int32_t j = 0; j < 2; ++j)
@@ -134,13 +139,11 @@ struct Choose {
           q[j * kMaxVision + k - 1] = k <= vision ? step_cell(c, dx, dy, k) : p;
         }
 #pragma unroll
-      for (int32_t i = 0; i < 2 * kMaxVision; ++i) o[i] = g.occ[q[i]];
-#pragma unroll
       for (int32_t i = 0; i < 2 * kMaxVision; ++i) sg[i] = g.sugar[q[i]];
 #pragma unroll
       for (int32_t i = 0; i < 2 * kMaxVision; ++i) {
         const int32_t k = i % kMaxVision + 1;
-        if (k > vision || o[i] != kNull) continue;
+        if (k > vision || (sg[i] & kOccupied)) continue;
         const int32_t s = sg[i];
         if (s > best_sugar || (s == best_sugar && (k < best_dist || (k == best_dist && q[i] < best)))) {
           best = q[i];
@@ -165,8 +168,11 @@ struct Move {
     const uint32_t wid = af<uint32_t>(h, self, kWorld);
     const bool moves = q != p && __hip_atomic_load(g.req + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == p;
     if (moves) {
+      // Distinct cells per mover: q was empty and p occupied when chosen.
       g.occ[q] = self;
       g.occ[p] = kNull;
+      g.sugar[q] |= kOccupied;
+      g.sugar[p] &= ~kOccupied;
       af<uint32_t>(h, self, kPos) = q;
       __hip_atomic_store(g.req + q, kInf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -188,13 +194,14 @@ struct Eat {
   using Args = Grid;
   static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
     const uint32_t p = af<uint32_t>(h, self, kPos);
-    const int32_t sugar = af<int32_t>(h, self, kSugar) + g.sugar[p] - af<int32_t>(h, self, kMetab);
+    const int32_t sugar = af<int32_t>(h, self, kSugar) + sugar_of(g.sugar[p]) - af<int32_t>(h, self, kMetab);
     const int32_t age = af<int32_t>(h, self, kAge) + 1;
-    g.sugar[p] = 0;
     if (sugar <= 0 || age >= g.max_age) {
+      g.sugar[p] = 0;
       g.occ[p] = kNull;
       return true;  // delete this; its fields are not written
     }
+    g.sugar[p] = kOccupied;  // eaten, still here
     af<int32_t>(h, self, kSugar) = sugar;
     af<int32_t>(h, self, kAge) = age;
     return false;
@@ -250,6 +257,7 @@ struct Birth {
       af<uint32_t>(h, o, kTarget) = kNull;
       af<uint32_t>(h, o, kWorld) = wid;
       g.occ[n] = o;
+      g.sugar[n] |= kOccupied;
     });
     return false;
   }
@@ -270,8 +278,8 @@ __global__ void regrow_kernel(Grid g) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < g.max_worlds) g.w_step[i] += 1;
   for (uint32_t c = i; c < g.arena; c += gridDim.x * blockDim.x) {
-    const int32_t s = g.sugar[c] + 1, k = g.cap[c];
-    g.sugar[c] = s < k ? s : k;
+    const int32_t w = g.sugar[c], s = sugar_of(w) + 1, k = g.cap[c];
+    g.sugar[c] = (s < k ? s : k) | (w & kOccupied);
   }
 }
 
@@ -307,6 +315,7 @@ __global__ void sugar_admit_kernel(DevHeap h, Grid g, uint32_t slot, uint32_t of
     af<uint32_t>(h, o, kTarget) = kNull;
     af<uint32_t>(h, o, kWorld) = slot;
     g.occ[q] = o;
+    g.sugar[q] |= kOccupied;
   });
 }
 
@@ -315,7 +324,7 @@ __global__ void sugar_read_kernel(DevHeap h, Grid g, uint32_t off, uint32_t n, i
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const uint32_t q = off + c;
-  sugar[c] = g.sugar[q];
+  sugar[c] = sugar_of(g.sugar[q]);
   const uint32_t o = g.occ[q];
   occ[c] = o != kNull;
   as[c] = o != kNull ? af<int32_t>(h, o, kSugar) : 0;
