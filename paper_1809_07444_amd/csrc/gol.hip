@@ -2,7 +2,8 @@
 // worlds sharing one heap.
 //
 // Types: Cell {alive} is created once per grid position and found through a
-// position -> handle index; Alive {cell, world, action} exists for every live
+// position -> handle index (whose words also carry a copy of the live flag,
+// so neighbour reads take one load); Alive {cell, world, action} exists for every live
 // cell; Candidate {cell, world, action} exists during a generation for every
 // dead cell next to a live one.  One generation is four do-alls:
 //   1 Alive:     count live neighbours -> action (die unless 2 or 3); create
@@ -28,8 +29,14 @@ enum : uint32_t { kCell = 0, kAlive = 1, kCand = 2 };
 enum : uint32_t { kCAlive = 0 };
 enum : uint32_t { kACell = 0, kAWorld = 1, kAAction = 2 };
 
+// A cell index word holds the Cell's handle and, in kLiveBit, a copy of its
+// live flag, so that reading a neighbour's state is one load; kNull when the
+// Cell is missing.  Handles stay below 2^31 (heaps of fewer than 2^25 blocks).
+constexpr uint32_t kLiveBit = 0x80000000u;
+__device__ __forceinline__ bool live_of(uint32_t wd) { return wd != kNull && (wd & kLiveBit) != 0; }
+
 struct World {
-  const uint32_t* cells;  // global cell index -> Cell handle
+  const uint32_t* cells;  // global cell index -> Cell handle | kLiveBit if alive
   const uint32_t* off;    // world -> first global cell index (num_worlds + 1 entries)
   const uint32_t* side;   // world -> side length
 };
@@ -37,8 +44,19 @@ struct World {
 // Field f of the Cell at global index g; a scratch word when the Cell is
 // missing (only after an out-of-memory init, which the OOM flag reports).
 __device__ __forceinline__ uint32_t* cell_field(const DevHeap& h, const World& w, uint32_t g, uint32_t f) {
-  const uint32_t hc = w.cells[g];
-  return hc == kNull ? reinterpret_cast<uint32_t*>(h.ctrl + kCtlWords - 1) : field_ptr<uint32_t>(h, hc, kCell, f);
+  const uint32_t wd = w.cells[g];
+  return wd == kNull ? reinterpret_cast<uint32_t*>(h.ctrl + kCtlWords - 1)
+                     : field_ptr<uint32_t>(h, wd & ~kLiveBit, kCell, f);
+}
+
+// Sets the live state of the Cell at global index g (its field and the copy
+// in its index word); only the cell's own Alive or Candidate does this.
+__device__ __forceinline__ void set_live(const DevHeap& h, const World& w, uint32_t g, uint32_t live) {
+  uint32_t* ix = const_cast<uint32_t*>(w.cells) + g;
+  const uint32_t wd = *ix;
+  if (wd == kNull) return;
+  *field_ptr<uint32_t>(h, wd & ~kLiveBit, kCell, kCAlive) = live;
+  *ix = live ? (wd | kLiveBit) : (wd & ~kLiveBit);
 }
 
 // The eight torus neighbours of global cell g of world wid.
@@ -117,18 +135,16 @@ struct AlivePrep {
       row[i] = off + torus_add(y, i - 2, side) * side;
       col[i] = torus_add(x, i - 2, side);
     }
-    // Live flags of the 24 surrounding cells; all loads are independent.
-    uint32_t hc[25];
+    // Live states of the 24 surrounding cells: one load each, all independent.
+    uint32_t wd[25];
 #pragma unroll
-    for (uint32_t b = 0; b < 25; ++b) hc[b] = b == 12 ? kNull : w.cells[row[b / 5] + col[b % 5]];
+    for (uint32_t b = 0; b < 25; ++b) wd[b] = b == 12 ? kNull : w.cells[row[b / 5] + col[b % 5]];
     uint32_t alive = 0, present = 0;
 #pragma unroll
     for (uint32_t b = 0; b < 25; ++b) {
       if (b == 12) continue;
-      const bool here = hc[b] != kNull;  // missing only after an out-of-memory init
-      const uint32_t v = *field_ptr<uint32_t>(h, here ? hc[b] : 0u, kCell, kCAlive);  // 0: any in-heap Cell slot
-      present |= (uint32_t)here << b;
-      alive |= (uint32_t)(here && v != 0) << b;
+      present |= (uint32_t)(wd[b] != kNull) << b;  // missing only after an out-of-memory init
+      alive |= (uint32_t)live_of(wd[b]) << b;
     }
     uint32_t claim = 0;
 #pragma unroll
@@ -158,7 +174,7 @@ struct CandPrep {
     const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
     const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
     uint32_t live = 0;
-    for_neighbours(w, wid, g, [&](uint32_t n) { live += *cell_field(h, w, n, kCAlive); });
+    for_neighbours(w, wid, g, [&](uint32_t n) { live += live_of(w.cells[n]) ? 1u : 0u; });
     *field_ptr<uint32_t>(h, self, type, kAAction) = live == 3 ? 1u : 0u;
     return false;
   }
@@ -169,7 +185,7 @@ struct AliveUpdate {
   using Args = World;
   static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& w) {
     if (*field_ptr<uint32_t>(h, self, type, kAAction) == 0) return false;
-    *cell_field(h, w, *field_ptr<uint32_t>(h, self, type, kACell), kCAlive) = 0;
+    set_live(h, w, *field_ptr<uint32_t>(h, self, type, kACell), 0);
     return true;
   }
 };
@@ -182,7 +198,7 @@ struct CandUpdate {
     const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
     const bool born = *field_ptr<uint32_t>(h, self, type, kAAction) != 0;
     if (born) {
-      *cell_field(h, w, g, kCAlive) = 1;
+      set_live(h, w, g, 1);
       const uint32_t o = dsoar_new(h, kAlive);
       if (o != kNull) {
         *field_ptr<uint32_t>(h, o, kAlive, kACell) = g;
@@ -211,7 +227,7 @@ __global__ void gol_init_kernel(DevHeap h, World w, uint32_t num_worlds, uint32_
   const uint32_t hc = dsoar_new(h, kCell);
   const uint32_t alive = grid[g] ? 1u : 0u;
   if (hc != kNull) *field_ptr<uint32_t>(h, hc, kCell, kCAlive) = alive;
-  const_cast<uint32_t*>(w.cells)[g] = hc;
+  const_cast<uint32_t*>(w.cells)[g] = hc == kNull ? kNull : (hc | (alive ? kLiveBit : 0u));
   if (alive) {
     const uint32_t o = dsoar_new(h, kAlive);
     if (o != kNull) {
@@ -225,8 +241,8 @@ __global__ void gol_init_kernel(DevHeap h, World w, uint32_t num_worlds, uint32_
 __global__ void gol_read_kernel(DevHeap h, World w, uint32_t off, uint32_t n, uint8_t* out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const uint32_t hc = w.cells[off + i];
-  out[i] = hc == kNull ? 0xFF : (uint8_t)*field_ptr<uint32_t>(h, hc, kCell, kCAlive);
+  const uint32_t wd = w.cells[off + i];
+  out[i] = wd == kNull ? 0xFF : (uint8_t)*field_ptr<uint32_t>(h, wd & ~kLiveBit, kCell, kCAlive);
 }
 
 // Records world slot's cell range in the world table.
@@ -243,7 +259,7 @@ __global__ void gol_admit_kernel(DevHeap h, World w, uint32_t slot, uint32_t off
   const uint32_t hc = dsoar_new(h, kCell);
   const uint32_t alive = grid[i] ? 1u : 0u;
   if (hc != kNull) *field_ptr<uint32_t>(h, hc, kCell, kCAlive) = alive;
-  const_cast<uint32_t*>(w.cells)[g] = hc;
+  const_cast<uint32_t*>(w.cells)[g] = hc == kNull ? kNull : (hc | (alive ? kLiveBit : 0u));
   new_many(h, kAlive, alive, [&](uint32_t, uint32_t o) {
     if (o == kNull) return;
     *field_ptr<uint32_t>(h, o, kAlive, kACell) = g;
@@ -257,7 +273,7 @@ __global__ void gol_retire_cells_kernel(DevHeap h, World w, uint32_t off, uint32
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t* c = const_cast<uint32_t*>(w.cells) + off + i;
-  dsoar_delete(h, *c);
+  if (*c != kNull) dsoar_delete(h, *c & ~kLiveBit);
   *c = kNull;
 }
 
@@ -270,7 +286,7 @@ struct GolDeleteWorld {
 };
 
 bool gol_heap_ok(const dsoar_heap* h) {
-  if (h->desc.num_types < 3) return false;
+  if (h->desc.num_types < 3 || h->desc.num_blocks >= (1u << 25)) return false;  // handles below kLiveBit
   const uint32_t want[3] = {1, 3, 3};
   for (uint32_t t = 0; t < 3; ++t) {
     const dsoar_type_layout& L = h->desc.types[t];
