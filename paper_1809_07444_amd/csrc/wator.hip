@@ -35,7 +35,7 @@ enum : uint32_t { kFish = 0, kShark = 1 };
 enum : uint32_t { kPos = 0, kAge = 1, kFTarget = 2 };  // Fish fields
 enum : uint32_t { kEnergy = 2, kSTarget = 3 };         // Shark fields after pos, age
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr int32_t kEmpty = 0, kIsFish = 1, kIsShark = 2;
+constexpr uint8_t kEmpty = 0, kIsFish = 1, kIsShark = 2;
 constexpr uint64_t kStreamFish = 40, kStreamShark = 41;
 
 // SplitMix64 output finaliser (Steele, Lea, Flood, OOPSLA 2014) and the
@@ -57,7 +57,7 @@ __device__ __forceinline__ uint32_t pick(uint64_t h, uint32_t n) {
 }
 
 struct Sea {
-  int32_t* kind;    // cell -> kEmpty, kIsFish or kIsShark
+  uint8_t* kind;    // cell -> kEmpty, kIsFish or kIsShark (one byte: the sea of 2048^2 fits an L2)
   uint64_t* req;    // cell -> smallest request key of the latest phase that asked for it
   uint32_t* step;   // [0]: index of the step in progress
   uint32_t side;
@@ -147,7 +147,7 @@ struct SharkDecide {
 #pragma unroll
     for (uint32_t d = 0; d < 4; ++d) {
       const uint32_t q = nb(a.side, c, d);
-      const int32_t k = a.kind[q];
+      const uint8_t k = a.kind[q];
       if (k == kIsFish) fishn[nf++] = q;
       if (k == kEmpty) empty[ne++] = q;
     }
@@ -242,7 +242,7 @@ __global__ void wator_init_kernel(DevHeap h, Sea a, const int32_t* kind, const i
   if (c == 0) a.step[0] = step0;
   if (c >= n) return;
   const int32_t k = kind[c];
-  a.kind[c] = k;
+  a.kind[c] = (uint8_t)k;
   a.req[c] = ~0ull;
   new_many(h, kFish, k == kIsFish ? 1u : 0u, [&](uint32_t, uint32_t o) {
     if (o == kNull) return;
@@ -321,7 +321,7 @@ extern "C" {
 size_t dsoar_wator_bytes(uint32_t side) {
   const uint64_t n = (uint64_t)side * side;
   if (side == 0 || n > (1ull << 30)) return 0;
-  return 256 + round256(n * 4) + round256(n * 8);
+  return 256 + round256(n) + round256(n * 8);
 }
 
 int dsoar_wator_create(dsoar_heap* heap, uint32_t side, const dsoar_wator_rules* rules, void* dev_mem,
@@ -341,8 +341,8 @@ int dsoar_wator_create(dsoar_heap* heap, uint32_t side, const dsoar_wator_rules*
   uint8_t* b = (uint8_t*)dev_mem;
   w->heap = heap;
   w->a.step = (uint32_t*)b;
-  w->a.kind = (int32_t*)(b + 256);
-  w->a.req = (uint64_t*)(b + 256 + round256(n * 4));
+  w->a.kind = b + 256;
+  w->a.req = (uint64_t*)(b + 256 + round256(n));
   w->a.side = side;
   w->a.seed = rules->seed;
   w->a.fish_breed = rules->fish_breed;

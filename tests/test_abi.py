@@ -81,7 +81,7 @@ def test_application_entry_points_validate_without_a_gpu():
     out = ctypes.c_void_p()
     # Sizes: 0 or too large is invalid; otherwise the documented layout.
     assert lib.dsoar_wator_bytes(0) == 0 and lib.dsoar_wator_bytes(1 << 16) == 0
-    assert lib.dsoar_wator_bytes(64) == 256 + 64 * 64 * 4 + 64 * 64 * 8
+    assert lib.dsoar_wator_bytes(64) == 256 + 64 * 64 + 64 * 64 * 8
     assert lib.dsoar_collide_bytes(0) == 0 and lib.dsoar_collide_bytes((1 << 24) + 1) == 0
     assert lib.dsoar_collide_bytes(100) == 1792 + 1024 + 512
     assert lib.dsoar_traffic_bytes(0, 8) == 0 and lib.dsoar_traffic_bytes(8, 0) == 0
