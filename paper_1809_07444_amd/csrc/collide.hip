@@ -50,6 +50,16 @@ __device__ __forceinline__ uint32_t from_lane(uint32_t v, uint32_t k) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, k);
 }
 
+// A wavefront's own 64-entry slice of LDS (do-all workgroups hold at most 16
+// wavefronts).  A chunk written there by its 64 lanes is read back entry by
+// entry with one broadcast load per entry; a wavefront's LDS accesses are
+// performed in program order, so no barrier is needed between them.
+template <class T>
+__device__ __forceinline__ T* wave_slice() {
+  __shared__ T slice[16 * 64];
+  return slice + (threadIdx.x >> 6) * 64;
+}
+
 // The per-id arrays are walked in chunks of 64 ids: lane l loads entry j0 + l
 // of the next chunk (clamped to the last id, so every load stays in bounds)
 // while the wavefront works through the current one.
@@ -73,17 +83,16 @@ struct BodyForce {
     const float x = fld<float>(h, self, kX), y = fld<float>(h, self, kY);
     const uint32_t n = a.n;
     float sx = 0.0f, sy = 0.0f;
+    float4* const t = wave_slice<float4>();
     float4 nxt = a.P[chunk_id(0, n)];
     for (uint32_t j0 = 0; j0 < n; j0 += 64) {
-      const float4 cur = nxt;
+      t[lane_id()] = nxt;
       nxt = a.P[chunk_id(j0 + 64, n)];
-      if (n - j0 >= 64) {
+      const uint32_t m = n - j0 < 64 ? n - j0 : 64;
 #pragma unroll 4
-        for (uint32_t k = 0; k < 64; ++k)
-          pair(a, x, y, from_lane(cur.x, k), from_lane(cur.y, k), from_lane(cur.z, k), sx, sy);
-      } else {
-        for (uint32_t k = 0; k < n - j0; ++k)
-          pair(a, x, y, from_lane(cur.x, k), from_lane(cur.y, k), from_lane(cur.z, k), sx, sy);
+      for (uint32_t k = 0; k < m; ++k) {
+        const float4 q = t[k];
+        pair(a, x, y, q.x, q.y, q.z, sx, sy);
       }
     }
     if (live) {
