@@ -68,10 +68,10 @@ def gol_kernel_bytes(kind, launches, st, M):
     A, K = 1, 2  # Alive, Candidate type ids
     va, vk = st["visits"][A] / 2, st["visits"][K] / 2     # each type is visited by two do-alls
     if kind == "gol_alive_prep":
-        # handles and live flags of the 24 cells around (5 x 5 neighbourhood)
-        return va * (12 + 192) + st["allocs"][K] * 16 + va / 64 * 12
+        # index words (handle and live bit) of the 24 cells around (5 x 5 neighbourhood)
+        return va * (12 + 96) + st["allocs"][K] * 16 + va / 64 * 12
     if kind == "gol_cand_prep":
-        return vk * (12 + 64) + vk / 64 * 12
+        return vk * (12 + 32) + vk / 64 * 12
     if kind == "gol_alive_update":
         return va * 4 + st["frees"][A] * 12 + va / 64 * 12
     if kind == "gol_cand_update":
@@ -305,7 +305,7 @@ class SugarWorkload(GolWorkload):
         # this-fields (read 24 B, write <= 12 B) + 5 * (4*vision+1) grid reads are counted for choose;
         # each phase's own fields otherwise.  Per agent visit of the phase:
         v = st["visits"][0] / 5  # five do-alls per step
-        per = {"sugar_choose": 12 + 4 + 25 * 8, "sugar_move": 12 + 8, "sugar_eat": 16 + 8 + 8,
+        per = {"sugar_choose": 12 + 4 + 25 * 4, "sugar_move": 12 + 8, "sugar_eat": 16 + 8 + 8,
                "sugar_request": 16 + 16 + 4, "sugar_birth": 12 + 4}
         if kind in per:
             return v * per[kind]
