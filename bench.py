@@ -77,6 +77,9 @@ def gol_kernel_bytes(kind, launches, st, M):
     if kind == "gol_cand_update":
         births = st["allocs"][A]
         return vk * 20 + births * 16 + vk / 64 * 12
+    if kind == "gol_update":  # phases 3 and 4 in one launch
+        return gol_kernel_bytes("gol_alive_update", launches, st, M) + \
+            gol_kernel_bytes("gol_cand_update", launches, st, M)
     if kind == "enumerate":
         return launches * (M / 8) + (va + vk) / 64 * 20
     return None

@@ -27,7 +27,7 @@ METHOD_VISIT_COUNT, METHOD_DELETE_IF_MOD, METHOD_MICRO_UPDATE, METHOD_MICRO_CULL
 BM_TRY_SET, BM_TRY_CLEAR, BM_SET, BM_CLEAR, BM_TRY_FIND_SET, BM_FIND_CLEAR = range(6)
 KIND_NAMES = {1: "enumerate", 10: "visit_count", 11: "delete_if_mod", 12: "gather", 20: "micro_update",
               21: "micro_cull", 30: "gol_alive_prep", 31: "gol_cand_prep", 32: "gol_alive_update",
-              33: "gol_cand_update", 40: "sugar_choose", 41: "sugar_move", 42: "sugar_eat",
+              33: "gol_cand_update", 35: "gol_update", 40: "sugar_choose", 41: "sugar_move", 42: "sugar_eat",
               43: "sugar_request", 44: "sugar_birth", 34: "gol_delete_world", 45: "sugar_delete_world",
               50: "traffic_decide", 51: "traffic_drive", 60: "collide_force", 61: "collide_move",
               62: "collide_root", 63: "collide_target", 64: "collide_merge", 65: "collide_remove",

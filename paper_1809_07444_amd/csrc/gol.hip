@@ -28,6 +28,7 @@ namespace {
 enum : uint32_t { kCell = 0, kAlive = 1, kCand = 2 };
 enum : uint32_t { kCAlive = 0 };
 enum : uint32_t { kACell = 0, kAWorld = 1, kAAction = 2 };
+constexpr uint32_t kKindGolUpdate = 35;  // timing id of the fused phases 3 and 4
 
 // A cell index word holds the Cell's handle and, in kLiveBit, a copy of its
 // live flag, so that reading a neighbour's state is one load; kNull when the
@@ -330,8 +331,14 @@ int gol_generation(dsoar_gol* g, uint32_t flags, hipStream_t s) {
   if (!rc) rc = launch_doall<CandPrep>(h, kCand, g->w, base, s);
   // Phase 2 creates and deletes nothing, phase 3 touches only Alive objects:
   // phases 3 and 4 reuse the enumerations of phases 1 and 2.
-  if (!rc) rc = launch_doall<AliveUpdate>(h, kAlive, g->w, base | DSOAR_DO_REUSE_ENUM, s);
-  if (!rc) rc = launch_doall<CandUpdate>(h, kCand, g->w, base | DSOAR_DO_REUSE_ENUM, s);
+  if (base & DSOAR_DO_PLAIN) {
+    if (!rc) rc = launch_doall<AliveUpdate>(h, kAlive, g->w, base | DSOAR_DO_REUSE_ENUM, s);
+    if (!rc) rc = launch_doall<CandUpdate>(h, kCand, g->w, base | DSOAR_DO_REUSE_ENUM, s);
+  } else if (!rc) {
+    // Phases 3 and 4 touch disjoint cells (dying ones, born ones) and each
+    // object only its own: one launch over both lists.
+    rc = launch_doall2<AliveUpdate, CandUpdate>(h, kAlive, g->w, kCand, g->w, kKindGolUpdate, s);
+  }
   return rc;
 }
 

@@ -353,17 +353,14 @@ __device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, c
 // (an id for per-kernel timing) and either
 //   static __device__ bool run(const DevHeap&, uint32_t type, uint32_t self, const Args&)
 // returning true to delete self, or the load / apply pair described above.
+// One wavefront's share of a do-all over one list: entries gw, gw + nw, ...
+// (or passes of several entries), visit and free counts accumulated.
 template <class Method>
-__global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, const uint32_t* __restrict__ R,
-                                                      const uint64_t* __restrict__ S, const uint32_t* count_ptr,
-                                                      typename Method::Args args) {
+__device__ __forceinline__ void doall_list(const DevHeap& h, uint32_t type, const uint32_t* __restrict__ R,
+                                           const uint64_t* __restrict__ S, uint32_t count, uint32_t gw,
+                                           uint32_t nw, const typename Method::Args& args, uint32_t& visits,
+                                           uint32_t& freed) {
   const uint32_t lane = lane_id();
-  const uint32_t wpb = blockDim.x >> 6;
-  const uint32_t gw = blockIdx.x * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const uint32_t nw = gridDim.x * wpb;
-  const uint32_t count = bcast32(*count_ptr);
-  uint32_t visits = 0, freed = 0;
-  bool done = false;
   const uint32_t c = cap_of(h, type);
   if constexpr (HasSplit<Method>::value) {
     // Several blocks per pass only when every wavefront gets that many.
@@ -374,11 +371,10 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
         doall_split64<Method, 4>(h, type, R, S, count, gw, nw, args, visits, freed);
       else
         doall_split64<Method, 2>(h, type, R, S, count, gw, nw, args, visits, freed);
-      done = true;
+      return;
     }
   }
-  if (done) {
-  } else if (c == 64) {
+  if (c == 64) {
     for (uint32_t e = gw; e < count; e += nw) {
       const uint32_t bid = R[e];
       const uint64_t snap = S[e];
@@ -407,8 +403,44 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
       }
     }
   }
+}
+
+// Wave-uniform index of this wavefront in the grid.
+__device__ __forceinline__ uint32_t grid_wave() {
+  return blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+template <class Method>
+__global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, const uint32_t* __restrict__ R,
+                                                      const uint64_t* __restrict__ S, const uint32_t* count_ptr,
+                                                      typename Method::Args args) {
+  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+  uint32_t visits = 0, freed = 0;
+  doall_list<Method>(h, type, R, S, bcast32(*count_ptr), grid_wave(), nw, args, visits, freed);
   if (visits) lead_add(shard(h) + kCntVisits + type, visits);
   if (freed) lead_add(shard(h) + kCntFrees + type, freed);
+}
+
+// Two do-alls in one launch, over the lists of two types: every wavefront
+// takes its share of the first list, then of the second.  For methods that
+// may run at the same time (neither reads what the other writes, apart from
+// the heap's own atomics): one kernel boundary and one launch fewer.
+template <class M1, class M2>
+__global__ void __launch_bounds__(1024) doall2_kernel(DevHeap h, uint32_t t1, const uint32_t* __restrict__ R1,
+                                                       const uint64_t* __restrict__ S1, const uint32_t* c1,
+                                                       typename M1::Args a1, uint32_t t2,
+                                                       const uint32_t* __restrict__ R2,
+                                                       const uint64_t* __restrict__ S2, const uint32_t* c2,
+                                                       typename M2::Args a2) {
+  const uint32_t nw = gridDim.x * (blockDim.x >> 6), gw = grid_wave();
+  uint32_t visits = 0, freed = 0;
+  doall_list<M1>(h, t1, R1, S1, bcast32(*c1), gw, nw, a1, visits, freed);
+  if (visits) lead_add(shard(h) + kCntVisits + t1, visits);
+  if (freed) lead_add(shard(h) + kCntFrees + t1, freed);
+  visits = freed = 0;
+  doall_list<M2>(h, t2, R2, S2, bcast32(*c2), gw, nw, a2, visits, freed);
+  if (visits) lead_add(shard(h) + kCntVisits + t2, visits);
+  if (freed) lead_add(shard(h) + kCntFrees + t2, freed);
 }
 
 // Enumerate (unless reusing) and launch the do-all of Method over `type`.
@@ -436,6 +468,22 @@ int launch_doall(dsoar_heap* h, uint32_t type, const typename Method::Args& args
   }
   launch_timed(h, Method::kKind, doall_kernel<Method>, dim3(grid), dim3(threads), s, h->dev, type,
                (const uint32_t*)eo.R, (const uint64_t*)eo.S, (const uint32_t*)&eo.st->count, args);
+  DSOAR_LAUNCHED(h);
+  return DSOAR_OK;
+}
+
+// Both do-alls of doall2_kernel, over the lists of their types' last
+// enumerations (no enumeration here), persistent grid; timed as `kind`.
+template <class M1, class M2>
+int launch_doall2(dsoar_heap* h, uint32_t t1, const typename M1::Args& a1, uint32_t t2,
+                  const typename M2::Args& a2, uint32_t kind, hipStream_t s) {
+  if (t1 >= h->desc.num_types || t2 >= h->desc.num_types) return DSOAR_ERR_INVALID_ARG;
+  const EnumOut& e1 = h->enum_out[t1];
+  const EnumOut& e2 = h->enum_out[t2];
+  launch_timed(h, kind, doall2_kernel<M1, M2>, dim3(h->num_cus * h->doall_wgs_per_cu),
+               dim3(h->doall_wg_threads), s, h->dev, t1, (const uint32_t*)e1.R, (const uint64_t*)e1.S,
+               (const uint32_t*)&e1.st->count, a1, t2, (const uint32_t*)e2.R, (const uint64_t*)e2.S,
+               (const uint32_t*)&e2.st->count, a2);
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }

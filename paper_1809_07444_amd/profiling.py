@@ -40,8 +40,16 @@ METHOD_KIND = {
 }
 
 
+# two-list do-alls (both methods in one launch) -> kind
+METHOD2_KIND = {("AliveUpdate", "CandUpdate"): "gol_update"}
+
+
 def kernel_kind(name: str) -> str | None:
     """Kernel kind of a rocprofv3 kernel name, 'calibration' for the add, or None."""
+    m2 = re.search(r"doall2_kernel<(?:[\w:]*::|\(anonymous namespace\)::)*(\w+),\s*"
+                   r"(?:[\w:]*::|\(anonymous namespace\)::)*(\w+)>", name)
+    if m2:
+        return METHOD2_KIND.get((m2.group(1), m2.group(2)))
     m = re.search(r"doall_kernel<(?:[\w:]*::|\(anonymous namespace\)::)*(\w+)>", name)
     if m:
         return METHOD_KIND.get(m.group(1))
