@@ -803,12 +803,15 @@ __device__ inline uint32_t dsoar_new(const DevHeap& h, uint32_t type) {
 //  1 Invalidate: compare-and-swap the object bitmap from 0 to all ones.  If
 //    that fails an allocation got in first and the block stays.  All ones
 //    reads as full, so no reservation can gain a slot from here on.
-//  2 Bump the version in the type word and mark it free, then wait until no
-//    reservation holds the block.  A reservation pins the block and then
+//  2 Bump the version in the type word and mark it free, and leave
+//    active[type] (clear with retry: it pairs with the set that made the
+//    bit true), so that no further lookup selects the block; then wait until
+//    no reservation holds it.  A reservation pins the block and then
 //    re-reads the type word (both sequentially consistent), so either it
-//    sees the change and withdraws, or this wait sees its pin.
-//  3 Leave active[type] and allocated[type] (clear with retry: each pairs
-//    with the set of the transition that made the bit true).
+//    sees the change and withdraws, or this wait sees its pin.  (Waiting
+//    with the block still active let the lookups of every other wavefront
+//    keep pinning it, and the wait could starve.)
+//  3 Leave allocated[type] (clear with retry).
 //  4 Reset the object bitmap, then set the free bit, in release order: an
 //    allocator that takes the block from the free bitmap sees the reset
 //    bitmap and the new type word.
@@ -827,6 +830,7 @@ __device__ inline bool try_release(const DevHeap& h, uint32_t type, uint32_t bid
     }
   }
   if (!bcast32(ok)) return false;
+  bm_clear(active_bm(h, type), bid);
   for (uint32_t spins = 0;; ++spins) {
     uint32_t p = 0;
     if (is_first_active()) p = __hip_atomic_load(h.pins + bid, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
@@ -837,7 +841,6 @@ __device__ inline bool try_release(const DevHeap& h, uint32_t type, uint32_t bid
     }
     __builtin_amdgcn_s_sleep(1);
   }
-  bm_clear(active_bm(h, type), bid);
   bm_clear(allocated_bm(h, type), bid);
   if (is_first_active()) __hip_atomic_store(h.obj_bitmap + bid, 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
