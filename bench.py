@@ -62,7 +62,8 @@ def parse():
 # ------------------------------------------------------------- bytes model --
 # Algorithmic bytes each kernel kind must move (this-object fields, other
 # objects' fields, new objects' fields, the compacted list), from the heap's
-# counters over the profiled pass.  See the design notes for the derivation.
+# counters over the profiled pass: per visited object the fields the method
+# reads and writes, per block the list entry (4 B id + 8 B snapshot).
 
 def gol_kernel_bytes(kind, launches, st, M):
     A, K = 1, 2  # Alive, Candidate type ids
@@ -572,7 +573,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
-                                   "(sharding across GPUs is described in the design notes, not built)"}))
+                                   "(the path runs on one GPU; sharding across GPUs is not implemented)"}))
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
