@@ -88,3 +88,11 @@ def test_nbody_mode_no_merge_radius():
     ref = check(inp, params, [7, 13])
     assert ref.merges == 0
     assert int((ref.m > 0).sum()) == 2048
+
+
+def test_benchmark_size_first_step():
+    # The benchmark's 65,536 bodies in a 32 x 32 box, its first step (graph
+    # replay, as timed) against the oracle, bit for bit.
+    inp = W.collide_inputs(65536, box=32.0)
+    ref = check(inp, W.COLLIDE_PARAMS, [1], flags=GRAPH)
+    assert ref.merges > 0

@@ -41,3 +41,11 @@ def test_micro_ragged(n, steps, seed, cap, flags):
     blocks = max(4, 4 * (-(-max(n, 1) // cap)))
     res = apps.micro_run(inp, blocks, cap, flags)
     compare(inp, res)
+
+
+def test_micro_scaled_full_config():
+    # The HBM-bound configuration the benchmark times: 2^22 blocks of 64 slots,
+    # 2^26 objects (16 per block on average), 2 steps, persistent do-alls.
+    inp = W.micro_inputs(16 << 22, 2)
+    res = apps.micro_run(inp, 1 << 22, 64)
+    compare(inp, res)
