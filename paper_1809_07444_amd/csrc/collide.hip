@@ -314,9 +314,7 @@ using namespace dsoar;
 struct dsoar_collide {
   dsoar_heap* heap;
   Bodies a;
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-  uint32_t graph_epoch;
+  StepGraphs graphs;
 };
 
 namespace {
@@ -376,8 +374,7 @@ int dsoar_collide_create(dsoar_heap* heap, uint32_t n, const dsoar_collide_param
 
 int dsoar_collide_destroy(dsoar_collide* c) {
   if (!c) return DSOAR_ERR_INVALID_ARG;
-  if (c->exec) (void)hipGraphExecDestroy(c->exec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
+  step_graphs_clear(c->graphs);
   delete c;
   return DSOAR_OK;
 }
@@ -397,28 +394,7 @@ int dsoar_collide_step(dsoar_collide* c, uint32_t steps, uint32_t flags, void* s
   dsoar_heap* h = c->heap;
   if (flags & DSOAR_GRAPH) {
     if (flags & DSOAR_DO_PLAIN) return DSOAR_ERR_INVALID_ARG;
-    if (c->exec && c->graph_epoch != h->config_epoch) {
-      (void)hipGraphExecDestroy(c->exec);
-      (void)hipGraphDestroy(c->graph);
-      c->exec = nullptr;
-      c->graph = nullptr;
-    }
-    if (!c->exec) {
-      DSOAR_HIP(h, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      const int rc = collide_one_step(c, 0, st);
-      hipGraph_t graph = nullptr;
-      const hipError_t e = hipStreamEndCapture(st, &graph);
-      if (rc) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
-      }
-      if (e != hipSuccess) return hip_fail(h, e);
-      c->graph = graph;
-      DSOAR_HIP(h, hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
-      c->graph_epoch = h->config_epoch;
-    }
-    for (uint32_t i = 0; i < steps; ++i) DSOAR_HIP(h, hipGraphLaunch(c->exec, st));
-    return DSOAR_OK;
+    return step_graphs_run(h, c->graphs, steps, st, [&](hipStream_t gs) { return collide_one_step(c, 0, gs); });
   }
   for (uint32_t i = 0; i < steps; ++i) {
     const int rc = collide_one_step(c, flags, st);

@@ -317,9 +317,7 @@ struct dsoar_gol {
   uint32_t* h_off;       // host copy of each slot's cell range (pool mode)
   uint32_t* h_side;
   uint8_t* live;         // slot holds a world (pool mode)
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-  uint32_t graph_epoch;  // heap config_epoch the graph was captured with
+  StepGraphs graphs;
 };
 
 namespace {
@@ -402,8 +400,7 @@ int dsoar_gol_destroy(dsoar_gol* g) {
   free(g->h_off);
   free(g->h_side);
   free(g->live);
-  if (g->exec) (void)hipGraphExecDestroy(g->exec);
-  if (g->graph) (void)hipGraphDestroy(g->graph);
+  step_graphs_clear(g->graphs);
   delete g;
   return DSOAR_OK;
 }
@@ -422,28 +419,7 @@ int dsoar_gol_step(dsoar_gol* g, uint32_t generations, uint32_t flags, void* str
   dsoar_heap* h = g->heap;
   if (flags & DSOAR_GOL_GRAPH) {
     if (flags & DSOAR_DO_PLAIN) return DSOAR_ERR_INVALID_ARG;  // plain mode synchronises
-    if (g->exec && g->graph_epoch != h->config_epoch) {  // launch shape or policy changed
-      (void)hipGraphExecDestroy(g->exec);
-      (void)hipGraphDestroy(g->graph);
-      g->exec = nullptr;
-      g->graph = nullptr;
-    }
-    if (!g->exec) {
-      DSOAR_HIP(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      const int rc = gol_generation(g, 0, s);
-      hipGraph_t graph = nullptr;
-      const hipError_t e = hipStreamEndCapture(s, &graph);
-      if (rc) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
-      }
-      if (e != hipSuccess) return hip_fail(h, e);
-      g->graph = graph;
-      DSOAR_HIP(h, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
-      g->graph_epoch = h->config_epoch;
-    }
-    for (uint32_t i = 0; i < generations; ++i) DSOAR_HIP(h, hipGraphLaunch(g->exec, s));
-    return DSOAR_OK;
+    return step_graphs_run(h, g->graphs, generations, s, [&](hipStream_t gs) { return gol_generation(g, 0, gs); });
   }
   for (uint32_t i = 0; i < generations; ++i) {
     const int rc = gol_generation(g, flags, s);

@@ -488,6 +488,59 @@ int launch_doall2(dsoar_heap* h, uint32_t t1, const typename M1::Args& a1, uint3
   return DSOAR_OK;
 }
 
+// The HIP graphs of an application's step: one of a single step and one of
+// kGraphSteps steps, captured on first use and replayed (a long run replays
+// the longer one, so graph boundaries come kGraphSteps times less often);
+// captured again when the heap's launch configuration changed since.
+constexpr uint32_t kGraphSteps = 10;
+struct StepGraphs {
+  hipGraph_t graph[2];
+  hipGraphExec_t exec[2];
+  uint32_t epoch;
+};
+
+inline void step_graphs_clear(StepGraphs& g) {
+  for (int i = 0; i < 2; ++i) {
+    if (g.exec[i]) (void)hipGraphExecDestroy(g.exec[i]);
+    if (g.graph[i]) (void)hipGraphDestroy(g.graph[i]);
+    g.exec[i] = nullptr;
+    g.graph[i] = nullptr;
+  }
+}
+
+// Runs `steps` steps of one_step(stream) (a function returning a status)
+// through the graphs.
+template <class F>
+int step_graphs_run(dsoar_heap* h, StepGraphs& g, uint32_t steps, hipStream_t s, F&& one_step) {
+  if (g.exec[0] && g.epoch != h->config_epoch) step_graphs_clear(g);
+  if (!g.exec[0]) {
+    const uint32_t reps[2] = {1, kGraphSteps};
+    for (int i = 0; i < 2; ++i) {
+      DSOAR_HIP(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      int rc = DSOAR_OK;
+      for (uint32_t k = 0; k < reps[i] && rc == DSOAR_OK; ++k) rc = one_step(s);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(s, &graph);
+      if (rc != DSOAR_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        step_graphs_clear(g);
+        return rc != DSOAR_OK ? rc : hip_fail(h, e);
+      }
+      g.graph[i] = graph;
+      const hipError_t ie = hipGraphInstantiate(&g.exec[i], graph, nullptr, nullptr, 0);
+      if (ie != hipSuccess) {
+        step_graphs_clear(g);
+        return hip_fail(h, ie);
+      }
+    }
+    g.epoch = h->config_epoch;
+  }
+  uint32_t left = steps;
+  for (; left >= kGraphSteps; left -= kGraphSteps) DSOAR_HIP(h, hipGraphLaunch(g.exec[1], s));
+  for (; left > 0; --left) DSOAR_HIP(h, hipGraphLaunch(g.exec[0], s));
+  return DSOAR_OK;
+}
+
 inline bool heap_ok(const dsoar_heap* h) { return h != nullptr && h->base != nullptr; }
 
 }  // namespace dsoar

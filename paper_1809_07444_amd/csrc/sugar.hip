@@ -353,9 +353,7 @@ struct dsoar_sugar {
   uint32_t* h_off;
   uint32_t* h_side;
   uint8_t* live;
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-  uint32_t graph_epoch;
+  StepGraphs graphs;
 };
 
 namespace {
@@ -510,8 +508,7 @@ int dsoar_sugar_create(dsoar_heap* heap, uint32_t side, const dsoar_sugar_rules*
 
 int dsoar_sugar_destroy(dsoar_sugar* s) {
   if (!s) return DSOAR_ERR_INVALID_ARG;
-  if (s->exec) (void)hipGraphExecDestroy(s->exec);
-  if (s->graph) (void)hipGraphDestroy(s->graph);
+  step_graphs_clear(s->graphs);
   free(s->h_off);
   free(s->h_side);
   free(s->live);
@@ -537,28 +534,7 @@ int dsoar_sugar_step(dsoar_sugar* s, uint32_t steps, uint32_t flags, void* strea
   dsoar_heap* h = s->heap;
   if (flags & DSOAR_GRAPH) {
     if (flags & DSOAR_DO_PLAIN) return DSOAR_ERR_INVALID_ARG;
-    if (s->exec && s->graph_epoch != h->config_epoch) {
-      (void)hipGraphExecDestroy(s->exec);
-      (void)hipGraphDestroy(s->graph);
-      s->exec = nullptr;
-      s->graph = nullptr;
-    }
-    if (!s->exec) {
-      DSOAR_HIP(h, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      const int rc = sugar_one_step(s, 0, st);
-      hipGraph_t graph = nullptr;
-      const hipError_t e = hipStreamEndCapture(st, &graph);
-      if (rc) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
-      }
-      if (e != hipSuccess) return hip_fail(h, e);
-      s->graph = graph;
-      DSOAR_HIP(h, hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
-      s->graph_epoch = h->config_epoch;
-    }
-    for (uint32_t i = 0; i < steps; ++i) DSOAR_HIP(h, hipGraphLaunch(s->exec, st));
-    return DSOAR_OK;
+    return step_graphs_run(h, s->graphs, steps, st, [&](hipStream_t gs) { return sugar_one_step(s, 0, gs); });
   }
   for (uint32_t i = 0; i < steps; ++i) {
     const int rc = sugar_one_step(s, flags, st);

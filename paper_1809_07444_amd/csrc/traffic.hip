@@ -156,9 +156,7 @@ using namespace dsoar;
 struct dsoar_traffic {
   dsoar_heap* heap;
   Road a;
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-  uint32_t graph_epoch;
+  StepGraphs graphs;
 };
 
 namespace {
@@ -216,8 +214,7 @@ int dsoar_traffic_create(dsoar_heap* heap, uint32_t roads, uint32_t length, cons
 
 int dsoar_traffic_destroy(dsoar_traffic* t) {
   if (!t) return DSOAR_ERR_INVALID_ARG;
-  if (t->exec) (void)hipGraphExecDestroy(t->exec);
-  if (t->graph) (void)hipGraphDestroy(t->graph);
+  step_graphs_clear(t->graphs);
   delete t;
   return DSOAR_OK;
 }
@@ -237,28 +234,7 @@ int dsoar_traffic_step(dsoar_traffic* t, uint32_t steps, uint32_t flags, void* s
   dsoar_heap* h = t->heap;
   if (flags & DSOAR_GRAPH) {
     if (flags & DSOAR_DO_PLAIN) return DSOAR_ERR_INVALID_ARG;
-    if (t->exec && t->graph_epoch != h->config_epoch) {
-      (void)hipGraphExecDestroy(t->exec);
-      (void)hipGraphDestroy(t->graph);
-      t->exec = nullptr;
-      t->graph = nullptr;
-    }
-    if (!t->exec) {
-      DSOAR_HIP(h, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      const int rc = traffic_one_step(t, 0, st);
-      hipGraph_t graph = nullptr;
-      const hipError_t e = hipStreamEndCapture(st, &graph);
-      if (rc) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
-      }
-      if (e != hipSuccess) return hip_fail(h, e);
-      t->graph = graph;
-      DSOAR_HIP(h, hipGraphInstantiate(&t->exec, t->graph, nullptr, nullptr, 0));
-      t->graph_epoch = h->config_epoch;
-    }
-    for (uint32_t i = 0; i < steps; ++i) DSOAR_HIP(h, hipGraphLaunch(t->exec, st));
-    return DSOAR_OK;
+    return step_graphs_run(h, t->graphs, steps, st, [&](hipStream_t gs) { return traffic_one_step(t, 0, gs); });
   }
   for (uint32_t i = 0; i < steps; ++i) {
     const int rc = traffic_one_step(t, flags, st);

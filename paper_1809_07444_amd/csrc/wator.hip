@@ -289,9 +289,7 @@ using namespace dsoar;
 struct dsoar_wator {
   dsoar_heap* heap;
   Sea a;
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-  uint32_t graph_epoch;
+  StepGraphs graphs;
 };
 
 namespace {
@@ -354,8 +352,7 @@ int dsoar_wator_create(dsoar_heap* heap, uint32_t side, const dsoar_wator_rules*
 
 int dsoar_wator_destroy(dsoar_wator* w) {
   if (!w) return DSOAR_ERR_INVALID_ARG;
-  if (w->exec) (void)hipGraphExecDestroy(w->exec);
-  if (w->graph) (void)hipGraphDestroy(w->graph);
+  step_graphs_clear(w->graphs);
   delete w;
   return DSOAR_OK;
 }
@@ -376,28 +373,7 @@ int dsoar_wator_step(dsoar_wator* w, uint32_t steps, uint32_t flags, void* strea
   dsoar_heap* h = w->heap;
   if (flags & DSOAR_GRAPH) {
     if (flags & DSOAR_DO_PLAIN) return DSOAR_ERR_INVALID_ARG;
-    if (w->exec && w->graph_epoch != h->config_epoch) {
-      (void)hipGraphExecDestroy(w->exec);
-      (void)hipGraphDestroy(w->graph);
-      w->exec = nullptr;
-      w->graph = nullptr;
-    }
-    if (!w->exec) {
-      DSOAR_HIP(h, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      const int rc = wator_one_step(w, 0, st);
-      hipGraph_t graph = nullptr;
-      const hipError_t e = hipStreamEndCapture(st, &graph);
-      if (rc) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
-      }
-      if (e != hipSuccess) return hip_fail(h, e);
-      w->graph = graph;
-      DSOAR_HIP(h, hipGraphInstantiate(&w->exec, w->graph, nullptr, nullptr, 0));
-      w->graph_epoch = h->config_epoch;
-    }
-    for (uint32_t i = 0; i < steps; ++i) DSOAR_HIP(h, hipGraphLaunch(w->exec, st));
-    return DSOAR_OK;
+    return step_graphs_run(h, w->graphs, steps, st, [&](hipStream_t gs) { return wator_one_step(w, 0, gs); });
   }
   for (uint32_t i = 0; i < steps; ++i) {
     const int rc = wator_one_step(w, flags, st);
