@@ -37,6 +37,9 @@ constexpr uint32_t kTypeNone = 0xFFu;
 constexpr int32_t kFail = -1;
 constexpr uint32_t kSpinLimit = 1u << 20;  // bound of every retry loop
 constexpr uint32_t kShards = 1024;         // counter shards (spread atomics)
+// s_waitcnt immediate for gfx9-family encodings: vmcnt 0 (bits 3:0 and
+// 15:14), expcnt 7 (bits 6:4) and lgkmcnt 15 (bits 11:8) left unconstrained.
+constexpr int kWaitVmem = 0x0F70;
 constexpr uint32_t kMultiBlocks = 8;  // active blocks one lookup may reserve in
 constexpr uint32_t kOomRetries = 4;        // active lookups retried before OOM
 
@@ -536,16 +539,31 @@ __device__ __forceinline__ void unpin_block(const DevHeap& h, uint32_t bid) {
 }
 
 // A block just taken from the free bitmap: its object bitmap first, then its
-// type word (release), so that a reservation that reads the new type word
-// also reads the initialised bitmap.  Per lane.  With online reclamation the
-// block may have been freed during this kernel: the acquire fence orders the
-// type-word read after the free-bitmap update that handed the block over.
-// Quiescent reclamation frees blocks only in earlier kernels.
+// type word, so that a reservation that reads the new type word also reads the
+// initialised bitmap.  Per lane.  With online reclamation the block may have
+// been freed during this kernel: the acquire fence orders the type-word read
+// after the free-bitmap update that handed the block over, and the type word
+// is a release store.  Quiescent reclamation frees blocks only in earlier
+// kernels, and every word involved is an agent-scope atomic, performed where
+// all XCDs see it; what must hold is that the bitmap store is complete before
+// the type word and the allocated / active sets that follow make the block
+// findable (else a reservation's OR could land before it and be overwritten).
+// The wave waits for its stores to complete (vmcnt 0) between the two stores;
+// an agent-scope release would also write back the XCD's whole L2, which only
+// plain stores need, once per block taken.  The signal fences keep the
+// compiler from moving either store across the wait.
 __device__ __forceinline__ uint32_t publish_block(const DevHeap& h, uint32_t bid, uint32_t type, uint64_t bits) {
   if (h.online_reclaim) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const uint32_t w = tw_with(__hip_atomic_load(h.block_type + bid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), type);
   __hip_atomic_store(h.obj_bitmap + bid, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(h.block_type + bid, w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (h.online_reclaim) {
+    __hip_atomic_store(h.block_type + bid, w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(kWaitVmem);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __hip_atomic_store(h.block_type + bid, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   return w;
 }
 
