@@ -86,12 +86,23 @@ def gol_kernel_bytes(kind, launches, st, M):
     return None
 
 
+def gol_init_bytes(cells, alive):
+    # Per cell: the input byte, the Cell's field and its index word; per live
+    # cell an Alive object's three fields; per new block its object bitmap
+    # and type word.
+    return cells * 9 + alive * 12 + (cells + alive) / 64 * 12
+
+
 def micro_kernel_bytes(kind, launches, st, M):
     v = st["visits"][0] / 2  # update and cull visit the same objects
     if kind == "micro_update":
         return v * 12 + v / 64 * 12
     if kind == "micro_cull":
         return v * 4 + st["frees"][0] * 0 + v / 64 * 12 + v / 64 * 8
+    if kind == "micro_create":
+        # x and v read from the inputs, id, x and v written; per block taken
+        # its object bitmap and type word.
+        return st["allocs"][0] * 20 + st["allocs"][0] / 64 * 12
     if kind == "enumerate":
         return launches * (M / 8) + v / 64 * 20
     return None
@@ -111,6 +122,7 @@ class GolWorkload:
         self.side, self.gens = 1024, 200
         self.grid = W.gol_grid(self.side, self.side, seed=args.seed)
         self.gol = apps.GameOfLife([self.grid])
+        self.init_objects = (int(self.grid.size), int((self.grid != 0).sum()))
         self.flags = C.DO_PERSISTENT | (0 if args.no_graph else C.GOL_GRAPH)
         self.M = self.gol.heap.num_blocks
         self.stream = self.gol.stream
@@ -133,6 +145,8 @@ class GolWorkload:
         return self.gol.heap.stats()
 
     def kernel_bytes(self, kind, launches, st):
+        if kind == "gol_init":
+            return gol_init_bytes(*self.init_objects)
         return gol_kernel_bytes(kind, launches, st, self.M)
 
     def heap(self):
@@ -222,6 +236,8 @@ class BatchedWorkload(GolWorkload):
             cfg, self.tune_table = batch.autotune(self.inp.grids, 10, cache_path=cache, log=log)
         self.cfg = cfg
         self.b = batch.BatchedGol(self.inp.grids, cfg)
+        self.init_objects = (sum(int(g.size) for g in self.inp.grids),
+                             sum(int((g != 0).sum()) for g in self.inp.grids))
         self.gol = self.b.gol
         self.M = self.gol.heap.num_blocks
         self.args = args
@@ -313,6 +329,8 @@ class SugarWorkload(GolWorkload):
                "sugar_request": 16 + 16 + 4, "sugar_birth": 12 + 4}
         if kind in per:
             return v * per[kind]
+        if kind == "sugar_regrow":  # sugar word and capacity read, sugar word written, per cell
+            return launches * self.side ** 2 * 12
         if kind == "enumerate":
             return launches * (self.M / 8) + (2 * v / 64) * 20
         return None
@@ -376,6 +394,13 @@ class TrafficWorkload(GolWorkload):
         per = {"traffic_decide": 12 + 4 * self.rules["vmax"], "traffic_drive": 8 + 8 + 8}
         if kind in per:
             return v * per[kind] + v / 64 * 12
+        cars0 = int((self.inp.vel >= 0).sum())
+        if kind == "traffic_entry":
+            # first cell of every road read; per entering car its three
+            # fields and the first cell written
+            return launches * self.roads * 4 + (st["allocs"][0] - cars0) * 16
+        if kind == "traffic_init":  # input speed read and cell written per cell, fields per car
+            return self.roads * self.length * 8 + cars0 * 12 + cars0 / 64 * 12
         if kind == "enumerate":
             return launches * (self.M / 8) + v / 64 * 20
         return None
@@ -437,6 +462,14 @@ class WatorWorkload(GolWorkload):
         if kind in per_s:
             extra = st["allocs"][1] * 16 if kind == "wator_shark_move" else 0
             return vs * per_s[kind] + vs / 64 * 12 + extra
+        if kind == "wator_init":
+            # kind, age, energy read, sea byte and request word written per
+            # cell; the fields of every animal
+            fish0 = int((self.inp.kind == 1).sum())
+            shark0 = int((self.inp.kind == 2).sum())
+            return self.side ** 2 * (12 + 1 + 8) + fish0 * 12 + shark0 * 16 + (fish0 + shark0) / 64 * 12
+        if kind == "wator_tick":
+            return launches * 8
         if kind == "enumerate":
             return launches * (self.M / 8) + (vf + vs) / 64 * 20
         return None
@@ -512,6 +545,10 @@ class CollideWorkload(GolWorkload):
                "collide_target": 16 + 4, "collide_merge": 24 + 4, "collide_remove": 8}
         if kind in per:
             return v * per[kind] + v / 64 * 12
+        if kind == "collide_init":
+            # five input arrays read; the per-id arrays (16 + 8 + 4 B) and the
+            # eight fields of every body written
+            return self.n * (20 + 28 + 32) + self.n / 64 * 12
         if kind == "enumerate":
             return launches * (self.M / 8) + v / 64 * 20
         return None

@@ -32,7 +32,10 @@ KIND_NAMES = {1: "enumerate", 10: "visit_count", 11: "delete_if_mod", 12: "gathe
               50: "traffic_decide", 51: "traffic_drive", 60: "collide_force", 61: "collide_move",
               62: "collide_root", 63: "collide_target", 64: "collide_merge", 65: "collide_remove",
               70: "wator_fish_decide", 71: "wator_fish_move", 72: "wator_shark_decide",
-              73: "wator_shark_move", 74: "wator_fish_eaten", 75: "wator_fish_read", 76: "wator_shark_read"}
+              73: "wator_shark_move", 74: "wator_fish_eaten", 75: "wator_fish_read", 76: "wator_shark_read",
+              22: "micro_create", 36: "gol_init", 37: "gol_admit", 46: "sugar_regrow", 47: "sugar_admit",
+              52: "traffic_entry", 53: "traffic_init", 66: "collide_init",
+              77: "wator_init", 78: "wator_tick"}
 INV_NAMES = ["bitmap_range", "allocated", "active", "active_implies_allocated", "free",
              "container", "live_count", "reserved"]
 

@@ -382,7 +382,7 @@ int dsoar_collide_destroy(dsoar_collide* c) {
 int dsoar_collide_init(dsoar_collide* c, const float* x_dev, const float* y_dev, const float* vx_dev,
                        const float* vy_dev, const float* m_dev, void* stream) {
   if (!c || !x_dev || !y_dev || !vx_dev || !vy_dev || !m_dev) return DSOAR_ERR_INVALID_ARG;
-  hipLaunchKernelGGL(collide_init_kernel, dim3((c->a.n + 255) / 256), dim3(256), 0, (hipStream_t)stream, c->heap->dev,
+  launch_timed(c->heap, kKindCollideInit, collide_init_kernel, dim3((c->a.n + 255) / 256), dim3(256), (hipStream_t)stream, c->heap->dev,
                      c->a, x_dev, y_dev, vx_dev, vy_dev, m_dev);
   DSOAR_LAUNCHED(c->heap);
   return DSOAR_OK;

@@ -407,7 +407,7 @@ int dsoar_gol_destroy(dsoar_gol* g) {
 
 int dsoar_gol_init(dsoar_gol* g, const uint8_t* grid_dev, void* stream) {
   if (!g || !grid_dev) return DSOAR_ERR_INVALID_ARG;
-  hipLaunchKernelGGL(gol_init_kernel, dim3((g->total + 255) / 256), dim3(256), 0, (hipStream_t)stream, g->heap->dev,
+  launch_timed(g->heap, kKindGolInit, gol_init_kernel, dim3((g->total + 255) / 256), dim3(256), (hipStream_t)stream, g->heap->dev,
                      g->w, g->num_worlds, g->total, grid_dev);
   DSOAR_LAUNCHED(g->heap);
   return DSOAR_OK;
@@ -488,7 +488,7 @@ int dsoar_gol_admit(dsoar_gol* g, uint32_t slot, uint32_t cell_offset, uint32_t 
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(gol_set_slot_kernel, dim3(1), dim3(1), 0, s, g->w, slot, cell_offset, side);
   DSOAR_LAUNCHED(g->heap);
-  hipLaunchKernelGGL(gol_admit_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, g->heap->dev, g->w, slot,
+  launch_timed(g->heap, kKindGolAdmit, gol_admit_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), s, g->heap->dev, g->w, slot,
                      cell_offset, (uint32_t)n, grid_dev);
   DSOAR_LAUNCHED(g->heap);
   g->h_off[slot] = cell_offset;

@@ -89,6 +89,18 @@ inline int hip_fail(dsoar_heap* h, hipError_t e) {
 
 constexpr uint32_t kTimingCap = 8192;
 constexpr uint32_t kKindEnumerate = 1;
+// Timing ids of the kernels outside the do-alls that create objects or
+// advance a step (the do-all methods carry their own).
+constexpr uint32_t kKindMicroCreate = 22;
+constexpr uint32_t kKindGolInit = 36;
+constexpr uint32_t kKindGolAdmit = 37;
+constexpr uint32_t kKindSugarRegrow = 46;
+constexpr uint32_t kKindSugarAdmit = 47;
+constexpr uint32_t kKindTrafficEntry = 52;
+constexpr uint32_t kKindTrafficInit = 53;
+constexpr uint32_t kKindCollideInit = 66;
+constexpr uint32_t kKindWatorInit = 77;
+constexpr uint32_t kKindWatorTick = 78;
 
 // Launches `kernel` on stream s.  With timing on (and room in the record), the
 // launch itself carries a start and a stop event (hipExtLaunchKernel): they

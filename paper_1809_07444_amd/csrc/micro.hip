@@ -34,16 +34,31 @@ struct MicroCull {
   }
 };
 
-// Lane i creates an object with id = id_mul * i and the i-th input values.
-__global__ void micro_create_kernel(DevHeap h, uint32_t type, uint32_t n, uint32_t id_mul, const float* xs,
-                                    const float* vs) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t o = dsoar_new(h, type);
-  if (o == kNull) return;
-  *field_ptr<int32_t>(h, o, type, kId) = (int32_t)(id_mul * i);
-  *field_ptr<float>(h, o, type, kX) = xs[i];
-  *field_ptr<float>(h, o, type, kV) = vs[i];
+// Object i gets id = id_mul * i and the i-th input values.  A wavefront
+// creates per_lane * 64 consecutive objects, lane l those at offsets l,
+// l + 64, ... (coalesced input reads), as one request of up to per_lane
+// objects per lane: a wavefront asking for four blocks' worth takes them with
+// one atomic on the free bitmap.  Large creations use four per lane (fewer,
+// longer requests); below kCreateWideMin objects one per lane keeps enough
+// wavefronts in flight to hide the allocation latency.
+constexpr uint32_t kCreatePerLane = 4;
+constexpr uint32_t kCreateWideMin = 1u << 22;
+constexpr uint32_t kCreateThreads = 256;
+
+__global__ void micro_create_kernel(DevHeap h, uint32_t type, uint32_t n, uint32_t per_lane, uint32_t id_mul,
+                                    const float* xs, const float* vs) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t wave = (uint64_t)blockIdx.x * (kCreateThreads / 64) + (threadIdx.x >> 6);
+  const uint64_t base = wave * (64u * per_lane) + lane;
+  uint32_t k = 0;
+  for (uint32_t j = 0; j < per_lane; ++j) k += base + j * 64u < n ? 1u : 0u;
+  new_many(h, type, k, [&](uint32_t j, uint32_t o) {
+    if (o == kNull) return;
+    const uint32_t i = (uint32_t)(base + j * 64u);
+    *field_ptr<int32_t>(h, o, type, kId) = (int32_t)(id_mul * i);
+    *field_ptr<float>(h, o, type, kX) = xs[i];
+    *field_ptr<float>(h, o, type, kV) = vs[i];
+  });
 }
 
 bool micro_type_ok(const dsoar_heap* h, uint32_t type) {
@@ -55,7 +70,10 @@ bool micro_type_ok(const dsoar_heap* h, uint32_t type) {
 int launch_create(dsoar_heap* h, uint32_t type, uint32_t n, uint32_t id_mul, const float* xs, const float* vs,
                   hipStream_t s) {
   if (n == 0) return DSOAR_OK;
-  hipLaunchKernelGGL(micro_create_kernel, dim3((n + 255) / 256), dim3(256), 0, s, h->dev, type, n, id_mul, xs, vs);
+  const uint32_t per_lane = n >= kCreateWideMin ? kCreatePerLane : 1u;
+  const uint64_t per_block = (uint64_t)kCreateThreads * per_lane;
+  launch_timed(h, kKindMicroCreate, micro_create_kernel, dim3((uint32_t)((n + per_block - 1) / per_block)),
+               dim3(kCreateThreads), s, h->dev, type, n, per_lane, id_mul, xs, vs);
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }

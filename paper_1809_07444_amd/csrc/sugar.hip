@@ -363,7 +363,7 @@ int sugar_one_step(dsoar_sugar* s, uint32_t flags, hipStream_t st) {
   const uint32_t base = flags & DSOAR_DO_PLAIN;
   const uint32_t grid = std::min<uint32_t>(std::max<uint32_t>((s->g.arena + 255) / 256, (s->g.max_worlds + 255) / 256),
                                            std::max<uint32_t>(h->num_cus * 16, (s->g.max_worlds + 255) / 256));
-  hipLaunchKernelGGL(regrow_kernel, dim3(grid), dim3(256), 0, st, s->g);
+  launch_timed(s->heap, kKindSugarRegrow, regrow_kernel, dim3(grid), dim3(256), st, s->g);
   DSOAR_LAUNCHED(h);
   int rc = launch_doall<Choose>(h, kAgent, s->g, base, st);
   // choose and move create and delete nothing: move and eat reuse the list.
@@ -454,7 +454,7 @@ int dsoar_sugar_admit(dsoar_sugar* s, uint32_t slot, uint32_t cell_offset, uint3
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(set_world_kernel, dim3(1), dim3(kMoveShards), 0, st, s->g, slot, cell_offset, side, seed, step0);
   DSOAR_LAUNCHED(s->heap);
-  hipLaunchKernelGGL(sugar_admit_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, s->heap->dev, s->g, slot,
+  launch_timed(s->heap, kKindSugarAdmit, sugar_admit_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), st, s->heap->dev, s->g, slot,
                      cell_offset, (uint32_t)n, sugar_dev, cap_dev, occ_dev, a_sugar_dev, a_metab_dev, a_vision_dev,
                      a_age_dev);
   DSOAR_LAUNCHED(s->heap);

@@ -10,9 +10,9 @@
 //     road's last cell deletes itself.  Moves never collide: a car ends
 //     before the old cell of the car ahead, so all handle writes are distinct.
 //   Entry (one thread per road): a car enters an empty first cell at speed 0
-//     with probability p_in, from hash(seed, 33, road, t).
-//   Tick: t += 1 (the step index lives on the device, so a captured step
-//     replays correctly).
+//     with probability p_in, from hash(seed, 33, road, t); the last workgroup
+//     of the entry kernel to finish advances t (the step index lives on the
+//     device, so a captured step replays correctly).
 #include <string.h>
 
 #include <new>
@@ -43,7 +43,7 @@ __device__ __forceinline__ uint64_t draw(uint64_t seed, uint64_t stream, uint64_
 
 struct Road {
   uint32_t* occ;   // cell -> car handle, kNull when empty
-  uint32_t* step;  // [0]: index of the step in progress
+  uint32_t* step;  // [0]: index of the step in progress; [1]: entry workgroups done
   uint32_t roads, length;
   uint64_t seed;
   int32_t vmax;
@@ -96,29 +96,43 @@ struct Drive {
   }
 };
 
-// A car enters road r's empty first cell with probability p_in.
+// A car enters road r's empty first cell with probability p_in.  Then the
+// step advances: each workgroup counts itself done after all its threads have
+// used t, and the last one to do so stores t + 1 (and resets the count), so no
+// thread of this launch can read the new value.
 __global__ void entry_kernel(DevHeap h, Road a) {
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= a.roads) return;
-  const uint32_t q = r * a.length;
-  const uint64_t hs = draw(a.seed, kStreamIn, r, a.step[0]);
-  const bool enter = a.occ[q] == kNull && (uint32_t)(hs >> 40) < a.p_in24;
-  new_many(h, kCar, enter ? 1u : 0u, [&](uint32_t, uint32_t o) {
-    if (o == kNull) return;
-    car<uint32_t>(h, o, kCellF) = q;
-    car<int32_t>(h, o, kSpeed) = 0;
-    car<int32_t>(h, o, kNext) = 0;
-    a.occ[q] = o;
-  });
+  const uint32_t t = a.step[0];
+  if (r < a.roads) {
+    const uint32_t q = r * a.length;
+    const uint64_t hs = draw(a.seed, kStreamIn, r, t);
+    const bool enter = a.occ[q] == kNull && (uint32_t)(hs >> 40) < a.p_in24;
+    new_many(h, kCar, enter ? 1u : 0u, [&](uint32_t, uint32_t o) {
+      if (o == kNull) return;
+      car<uint32_t>(h, o, kCellF) = q;
+      car<int32_t>(h, o, kSpeed) = 0;
+      car<int32_t>(h, o, kNext) = 0;
+      a.occ[q] = o;
+    });
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t done = __hip_atomic_fetch_add(a.step + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == gridDim.x - 1) {
+      __hip_atomic_store(a.step + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a.step[0] = t + 1;
+    }
+  }
 }
-
-__global__ void tick_kernel(Road a) { a.step[0] += 1; }
 
 // Initial state: a car in every cell whose speed is >= 0.
 __global__ void traffic_init_kernel(DevHeap h, Road a, const int32_t* vel, uint32_t step0) {
   const uint64_t n = (uint64_t)a.roads * a.length;
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c == 0) a.step[0] = step0;
+  if (c == 0) {
+    a.step[0] = step0;
+    a.step[1] = 0;
+  }
   if (c >= n) return;
   a.occ[c] = kNull;
   const int32_t v = vel[c];
@@ -168,9 +182,7 @@ int traffic_one_step(dsoar_traffic* t, uint32_t flags, hipStream_t st) {
   // Decide creates and deletes nothing: Drive reuses its list.
   if (!rc) rc = launch_doall<Drive>(h, kCar, t->a, base | DSOAR_DO_REUSE_ENUM, st);
   if (rc) return rc;
-  hipLaunchKernelGGL(entry_kernel, dim3((t->a.roads + 255) / 256), dim3(256), 0, st, h->dev, t->a);
-  DSOAR_LAUNCHED(h);
-  hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, st, t->a);
+  launch_timed(h, kKindTrafficEntry, entry_kernel, dim3((t->a.roads + 255) / 256), dim3(256), st, h->dev, t->a);
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }
@@ -222,7 +234,7 @@ int dsoar_traffic_destroy(dsoar_traffic* t) {
 int dsoar_traffic_init(dsoar_traffic* t, const int32_t* vel_dev, uint32_t step0, void* stream) {
   if (!t || !vel_dev) return DSOAR_ERR_INVALID_ARG;
   const uint64_t n = (uint64_t)t->a.roads * t->a.length;
-  hipLaunchKernelGGL(traffic_init_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+  launch_timed(t->heap, kKindTrafficInit, traffic_init_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), (hipStream_t)stream,
                      t->heap->dev, t->a, vel_dev, step0);
   DSOAR_LAUNCHED(t->heap);
   return DSOAR_OK;

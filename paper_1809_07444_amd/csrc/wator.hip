@@ -305,7 +305,7 @@ int wator_one_step(dsoar_wator* w, uint32_t flags, hipStream_t st) {
   if (!rc) rc = launch_doall<SharkMove>(h, kShark, w->a, reuse, st);
   if (!rc) rc = launch_doall<FishEaten>(h, kFish, w->a, base, st);
   if (rc) return rc;
-  hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, st, w->a);
+  launch_timed(w->heap, kKindWatorTick, tick_kernel, dim3(1), dim3(1), st, w->a);
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }
@@ -361,7 +361,7 @@ int dsoar_wator_init(dsoar_wator* w, const int32_t* kind_dev, const int32_t* age
                      uint32_t step0, void* stream) {
   if (!w || !kind_dev || !age_dev || !energy_dev) return DSOAR_ERR_INVALID_ARG;
   const uint64_t n = (uint64_t)w->a.side * w->a.side;
-  hipLaunchKernelGGL(wator_init_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+  launch_timed(w->heap, kKindWatorInit, wator_init_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), (hipStream_t)stream,
                      w->heap->dev, w->a, kind_dev, age_dev, energy_dev, step0);
   DSOAR_LAUNCHED(w->heap);
   return DSOAR_OK;

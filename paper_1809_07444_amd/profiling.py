@@ -44,6 +44,18 @@ METHOD_KIND = {
 METHOD2_KIND = {("AliveUpdate", "CandUpdate"): "gol_update"}
 
 
+# Kernels outside the do-alls that carry a timing kind: (function name, a
+# substring of the argument list that tells same-named kernels apart).
+PLAIN_KIND = [
+    ("micro_create_kernel", "", "micro_create"), ("gol_init_kernel", "", "gol_init"),
+    ("gol_admit_kernel", "", "gol_admit"), ("regrow_kernel", "", "sugar_regrow"),
+    ("sugar_admit_kernel", "", "sugar_admit"), ("entry_kernel", "", "traffic_entry"),
+    ("traffic_init_kernel", "", "traffic_init"),
+    ("collide_init_kernel", "", "collide_init"), ("wator_init_kernel", "", "wator_init"),
+    ("tick_kernel", "Sea", "wator_tick"),
+]
+
+
 def kernel_kind(name: str) -> str | None:
     """Kernel kind of a rocprofv3 kernel name, 'calibration' for the add, or None."""
     m2 = re.search(r"doall2_kernel<(?:[\w:]*::|\(anonymous namespace\)::)*(\w+),\s*"
@@ -55,6 +67,11 @@ def kernel_kind(name: str) -> str | None:
         return METHOD_KIND.get(m.group(1))
     if "enumerate_kernel" in name:
         return "enumerate"
+    m = re.search(r"(\w+)\((.*)\)\s*$", name)
+    if m:
+        for fn, arg, kind in PLAIN_KIND:
+            if m.group(1) == fn and arg in m.group(2):
+                return kind
     if "elementwise" in name and "add" in name.lower():
         return "calibration"
     return None
