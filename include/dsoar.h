@@ -168,6 +168,18 @@ int dsoar_heap_set_launch(dsoar_heap* heap, uint32_t wg_threads, uint32_t wgs_pe
  * capacity. */
 int dsoar_heap_set_policy(dsoar_heap* heap, uint32_t bulk_min);
 
+/* Per-type allocation policy.  DSOAR_POLICY_DENSE (the default for every
+ * type) is the dense policy above.  With DSOAR_POLICY_FRESH a request of the
+ * type skips the active lookup: a wavefront opens free blocks of its own
+ * (whole ones while it needs at least a block's worth, then one block for the
+ * rest, which stays active like any other partly filled block).  Meant for
+ * types whose objects all die within one phase, so that dense packing buys
+ * nothing and the lookup is pure latency (the Game of Life's Candidates).
+ * The slot placement differs, the results do not.  type >= the heap's
+ * number of types or another policy value: DSOAR_ERR_INVALID_ARG. */
+enum { DSOAR_POLICY_DENSE = 0, DSOAR_POLICY_FRESH = 1 };
+int dsoar_heap_set_type_policy(dsoar_heap* heap, uint32_t type, uint32_t policy);
+
 /* Block reclamation.  By default (online = 0) a block emptied by deletes
  * stays allocated to its type until the next enumeration of that type or
  * dsoar_reclaim returns it to the free bitmap, at a point where no kernel of

@@ -23,6 +23,7 @@ ERR_OOM, ERR_RETRY_LIMIT, ERR_DOUBLE_FREE = -2, -3, -5
 
 DO_PERSISTENT, DO_PLAIN, DO_REUSE_ENUM = 0, 1, 2
 GRAPH = GOL_GRAPH = 0x100
+POLICY_DENSE, POLICY_FRESH = 0, 1
 METHOD_VISIT_COUNT, METHOD_DELETE_IF_MOD, METHOD_MICRO_UPDATE, METHOD_MICRO_CULL, METHOD_FIELD_GATHER = 1, 2, 3, 4, 5
 BM_TRY_SET, BM_TRY_CLEAR, BM_SET, BM_CLEAR, BM_TRY_FIND_SET, BM_FIND_CLEAR = range(6)
 KIND_NAMES = {1: "enumerate", 10: "visit_count", 11: "delete_if_mod", 12: "gather", 20: "micro_update",
@@ -108,6 +109,7 @@ SIGNATURES = {
     "dsoar_heap_get_layout": (ctypes.c_int, [H, ctypes.POINTER(HeapLayout)]),
     "dsoar_heap_set_launch": (ctypes.c_int, [H, u32, u32]),
     "dsoar_heap_set_policy": (ctypes.c_int, [H, u32]),
+    "dsoar_heap_set_type_policy": (ctypes.c_int, [H, u32, u32]),
     "dsoar_heap_set_unroll": (ctypes.c_int, [H, u32]),
     "dsoar_heap_set_reclaim": (ctypes.c_int, [H, ctypes.c_int]),
     "dsoar_stress_churn": (ctypes.c_int, [H, u32, u32, u32, u32, u32, vp, vp, vp]),

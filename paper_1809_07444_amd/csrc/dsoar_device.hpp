@@ -78,6 +78,7 @@ struct DevHeap {
   uint32_t nlevels;
   uint32_t bm_words;        // words per bitmap (all levels, padded)
   uint32_t bulk_min;        // requests of at least this many take whole free blocks
+  uint32_t fresh_types;     // bit t: requests of type t skip the active lookup
   uint32_t doall_unroll;    // blocks per wavefront pass of split do-alls (1, 2, 4, 8)
   uint32_t online_reclaim;  // 1: the delete that empties a block frees it at once
   // Field f of type t: byte offset of its array in a block (low 24 bits)
@@ -609,6 +610,11 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
   int32_t cur = kFail;     // block of the last reservation, if it still had room
   uint64_t cur_avail = 0;  // its free bits right after that reservation
   uint32_t cur_tw = 0;     // its type word then (online reclamation: checked on reuse)
+  // A type with the fresh policy looks for active blocks only once no free
+  // block is left (active_first); until then the request goes on as if the
+  // lookup had found none.
+  const bool fresh = (h.fresh_types >> type) & 1u;
+  if (fresh) none_active = true;
   for (uint32_t it = 0; served < n; ++it) {
     if (it >= kSpinLimit) {
       lead_flag(h.ctrl + kCtlRetryLimit);
@@ -647,7 +653,7 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
     int32_t bid = cur;
     uint64_t avail = cur_avail;
     uint64_t got;
-    if (bid == kFail) {
+    if (bid == kFail && (!fresh || active_first)) {
       uint64_t wbits = 0;
       const int32_t aw = bm_find_word(active, start, &wbits);
       if (aw == kFail) {

@@ -81,6 +81,9 @@ class Heap:
     def set_policy(self, bulk_min: int):
         C.check(self.lib.dsoar_heap_set_policy(self.h, bulk_min), "dsoar_heap_set_policy")
 
+    def set_type_policy(self, type_id: int, policy: int):
+        C.check(self.lib.dsoar_heap_set_type_policy(self.h, type_id, policy), "dsoar_heap_set_type_policy")
+
     def set_reclaim(self, online: bool):
         """Free emptied blocks at the delete that empties them (online) or at enumeration."""
         C.check(self.lib.dsoar_heap_set_reclaim(self.h, 1 if online else 0), "dsoar_heap_set_reclaim")

@@ -17,7 +17,7 @@ import numpy as np
 import torch
 
 from . import _capi as C
-from .apps import GOL_TYPES, SUGAR_TYPE, GameOfLife
+from .apps import GOL_CAND, GOL_TYPES, SUGAR_TYPE, GameOfLife
 from .heap import Heap
 
 
@@ -81,6 +81,7 @@ class Pool:
         self.heap = Heap(blocks, 64, types, device=device, stream=self.stream)
         if kind == "gol":
             self.heap.set_policy(GameOfLife.BULK_MIN)  # as the single-pool GoL driver
+            self.heap.set_type_policy(GOL_CAND, GameOfLife.CAND_POLICY)
         self.lib = self.heap.lib
         self.blocks = blocks
         self.budget = blocks

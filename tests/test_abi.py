@@ -100,3 +100,4 @@ def test_application_entry_points_validate_without_a_gpu():
     assert lib.dsoar_traffic_step(None, 1, 0, None) == -1
     assert lib.dsoar_wator_read(None, None, None, None, None) == -1
     assert lib.dsoar_wator_init(None, None, None, None, 0, None) == -1
+    assert lib.dsoar_heap_set_type_policy(None, 0, C.POLICY_FRESH) == -1

@@ -28,8 +28,10 @@ def expected_counts(grids, gens):
     return finals, allocs, frees
 
 
-def run_and_compare(grids, gens, flags=C.DO_PERSISTENT, capacity=64, split=None):
+def run_and_compare(grids, gens, flags=C.DO_PERSISTENT, capacity=64, split=None, cand_policy=None):
     gol = apps.GameOfLife(grids, capacity=capacity)
+    if cand_policy is not None:
+        gol.heap.set_type_policy(apps.GOL_CAND, cand_policy)
     gol.init()
     if split:
         for k in split:
@@ -82,6 +84,22 @@ def test_random_small_worlds(seed, capacity):
 def test_modes_agree_medium(flags):
     grids = [W.gol_grid(200, 200, seed=11), W.gol_grid(97, 97, seed=12)]
     run_and_compare(grids, 40, flags=flags, split=[1, 13, 26])
+
+
+@pytest.mark.parametrize("policy", [C.POLICY_DENSE, C.POLICY_FRESH])
+def test_candidate_policies_agree(policy):
+    # Candidates from active blocks first (dense) or from blocks of their own
+    # (fresh): placement differs, grids and object counts do not.
+    grids = [W.gol_grid(256, 256, seed=21), W.gol_grid(61, 61, seed=22)]
+    run_and_compare(grids, 60, flags=C.DO_PERSISTENT | C.GOL_GRAPH, cand_policy=policy)
+
+
+def test_type_policy_validates():
+    gol = apps.GameOfLife([W.gol_grid(16, 16, seed=3)])
+    with pytest.raises(Exception):
+        gol.heap.set_type_policy(3, C.POLICY_FRESH)  # three types: 0, 1, 2
+    with pytest.raises(Exception):
+        gol.heap.set_type_policy(0, 2)
 
 
 def test_full_config_1024_200_generations():
