@@ -66,6 +66,42 @@ def test_ragged_alloc_and_oom():
     assert chk == {"sticky": "DSOAR_ERR_OOM"}
 
 
+@pytest.mark.parametrize("policy,blocks", [(C.POLICY_DENSE, 1), (C.POLICY_FRESH, 2)])
+def test_type_policy_fresh_opens_own_blocks(policy, blocks):
+    # Two requests of 10: the dense policy puts the second into the block the
+    # first left active; the fresh policy opens a block for each.
+    heap = Heap(64, 64, [(4,)])
+    heap.set_type_policy(0, policy)
+    a = heap.alloc_n(0, 10).cpu().numpy().view(np.uint32)
+    b = heap.alloc_n(0, 10).cpu().numpy().view(np.uint32)
+    h = np.concatenate([a, b])
+    assert (h != C.NULL).all() and len(np.unique(h)) == 20
+    st = heap.stats()
+    assert st["live"] == [20] and st["allocated_blocks"] == [blocks] and st["active_blocks"] == [blocks]
+    assert heap.check() == {}
+
+
+def test_type_policy_fresh_falls_back_to_active_blocks():
+    # Every block full, then 10 slots freed in each: no free block is left,
+    # so fresh requests must take the freed slots, all of them, before OOM.
+    heap = Heap(16, 64, [(4,)])
+    heap.set_type_policy(0, C.POLICY_FRESH)
+    h = heap.alloc_n(0, 16 * 64)
+    hn = h.cpu().numpy().view(np.uint32)
+    assert (hn != C.NULL).all()
+    freed = torch.from_numpy(np.sort(hn)[np.arange(16 * 64) % 64 < 10].view(np.int32)).to(h.device)
+    heap.free_n(freed)
+    st = heap.stats()
+    assert st["live"] == [16 * 64 - 160] and st["free_blocks"] == 0 and st["active_blocks"] == [16]
+    again = heap.alloc_n(0, 160).cpu().numpy().view(np.uint32)
+    assert (again != C.NULL).all()
+    assert set(again.tolist()) == set(freed.cpu().numpy().view(np.uint32).tolist())
+    st = heap.stats(raise_sticky=False)
+    assert st["live"] == [16 * 64] and st["oom"] == 0
+    assert heap.alloc_n(0, 1).cpu().numpy().view(np.uint32)[0] == C.NULL
+    assert heap.check() == {"sticky": "DSOAR_ERR_OOM"}
+
+
 @pytest.mark.parametrize("cap,ntypes", [(64, 1), (64, 3), (32, 2)])
 def test_churn_invariants_and_visits(cap, ntypes):
     rng = np.random.default_rng(cap + ntypes)
