@@ -197,13 +197,19 @@ int dsoar_heap_set_reclaim(dsoar_heap* heap, int online);
  * blocks; results do not depend on it.  Other values: DSOAR_ERR_INVALID_ARG. */
 int dsoar_heap_set_unroll(dsoar_heap* heap, uint32_t blocks_per_pass);
 
-/* Per-launch timing: when enabled, every enumeration and do-all launch of
- * this heap is bracketed by a pair of HIP events on its stream (at most 8192
- * launches are recorded between reports).  dsoar_heap_timing synchronises on
- * the last event, aggregates the recorded launches by kernel kind (1 =
- * enumeration; do-all kinds: 10 visit count, 11 delete-if-mod, 12 gather,
- * 20/21 micro update/cull, 30..33 Game of Life phases 1..4, 40.. Sugarscape
- * phases) into kinds/counts/total_ms, and clears the records. */
+/* Per-launch timing: when enabled, every enumeration, do-all and
+ * object-creating launch of this heap is bracketed by a pair of HIP events
+ * on its stream (at most 8192 launches are recorded between reports).
+ * dsoar_heap_timing synchronises on the last event, aggregates the recorded
+ * launches by kernel kind into kinds/counts/total_ms, and clears the records.
+ * Kinds: 1 enumeration; do-alls 10 visit count, 11 delete-if-mod, 12 gather,
+ * 20/21 micro update/cull, 30..33 Game of Life phases 1..4 (35: phases 3 and
+ * 4 in one launch, 34 world deletion), 40..45 Sugarscape phases and world
+ * deletion, 50/51 traffic decide/drive, 60..65 collisions, 70..76 wa-tor;
+ * other kernels 22 micro creation, 36/37 Game of Life initial cells and
+ * admission, 46/47 Sugarscape regrow and admission, 52/53 traffic entry and
+ * initial cars, 66 collisions initial bodies, 77/78 wa-tor initial sea and
+ * step tick. */
 int dsoar_heap_set_timing(dsoar_heap* heap, int enable);
 int dsoar_heap_timing(dsoar_heap* heap, uint32_t* kinds, uint32_t* counts, double* total_ms,
                       uint32_t max_kinds, uint32_t* num_kinds);
