@@ -54,6 +54,8 @@ def parse():
                    help="allocation policy: requests of at least this many take whole free blocks first "
                         "('never' = the dense default)")
     p.add_argument("--unroll", type=int, default=None, help="blocks per wavefront pass of split do-alls")
+    p.add_argument("--reclaim", default="quiescent", choices=["quiescent", "online"],
+                   help="free emptied blocks at enumeration (default) or at the delete that empties them")
     p.add_argument("--bodies", type=int, default=65536,
                    help="collisions: number of bodies (the box side grows with sqrt(bodies), fixed density)")
     return p.parse_args()
@@ -638,6 +640,9 @@ def main():
     if args.unroll is not None:
         wl.heap().set_unroll(args.unroll)
         wl.config["unroll"] = args.unroll
+    if args.reclaim == "online":
+        wl.heap().set_reclaim(True)
+        wl.config["reclaim"] = "online"
 
     for _ in range(args.warmup):
         wl.step()
@@ -723,6 +728,7 @@ def main():
         "per_step": {"allocs": st1["allocs"], "frees": st1["frees"], "doall_visits": st1["visits"],
                      "reserve_retries": st1["reserve_retries"], "slow_paths": st1["slow_paths"],
                      "find_fails": st1["find_fails"], "method_atomics": st1["method_atomics"],
+                     "online_releases": st1["online_releases"],
                      "allocated_blocks_end": st1["allocated_blocks"]},
         "roofline": roof, "cpu_baseline": cpu, "kernels": kernels,
     }

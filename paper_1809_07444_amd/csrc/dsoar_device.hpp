@@ -19,7 +19,10 @@
 // block-state bitmaps are eventually consistent hints.  No release/acquire
 // fences are used: object fields written in one kernel are read in later
 // kernels (kernel boundaries order them), and a method that deletes `this`
-// must not write this's fields in the same call.
+// must not write this's fields in the same call.  Where one metadata access
+// must be performed before another (a block's publication, the pins of
+// online reclamation), the wave waits for its accesses to complete
+// (wait_performed) before it issues the next.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -527,44 +530,49 @@ __device__ __forceinline__ F* field_ptr(const DevHeap& h, uint32_t obj, uint32_t
                               ((uint64_t)obj_slot(obj) << (loc >> 24)));
 }
 
+// Waits until every memory access this wave has issued has completed; for
+// the agent-scope atomics of the heap metadata that means performed where all
+// XCDs see them.  The signal fences keep the compiler from moving memory
+// accesses across the wait.  Every ordering the allocator needs is between
+// such atomics, so this wait is what it uses instead of release / acquire
+// fences, which on this part also write back or invalidate the XCD's whole L2
+// (needed only for plain stores and loads).
+__device__ __forceinline__ void wait_performed() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(kWaitVmem);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Reservation side of online reclamation: pin block `bid` (per lane) if its
-// type word still reads `w`; false (and no pin held) otherwise.
+// type word still reads `w`; false (and no pin held) otherwise.  The pin is
+// performed before the type word is read again, and the releaser's type-word
+// store before it reads the pins, so at least one of the two sees the other.
 __device__ __forceinline__ bool pin_block(const DevHeap& h, uint32_t bid, uint32_t w) {
-  __hip_atomic_fetch_add(h.pins + bid, 1u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
-  if (__hip_atomic_load(h.block_type + bid, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT) == w) return true;
-  __hip_atomic_fetch_sub(h.pins + bid, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(h.pins + bid, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  wait_performed();
+  if (__hip_atomic_load(h.block_type + bid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == w) return true;
+  __hip_atomic_fetch_sub(h.pins + bid, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return false;
 }
+// The reservation made under the pin is performed before the pin goes.
 __device__ __forceinline__ void unpin_block(const DevHeap& h, uint32_t bid) {
-  __hip_atomic_fetch_sub(h.pins + bid, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  wait_performed();
+  __hip_atomic_fetch_sub(h.pins + bid, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // A block just taken from the free bitmap: its object bitmap first, then its
 // type word, so that a reservation that reads the new type word also reads the
-// initialised bitmap.  Per lane.  With online reclamation the block may have
-// been freed during this kernel: the acquire fence orders the type-word read
-// after the free-bitmap update that handed the block over, and the type word
-// is a release store.  Quiescent reclamation frees blocks only in earlier
-// kernels, and every word involved is an agent-scope atomic, performed where
-// all XCDs see it; what must hold is that the bitmap store is complete before
-// the type word and the allocated / active sets that follow make the block
-// findable (else a reservation's OR could land before it and be overwritten).
-// The wave waits for its stores to complete (vmcnt 0) between the two stores;
-// an agent-scope release would also write back the XCD's whole L2, which only
-// plain stores need, once per block taken.  The signal fences keep the
-// compiler from moving either store across the wait.
+// initialised bitmap, and the bitmap complete before the allocated / active
+// sets that follow make the block findable (else a reservation's OR could
+// land before it and be overwritten).  Per lane.  The type word is read only
+// after the free-bitmap update that handed the block over has returned (the
+// block id comes from it), so with online reclamation it reads the version
+// the releaser stored before it set the free bit.
 __device__ __forceinline__ uint32_t publish_block(const DevHeap& h, uint32_t bid, uint32_t type, uint64_t bits) {
-  if (h.online_reclaim) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const uint32_t w = tw_with(__hip_atomic_load(h.block_type + bid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), type);
   __hip_atomic_store(h.obj_bitmap + bid, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (h.online_reclaim) {
-    __hip_atomic_store(h.block_type + bid, w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  } else {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(kWaitVmem);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __hip_atomic_store(h.block_type + bid, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  wait_performed();
+  __hip_atomic_store(h.block_type + bid, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return w;
 }
 
@@ -836,28 +844,30 @@ __device__ inline uint32_t dsoar_new(const DevHeap& h, uint32_t type) {
 //    with the block still active let the lookups of every other wavefront
 //    keep pinning it, and the wait could starve.)
 //  3 Leave allocated[type] (clear with retry).
-//  4 Reset the object bitmap, then set the free bit, in release order: an
-//    allocator that takes the block from the free bitmap sees the reset
-//    bitmap and the new type word.
+//  4 Reset the object bitmap, then set the free bit once the reset is
+//    performed: an allocator that takes the block from the free bitmap sees
+//    the reset bitmap and the new type word.
 // Returns whether the block was freed (wave-uniform).
 __device__ inline bool try_release(const DevHeap& h, uint32_t type, uint32_t bid) {
   uint32_t ok = 0;
   if (is_first_active()) {
     uint64_t expected = 0;
-    ok = __hip_atomic_compare_exchange_strong(h.obj_bitmap + bid, &expected, ~0ull, __ATOMIC_ACQ_REL,
+    ok = __hip_atomic_compare_exchange_strong(h.obj_bitmap + bid, &expected, ~0ull, __ATOMIC_RELAXED,
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
              ? 1u
              : 0u;
     if (ok) {
       const uint32_t w = __hip_atomic_load(h.block_type + bid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(h.block_type + bid, tw_freed(w), __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(h.block_type + bid, tw_freed(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
+  // The freed type word is performed before the pins are read (pin_block).
+  wait_performed();
   if (!bcast32(ok)) return false;
   bm_clear(active_bm(h, type), bid);
   for (uint32_t spins = 0;; ++spins) {
     uint32_t p = 0;
-    if (is_first_active()) p = __hip_atomic_load(h.pins + bid, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+    if (is_first_active()) p = __hip_atomic_load(h.pins + bid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (bcast32(p) == 0) break;
     if (spins >= kSpinLimit) {
       lead_flag(h.ctrl + kCtlRetryLimit);
@@ -866,8 +876,8 @@ __device__ inline bool try_release(const DevHeap& h, uint32_t type, uint32_t bid
     __builtin_amdgcn_s_sleep(1);
   }
   bm_clear(allocated_bm(h, type), bid);
-  if (is_first_active()) __hip_atomic_store(h.obj_bitmap + bid, 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (is_first_active()) __hip_atomic_store(h.obj_bitmap + bid, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  wait_performed();
   bm_set(free_bm(h), bid);
   lead_add(shard(h) + kCntReleases, 1);
   return true;
