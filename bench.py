@@ -324,15 +324,15 @@ class SugarWorkload(GolWorkload):
         return self.sim.heap
 
     def kernel_bytes(self, kind, launches, st):
-        # this-fields (read 24 B, write <= 12 B) + 5 * (4*vision+1) grid reads are counted for choose;
+        # choose: this-fields (12 B), the target word (4 B) and the 25 cells in sight (one byte each);
         # each phase's own fields otherwise.  Per agent visit of the phase:
         v = st["visits"][0] / 5  # five do-alls per step
-        per = {"sugar_choose": 12 + 4 + 25 * 4, "sugar_move": 12 + 8, "sugar_eat": 16 + 8 + 8,
+        per = {"sugar_choose": 12 + 4 + 25 * 1, "sugar_move": 12 + 8, "sugar_eat": 16 + 8 + 8,
                "sugar_request": 16 + 16 + 4, "sugar_birth": 12 + 4}
         if kind in per:
             return v * per[kind]
-        if kind == "sugar_regrow":  # sugar word and capacity read, sugar word written, per cell
-            return launches * self.side ** 2 * 12
+        if kind == "sugar_regrow":  # sugar byte and capacity read, sugar byte written, per cell
+            return launches * self.side ** 2 * 6
         if kind == "enumerate":
             return launches * (self.M / 8) + (2 * v / 64) * 20
         return None

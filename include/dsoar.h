@@ -441,10 +441,12 @@ int dsoar_sugar_create(dsoar_heap* heap, uint32_t side, const dsoar_sugar_rules*
                        size_t dev_bytes, dsoar_sugar** out);
 int dsoar_sugar_destroy(dsoar_sugar* sugar);
 /* Initial state from per-cell device arrays (side*side each): sugar and cap
- * (int32), occ (uint8, 1 = an agent starts here) and the agents' sugar,
- * metabolism, vision and age (int32, read where occ).  Vision is 1..6 (the
- * choose phase looks at most 6 cells along each axis).  step0 = index of the
- * first step (it keys the random draws).  The heap should be freshly reset. */
+ * (int32, 0..127: a cell keeps its sugar in one byte beside its occupancy
+ * bit; values outside are clamped into that range), occ (uint8, 1 = an agent
+ * starts here) and the agents' sugar, metabolism, vision and age (int32, read
+ * where occ).  Vision is 1..6 (the choose phase looks at most 6 cells along
+ * each axis).  step0 = index of the first step (it keys the random draws).
+ * The heap should be freshly reset. */
 int dsoar_sugar_init(dsoar_sugar* sugar, const int32_t* sugar_dev, const int32_t* cap_dev,
                      const uint8_t* occ_dev, const int32_t* a_sugar_dev, const int32_t* a_metab_dev,
                      const int32_t* a_vision_dev, const int32_t* a_age_dev, uint32_t step0, void* stream);

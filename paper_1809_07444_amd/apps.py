@@ -174,6 +174,9 @@ class SugarGpuState:
     stats: dict
 
 
+SUGAR_MAX = 127  # a cell keeps its sugar and capacity in seven bits
+
+
 class Sugarscape:
     """The Sugarscape-style agent model of one world as objects in a device heap."""
 
@@ -181,6 +184,10 @@ class Sugarscape:
                  device="cuda"):
         self.side = inp.side
         n = self.side * self.side
+        for name in ("sugar", "cap"):
+            a = np.asarray(getattr(inp, name))
+            if a.size and (a.min() < 0 or a.max() > SUGAR_MAX):
+                raise ValueError(f"{name} per cell must lie in 0..{SUGAR_MAX}")
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         blocks = num_blocks or max(64, 1 << (max(1, -(-n // (capacity or 64))) - 1).bit_length())
         self.heap = Heap(blocks, capacity, SUGAR_TYPE, device=device, stream=self.stream)

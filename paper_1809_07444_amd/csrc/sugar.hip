@@ -55,13 +55,17 @@ __device__ __forceinline__ int32_t uniform_int(uint64_t h, int32_t lo, int32_t h
 // side^2) of the cell arena; pos and target are arena indices.  Each slot has
 // its own seed, step index and move count, so a world evolves exactly as it
 // would alone.
-// A cell's sugar word also carries its occupancy (kOccupied), so that the
-// cells an agent looks at take one load each; occ keeps the agent handle.
-constexpr int32_t kOccupied = 1 << 30;
-__device__ __forceinline__ int32_t sugar_of(int32_t w) { return w & ~kOccupied; }
+// A cell's sugar is one byte, its low seven bits the amount and the top bit
+// the occupancy (kOccupied), so that the cells an agent looks at take one
+// load each and the grid of a 2048^2 world (4 MB) stays in an XCD's L2; occ
+// keeps the agent handle.  Amounts and capacities are 0..kMaxSugar.
+constexpr int32_t kOccupied = 0x80;
+constexpr int32_t kMaxSugar = 0x7F;
+__device__ __forceinline__ int32_t sugar_of(int32_t w) { return w & kMaxSugar; }
+__device__ __forceinline__ int32_t clamp_sugar(int32_t v) { return v < 0 ? 0 : (v > kMaxSugar ? kMaxSugar : v); }
 
 struct Grid {
-  int32_t* sugar;     // sugar | kOccupied when an agent stands there
+  uint8_t* sugar;     // sugar | kOccupied when an agent stands there
   const int32_t* cap;
   uint32_t* occ;      // agent handle or kNull
   uint32_t* req;      // lowest requesting cell index or kInf
@@ -171,8 +175,8 @@ struct Move {
       // Distinct cells per mover: q was empty and p occupied when chosen.
       g.occ[q] = self;
       g.occ[p] = kNull;
-      g.sugar[q] |= kOccupied;
-      g.sugar[p] &= ~kOccupied;
+      g.sugar[q] = (uint8_t)(g.sugar[q] | kOccupied);
+      g.sugar[p] = (uint8_t)sugar_of(g.sugar[p]);
       af<uint32_t>(h, self, kPos) = q;
       __hip_atomic_store(g.req + q, kInf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -257,7 +261,7 @@ struct Birth {
       af<uint32_t>(h, o, kTarget) = kNull;
       af<uint32_t>(h, o, kWorld) = wid;
       g.occ[n] = o;
-      g.sugar[n] |= kOccupied;
+      g.sugar[n] = (uint8_t)(g.sugar[n] | kOccupied);
     });
     return false;
   }
@@ -279,7 +283,7 @@ __global__ void regrow_kernel(Grid g) {
   if (i < g.max_worlds) g.w_step[i] += 1;
   for (uint32_t c = i; c < g.arena; c += gridDim.x * blockDim.x) {
     const int32_t w = g.sugar[c], s = sugar_of(w) + 1, k = g.cap[c];
-    g.sugar[c] = (s < k ? s : k) | (w & kOccupied);
+    g.sugar[c] = (uint8_t)((s < k ? s : k) | (w & kOccupied));
   }
 }
 
@@ -300,8 +304,8 @@ __global__ void sugar_admit_kernel(DevHeap h, Grid g, uint32_t slot, uint32_t of
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const uint32_t q = off + c;
-  g.sugar[q] = sugar[c];
-  const_cast<int32_t*>(g.cap)[q] = cap[c];
+  g.sugar[q] = (uint8_t)clamp_sugar(sugar[c]);
+  const_cast<int32_t*>(g.cap)[q] = clamp_sugar(cap[c]);
   g.req[q] = kInf;
   g.breq[q] = kInf;
   g.occ[q] = kNull;
@@ -315,7 +319,7 @@ __global__ void sugar_admit_kernel(DevHeap h, Grid g, uint32_t slot, uint32_t of
     af<uint32_t>(h, o, kTarget) = kNull;
     af<uint32_t>(h, o, kWorld) = slot;
     g.occ[q] = o;
-    g.sugar[q] |= kOccupied;
+    g.sugar[q] = (uint8_t)(g.sugar[q] | kOccupied);
   });
 }
 
@@ -424,7 +428,7 @@ int dsoar_sugarpool_create(dsoar_heap* heap, uint32_t max_worlds, uint32_t arena
   g.w_moves = (uint64_t*)(b + ((uint64_t)max_worlds * 20 + 255) / 256 * 256);
   uint8_t* planes = b + table_bytes(max_worlds);
   const uint64_t plane = plane_bytes(arena_cells);
-  g.sugar = (int32_t*)planes;
+  g.sugar = planes;  // one byte per cell in a plane sized like the others
   g.cap = (const int32_t*)(planes + plane);
   g.occ = (uint32_t*)(planes + 2 * plane);
   g.req = (uint32_t*)(planes + 3 * plane);

@@ -1,9 +1,11 @@
 """The C-ABI library loads without a GPU and exports every function that
 include/dsoar.h declares; host-only entry points validate their arguments."""
 import ctypes
+import dataclasses
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1809_07444_amd import _capi as C
@@ -101,3 +103,15 @@ def test_application_entry_points_validate_without_a_gpu():
     assert lib.dsoar_wator_read(None, None, None, None, None) == -1
     assert lib.dsoar_wator_init(None, None, None, None, 0, None) == -1
     assert lib.dsoar_heap_set_type_policy(None, 0, C.POLICY_FRESH) == -1
+
+
+def test_sugarscape_rejects_sugar_beyond_one_byte():
+    # A cell keeps its sugar and capacity in seven bits beside the occupancy
+    # bit: the wrapper refuses larger inputs before any device work.
+    from paper_1809_07444_amd import apps
+    from synth import workloads as W
+    inp = W.sugar_inputs(16, 8, seed=5)
+    for name in ("sugar", "cap"):
+        bad = dataclasses.replace(inp, **{name: np.full_like(getattr(inp, name), apps.SUGAR_MAX + 1)})
+        with pytest.raises(ValueError):
+            apps.Sugarscape(bad, W.SUGAR_RULES)
