@@ -175,9 +175,15 @@ int dsoar_heap_set_policy(dsoar_heap* heap, uint32_t bulk_min);
  * rest, which stays active like any other partly filled block).  Meant for
  * types whose objects all die within one phase, so that dense packing buys
  * nothing and the lookup is pure latency (the Game of Life's Candidates).
- * The slot placement differs, the results do not.  type >= the heap's
- * number of types or another policy value: DSOAR_ERR_INVALID_ARG. */
-enum { DSOAR_POLICY_DENSE = 0, DSOAR_POLICY_FRESH = 1 };
+ * DSOAR_POLICY_BOUNDED is the dense policy with at most two passes over
+ * active blocks per request; what is still missing then comes from a free
+ * block: for types whose active blocks hold only a slot or two each, where
+ * filling every hole costs many passes.  Under FRESH and BOUNDED a request
+ * that finds no free block goes back to the active blocks, so the heap is
+ * still out of memory only when it is full.  The slot placement differs, the
+ * results do not.  type >= the heap's number of types or another policy
+ * value: DSOAR_ERR_INVALID_ARG. */
+enum { DSOAR_POLICY_DENSE = 0, DSOAR_POLICY_FRESH = 1, DSOAR_POLICY_BOUNDED = 2 };
 int dsoar_heap_set_type_policy(dsoar_heap* heap, uint32_t type, uint32_t policy);
 
 /* Block reclamation.  By default (online = 0) a block emptied by deletes

@@ -23,7 +23,7 @@ ERR_OOM, ERR_RETRY_LIMIT, ERR_DOUBLE_FREE = -2, -3, -5
 
 DO_PERSISTENT, DO_PLAIN, DO_REUSE_ENUM = 0, 1, 2
 GRAPH = GOL_GRAPH = 0x100
-POLICY_DENSE, POLICY_FRESH = 0, 1
+POLICY_DENSE, POLICY_FRESH, POLICY_BOUNDED = 0, 1, 2
 METHOD_VISIT_COUNT, METHOD_DELETE_IF_MOD, METHOD_MICRO_UPDATE, METHOD_MICRO_CULL, METHOD_FIELD_GATHER = 1, 2, 3, 4, 5
 BM_TRY_SET, BM_TRY_CLEAR, BM_SET, BM_CLEAR, BM_TRY_FIND_SET, BM_FIND_CLEAR = range(6)
 KIND_NAMES = {1: "enumerate", 10: "visit_count", 11: "delete_if_mod", 12: "gather", 20: "micro_update",

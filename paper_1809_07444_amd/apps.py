@@ -256,6 +256,11 @@ class Traffic:
         # At most one car per cell, plus partly filled blocks.
         blocks = num_blocks or max(64, 1 << (2 * -(-n // (capacity or 64)) - 1).bit_length())
         self.heap = Heap(blocks, capacity, TRAFFIC_TYPE, device=device, stream=self.stream)
+        # Cars leave their blocks one by one, so the active blocks hold a slot
+        # or two each: the entering cars take at most two lookups' worth of
+        # them and a free block for the rest (16.9 against 23.1 ms per 500
+        # steps of 1024 roads on MI355X, 28 % more blocks, same results).
+        self.heap.set_type_policy(0, C.POLICY_BOUNDED)
         self.lib = self.heap.lib
         nbytes = int(self.lib.dsoar_traffic_bytes(self.roads, self.length))
         if nbytes == 0:
@@ -391,6 +396,12 @@ class Wator:
         # At most one animal per cell; room for both types' partly filled blocks.
         blocks = num_blocks or max(64, 1 << (4 * -(-n // (capacity or 64)) - 1).bit_length())
         self.heap = Heap(blocks, capacity, WATOR_TYPES, device=device, stream=self.stream)
+        # Fish and sharks leave holes one by one (eaten, starved): their
+        # newborns take at most two lookups' worth of holes and a free block
+        # for the rest (57.6 against 60.8 ms per 200 steps of 2048^2 on MI355X,
+        # 7 % more blocks, same results).
+        for t in range(len(WATOR_TYPES)):
+            self.heap.set_type_policy(t, C.POLICY_BOUNDED)
         self.lib = self.heap.lib
         nbytes = int(self.lib.dsoar_wator_bytes(self.side))
         if nbytes == 0:

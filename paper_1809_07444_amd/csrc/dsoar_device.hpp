@@ -43,6 +43,7 @@ constexpr uint32_t kShards = 1024;         // counter shards (spread atomics)
 // s_waitcnt immediate for gfx9-family encodings: vmcnt 0 (bits 3:0 and
 // 15:14), expcnt 7 (bits 6:4) and lgkmcnt 15 (bits 11:8) left unconstrained.
 constexpr int kWaitVmem = 0x0F70;
+constexpr uint32_t kBoundedPasses = 2;  // active lookups per request under the bounded policy
 constexpr uint32_t kMultiBlocks = 8;  // active blocks one lookup may reserve in
 constexpr uint32_t kOomRetries = 4;        // active lookups retried before OOM
 
@@ -82,6 +83,7 @@ struct DevHeap {
   uint32_t bm_words;        // words per bitmap (all levels, padded)
   uint32_t bulk_min;        // requests of at least this many take whole free blocks
   uint32_t fresh_types;     // bit t: requests of type t skip the active lookup
+  uint32_t bounded_types;   // bit t: at most kBoundedPasses active lookups per request of type t
   uint32_t doall_unroll;    // blocks per wavefront pass of split do-alls (1, 2, 4, 8)
   uint32_t online_reclaim;  // 1: the delete that empties a block frees it at once
   // Field f of type t: byte offset of its array in a block (low 24 bits)
@@ -623,6 +625,10 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
   // lookup had found none.
   const bool fresh = (h.fresh_types >> type) & 1u;
   if (fresh) none_active = true;
+  // The bounded policy stops looking for active blocks after kBoundedPasses
+  // lookups (until no free block is left).
+  const uint32_t max_lookups = (h.bounded_types >> type) & 1u ? kBoundedPasses : kSpinLimit;
+  uint32_t lookups = 0;
   for (uint32_t it = 0; served < n; ++it) {
     if (it >= kSpinLimit) {
       lead_flag(h.ctrl + kCtlRetryLimit);
@@ -661,7 +667,8 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
     int32_t bid = cur;
     uint64_t avail = cur_avail;
     uint64_t got;
-    if (bid == kFail && (!fresh || active_first)) {
+    if (bid == kFail && (active_first || (!fresh && lookups < max_lookups))) {
+      ++lookups;
       uint64_t wbits = 0;
       const int32_t aw = bm_find_word(active, start, &wbits);
       if (aw == kFail) {

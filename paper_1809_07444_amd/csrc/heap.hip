@@ -770,6 +770,7 @@ int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_byt
   h->doall_wgs_per_cu = 8;
   d.bulk_min = 0xFFFFFFFFu;  // dense policy: active blocks first
   d.fresh_types = 0;
+  d.bounded_types = 0;
   d.doall_unroll = 4;
   const int rc = init_device_state(h, (hipStream_t)stream);
   if (rc) {
@@ -878,9 +879,11 @@ int dsoar_heap_set_policy(dsoar_heap* h, uint32_t bulk_min) {
 }
 
 int dsoar_heap_set_type_policy(dsoar_heap* h, uint32_t type, uint32_t policy) {
-  if (!heap_ok(h) || type >= h->desc.num_types || policy > DSOAR_POLICY_FRESH) return DSOAR_ERR_INVALID_ARG;
+  if (!heap_ok(h) || type >= h->desc.num_types || policy > DSOAR_POLICY_BOUNDED) return DSOAR_ERR_INVALID_ARG;
   const uint32_t bit = 1u << type;
   h->dev.fresh_types = policy == DSOAR_POLICY_FRESH ? (h->dev.fresh_types | bit) : (h->dev.fresh_types & ~bit);
+  h->dev.bounded_types =
+      policy == DSOAR_POLICY_BOUNDED ? (h->dev.bounded_types | bit) : (h->dev.bounded_types & ~bit);
   h->config_epoch++;
   return DSOAR_OK;
 }

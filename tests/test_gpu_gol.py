@@ -99,7 +99,7 @@ def test_type_policy_validates():
     with pytest.raises(Exception):
         gol.heap.set_type_policy(3, C.POLICY_FRESH)  # three types: 0, 1, 2
     with pytest.raises(Exception):
-        gol.heap.set_type_policy(0, 2)
+        gol.heap.set_type_policy(0, 3)
 
 
 def test_full_config_1024_200_generations():

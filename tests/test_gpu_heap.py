@@ -81,6 +81,28 @@ def test_type_policy_fresh_opens_own_blocks(policy, blocks):
     assert heap.check() == {}
 
 
+@pytest.mark.parametrize("policy,active_after", [(C.POLICY_DENSE, 1), (C.POLICY_BOUNDED, 17)])
+def test_type_policy_bounded_stops_after_two_lookups(policy, active_after):
+    # 32 full blocks with one hole each (all under one level-0 word), then one
+    # wavefront asks for 64: each lookup reserves in up to 8 of those blocks.
+    # Dense fills all 32 holes (four lookups) and opens one block for the other
+    # 32; bounded stops after two lookups (16 holes) and opens one block for 48.
+    heap = Heap(64, 64, [(4,)])
+    heap.set_type_policy(0, policy)
+    h = heap.alloc_n(0, 32 * 64)
+    hn = np.sort(h.cpu().numpy().view(np.uint32))
+    holes = hn[np.arange(32 * 64) % 64 == 5]
+    heap.free_n(torch.from_numpy(holes.view(np.int32)).to(h.device))
+    assert heap.stats()["active_blocks"] == [32]
+    got = heap.alloc_n(0, 64).cpu().numpy().view(np.uint32)
+    assert (got != C.NULL).all() and len(np.unique(got)) == 64
+    st = heap.stats()
+    assert st["live"] == [32 * 64 + 32] and st["allocated_blocks"] == [33]
+    assert st["active_blocks"] == [active_after]
+    assert len(set(got.tolist()) & set(holes.tolist())) == 64 - (32 if policy == C.POLICY_DENSE else 48)
+    assert heap.check() == {}
+
+
 def test_type_policy_fresh_falls_back_to_active_blocks():
     # Every block full, then 10 slots freed in each: no free block is left,
     # so fresh requests must take the freed slots, all of them, before OOM.
