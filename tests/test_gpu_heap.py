@@ -103,11 +103,13 @@ def test_type_policy_bounded_stops_after_two_lookups(policy, active_after):
     assert heap.check() == {}
 
 
-def test_type_policy_fresh_falls_back_to_active_blocks():
+@pytest.mark.parametrize("policy", [C.POLICY_FRESH, C.POLICY_BOUNDED])
+def test_type_policy_falls_back_to_active_blocks(policy):
     # Every block full, then 10 slots freed in each: no free block is left,
-    # so fresh requests must take the freed slots, all of them, before OOM.
+    # so fresh and bounded requests must take the freed slots, all of them,
+    # before OOM.
     heap = Heap(16, 64, [(4,)])
-    heap.set_type_policy(0, C.POLICY_FRESH)
+    heap.set_type_policy(0, policy)
     h = heap.alloc_n(0, 16 * 64)
     hn = h.cpu().numpy().view(np.uint32)
     assert (hn != C.NULL).all()

@@ -127,3 +127,25 @@ def test_traffic_and_sugarscape_online_equal_oracle():
                            sug.a_age)
     ref = oracle.sugar_run(st, 60, sug.seed, W.SUGAR_RULES)
     assert np.array_equal(got.sugar, ref.sugar) and np.array_equal(got.occ, ref.occ)
+
+
+@pytest.mark.parametrize("policy", [C.POLICY_BOUNDED, C.POLICY_DENSE])
+def test_wator_online_equals_oracle(policy):
+    # Many sharks (40 % of the cells) starve within a few steps and empty
+    # their blocks, which online release frees inside the kernel and the
+    # newborns take again; the sea and the object counts stay the oracle's.
+    inp = W.wator_inputs(96, seed=9, fish24=int(0.2 * (1 << 24)), shark24=int(0.4 * (1 << 24)))
+    sea = apps.Wator(inp, W.WATOR_RULES)
+    for t in range(2):
+        sea.heap.set_type_policy(t, policy)
+    sea.heap.set_reclaim(True)
+    sea.init()
+    sea.step(40, C.DO_PERSISTENT | C.GRAPH)
+    got = sea.read()
+    ref = oracle.wator_run(oracle.WatorState(inp.kind, inp.age, inp.energy), 40, inp.seed, W.WATOR_RULES)
+    for f in ("kind", "age", "energy"):
+        assert np.array_equal(getattr(got, f), getattr(ref, f)), f
+    assert got.stats["live"] == [int((ref.kind == 1).sum()), int((ref.kind == 2).sum())]
+    assert got.stats["online_releases"] > 0
+    assert sea.heap.check() == {}
+    sea.close()
