@@ -51,8 +51,10 @@ def test_churn_hands_every_slot_out_once(online, M, seed, capacity, rounds):
         f0 = heap.field_read(t, 0, torch.tensor(mine.view(np.int32), device="cuda")).cpu().numpy().view(np.uint32)
         assert np.array_equal(f0, mine)                            # nobody else wrote into a kept object
         assert st["allocs"][t] - st["frees"][t] == len(mine)
-    if online:
-        assert st["online_releases"] > 0
+    # Whether a block empties while online release is on depends on how the
+    # wavefronts interleave (a fifth of every wavefront's objects are kept),
+    # so the number of releases is not checked here; the test below, which
+    # keeps nothing, needs them.
     heap.reclaim()
     assert heap.check() == {}
 
@@ -66,6 +68,7 @@ def test_online_reclaim_reuses_blocks_across_types():
     heap, out, errors = churn(True, M=2048, keep=1 << 30, spread=0)
     st = heap.stats(raise_sticky=False)
     assert errors == 0 and st["oom"] == 0 and st["retry_limit_hit"] == 0
+    assert st["online_releases"] >= 2048
     assert (out == C.NULL).all() and st["live"] == [0, 0, 0, 0]
     heap.reclaim()
     assert heap.check() == {}
