@@ -77,6 +77,26 @@ def test_random_worlds(side, agents, seed, cap):
     assert sim.heap.check() == {}
 
 
+def test_sugar_at_the_top_of_its_byte():
+    # A cell keeps its sugar in seven bits beside the occupancy bit: capacities
+    # and sugar of 100..127 (the largest the grid holds), regrowing and eaten
+    # every step, still give the oracle's world.
+    import dataclasses
+    inp = W.sugar_inputs(48, 500, seed=11)
+    cap = np.random.default_rng(11).integers(100, 128, size=inp.cap.shape).astype(inp.cap.dtype)
+    inp = dataclasses.replace(inp, cap=cap, sugar=cap.copy())
+    sim = apps.Sugarscape(inp, RULES)
+    sim.init()
+    ref = to_state(inp)
+    done = 0
+    for k in (1, 9, 30):
+        sim.step(k, C.DO_PERSISTENT | C.GRAPH)
+        ref = oracle.sugar_run(ref, k, inp.seed, RULES, step0=done)
+        done += k
+        compare(sim.read(), ref, int(inp.occ.sum()))
+    assert sim.heap.check() == {}
+
+
 def test_full_config_2048_1M_agents_500_steps():
     # 2048 x 2048 torus, 2^20 agents, 500 steps; stored oracle digests every 100 steps.
     ref = json.load(open(GOLDEN))
