@@ -81,3 +81,20 @@ def test_summary_round_trip_with_calibration(tmp_path):
     back = P.read_summary(str(out))
     assert back["source_hash"] == "abcd" and back["kernels"] == {"gol_alive_prep": (200.0 * 2 + 50.0) * 1024}
     assert P.read_summary(str(tmp_path / "missing.txt")) is None
+
+
+def test_kernel_kinds_of_the_sources_are_named_once():
+    # The device code tags each timed launch with a kind number; the binding
+    # names them.  Every number in the sources has a name, none is used twice,
+    # and no name is left without a kernel.
+    import glob
+    import os
+    import re
+    csrc = os.path.join(os.path.dirname(C.__file__), "csrc")
+    nums = []
+    for path in sorted(glob.glob(os.path.join(csrc, "*.h*p*"))):
+        with open(path) as fh:
+            nums += [int(n) for n in re.findall(r"\bkKind\w* = (\d+)", fh.read())]
+    assert len(nums) == len(set(nums))
+    assert set(nums) == set(C.KIND_NAMES)
+    assert len(set(C.KIND_NAMES.values())) == len(C.KIND_NAMES)
