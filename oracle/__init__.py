@@ -72,6 +72,8 @@ def lib() -> ctypes.CDLL:
         L.orc_bm_op.argtypes = [vp, ctypes.c_int, i64, ctypes.POINTER(i64)]
         L.orc_type_capacity.restype = i32
         L.orc_type_capacity.argtypes = [vp, i32, i32]
+        L.orc_visit_types.restype = ctypes.c_uint32
+        L.orc_visit_types.argtypes = [vp, i32, i32]
         L.orc_heap_new.restype = vp
         L.orc_heap_new.argtypes = [i32, i32, i32]
         L.orc_heap_delete.argtypes = [vp]
@@ -107,6 +109,15 @@ def type_capacity(sizes, t: int) -> int:
     """Slots per block of type t (Sec. 2 byte-size rule) among types of the given byte sizes."""
     a = np.ascontiguousarray(sizes, dtype=np.int32)
     return int(lib().orc_type_capacity(a.ctypes.data_as(ctypes.c_void_p), len(a), t))
+
+
+def visit_types(parents, t: int) -> set:
+    """Types a do-all over type t visits (t and every type inheriting from
+    it); parents[u] is u's parent index or None.  Empty set if the parent
+    links are not a forest."""
+    a = np.array([-1 if p is None else p for p in parents], dtype=np.int32)
+    m = int(lib().orc_visit_types(a.ctypes.data_as(ctypes.c_void_p), len(a), t))
+    return {u for u in range(len(a)) if m >> u & 1}
 
 
 def _p(a: np.ndarray):

@@ -238,6 +238,29 @@ int32_t orc_type_capacity(const int32_t *sizes, int32_t ntypes, int32_t t) {
   return best;
 }
 
+/* Sec. 1.2: a do-all over type t visits the objects of t and of every type
+ * that inherits from t.  Type u inherits from t when the chain of parent
+ * links starting at u reaches t; the chain is followed one link at a time,
+ * and a chain longer than the number of types has a cycle. */
+uint32_t orc_visit_types(const int32_t *parent, int32_t ntypes, int32_t t) {
+  if (ntypes < 1 || ntypes > 32 || t < 0 || t >= ntypes) return 0;
+  /* A forest: every chain ends (at -1) within ntypes links. */
+  for (int32_t u = 0; u < ntypes; u++) {
+    int32_t a = u, steps = 0;
+    while (a != -1) {
+      if (a < 0 || a >= ntypes || ++steps > ntypes) return 0;
+      a = parent[a];
+    }
+  }
+  uint32_t mask = 0;
+  for (int32_t u = 0; u < ntypes; u++) {
+    int32_t a = u;
+    while (a != -1 && a != t) a = parent[a];
+    if (a == t) mask |= 1u << u;
+  }
+  return mask;
+}
+
 /* ================================================================ heap model
  * Sec. 2: M blocks of `capacity` object slots, each holding objects of one
  * type; a 64-bit object allocation bitmap per block; block states free,

@@ -73,6 +73,14 @@ int orc_bm_op(void *b, int op, int64_t pos, int64_t *result);
  * at least 1. */
 int32_t orc_type_capacity(const int32_t *sizes, int32_t ntypes, int32_t t);
 
+/* ---------------------------------------------------------- subclasses --- */
+/* Sec. 1.2 (class inheritance): parent[u] is the index of type u's parent, or
+ * -1.  A do-all over type t runs its method on every object whose type is t
+ * or inherits from t through any number of parent links.  Returns that set
+ * of types as a bit mask (bit u = type u), or 0 if the parent links are not
+ * a forest (a link out of range, or a cycle). */
+uint32_t orc_visit_types(const int32_t *parent, int32_t ntypes, int32_t t);
+
 /* ---------------------------------------------------------- heap model --- */
 void *orc_heap_new(int32_t num_blocks, int32_t capacity, int32_t num_types);
 void orc_heap_delete(void *h);
