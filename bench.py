@@ -1,14 +1,21 @@
 """Benchmark of the object heap + parallel do-all on one MI355X.
 
-Default workload: Game of Life as objects on a 1024 x 1024 torus, Bernoulli(0.1)
-alive, 200 generations.  One step = reset the heap, create the initial objects
-and run the 200 generations (4 do-alls each, replayed from a HIP graph), with
-the seeded input grid already resident in device memory.
+Default workload: 256 independent Game-of-Life worlds as objects in one heap,
+sides log-uniform from 64 to 1024 (48.8 M cells), Bernoulli(0.1) alive, 100
+generations.  One step = reset the heap, create every world's initial objects
+and run the 100 generations (one persistent do-all per phase covering all
+worlds, replayed from HIP graphs), with the seeded input grids already
+resident in device memory; block capacity, do-all launch shape and allocation
+policy come from the autotuner's cached choice.  The same worlds, each with
+its own heap and its own launches one world after another (the plain
+baseline), are timed beside it.
 
 Prints one JSON line with the headline throughput (allocations + frees per
-second), do-all objects per second, the roofline entry of the dominant kernel
-(per-launch HIP-event timing over a profiled pass of the same workload) and
-the CPU baseline (the oracle, single thread, on a bounded sample).
+second), do-all objects per second, cells x generations per second, the
+roofline entry of the dominant kernel (per-launch HIP-event timing over a
+profiled pass of the same workload), batched against plain, and the CPU
+baseline (the oracle, single thread, on a bounded sample).  --workload
+selects the other configurations.
 """
 from __future__ import annotations
 
@@ -33,7 +40,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="gol",
+    p.add_argument("--workload", default="batched",
                    choices=["gol", "micro", "micro_scaled", "batched", "sugarscape", "traffic", "collisions", "nbody",
                             "wator",
                             "serve"])
@@ -62,37 +69,73 @@ def parse():
 
 
 # ------------------------------------------------------------- bytes model --
-# Algorithmic bytes each kernel kind must move (this-object fields, other
-# objects' fields, new objects' fields, the compacted list), from the heap's
-# counters over the profiled pass: per visited object the fields the method
-# reads and writes, per block the list entry (4 B id + 8 B snapshot).
+# Algorithmic bytes each kernel kind must move, from the heap's counters over
+# the profiled pass.  A do-all visit counts the visited object's own fields
+# read and written; an allocation the fields of the object it creates; each
+# listed block its entry (4 B id + 8 B snapshot).  Reads and writes of other
+# objects' state (a Game of Life cell's neighbours, the Cell a dying or born
+# cell updates, the world table) are counted apart as "other" bytes and are
+# not part of the roofline's achieved figure.  Kinds may return one number
+# (no other-object traffic) or a pair (algorithmic, other).
 
-def gol_kernel_bytes(kind, launches, st, M):
+def gol_kernel_bytes(kind, launches, st, M, init_alive):
     A, K = 1, 2  # Alive, Candidate type ids
     va, vk = st["visits"][A] / 2, st["visits"][K] / 2     # each type is visited by two do-alls
+    cands = st["allocs"][K]
+    births, deaths = st["allocs"][A] - init_alive, st["frees"][A]
     if kind == "gol_alive_prep":
-        # index words (handle and live bit) of the 24 cells around (5 x 5 neighbourhood)
-        return va * (12 + 96) + st["allocs"][K] * 16 + va / 64 * 12
+        # this: cell and world read, action written; new Candidates: their
+        # three fields; other: the live bytes of the 24 surrounding cells and
+        # the world's offset and side.
+        return va * 12 + cands * 12 + va / 64 * 12, va * (24 + 8)
     if kind == "gol_cand_prep":
-        return vk * (12 + 32) + vk / 64 * 12
+        return vk * 12 + vk / 64 * 12, vk * (8 + 8)
     if kind == "gol_alive_update":
-        return va * 4 + st["frees"][A] * 12 + va / 64 * 12
+        # this: action read, and the cell of a dying one; other: its Cell's
+        # index word and field and its live byte.
+        return va * 4 + deaths * 4 + va / 64 * 12, deaths * (4 + 4 + 1)
     if kind == "gol_cand_update":
-        births = st["allocs"][A]
-        return vk * 20 + births * 16 + vk / 64 * 12
+        # this: cell, world and action read; new Alive objects: three fields;
+        # other: the born cell's index word, Cell field and live byte.
+        return vk * 12 + births * 12 + vk / 64 * 12, births * (4 + 4 + 1)
     if kind == "gol_update":  # phases 3 and 4 in one launch
-        return gol_kernel_bytes("gol_alive_update", launches, st, M) + \
-            gol_kernel_bytes("gol_cand_update", launches, st, M)
+        a = gol_kernel_bytes("gol_alive_update", launches, st, M, init_alive)
+        c = gol_kernel_bytes("gol_cand_update", launches, st, M, init_alive)
+        return a[0] + c[0], a[1] + c[1]
     if kind == "enumerate":
         return launches * (M / 8) + (va + vk) / 64 * 20
     return None
 
 
 def gol_init_bytes(cells, alive):
-    # Per cell: the input byte, the Cell's field and its index word; per live
-    # cell an Alive object's three fields; per new block its object bitmap
-    # and type word.
-    return cells * 9 + alive * 12 + (cells + alive) / 64 * 12
+    # New objects: each Cell's field, each initial Alive's three fields.
+    # Other: the input byte, the index word and live byte of every cell.
+    return cells * 4 + alive * 12 + (cells + alive) / 64 * 12, cells * (1 + 4 + 1)
+
+
+def sugar_kernel_bytes(kind, launches, st, M, init_agents, cells):
+    """(this + new-object bytes, other bytes) of the Sugarscape kernels.  Per
+    agent visit, this: choose reads pos, vision and world and writes target;
+    move reads pos, target and world and writes pos; eat reads pos, sugar,
+    metabolism and age and writes sugar and age; request reads sugar and age
+    and writes target; birth reads target, pos and world.  New objects: a
+    child's seven fields.  Other: the grid cells in sight (one byte each, 25
+    loaded), the world table, request words and the cells a move, meal,
+    request or birth touches."""
+    v = st["visits"][0] / 5  # five do-alls per step
+    births = st["allocs"][0] - init_agents
+    per = {"sugar_choose": (16, 25 + 8 + 4), "sugar_move": (16, 4 + 16), "sugar_eat": (24, 2 + 4),
+           "sugar_request": (12, 8 + 16 + 4), "sugar_birth": (12, 4)}
+    if kind in per:
+        this, other = per[kind]
+        if kind == "sugar_birth":  # a child's seven fields; its cell's occupant word and byte
+            return v * this + v / 64 * 12 + births * 28, v * other + births * 5
+        return v * this + v / 64 * 12, v * other
+    if kind == "sugar_regrow":  # other state only: sugar byte and capacity read, sugar byte written, per cell
+        return 0.0, launches * cells * 6
+    if kind == "enumerate":
+        return launches * (M / 8) + (2 * v / 64) * 20
+    return None
 
 
 def micro_kernel_bytes(kind, launches, st, M):
@@ -129,6 +172,7 @@ class GolWorkload:
         self.M = self.gol.heap.num_blocks
         self.stream = self.gol.stream
         self.torch = torch
+        self.cells_gens = self.side ** 2 * self.gens
         self.config = {"workload": f"gol-{self.side}x{self.side}-bernoulli0.1-{self.gens}gen",
                        "worlds": 1, "cells": self.side ** 2, "generations": self.gens,
                        "heap_blocks": self.M, "block_capacity": 64, "graph": not args.no_graph,
@@ -149,7 +193,7 @@ class GolWorkload:
     def kernel_bytes(self, kind, launches, st):
         if kind == "gol_init":
             return gol_init_bytes(*self.init_objects)
-        return gol_kernel_bytes(kind, launches, st, self.M)
+        return gol_kernel_bytes(kind, launches, st, self.M, self.init_objects[1])
 
     def heap(self):
         return self.gol.heap
@@ -157,14 +201,14 @@ class GolWorkload:
     def cpu_baseline(self):
         import oracle
         t0 = time.perf_counter()
-        _, counts = oracle.gol_run(self.grid, self.gens)
+        oracle.gol_run(self.grid, self.gens)
         dt = time.perf_counter() - t0
-        # The object model's allocations and frees for the same generations:
-        # candidates are created and deleted, births create, deaths delete.
-        ops = int(2 * counts[:, 0].sum() + counts[:, 1].sum() + counts[:, 2].sum())
-        return {"value": ops / dt, "unit": "allocs+frees/s", "cores": 1, "kind": "oracle",
+        # The oracle is a dense stencil: it updates every cell of every
+        # generation and allocates nothing, so its rate is cells x generations
+        # per second (compare with the line's cells_gens_per_s).
+        return {"value": self.side ** 2 * self.gens / dt, "unit": "cells*gens/s", "cores": 1, "kind": "oracle",
                 "sample": f"dense B3/S23 oracle, full {self.side}x{self.side} torus, {self.gens} generations, "
-                          f"{dt:.2f} s; rate = object-model allocs+frees of those generations / oracle time"}
+                          f"{dt:.2f} s"}
 
 
 class MicroWorkload:
@@ -242,6 +286,7 @@ class BatchedWorkload(GolWorkload):
                              sum(int((g != 0).sum()) for g in self.inp.grids))
         self.gol = self.b.gol
         self.M = self.gol.heap.num_blocks
+        self.cells_gens = int(self.gol.total) * self.gens
         self.args = args
         from dataclasses import asdict
         self.config = {"workload": f"gol-batched-256worlds-loguniform64..1024-bernoulli0.1-{self.gens}gen",
@@ -274,18 +319,18 @@ class BatchedWorkload(GolWorkload):
     def cpu_baseline(self):
         import oracle
         # Bounded sample: the first worlds in order until ~10 s of oracle work.
+        # The oracle is a dense stencil (no allocation): cells x generations per second.
         t0 = time.perf_counter()
-        ops = cells = 0
+        cells = 0
         n = 0
         for g in self.inp.grids:
-            _, c = oracle.gol_run(g, self.gens)
-            ops += int(2 * c[:, 0].sum() + c[:, 1].sum() + c[:, 2].sum())
+            oracle.gol_run(g, self.gens)
             cells += g.size
             n += 1
             if time.perf_counter() - t0 > 10:
                 break
         dt = time.perf_counter() - t0
-        return {"value": ops / dt, "unit": "allocs+frees/s", "cores": 1, "kind": "oracle",
+        return {"value": cells * self.gens / dt, "unit": "cells*gens/s", "cores": 1, "kind": "oracle",
                 "sample": f"dense B3/S23 oracle on the first {n} of 256 worlds ({cells} cells), {self.gens} "
                           f"generations, {dt:.1f} s"}
 
@@ -324,18 +369,7 @@ class SugarWorkload(GolWorkload):
         return self.sim.heap
 
     def kernel_bytes(self, kind, launches, st):
-        # choose: this-fields (12 B), the target word (4 B) and the 25 cells in sight (one byte each);
-        # each phase's own fields otherwise.  Per agent visit of the phase:
-        v = st["visits"][0] / 5  # five do-alls per step
-        per = {"sugar_choose": 12 + 4 + 25 * 1, "sugar_move": 12 + 8, "sugar_eat": 16 + 8 + 8,
-               "sugar_request": 16 + 16 + 4, "sugar_birth": 12 + 4}
-        if kind in per:
-            return v * per[kind]
-        if kind == "sugar_regrow":  # sugar byte and capacity read, sugar byte written, per cell
-            return launches * self.side ** 2 * 6
-        if kind == "enumerate":
-            return launches * (self.M / 8) + (2 * v / 64) * 20
-        return None
+        return sugar_kernel_bytes(kind, launches, st, self.M, self.agents, self.side ** 2)
 
     def cpu_baseline(self):
         import oracle
@@ -390,19 +424,20 @@ class TrafficWorkload(GolWorkload):
 
     def kernel_bytes(self, kind, launches, st):
         v = st["visits"][0] / 2  # two do-alls per step visit every car
-        # Decide: cell, speed read, next speed written, up to vmax cells ahead
-        # read; Drive: next speed and cell read, speed and cell written, two
-        # road cells written.
-        per = {"traffic_decide": 12 + 4 * self.rules["vmax"], "traffic_drive": 8 + 8 + 8}
+        # (this + new objects, other).  Decide: cell and speed read, next
+        # speed written; other: up to vmax road cells ahead.  Drive: next
+        # speed and cell read, speed and cell written; other: two road cells.
+        per = {"traffic_decide": (12, 4 * self.rules["vmax"]), "traffic_drive": (16, 8)}
         if kind in per:
-            return v * per[kind] + v / 64 * 12
+            return v * per[kind][0] + v / 64 * 12, v * per[kind][1]
         cars0 = int((self.inp.vel >= 0).sum())
         if kind == "traffic_entry":
-            # first cell of every road read; per entering car its three
-            # fields and the first cell written
-            return launches * self.roads * 4 + (st["allocs"][0] - cars0) * 16
-        if kind == "traffic_init":  # input speed read and cell written per cell, fields per car
-            return self.roads * self.length * 8 + cars0 * 12 + cars0 / 64 * 12
+            # new cars: three fields each; other: every road's first cell read
+            # and an entering car's first cell written
+            entered = st["allocs"][0] - cars0
+            return entered * 12, launches * self.roads * 4 + entered * 4
+        if kind == "traffic_init":  # new cars' fields; other: input speed read and cell written per cell
+            return cars0 * 12 + cars0 / 64 * 12, self.roads * self.length * 8
         if kind == "enumerate":
             return launches * (self.M / 8) + v / 64 * 20
         return None
@@ -456,20 +491,22 @@ class WatorWorkload(GolWorkload):
         # Fields read and written, the four neighbours' kinds, the request
         # word (an atomic in Decide, a read in Move), the sea cells written,
         # and the newborns' fields.
-        per_f = {"wator_fish_decide": 8 + 16 + 8, "wator_fish_move": 12 + 8 + 16, "wator_fish_eaten": 8}
-        per_s = {"wator_shark_decide": 12 + 16 + 8, "wator_shark_move": 16 + 12 + 20}
+        # (this, other) per visit: the animal's own fields; the four
+        # neighbours' kinds, the request words and the sea cells written.
+        per_f = {"wator_fish_decide": (8, 16 + 8), "wator_fish_move": (12, 8 + 16), "wator_fish_eaten": (8, 0)}
+        per_s = {"wator_shark_decide": (12, 16 + 8), "wator_shark_move": (16, 12 + 20)}
+        fish0 = int((self.inp.kind == 1).sum())
+        shark0 = int((self.inp.kind == 2).sum())
         if kind in per_f:
-            extra = st["allocs"][0] * 12 if kind == "wator_fish_move" else 0
-            return vf * per_f[kind] + vf / 64 * 12 + extra
+            born = (st["allocs"][0] - fish0) * 12 if kind == "wator_fish_move" else 0  # newborns' fields
+            return vf * per_f[kind][0] + vf / 64 * 12 + born, vf * per_f[kind][1]
         if kind in per_s:
-            extra = st["allocs"][1] * 16 if kind == "wator_shark_move" else 0
-            return vs * per_s[kind] + vs / 64 * 12 + extra
+            born = (st["allocs"][1] - shark0) * 16 if kind == "wator_shark_move" else 0
+            return vs * per_s[kind][0] + vs / 64 * 12 + born, vs * per_s[kind][1]
         if kind == "wator_init":
-            # kind, age, energy read, sea byte and request word written per
-            # cell; the fields of every animal
-            fish0 = int((self.inp.kind == 1).sum())
-            shark0 = int((self.inp.kind == 2).sum())
-            return self.side ** 2 * (12 + 1 + 8) + fish0 * 12 + shark0 * 16 + (fish0 + shark0) / 64 * 12
+            # new animals' fields; other: kind, age, energy read, sea byte
+            # and request word written per cell
+            return fish0 * 12 + shark0 * 16 + (fish0 + shark0) / 64 * 12, self.side ** 2 * (12 + 1 + 8)
         if kind == "wator_tick":
             return launches * 8
         if kind == "enumerate":
@@ -573,39 +610,149 @@ class CollideWorkload(GolWorkload):
 
 
 def serve_bench(args):
+    """Serving: capacity (every episode at t = 0), then a sweep of Poisson
+    arrival rates.  Every retired world of every run is checked against the
+    same episode run alone (result digests) and both pools' heaps against
+    their invariants and sticky flags; a sample is also checked against the
+    oracle in the CPU-baseline leg."""
     import torch
     from paper_1809_07444_amd import serve
     from synth import workloads as W
     torch.cuda.set_device(0)
     n = args.episodes
+    srv = serve.Server()
+    mismatches, checked = [], 0
 
-    def run(specs):
+    def run(specs, alone=None):
+        nonlocal checked
         inputs = {s.eid: W.episode_inputs(s) for s in specs}      # requests carry their data
-        srv = serve.Server()
-        try:
-            recs, _, st = srv.run(specs, lambda s: inputs[s.eid], keep_results=False)
-        finally:
-            srv.close()
-        return serve.summarize(recs, st["wall_s"]), st
+        recs, digests, st = srv.run(specs, lambda s: inputs[s.eid], digests=True)
+        bad = srv.check()
+        if bad:
+            raise RuntimeError(f"serving heaps failed their check: {bad}")
+        if alone is not None:
+            for e in specs:
+                checked += 1
+                if digests[e.eid] != alone[e.eid]:
+                    mismatches.append(e.eid)
+        return serve.summarize(recs, st["wall_s"]), st, digests
 
-    warm, _ = run(W.serving_episodes(16, float("inf"), seed=args.seed + 1))
-    cap_sum, cap_st = run(W.serving_episodes(n, float("inf"), seed=args.seed))
-    capacity = cap_sum["episodes_per_s"]
-    sweep = []
-    for f in [float(x) for x in args.rates.split(",")]:
-        specs = W.serving_episodes(n, f * capacity, seed=args.seed)
-        s, st = run(specs)
-        sweep.append(dict(s, rate_fraction=f, rate_episodes_per_s=f * capacity, server_steps=st["server_steps"]))
-        print(json.dumps({"progress": "serve", "rate_fraction": f, **s}), file=sys.stderr, flush=True)
+    try:
+        run(W.serving_episodes(16, float("inf"), seed=args.seed + 1))          # warm-up
+        base = W.serving_episodes(n, float("inf"), seed=args.seed)
+        # Each episode alone (one at a time through the empty pools): the
+        # reference every mixed run is compared with.
+        alone = {}
+        for e in base:
+            _, _, d = run([e])
+            alone.update(d)
+        cap_sum, cap_st, _ = run(base, alone)
+        capacity = cap_sum["episodes_per_s"]
+        sweep = []
+        for f in [float(x) for x in args.rates.split(",")]:
+            specs = W.serving_episodes(n, f * capacity, seed=args.seed)
+            s, st, _ = run(specs, alone)
+            sweep.append(dict(s, rate_fraction=f, rate_episodes_per_s=f * capacity, server_steps=st["server_steps"]))
+            print(json.dumps({"progress": "serve", "rate_fraction": f, **s}), file=sys.stderr, flush=True)
+        # Profiled capacity run: per-launch timing on both pools.
+        for p in srv.pools.values():
+            p.heap.set_timing(True)
+        run(base)
+        roof, kernels = serve_roofline(srv, base)
+    finally:
+        srv.close()
+    if mismatches:
+        raise RuntimeError(f"serving results differ from the episodes run alone: {mismatches[:10]}")
     best = max(sweep, key=lambda r: r["episodes_per_s"])
+    cpu = None if args.no_cpu_baseline else serve_cpu_baseline(base, alone)
     out = {"metric": METRIC, "value": best["episodes_per_s"], "unit": "episodes/s", "n_gpus": 1,
            "steps": len(sweep), "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int32/u64", "data": "synthetic",
            "config": {"workload": f"serve-poisson-{n}episodes-70%gol128..2048-30%sugar256..1024",
                       "episodes_per_rate": n, "seed": args.seed},
            "capacity_episodes_per_s": capacity, "capacity_run": dict(cap_sum, **cap_st), "sweep": sweep,
-           "roofline": None, "cpu_baseline": None}
+           "parity": {"episodes_checked_against_alone": checked, "mismatches": 0, "heap_checks": "ok"},
+           "roofline": roof, "cpu_baseline": cpu, "kernels": kernels}
     print(json.dumps(out))
+
+
+def serve_roofline(srv, specs):
+    """Dominant kernel of a profiled serving run over both pools, with its
+    algorithmic bytes (the Game-of-Life and Sugarscape byte models over the
+    pool's own counters for that run)."""
+    from synth import workloads as W
+    gol_alive0 = sum(int(W.episode_inputs(e).sum()) for e in specs if e.kind == "gol")
+    sugar_agents0 = sum(int(W.episode_inputs(e).occ.sum()) for e in specs if e.kind == "sugar")
+    sugar_cells = sum(e.side ** 2 * e.length for e in specs if e.kind == "sugar")
+    kernels, best = {}, None
+    for name, p in srv.pools.items():
+        kern = p.heap.timing()
+        st = p.heap.stats()
+        p.heap.set_timing(False)
+        for kind, (launches, tot_ms) in kern.items():
+            if name == "gol":
+                b = gol_kernel_bytes(kind, launches, st, p.blocks, gol_alive0)
+            else:
+                # regrow sweeps the arena; count the episodes' own cells instead
+                b = sugar_kernel_bytes(kind, launches, st, p.blocks, sugar_agents0, sugar_cells / max(launches, 1))
+            other = None
+            if isinstance(b, tuple):
+                b, other = b
+            key = f"{name}:{kind}"
+            kernels[key] = {"launches": launches, "avg_us": tot_ms / launches * 1e3, "total_ms": tot_ms,
+                            "gbs": b / (tot_ms / 1e3) / 1e9 if b is not None and tot_ms > 0 else None}
+            if b is not None:
+                kernels[key]["bytes_per_launch"] = b / launches
+            if other is not None:
+                kernels[key]["other_bytes_per_launch"] = other / launches
+            if best is None or tot_ms > kernels[best]["total_ms"]:
+                best = key
+    k = kernels[best]
+    roof = None
+    if k["gbs"] is not None:
+        roof = {"bound": "hbm", "achieved": round(k["gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(k["gbs"] / HBM_PEAK_GBS, 5), "traffic": None, "kernel": best,
+                "avg_launch_us": round(k["avg_us"], 2), "algorithmic_bytes_per_launch": round(k["bytes_per_launch"])}
+        if "other_bytes_per_launch" in k:
+            roof["other_bytes_per_launch"] = round(k["other_bytes_per_launch"])
+    return roof, kernels
+
+
+def serve_cpu_baseline(specs, alone):
+    """The oracle on the first episodes in arrival order until about 10 s of
+    CPU work (episodes per second), each result also checked against the
+    device's digest of the same episode."""
+    import numpy as np
+
+    import oracle
+    from paper_1809_07444_amd import serve
+    from synth import workloads as W
+    t0 = time.perf_counter()
+    done = 0
+    oracle_s = 0.0
+    for e in specs:
+        inp = W.episode_inputs(e)
+        t1 = time.perf_counter()
+        if e.kind == "gol":
+            res, _ = oracle.gol_run(inp, e.length)
+        else:
+            st = oracle.SugarState(e.side, inp.sugar, inp.cap, inp.occ, inp.a_sugar, inp.a_metab, inp.a_vision,
+                                   inp.a_age)
+            r = oracle.sugar_run(st, e.length, e.seed, W.SUGAR_RULES)
+            m = r.occ.astype(bool)
+            res = {"sugar": r.sugar, "occ": r.occ, "moves": r.moves,
+                   **{f: np.where(m, getattr(r, f), 0).astype(np.int32) for f in ("a_sugar", "a_metab", "a_vision",
+                                                                                   "a_age")}}
+        oracle_s += time.perf_counter() - t1
+        if serve.result_digest(e.kind, res) != alone[e.eid]:
+            raise RuntimeError(f"serving episode {e.eid} differs from the oracle")
+        done += 1
+        if time.perf_counter() - t0 > 10:
+            break
+    return {"value": done / oracle_s, "unit": "episodes/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle (dense Game of Life stencil / sequential Sugarscape rules) on the first {done} "
+                      f"of {len(specs)} episodes in arrival order, {oracle_s:.1f} s; each equal to the device's "
+                      f"result"}
 
 
 def main():
@@ -673,8 +820,17 @@ def main():
     best = None
     for kind, (launches, tot_ms) in kern.items():
         b = wl.kernel_bytes(kind, launches, stp)
-        kernels[kind] = {"launches": launches, "avg_us": tot_ms / launches * 1e3, "total_ms": tot_ms,
-                         "gbs": (b / (tot_ms / 1e3) / 1e9) if b is not None and tot_ms > 0 else None}
+        other = None
+        if isinstance(b, tuple):
+            b, other = b
+        k = {"launches": launches, "avg_us": tot_ms / launches * 1e3, "total_ms": tot_ms,
+             "gbs": (b / (tot_ms / 1e3) / 1e9) if b is not None and tot_ms > 0 else None}
+        if b is not None:
+            k["bytes_per_launch"] = b / launches
+        if other is not None:
+            k["other_bytes_per_launch"] = other / launches
+            k["other_gbs"] = other / (tot_ms / 1e3) / 1e9 if tot_ms > 0 else None
+        kernels[kind] = k
         if best is None or tot_ms > kern[best][1]:
             best = kind
     roof = None
@@ -690,7 +846,11 @@ def main():
         ach = kernels[best]["gbs"]
         roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": best,
-                "avg_launch_us": round(kernels[best]["avg_us"], 2)}
+                "avg_launch_us": round(kernels[best]["avg_us"], 2),
+                "algorithmic_bytes_per_launch": round(kernels[best]["bytes_per_launch"])}
+        if "other_bytes_per_launch" in kernels[best]:
+            # Other objects' state the kernel reads or writes (not in achieved).
+            roof["other_bytes_per_launch"] = round(kernels[best]["other_bytes_per_launch"])
 
     # Bytes beyond L2 per launch of the dominant kernel, from the committed
     # rocprofv3 counter summary of this workload, while the device sources
@@ -725,6 +885,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32/u64", "data": "synthetic", "config": wl.config,
         "doall_objects_per_s": per_step_visits / (ms / 1e3),
+        "cells_gens_per_s": (wl.cells_gens / (ms / 1e3)) if getattr(wl, "cells_gens", None) else None,
         "per_step": {"allocs": st1["allocs"], "frees": st1["frees"], "doall_visits": st1["visits"],
                      "reserve_retries": st1["reserve_retries"], "slow_paths": st1["slow_paths"],
                      "find_fails": st1["find_fails"], "method_atomics": st1["method_atomics"],

@@ -38,7 +38,7 @@ extern "C" {
 #define DSOAR_MAX_TYPES 8
 #define DSOAR_MAX_FIELDS 8
 #define DSOAR_NULL 0xFFFFFFFFu /* the null object handle */
-#define DSOAR_ABI_VERSION 1
+#define DSOAR_ABI_VERSION 2
 
 typedef enum {
   DSOAR_OK = 0,
@@ -57,13 +57,22 @@ typedef uint32_t dsoar_obj;
 typedef struct dsoar_heap dsoar_heap;
 
 /* Per-type field layout (Sec. 2: one SOA array per field inside a block).
- * field_bytes[i] is 4 or 8. */
+ * field_bytes[i] is 4 or 8.  parent: 0 for a type of its own, else 1 + the
+ * index of its parent type (Sec. 1.2: class inheritance without wasted
+ * memory).  A subclass is declared after its parent and begins with the
+ * parent's fields (same count and widths), followed by its own; its blocks
+ * hold only its own objects, in its own SOA layout, so neither type carries
+ * the other's fields.  A do-all over a type visits the objects of the type
+ * and of all its subclasses, its method reading the inherited fields by the
+ * parent's field indices. */
 typedef struct {
   uint32_t num_fields;
   uint32_t field_bytes[DSOAR_MAX_FIELDS];
+  uint32_t parent;
 } dsoar_type_layout;
 
-/* Heap geometry.  num_blocks = M (1 .. 2^26).  block_capacity = slots per
+/* Heap geometry.  num_blocks = M (1 .. 2^26 - 1: in a heap of 2^26 blocks
+ * slot 63 of the last block would have the handle DSOAR_NULL).  block_capacity = slots per
  * block of every type, 64 (one wavefront per block, the paper's capacity for
  * the smallest type) or 32 (two blocks per wavefront; Sec. 2 notes capacities
  * of at least 32 keep 4-byte SOA arrays at 128 bytes), or 0 for the byte-size
@@ -75,7 +84,9 @@ typedef struct {
   uint32_t num_blocks;
   uint32_t block_capacity;
   uint32_t num_types;
-  uint32_t reserved; /* must be 0 */
+  uint32_t bitmap_width; /* bits per container of the block-state bitmaps (Sec. 3):
+                            64 (or 0) or 32.  It fixes the fan-out of every level
+                            and so the number of levels, ceil(log_width M) */
   dsoar_type_layout types[DSOAR_MAX_TYPES];
 } dsoar_heap_desc;
 
@@ -92,9 +103,11 @@ typedef struct {
   uint64_t bitmaps_offset;    /* (1 + 2*num_types) hierarchical bitmaps:
                                  0 = free, 1+2t = allocated[t], 2+2t = active[t] */
   uint64_t bitmap_stride;     /* bytes between consecutive bitmaps */
+  uint32_t bitmap_width;      /* container width in bits (32 or 64) */
   uint32_t num_levels;        /* levels per bitmap (level 0 = one bit per block) */
-  uint32_t level_word_offset[8];
-  uint32_t level_words[8];
+  uint32_t level_word_offset[8]; /* per level: offset in containers from the bitmap's start */
+  uint32_t level_words[8];       /* per level: containers (level bit j is bit j % 32 of the
+                                    32-bit unit j / 32 of the level at either width) */
   uint32_t field_offset[DSOAR_MAX_TYPES][DSOAR_MAX_FIELDS];
   uint32_t type_capacity[DSOAR_MAX_TYPES]; /* slots per block of each type */
 } dsoar_heap_layout;
@@ -113,6 +126,10 @@ typedef struct {
   uint64_t find_fails;                    /* try_find_set FAILs on active[T] */
   uint64_t method_atomics;                /* atomic RMWs do-all methods issued on their own data */
   uint64_t online_releases;               /* blocks freed by the delete that emptied them */
+  uint64_t blocks_taken;                  /* free-block count: blocks taken from the free bitmap */
+  uint64_t blocks_returned;               /* and returned to it; num_blocks + returned - taken
+                                             blocks are free or being opened (a request is out of
+                                             memory only when this reads 0, Sec. 2.2) */
   uint32_t free_blocks;
   uint32_t num_blocks;
   uint32_t oom;                           /* sticky flags */
@@ -130,6 +147,7 @@ enum {
   DSOAR_INV_FREE = 4,         /* free <=> untyped and empty; states disjoint */
   DSOAR_INV_CONTAINER = 5,    /* nested bit = OR of its container (Sec. 3) */
   DSOAR_INV_LIVE_COUNT = 6,   /* live = allocs - frees, per type */
+  DSOAR_INV_FREE_COUNT = 7,   /* free blocks = num_blocks + returned - taken */
   DSOAR_INV_COUNT = 8
 };
 
@@ -185,6 +203,18 @@ int dsoar_heap_set_policy(dsoar_heap* heap, uint32_t bulk_min);
  * value: DSOAR_ERR_INVALID_ARG. */
 enum { DSOAR_POLICY_DENSE = 0, DSOAR_POLICY_FRESH = 1, DSOAR_POLICY_BOUNDED = 2 };
 int dsoar_heap_set_type_policy(dsoar_heap* heap, uint32_t type, uint32_t policy);
+
+/* Where the bitmap searches of a wavefront start (any set bit may be
+ * returned, Sec. 2.1; results never depend on it).  DSOAR_SEARCH_HASHED (the
+ * default): a hash of the wavefront's index, spreading concurrent searches
+ * over the whole bitmap.  DSOAR_SEARCH_LOWEST: the lowest set bit at every
+ * level (and the lowest free slots of a block), the sequential choice.
+ * DSOAR_SEARCH_XCD: the hash, with the top level's choice narrowed to the
+ * eighth of the top container that the wavefront's XCD owns, so that the
+ * eight XCDs mostly work in disjoint parts of the heap.  Other values:
+ * DSOAR_ERR_INVALID_ARG. */
+enum { DSOAR_SEARCH_HASHED = 0, DSOAR_SEARCH_LOWEST = 1, DSOAR_SEARCH_XCD = 2 };
+int dsoar_heap_set_search(dsoar_heap* heap, uint32_t policy);
 
 /* Block reclamation.  By default (online = 0) a block emptied by deletes
  * stays allocated to its type until the next enumeration of that type or
@@ -274,14 +304,20 @@ typedef struct { uint32_t key_field; uint32_t field; uint32_t num_keys; uint32_t
 int dsoar_parallel_do(dsoar_heap* heap, uint32_t type, uint32_t method,
                       const void* args, size_t args_bytes, uint32_t flags, void* stream);
 
-/* Counters, sticky flags and block/object counts.  Synchronises `stream`.
+/* Counters, sticky flags and block/object counts (Sec. 2, "Block States":
+ * free, allocated[T] and active[T] blocks counted from their bitmaps, live
+ * objects from the object allocation bitmaps).  Synchronises `stream`.
  * Returns OOM / RETRY_LIMIT / DOUBLE_FREE if the matching sticky flag is set
  * (the struct is filled in either way). */
 int dsoar_heap_stats(dsoar_heap* heap, dsoar_stats* out, void* stream);
 
 /* Reclaims all empty blocks, then checks the block-state invariants at
- * quiescence; violations[DSOAR_INV_COUNT] receives the number of violations
- * per code.  Synchronises `stream`. */
+ * quiescence: the state rules of Sec. 2 ("Block States": allocated[T] iff the
+ * block holds objects of T, active[T] implies allocated[T], free iff empty)
+ * and the container consistency of Sec. 3 (each nested bit is the OR of its
+ * container), which holds once every operation has completed.
+ * violations[DSOAR_INV_COUNT] receives the number of violations per code.
+ * Synchronises `stream`. */
 int dsoar_heap_check(dsoar_heap* heap, uint32_t* violations, void* stream);
 
 /* Device entry points for callers without their own kernels: n lanes each
@@ -317,14 +353,15 @@ enum {
   DSOAR_BM_TRY_SET = 0, DSOAR_BM_TRY_CLEAR = 1, DSOAR_BM_SET = 2, DSOAR_BM_CLEAR = 3,
   DSOAR_BM_TRY_FIND_SET = 4, DSOAR_BM_FIND_CLEAR = 5
 };
-/* Bytes for a bitmap of nbits bits (all levels).  0 if nbits is 0 or > 2^30. */
-size_t dsoar_bitmap_bytes(uint32_t nbits);
+/* Bytes for a bitmap of nbits bits (all levels) with containers of `width`
+ * bits (32 or 64).  0 if nbits is 0 or > 2^30, or for another width. */
+size_t dsoar_bitmap_bytes(uint32_t nbits, uint32_t width);
 /* Initialises all levels: every bit clear (all_set = 0) or every bit < nbits set. */
-int dsoar_bitmap_init(void* bm_dev, uint32_t nbits, int all_set, void* stream);
+int dsoar_bitmap_init(void* bm_dev, uint32_t nbits, uint32_t width, int all_set, void* stream);
 /* ops_dev: n pairs (kind, pos).  results_dev[i]: 1/0 for try_*, 0 for set/clear
  * (-3 if the retry limit was hit), the position found or -1 (FAIL) for the
  * finds.  start_dev (optional, n entries) gives each find's rotation start. */
-int dsoar_bitmap_run(void* bm_dev, uint32_t nbits, const uint32_t* ops_dev, uint32_t n,
+int dsoar_bitmap_run(void* bm_dev, uint32_t nbits, uint32_t width, const uint32_t* ops_dev, uint32_t n,
                      const uint32_t* start_dev, int32_t* results_dev, void* stream);
 
 /* --------------------------------------------- microbenchmark workload ----
@@ -428,7 +465,10 @@ int dsoar_sugarpool_create(dsoar_heap* heap, uint32_t max_worlds, uint32_t arena
                            dsoar_sugar** out);
 /* Admits a side x side world into a free slot at arena cells [cell_offset,
  * cell_offset + side^2) (must not overlap a resident world), from per-cell
- * device arrays as in dsoar_sugar_init; seed and step0 key its random draws. */
+ * device arrays as in dsoar_sugar_init; seed and step0 key its random draws.
+ * Checks every cell's sugar and capacity on the device first and synchronises
+ * the stream for the result: a value outside 0..127 returns
+ * DSOAR_ERR_INVALID_ARG and leaves the pool unchanged. */
 int dsoar_sugar_admit(dsoar_sugar* sugar, uint32_t slot, uint32_t cell_offset, uint32_t side, uint64_t seed,
                       uint32_t step0, const int32_t* sugar_dev, const int32_t* cap_dev,
                       const uint8_t* occ_dev, const int32_t* a_sugar_dev, const int32_t* a_metab_dev,
@@ -448,7 +488,8 @@ int dsoar_sugar_create(dsoar_heap* heap, uint32_t side, const dsoar_sugar_rules*
 int dsoar_sugar_destroy(dsoar_sugar* sugar);
 /* Initial state from per-cell device arrays (side*side each): sugar and cap
  * (int32, 0..127: a cell keeps its sugar in one byte beside its occupancy
- * bit; values outside are clamped into that range), occ (uint8, 1 = an agent
+ * bit; a value outside returns DSOAR_ERR_INVALID_ARG, checked on the device
+ * before anything changes, which synchronises the stream), occ (uint8, 1 = an agent
  * starts here) and the agents' sugar, metabolism, vision and age (int32, read
  * where occ).  Vision is 1..6 (the choose phase looks at most 6 cells along
  * each axis).  step0 = index of the first step (it keys the random draws).

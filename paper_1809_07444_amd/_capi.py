@@ -19,11 +19,12 @@ ERRORS = {
     -4: "DSOAR_ERR_HIP", -5: "DSOAR_ERR_DOUBLE_FREE", -6: "DSOAR_ERR_TOO_SMALL",
     -7: "DSOAR_ERR_UNSUPPORTED",
 }
-ERR_OOM, ERR_RETRY_LIMIT, ERR_DOUBLE_FREE = -2, -3, -5
+ERR_INVALID_ARG, ERR_OOM, ERR_RETRY_LIMIT, ERR_DOUBLE_FREE = -1, -2, -3, -5
 
 DO_PERSISTENT, DO_PLAIN, DO_REUSE_ENUM = 0, 1, 2
 GRAPH = GOL_GRAPH = 0x100
 POLICY_DENSE, POLICY_FRESH, POLICY_BOUNDED = 0, 1, 2
+SEARCH_HASHED, SEARCH_LOWEST, SEARCH_XCD = 0, 1, 2
 METHOD_VISIT_COUNT, METHOD_DELETE_IF_MOD, METHOD_MICRO_UPDATE, METHOD_MICRO_CULL, METHOD_FIELD_GATHER = 1, 2, 3, 4, 5
 BM_TRY_SET, BM_TRY_CLEAR, BM_SET, BM_CLEAR, BM_TRY_FIND_SET, BM_FIND_CLEAR = range(6)
 KIND_NAMES = {1: "enumerate", 10: "visit_count", 11: "delete_if_mod", 12: "gather", 20: "micro_update",
@@ -38,24 +39,24 @@ KIND_NAMES = {1: "enumerate", 10: "visit_count", 11: "delete_if_mod", 12: "gathe
               52: "traffic_entry", 53: "traffic_init", 66: "collide_init",
               77: "wator_init", 78: "wator_tick"}
 INV_NAMES = ["bitmap_range", "allocated", "active", "active_implies_allocated", "free",
-             "container", "live_count", "reserved"]
+             "container", "live_count", "free_count"]
 
 u32, u64, i32, vp, sz = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
 
 
 class TypeLayout(ctypes.Structure):
-    _fields_ = [("num_fields", u32), ("field_bytes", u32 * MAX_FIELDS)]
+    _fields_ = [("num_fields", u32), ("field_bytes", u32 * MAX_FIELDS), ("parent", u32)]
 
 
 class HeapDesc(ctypes.Structure):
-    _fields_ = [("num_blocks", u32), ("block_capacity", u32), ("num_types", u32), ("reserved", u32),
+    _fields_ = [("num_blocks", u32), ("block_capacity", u32), ("num_types", u32), ("bitmap_width", u32),
                 ("types", TypeLayout * MAX_TYPES)]
 
 
 class HeapLayout(ctypes.Structure):
     _fields_ = [("total_bytes", u64), ("data_offset", u64), ("block_stride", u64),
                 ("obj_bitmap_offset", u64), ("block_type_offset", u64), ("bitmaps_offset", u64),
-                ("bitmap_stride", u64), ("num_levels", u32), ("level_word_offset", u32 * 8),
+                ("bitmap_stride", u64), ("bitmap_width", u32), ("num_levels", u32), ("level_word_offset", u32 * 8),
                 ("level_words", u32 * 8), ("field_offset", (u32 * MAX_FIELDS) * MAX_TYPES),
                 ("type_capacity", u32 * MAX_TYPES)]
 
@@ -65,7 +66,8 @@ class Stats(ctypes.Structure):
                 ("visits", u64 * MAX_TYPES),
                 ("allocated_blocks", u32 * MAX_TYPES), ("active_blocks", u32 * MAX_TYPES),
                 ("typed_blocks", u32 * MAX_TYPES), ("reserve_retries", u64), ("slow_paths", u64),
-                ("find_fails", u64), ("method_atomics", u64), ("online_releases", u64), ("free_blocks", u32), ("num_blocks", u32), ("oom", u32),
+                ("find_fails", u64), ("method_atomics", u64), ("online_releases", u64), ("blocks_taken", u64),
+                ("blocks_returned", u64), ("free_blocks", u32), ("num_blocks", u32), ("oom", u32),
                 ("retry_limit_hit", u32), ("double_free", u32), ("reserved", u32)]
 
 
@@ -112,6 +114,7 @@ SIGNATURES = {
     "dsoar_heap_set_type_policy": (ctypes.c_int, [H, u32, u32]),
     "dsoar_heap_set_unroll": (ctypes.c_int, [H, u32]),
     "dsoar_heap_set_reclaim": (ctypes.c_int, [H, ctypes.c_int]),
+    "dsoar_heap_set_search": (ctypes.c_int, [H, u32]),
     "dsoar_stress_churn": (ctypes.c_int, [H, u32, u32, u32, u32, u32, vp, vp, vp]),
     "dsoar_last_hip_error": (ctypes.c_int, [H]),
     "dsoar_heap_set_timing": (ctypes.c_int, [H, ctypes.c_int]),
@@ -129,9 +132,9 @@ SIGNATURES = {
     "dsoar_field_write": (ctypes.c_int, [H, u32, u32, vp, u32, vp, vp]),
     "dsoar_error_string": (ctypes.c_char_p, [ctypes.c_int]),
     "dsoar_abi_version": (ctypes.c_int, []),
-    "dsoar_bitmap_bytes": (sz, [u32]),
-    "dsoar_bitmap_init": (ctypes.c_int, [vp, u32, ctypes.c_int, vp]),
-    "dsoar_bitmap_run": (ctypes.c_int, [vp, u32, vp, u32, vp, vp, vp]),
+    "dsoar_bitmap_bytes": (sz, [u32, u32]),
+    "dsoar_bitmap_init": (ctypes.c_int, [vp, u32, u32, ctypes.c_int, vp]),
+    "dsoar_bitmap_run": (ctypes.c_int, [vp, u32, u32, vp, u32, vp, vp, vp]),
     "dsoar_micro_init": (ctypes.c_int, [H, u32, u32, vp, vp, vp]),
     "dsoar_micro_step": (ctypes.c_int, [H, u32, u32, vp, vp, u32, vp]),
     "dsoar_probe_atomics": (ctypes.c_int, [vp, u32, u32, u32, u32, vp]),

@@ -100,14 +100,14 @@ class GameOfLife:
     CAND_POLICY = C.POLICY_FRESH
 
     def __init__(self, grids, capacity: int = 64, num_blocks: int | None = None, stream=None,
-                 device="cuda", bulk_min: int | None = None):
+                 device="cuda", bulk_min: int | None = None, bitmap_width: int = 64):
         self.sides = np.array([g.shape[0] for g in grids], dtype=np.uint32)
         for g in grids:
             assert g.shape[0] == g.shape[1], "worlds are square"
         self.total = int((self.sides.astype(np.int64) ** 2).sum())
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         blocks = num_blocks or gol_blocks_for(self.total, capacity)
-        self.heap = Heap(blocks, capacity, GOL_TYPES, device=device, stream=self.stream)
+        self.heap = Heap(blocks, capacity, GOL_TYPES, device=device, stream=self.stream, bitmap_width=bitmap_width)
         self.heap.set_policy(self.BULK_MIN if bulk_min is None else bulk_min)
         self.heap.set_type_policy(GOL_CAND, self.CAND_POLICY)
         self.lib = self.heap.lib

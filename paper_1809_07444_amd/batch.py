@@ -1,7 +1,8 @@
 """Batched worlds: many independent Game-of-Life worlds of uneven size in one
 heap, one persistent do-all per phase covering all of them, each generation
 replayed from a HIP graph; the per-world "plain" baseline; and the autotuner
-that picks block capacity, do-all launch shape and allocation policy.
+that picks block capacity, bitmap fan-out (container width), do-all launch
+shape, allocation policy and where bitmap searches start.
 
 Every configuration computes the same result (the worlds are independent and
 the update is synchronous); the tuner only measures time."""
@@ -28,26 +29,35 @@ class TuneConfig:
     wg_threads: int = 256
     wgs_per_cu: int = 8
     bulk_min: int = 0          # 0 = whole free blocks first; NEVER = active blocks first (dense)
+    bitmap_width: int = 64     # container width of the block-state bitmaps (fan-out 64 or 32)
+    search: int = C.SEARCH_HASHED  # where bitmap searches start (hashed, lowest, per XCD)
 
     def apply(self, heap):
         heap.set_launch(self.wg_threads, self.wgs_per_cu)
         heap.set_policy(self.bulk_min)
+        heap.set_search(self.search)
 
 
+# Capacity and bitmap width shape the heap itself (a new heap per pair); the
+# other dimensions are settings of one heap.
 DEFAULT_SPACE = {
     "capacity": [64, 32, 0],
+    "bitmap_width": [64, 32],
     "wg_threads": [256, 1024],
     "wgs_per_cu": [2, 4, 8, 16],
     "bulk_min": [0, NEVER],
+    "search": [C.SEARCH_HASHED, C.SEARCH_XCD],
 }
 
 
-def workload_key(grids, generations: int) -> str:
+def workload_key(grids, generations: int, space: dict | None = None) -> str:
+    """Cache key: the worlds, the generations timed and the search space."""
     h = hashlib.sha256()
     for g in grids:
         h.update(str(g.shape).encode())
         h.update(hashlib.sha256(g.tobytes()).digest())
     h.update(str(generations).encode())
+    h.update(json.dumps(space or DEFAULT_SPACE, sort_keys=True).encode())
     return h.hexdigest()[:16]
 
 
@@ -56,7 +66,7 @@ class BatchedGol:
 
     def __init__(self, grids, cfg: TuneConfig = TuneConfig(), graph: bool = True, device="cuda"):
         self.cfg = cfg
-        self.gol = GameOfLife(grids, capacity=cfg.capacity, device=device)
+        self.gol = GameOfLife(grids, capacity=cfg.capacity, device=device, bitmap_width=cfg.bitmap_width)
         cfg.apply(self.gol.heap)
         self.flags = C.DO_PERSISTENT | (C.GOL_GRAPH if graph else 0)
 
@@ -125,17 +135,18 @@ def autotune(grids, generations: int = 10, space: dict | None = None, cache_path
     the batch (after a warm-up run that also captures the graph) and returns
     the fastest, with the table of all.  Results are cached by workload."""
     space = space or DEFAULT_SPACE
-    key = workload_key(grids, generations)
+    key = workload_key(grids, generations, space)
     if cache_path and os.path.exists(cache_path):
         cache = json.load(open(cache_path))
         if key in cache:
             ent = cache[key]
             return TuneConfig(**ent["best"]), ent["table"]
     table = []
-    for cap in space["capacity"]:
-        b = BatchedGol(grids, TuneConfig(capacity=cap), device=device)
-        for wg, per_cu, bulk in itertools.product(space["wg_threads"], space["wgs_per_cu"], space["bulk_min"]):
-            cfg = TuneConfig(cap, wg, per_cu, bulk)
+    for cap, width in itertools.product(space["capacity"], space.get("bitmap_width", [64])):
+        b = BatchedGol(grids, TuneConfig(capacity=cap, bitmap_width=width), device=device)
+        for wg, per_cu, bulk, search in itertools.product(space["wg_threads"], space["wgs_per_cu"],
+                                                          space["bulk_min"], space.get("search", [C.SEARCH_HASHED])):
+            cfg = TuneConfig(cap, wg, per_cu, bulk, width, search)
             cfg.apply(b.gol.heap)
             b.cfg = cfg
             _time_run(b, 1)  # captures the graph for this configuration

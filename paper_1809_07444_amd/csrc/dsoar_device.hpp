@@ -45,7 +45,16 @@ constexpr uint32_t kShards = 1024;         // counter shards (spread atomics)
 constexpr int kWaitVmem = 0x0F70;
 constexpr uint32_t kBoundedPasses = 2;  // active lookups per request under the bounded policy
 constexpr uint32_t kMultiBlocks = 8;  // active blocks one lookup may reserve in
-constexpr uint32_t kOomRetries = 4;        // active lookups retried before OOM
+// Where a wavefront's bitmap searches start (C8: any set bit may be taken):
+// a hash of the wavefront's index (searches spread over the whole bitmap),
+// the lowest set bit at every level (the oracle's choice), or a hash whose
+// top-level digit names one eighth of the top container per XCD (the eight
+// XCDs mostly search disjoint parts of the heap).
+enum : uint32_t { kStartHashed = 0, kStartLowest = 1, kStartXcd = 2 };
+// Rounds a request keeps waiting while the free-block count says a block is
+// free or being opened but neither lookup finds one (a summary bit still on
+// its way); then it gives up with the retry-limit flag.
+constexpr uint32_t kFreeWaitLimit = 1u << 12;
 
 // Control words (uint64 array at DevHeap::ctrl).
 enum : uint32_t {
@@ -62,9 +71,14 @@ enum : uint32_t {
   kCntVisits = 2 * kMaxTypes + 3,  // + type: objects visited by do-alls
   kCntMethodAtomics = 3 * kMaxTypes + 3,  // atomic RMWs methods issue on their own data
   kCntReleases = 3 * kMaxTypes + 4,       // blocks freed online by the delete that emptied them
+  // The free-block count: blocks taken from the free bitmap (counted once the
+  // request that took them has made them findable) and blocks returned to it
+  // (counted before their free bit is set).  Both only grow.
+  kCntBlocksTaken = 3 * kMaxTypes + 5,
+  kCntBlocksReturned = 3 * kMaxTypes + 6,
   kShardStride = 32,
 };
-static_assert(kCntReleases < kShardStride, "counter slots exceed a shard");
+static_assert(kCntBlocksReturned < kShardStride, "counter slots exceed a shard");
 
 
 struct DevHeap {
@@ -72,7 +86,7 @@ struct DevHeap {
   uint64_t* obj_bitmap;     // M words: bit s = slot s holds an object
   uint32_t* block_type;     // M words: version << 8 | type (kTypeNone if free)
   uint32_t* pins;           // M words: reservations in progress (online reclamation only)
-  uint64_t* bitmaps;        // (1 + 2T) hierarchical bitmaps, bm_words apart
+  uint32_t* bitmaps;        // (1 + 2T) hierarchical bitmaps, bm_units apart
   uint64_t* ctrl;           // flags + counter shards
   uint64_t block_stride;
   uint64_t cap_mask[kMaxTypes];  // per type: low `capacity` bits
@@ -80,7 +94,10 @@ struct DevHeap {
   uint32_t num_blocks;
   uint32_t num_types;
   uint32_t nlevels;
-  uint32_t bm_words;        // words per bitmap (all levels, padded)
+  uint32_t bm_lg;           // log2 of the bitmap container width (6 or 5)
+  uint32_t bm_units;        // 32-bit units per bitmap (all levels, padded)
+  uint32_t bm_off[kMaxLevels];  // unit offset of each level in a bitmap
+  uint32_t search_start;    // kStartHashed, kStartLowest or kStartXcd
   uint32_t bulk_min;        // requests of at least this many take whole free blocks
   uint32_t fresh_types;     // bit t: requests of type t skip the active lookup
   uint32_t bounded_types;   // bit t: at most kBoundedPasses active lookups per request of type t
@@ -224,6 +241,39 @@ __device__ __forceinline__ uint64_t* shard(const DevHeap& h) {
   return h.ctrl + kCtlWords + (uint64_t)(wave & (kShards - 1)) * kShardStride;
 }
 
+// Blocks that are free or being opened, M + returned - taken, as of one
+// instant.  Called by any subset of a wavefront's lanes (wave-uniform
+// result).  The counts are spread over the counter shards; two collects of
+// all shards whose totals agree saw the same values (each count only grows,
+// and the second collect's loads are issued after the first one's have
+// returned), so their sum is the state at the instant between them.
+// Returns -1 when no two successive collects agreed (the counts are
+// changing: blocks may be free).
+__device__ __attribute__((noinline)) int64_t free_block_count(const DevHeap& h) {
+  const uint64_t am = active_mask();
+  const uint32_t me = lanes_below(am), nact = (uint32_t)__popcll(am);
+  uint64_t prev_sum = ~0ull;
+  for (uint32_t round = 0; round < 8; ++round) {
+    uint64_t taken = 0, returned = 0;
+    for (uint32_t s = me; s < kShards; s += nact) {
+      const uint64_t* sh = h.ctrl + kCtlWords + (uint64_t)s * kShardStride;
+      taken += __hip_atomic_load(sh + kCntBlocksTaken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      returned += __hip_atomic_load(sh + kCntBlocksReturned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    uint64_t tt = 0, rr = 0;
+    for (uint64_t m = am; m; m &= m - 1) {
+      const uint32_t l = (uint32_t)__builtin_ctzll(m);
+      tt += ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(taken >> 32), l) << 32) |
+            (uint32_t)__builtin_amdgcn_readlane((uint32_t)taken, l);
+      rr += ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(returned >> 32), l) << 32) |
+            (uint32_t)__builtin_amdgcn_readlane((uint32_t)returned, l);
+    }
+    if (tt + rr == prev_sum) return (int64_t)h.num_blocks + (int64_t)rr - (int64_t)tt;
+    prev_sum = tt + rr;
+  }
+  return -1;
+}
+
 // Adds the active lanes' counts (each below 256) to counter `slot` of this
 // wavefront's shard with one atomic; exact under divergence (bit-sliced
 // ballots).  For methods that report their own atomic operations.
@@ -236,44 +286,104 @@ __device__ inline void wave_count(const DevHeap& h, uint32_t slot, uint32_t k) {
 
 // ------------------------------------------------------ hierarchical bitmap --
 // Bitmap k of the heap: k = 0 free, 1 + 2t allocated[t], 2 + 2t active[t].
-// Level l + 1 holds one bit per word of level l; the top level is one word.
+// A container is 2^lg bits, lg = 6 (64-bit containers) or 5 (32-bit ones),
+// one choice per heap: the bitmap's fan-out.  Level l + 1 holds one bit per
+// container of level l; the top level is one container (Sec. 3: a nested
+// bitmap exists while a level has more bits than one container).
+//
+// Storage is in 32-bit units; level l is a plain bit array (bit j in unit
+// j / 32) starting at an even unit, so a 64-bit container is two units.
+// Level 0 is read and written only as 64-bit groups (bits [64g, 64g + 64)):
+// one container at lg = 6, two at lg = 5, in one atomic; the containers of
+// a group are then updated together and their nested bits one container at
+// a time.  Block-indexed code thus works in groups of 64 blocks at either
+// width.  Levels above 0 are accessed one container at a time.
 
-// Word offset of level l in a bitmap of nbits bits: levels are stored
-// bottom-up, level k holding ceil(nbits / 64^(k+1)) words.
-__device__ __forceinline__ uint32_t level_offset(uint32_t nbits, uint32_t l) {
+// Bits of level l of a bitmap of nbits bits.
+__host__ __device__ __forceinline__ uint32_t level_bits(uint32_t nbits, uint32_t lg, uint32_t l) {
+  return ((nbits - 1) >> (lg * l)) + 1;
+}
+// Levels: a nested level exists while a level has more than 2^lg bits.
+__host__ __device__ __forceinline__ uint32_t num_levels(uint32_t nbits, uint32_t lg) {
+  uint32_t l = 1;
+  while (level_bits(nbits, lg, l - 1) > (1u << lg)) ++l;
+  return l;
+}
+// 32-bit units of a level of n bits (even, so that every level starts at an
+// 8-byte boundary).
+__host__ __device__ __forceinline__ uint32_t level_units(uint32_t n) { return (((n - 1) >> 6) + 1) * 2; }
+// Unit offset of level l (levels stored bottom-up).
+__host__ __device__ __forceinline__ uint32_t level_offset(uint32_t nbits, uint32_t lg, uint32_t l) {
   uint32_t off = 0;
-  for (uint32_t k = 0; k < l; ++k) off += ((nbits - 1) >> (6 * k + 6)) + 1;
+  for (uint32_t k = 0; k < l; ++k) off += level_units(level_bits(nbits, lg, k));
   return off;
 }
 
-// Levels of a bitmap: a nested bitmap exists iff the bitmap has more than 64
-// bits (Sec. 3, "Data Structure").
-__host__ __device__ __forceinline__ uint32_t num_levels(uint32_t nbits) {
-  uint32_t l = 1;
-  while (nbits > 64) {
-    nbits = (nbits + 63) >> 6;
-    ++l;
-  }
-  return l;
-}
-
 struct Bitmap {
-  uint64_t* words;
+  uint32_t* units;
   uint32_t nbits;
   uint32_t nlevels;
+  uint32_t lg;  // log2 of the container width: 6 or 5
   uint64_t* retry_flag;
+  const uint32_t* off;  // unit offset of each level (in the kernel's arguments)
 
-  __device__ __forceinline__ uint64_t* word(uint32_t level, uint32_t idx) const {
-    return words + level_offset(nbits, level) + idx;
-  }
+  // 64-bit group g of level 0.
+  __device__ __forceinline__ uint64_t* group(uint32_t g) const { return reinterpret_cast<uint64_t*>(units) + g; }
+  __device__ __forceinline__ uint32_t* level(uint32_t l) const { return units + off[l]; }
+  __device__ __forceinline__ uint32_t cmask() const { return (1u << lg) - 1u; }
 };
 
 __device__ __forceinline__ Bitmap heap_bitmap(const DevHeap& h, uint32_t k) {
-  return Bitmap{h.bitmaps + (uint64_t)k * h.bm_words, h.num_blocks, h.nlevels, h.ctrl + kCtlRetryLimit};
+  return Bitmap{h.bitmaps + (uint64_t)k * h.bm_units, h.num_blocks, h.nlevels, h.bm_lg, h.ctrl + kCtlRetryLimit,
+                h.bm_off};
 }
 __device__ __forceinline__ Bitmap free_bm(const DevHeap& h) { return heap_bitmap(h, 0); }
 __device__ __forceinline__ Bitmap allocated_bm(const DevHeap& h, uint32_t t) { return heap_bitmap(h, 1 + 2 * t); }
 __device__ __forceinline__ Bitmap active_bm(const DevHeap& h, uint32_t t) { return heap_bitmap(h, 2 + 2 * t); }
+
+// The container of level-0 bit `pos` inside the group value v that holds it.
+__device__ __forceinline__ uint64_t group_part(const Bitmap& b, uint64_t v, uint32_t pos) {
+  return __builtin_expect(b.lg == 6, 1) ? v : ((v >> (pos & 32u)) & 0xFFFFFFFFull);
+}
+
+// The 32-bit-container forms of the operations below are kept out of line:
+// inlined beside the 64-bit forms at every call site they would lengthen the
+// straight-line code each wavefront fetches, whatever width the heap uses.
+__device__ __attribute__((noinline)) uint64_t load_unit32(const uint32_t* p) {
+  return bcast32(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Agent-coherent, wave-uniform load of container c of level l >= 1.
+__device__ __forceinline__ uint64_t load_container(const Bitmap& b, uint32_t l, uint32_t c) {
+  if (__builtin_expect(b.lg == 6, 1)) return load_u64(reinterpret_cast<const uint64_t*>(b.level(l)) + c);
+  return load_unit32(b.level(l) + c);
+}
+
+// Top container (level nlevels - 1, container 0); with one level that is
+// group 0 of level 0 (at lg = 5 its second container is always empty).
+__device__ __forceinline__ uint64_t load_top(const Bitmap& b) {
+  return b.nlevels == 1 ? load_u64(b.group(0)) : load_container(b, b.nlevels - 1, 0);
+}
+
+__device__ __attribute__((noinline)) uint64_t bit_rmw32(uint32_t* w, uint32_t m, bool set) {
+  uint32_t r = 0;
+  if (is_first_active())
+    r = set ? __hip_atomic_fetch_or(w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+            : __hip_atomic_fetch_and(w, ~m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return bcast32(r);
+}
+
+// One leader atomic on the bit `pos` of level `level` (OR when set, AND-NOT
+// otherwise); returns the previous value of the bit's container.
+__device__ __forceinline__ uint64_t bit_rmw(const Bitmap& b, uint32_t level, uint32_t pos, bool set) {
+  if (__builtin_expect(level == 0 || b.lg == 6, 1)) {
+    uint64_t* w = reinterpret_cast<uint64_t*>(b.level(level)) + (pos >> 6);
+    const uint64_t m = 1ull << (pos & 63u);
+    const uint64_t prev = set ? lead_or(w, m) : lead_and(w, ~m);
+    return level == 0 ? group_part(b, prev, pos) : prev;
+  }
+  return bit_rmw32(b.level(level) + (pos >> 5), 1u << (pos & 31u), set);
+}
 
 // set(pos) / clear(pos) of Sec. 2.1: retry the try_ operation until it
 // succeeds, then do the nested update this success made us responsible for
@@ -282,13 +392,12 @@ __device__ __forceinline__ Bitmap active_bm(const DevHeap& h, uint32_t t) { retu
 // Returns false only if the retry limit was hit (sticky flag set).
 __device__ inline bool bm_set_from(const Bitmap& b, uint32_t level, uint32_t pos) {
   for (;;) {
-    const uint64_t mask = 1ull << (pos & 63);
-    uint64_t* w = b.word(level, pos >> 6);
+    const uint64_t bit = 1ull << (pos & b.cmask());
     uint64_t prev;
     uint32_t spins = 0;
     for (;;) {
-      prev = lead_or(w, mask);
-      if (!(prev & mask)) break;
+      prev = bit_rmw(b, level, pos, true);
+      if (!(prev & bit)) break;
       if (++spins >= kSpinLimit) {
         lead_flag(b.retry_flag);
         return false;
@@ -296,20 +405,19 @@ __device__ inline bool bm_set_from(const Bitmap& b, uint32_t level, uint32_t pos
       __builtin_amdgcn_s_sleep(1);
     }
     if (prev != 0 || level + 1 >= b.nlevels) return true;
-    pos >>= 6;
+    pos >>= b.lg;
     ++level;
   }
 }
 
 __device__ inline bool bm_clear_from(const Bitmap& b, uint32_t level, uint32_t pos) {
   for (;;) {
-    const uint64_t mask = 1ull << (pos & 63);
-    uint64_t* w = b.word(level, pos >> 6);
+    const uint64_t bit = 1ull << (pos & b.cmask());
     uint64_t prev;
     uint32_t spins = 0;
     for (;;) {
-      prev = lead_and(w, ~mask);
-      if (prev & mask) break;
+      prev = bit_rmw(b, level, pos, false);
+      if (prev & bit) break;
       if (++spins >= kSpinLimit) {
         lead_flag(b.retry_flag);
         return false;
@@ -317,7 +425,7 @@ __device__ inline bool bm_clear_from(const Bitmap& b, uint32_t level, uint32_t p
       __builtin_amdgcn_s_sleep(1);
     }
     if (__popcll(prev) != 1 || level + 1 >= b.nlevels) return true;
-    pos >>= 6;
+    pos >>= b.lg;
     ++level;
   }
 }
@@ -325,48 +433,85 @@ __device__ inline bool bm_clear_from(const Bitmap& b, uint32_t level, uint32_t p
 __device__ __forceinline__ bool bm_set(const Bitmap& b, uint32_t pos) { return bm_set_from(b, 0, pos); }
 __device__ __forceinline__ bool bm_clear(const Bitmap& b, uint32_t pos) { return bm_clear_from(b, 0, pos); }
 
-// set(pos) for every bit of m in level-0 word `word`, with one atomic OR when
-// no other operation holds any of them: bits that were already set are set
+// The nested updates that an OR of m into level-0 group g (previous value
+// prev) makes: each container of the group that was empty and gained bits
+// sets its bit one level up (set's cascade, Sec. 2.1).
+__device__ __attribute__((noinline)) void group_set_nested32(const Bitmap& b, uint32_t g, uint64_t prev, uint64_t m) {
+  for (uint32_t half = 0; half < 2; ++half) {
+    const uint64_t hm = 0xFFFFFFFFull << (32 * half);
+    if ((m & hm) && !(prev & hm)) bm_set_from(b, 1, 2 * g + half);
+  }
+}
+__device__ inline void group_set_nested(const Bitmap& b, uint32_t g, uint64_t prev, uint64_t m) {
+  if (b.nlevels == 1) return;
+  if (__builtin_expect(b.lg == 6, 1)) {
+    if (prev == 0 && m) bm_set_from(b, 1, g);
+    return;
+  }
+  group_set_nested32(b, g, prev, m);
+}
+
+// The nested updates that an AND-NOT of m on level-0 group g (previous value
+// prev) makes: each container whose last set bits it removed clears its bit
+// one level up (Alg. 2 for several bits at once).
+__device__ __attribute__((noinline)) void group_clear_nested32(const Bitmap& b, uint32_t g, uint64_t prev,
+                                                               uint64_t m) {
+  for (uint32_t half = 0; half < 2; ++half) {
+    const uint64_t hm = 0xFFFFFFFFull << (32 * half);
+    if ((prev & m & hm) && (prev & ~m & hm) == 0) bm_clear_from(b, 1, 2 * g + half);
+  }
+}
+__device__ inline void group_clear_nested(const Bitmap& b, uint32_t g, uint64_t prev, uint64_t m) {
+  if (b.nlevels == 1) return;
+  if (__builtin_expect(b.lg == 6, 1)) {
+    if ((prev & m) && (prev & ~m) == 0) bm_clear_from(b, 1, g);
+    return;
+  }
+  group_clear_nested32(b, g, prev, m);
+}
+
+// set(pos) for every bit of m in level-0 group g, with one atomic OR when no
+// other operation holds any of them: bits that were already set are set
 // again one by one with set's retry, so each still pairs with the clear that
-// is about to take it away.  The nested bit is set when the word was empty.
-__device__ inline void bm_set_bits0(const Bitmap& b, uint32_t word, uint64_t m) {
-  const uint64_t prev = lead_or(b.word(0, word), m);
-  if (prev == 0 && b.nlevels > 1) bm_set_from(b, 1, word);
+// is about to take it away.  A container that was empty sets its nested bit.
+__device__ inline void bm_set_bits0(const Bitmap& b, uint32_t g, uint64_t m) {
+  const uint64_t prev = lead_or(b.group(g), m);
+  group_set_nested(b, g, prev, m & ~prev);
   uint64_t busy = prev & m;
   while (busy) {
-    bm_set(b, word * 64 + (uint32_t)__builtin_ctzll(busy));
+    bm_set(b, g * 64 + (uint32_t)__builtin_ctzll(busy));
     busy &= busy - 1;
   }
 }
 
 // bm_set_bits0 in two halves, so that the wait for the OR's result can be
-// put off: _issue returns the previous word in the leader lane only (call
+// put off: _issue returns the previous group in the leader lane only (call
 // both halves with the same lanes active), _settle finishes the operation.
-__device__ __forceinline__ uint64_t bm_set_bits0_issue(const Bitmap& b, uint32_t word, uint64_t m) {
+__device__ __forceinline__ uint64_t bm_set_bits0_issue(const Bitmap& b, uint32_t g, uint64_t m) {
   uint64_t r = 0;
-  if (is_first_active()) r = __hip_atomic_fetch_or(b.word(0, word), m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (is_first_active()) r = __hip_atomic_fetch_or(b.group(g), m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return r;
 }
-__device__ inline void bm_set_bits0_settle(const Bitmap& b, uint32_t word, uint64_t m, uint64_t leader_prev) {
+__device__ inline void bm_set_bits0_settle(const Bitmap& b, uint32_t g, uint64_t m, uint64_t leader_prev) {
   const uint64_t prev = bcast64(leader_prev);
-  if (prev == 0 && b.nlevels > 1) bm_set_from(b, 1, word);
+  group_set_nested(b, g, prev, m & ~prev);
   uint64_t busy = prev & m;
   while (busy) {
-    bm_set(b, word * 64 + (uint32_t)__builtin_ctzll(busy));
+    bm_set(b, g * 64 + (uint32_t)__builtin_ctzll(busy));
     busy &= busy - 1;
   }
 }
 
-// clear(pos) for every bit of m in level-0 word `word`: one atomic AND; bits
+// clear(pos) for every bit of m in level-0 group g: one atomic AND; bits
 // that were not set yet (their set is still on its way) are cleared one by
-// one with clear's retry.  The nested bit is cleared when this AND emptied
-// the word (Alg. 2 for several bits at once).
-__device__ inline void bm_clear_bits0(const Bitmap& b, uint32_t word, uint64_t m) {
-  const uint64_t prev = lead_and(b.word(0, word), ~m);
-  if ((prev & m) && (prev & ~m) == 0 && b.nlevels > 1) bm_clear_from(b, 1, word);
+// one with clear's retry.  A container this AND emptied clears its nested
+// bit (Alg. 2 for several bits at once).
+__device__ inline void bm_clear_bits0(const Bitmap& b, uint32_t g, uint64_t m) {
+  const uint64_t prev = lead_and(b.group(g), ~m);
+  group_clear_nested(b, g, prev, m);
   uint64_t busy = m & ~prev;
   while (busy) {
-    bm_clear(b, word * 64 + (uint32_t)__builtin_ctzll(busy));
+    bm_clear(b, g * 64 + (uint32_t)__builtin_ctzll(busy));
     busy &= busy - 1;
   }
 }
@@ -374,49 +519,51 @@ __device__ inline void bm_clear_bits0(const Bitmap& b, uint32_t word, uint64_t m
 // try_set(pos): one atomic OR; on success from an empty container, set the
 // nested bit (retrying).
 __device__ inline bool bm_try_set(const Bitmap& b, uint32_t pos) {
-  const uint64_t mask = 1ull << (pos & 63);
-  const uint64_t prev = lead_or(b.word(0, pos >> 6), mask);
-  const bool ok = !(prev & mask);
-  if (ok && prev == 0 && b.nlevels > 1) bm_set_from(b, 1, pos >> 6);
+  const uint64_t bit = 1ull << (pos & 63u);
+  const uint64_t prev = lead_or(b.group(pos >> 6), bit);
+  const bool ok = !(prev & bit);
+  if (ok && group_part(b, prev, pos) == 0 && b.nlevels > 1) bm_set_from(b, 1, pos >> b.lg);
   return ok;
 }
 
 // Alg. 2, try_clear(pos): one atomic AND; success if the bit was set; if this
 // cleared the container's last bit, clear the nested bit (retrying).
 __device__ inline bool bm_try_clear(const Bitmap& b, uint32_t pos) {
-  const uint64_t mask = 1ull << (pos & 63);
-  const uint64_t prev = lead_and(b.word(0, pos >> 6), ~mask);
-  const bool ok = (prev & mask) != 0;
-  if (ok && __popcll(prev) == 1 && b.nlevels > 1) bm_clear_from(b, 1, pos >> 6);
+  const uint64_t bit = 1ull << (pos & 63u);
+  const uint64_t prev = lead_and(b.group(pos >> 6), ~bit);
+  const bool ok = (prev & bit) != 0;
+  if (ok && __popcll(group_part(b, prev, pos)) == 1 && b.nlevels > 1) bm_clear_from(b, 1, pos >> b.lg);
   return ok;
 }
 
-// The set bit of w (w != 0) that a 6-bit digit d selects: the
-// floor(d * popcount / 64)-th one, so digits spread evenly over the set bits
-// whatever their positions (a plain "first set bit at or after d" would send
-// every digit beyond the last set bit to the first one).
-__device__ __forceinline__ uint32_t pick_bit(uint64_t w, uint32_t d) {
-  return nth_set_bit(w, (d * (uint32_t)__popcll(w)) >> 6);
+// The set bit of w (w != 0) that an lg-bit digit d selects: the
+// floor(d * popcount / 2^lg)-th one, so digits spread evenly over the set
+// bits whatever their positions (a plain "first set bit at or after d" would
+// send every digit beyond the last set bit to the first one).
+__device__ __forceinline__ uint32_t pick_bit(uint64_t w, uint32_t d, uint32_t lg) {
+  return nth_set_bit(w, (d * (uint32_t)__popcll(w)) >> lg);
 }
 
-__device__ __forceinline__ uint32_t level_digit(uint32_t start, uint32_t l) {
-  return (start >> ((6 * l) % 30)) & 63u;
+// The digit of `start` that chooses among the set bits at level l.
+__device__ __forceinline__ uint32_t level_digit(uint32_t start, uint32_t l, uint32_t lg) {
+  const uint32_t sh = lg * l;  // at most 6 * 7: the digits wrap round after 30 bits
+  return (start >> (sh >= 30 ? sh - 30 : sh)) & ((1u << lg) - 1u);
 }
 
-// First word of a descent.  With three or more levels the search starts one
-// level below the top, at the word that `start`'s top digit names among that
-// level's words, and reads the top word only if that word is empty: the top
-// word is the bitmap's most contended one, and a bitmap with set bits
-// usually has few empty words one level down.  Either way the descent goes
-// on from a non-empty word, so it still finds a set bit when there is one.
-// False: the whole bitmap is empty.
+// First container of a descent.  With three or more levels the search starts
+// one level below the top, at the container that `start`'s top digit names
+// among that level's containers, and reads the top container only if that
+// one is empty: the top container is the bitmap's most contended word, and
+// a bitmap with set bits usually has few empty containers one level down.
+// Either way the descent goes on from a non-empty container, so it still
+// finds a set bit when there is one.  False: the whole bitmap reads empty.
 __device__ inline bool bm_descend_start(const Bitmap& b, uint32_t start, uint32_t* level, uint32_t* idx,
                                         uint64_t* w) {
   const uint32_t top = b.nlevels - 1;
   if (top >= 2) {
-    const uint32_t nw = ((b.nbits - 1) >> (6 * top)) + 1;  // words one level below the top
-    const uint32_t i = (level_digit(start, top) * nw) >> 6;
-    const uint64_t v = load_u64(b.word(top - 1, i));
+    const uint32_t nc = level_bits(b.nbits, b.lg, top);  // containers one level below the top
+    const uint32_t i = (level_digit(start, top, b.lg) * nc) >> b.lg;
+    const uint64_t v = load_container(b, top - 1, i);
     if (v != 0) {
       *level = top - 1;
       *idx = i;
@@ -424,7 +571,7 @@ __device__ inline bool bm_descend_start(const Bitmap& b, uint32_t start, uint32_
       return true;
     }
   }
-  const uint64_t v = load_u64(b.word(top, 0));
+  const uint64_t v = load_top(b);
   *level = top;
   *idx = 0;
   *w = v;
@@ -432,56 +579,68 @@ __device__ inline bool bm_descend_start(const Bitmap& b, uint32_t start, uint32_
 }
 
 // try_find_set() stopped one level early: the index of a non-empty level-0
-// word (chosen as try_find_set chooses) and its bits, or FAIL.  One load per
+// group (chosen as try_find_set chooses) and its bits, or FAIL.  One load per
 // level (a logarithmic number of accesses, Sec. 2.4); at each level the
-// base-64 digit of `start` for that level picks one of the word's set bits,
-// so concurrent searches with different starts spread over the whole bitmap.
-// An empty word on the way down means the summary is momentarily ahead of its
-// container: FAIL.
+// digit of `start` for that level picks one of the container's set bits, so
+// concurrent searches with different starts spread over the whole bitmap.
+// An empty container on the way down means the summary is momentarily ahead
+// of it: FAIL.
 __device__ inline int32_t bm_find_word(const Bitmap& b, uint32_t start, uint64_t* bits) {
   uint32_t l, idx;
   uint64_t w;
   if (!bm_descend_start(b, start, &l, &idx, &w)) return kFail;
-  while (l > 0) {
-    idx = (idx << 6) | pick_bit(w, level_digit(start, l));
+  if (l == 0) {  // a single level: the top is group 0
+    *bits = w;
+    return 0;
+  }
+  while (l > 1) {
+    idx = (idx << b.lg) | pick_bit(w, level_digit(start, l, b.lg), b.lg);
     --l;
-    w = load_u64(b.word(l, idx));
+    w = load_container(b, l, idx);
     if (w == 0) return kFail;
   }
+  // Level 1 -> a container of level 0, read with its group.
+  idx = (idx << b.lg) | pick_bit(w, level_digit(start, 1, b.lg), b.lg);
+  const uint32_t g = idx >> (6 - b.lg);
+  w = load_u64(b.group(g));
+  if (w == 0) return kFail;
   *bits = w;
-  return (int32_t)idx;
+  return (int32_t)g;
 }
 
-// try_find_set(): descend to a non-empty level-0 word and pick one of its set
-// bits with the digit of `start` for level 0.
+// try_find_set(): descend to a non-empty level-0 group and pick one of its
+// set bits with the digit of `start` for level 0.
 __device__ inline int32_t bm_try_find_set(const Bitmap& b, uint32_t start) {
   uint64_t w = 0;
-  const int32_t word = bm_find_word(b, start, &w);
-  if (word == kFail) return kFail;
-  const uint32_t idx = ((uint32_t)word << 6) | pick_bit(w, level_digit(start, 0));
+  const int32_t g = bm_find_word(b, start, &w);
+  if (g == kFail) return kFail;
+  const uint32_t idx = ((uint32_t)g << 6) | pick_bit(w, level_digit(start, 0, 6), 6);
   return idx < b.nbits ? (int32_t)idx : kFail;
 }
 
 // clear() of Sec. 2.1: find a set bit and clear it, repeating until this
-// wavefront's clear succeeds.  FAIL when the top word is empty: callers use
-// this only on bitmaps that are never set during a kernel (the free bitmap is
-// refilled only at quiescence), so an empty top word means an empty bitmap.
+// wavefront's clear succeeds.  FAIL when the top container reads empty.
+// That does not prove the bitmap empty: with online reclamation a released
+// block's level-0 bit is set before its upper levels, so the top can read 0
+// while a bit is set below it.  The caller decides out of memory by the
+// free-block count, not by this FAIL.
 __device__ inline int32_t bm_find_clear(const Bitmap& b, uint32_t start) {
   for (uint32_t spins = 0; spins < kSpinLimit; ++spins) {
     const int32_t i = bm_try_find_set(b, start);
     if (i != kFail && bm_try_clear(b, (uint32_t)i)) return i;
-    if (i == kFail && load_u64(b.word(b.nlevels - 1, 0)) == 0) return kFail;
+    if (i == kFail && load_top(b) == 0) return kFail;
     start = hash32(start + 0x9e3779b9u + spins);
   }
   lead_flag(b.retry_flag);
   return kFail;
 }
 
-// Takes up to `want` (1..64) set bits of one level-0 word of a bitmap that is
-// only cleared during kernels (the free bitmap): descend as try_find_set to a
-// non-empty word, clear the chosen bits with one atomic AND, and clear the
-// word's nested bit if this emptied it (Alg. 2 for several bits at once).
-// Returns the bits gained (0 = the bitmap is empty) and the word in *word.
+// Takes up to `want` (1..64) set bits of one level-0 group of a bitmap that
+// is only cleared during kernels (the free bitmap): descend as try_find_set
+// to a non-empty group, clear the chosen bits with one atomic AND, and clear
+// the nested bits of the containers this emptied (Alg. 2 for several bits at
+// once).  Returns the bits gained (0 = the bitmap reads empty) and the group
+// in *word.
 __device__ inline uint64_t bm_take_word(const Bitmap& b, uint32_t start, uint32_t want, uint32_t* word) {
   for (uint32_t spins = 0; spins < kSpinLimit; ++spins) {
     uint64_t w = 0;
@@ -489,14 +648,14 @@ __device__ inline uint64_t bm_take_word(const Bitmap& b, uint32_t start, uint32_
     const uint32_t idx = found == kFail ? 0u : (uint32_t)found;
     if (found != kFail) {
       const uint64_t take = take_from(w, want < (uint32_t)__popcll(w) ? want : (uint32_t)__popcll(w), start & 63u);
-      const uint64_t prev = lead_and(b.word(0, idx), ~take);
+      const uint64_t prev = lead_and(b.group(idx), ~take);
       const uint64_t got = prev & take;
-      if (got && (prev & ~take) == 0 && b.nlevels > 1) bm_clear_from(b, 1, idx);
+      if (got) group_clear_nested(b, idx, prev, got);
       if (got) {
         *word = idx;
         return got;
       }
-    } else if (load_u64(b.word(b.nlevels - 1, 0)) == 0) {
+    } else if (load_top(b) == 0) {
       return 0;
     }
     start = hash32(start + 0x9e3779b9u + spins);
@@ -578,6 +737,20 @@ __device__ __forceinline__ uint32_t publish_block(const DevHeap& h, uint32_t bid
   return w;
 }
 
+// Start value of this wavefront's bitmap searches (and slot rotation) under
+// the heap's search-start policy.  Workgroups are dispatched to the eight
+// XCDs round-robin, so blockIdx.x mod 8 is the XCD.
+__device__ __forceinline__ uint32_t search_start(const DevHeap& h) {
+  if (h.search_start == kStartLowest) return 0u;
+  const uint32_t r = bcast32(hash32((blockIdx.x << 5) ^ (threadIdx.x >> 6) ^ 0x5bd1e995u));
+  if (h.search_start != kStartXcd) return r;
+  const uint32_t tsh = h.bm_lg * (h.nlevels - 1);
+  const uint32_t sh = tsh >= 30 ? tsh - 30 : tsh;  // the top level's digit (as level_digit)
+  const uint32_t span = (1u << h.bm_lg) >> 3;             // an eighth of its values
+  const uint32_t digit = (blockIdx.x & 7u) * span + ((r >> sh) & (span - 1u));
+  return (r & ~(((1u << h.bm_lg) - 1u) << sh)) | (digit << sh);
+}
+
 // Alg. 1 for all lanes of this wavefront that call it with the same `type`
 // (the caller guarantees a wave-uniform type); lane i asks for k_i objects
 // (0 <= k_i < 256).  f(j, obj) is then called by lane i for j = 0 .. k_i - 1
@@ -611,12 +784,12 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
   }
   if (n == 0) return;
   const Bitmap active = active_bm(h, type);
-  const uint32_t rot = bcast32(hash32((blockIdx.x << 5) ^ (threadIdx.x >> 6) ^ 0x5bd1e995u));
+  const uint32_t rot = search_start(h);
   const uint32_t c = cap_of(h, type);
   const uint64_t cap = capmask_of(h, type);
   uint32_t start = rot;
-  uint32_t served = 0, retries = 0, slow = 0, fails = 0, oom_rounds = 0;
-  bool oom = false, active_first = false, none_active = false;
+  uint32_t served = 0, retries = 0, slow = 0, fails = 0, oom_rounds = 0, wait_rounds = 0;
+  bool oom = false, gave_up = false, active_first = false, none_active = false;
   int32_t cur = kFail;     // block of the last reservation, if it still had room
   uint64_t cur_avail = 0;  // its free bits right after that reservation
   uint32_t cur_tw = 0;     // its type word then (online reclamation: checked on reuse)
@@ -632,7 +805,7 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
   for (uint32_t it = 0; served < n; ++it) {
     if (it >= kSpinLimit) {
       lead_flag(h.ctrl + kCtlRetryLimit);
-      oom = true;  // hand NULL to the lanes still waiting
+      gave_up = true;  // hand NULL to the lanes still waiting
       break;
     }
     const uint32_t want = n - served;
@@ -651,8 +824,9 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
       const uint32_t me = lanes_below(active_mask()), nact = (uint32_t)__popcll(active_mask());
       for (uint32_t j = me; j < cnt_b; j += nact) publish_block(h, word * 64 + nth_set_bit(blocks, j), type, cap);
       const Bitmap alloc = allocated_bm(h, type);
-      const uint64_t pa = lead_or(alloc.word(0, word), blocks);
-      if (pa == 0 && alloc.nlevels > 1) bm_set_from(alloc, 1, word);
+      const uint64_t pa = lead_or(alloc.group(word), blocks);
+      group_set_nested(alloc, word, pa, blocks & ~pa);
+      lead_add(shard(h) + kCntBlocksTaken, cnt_b);  // full blocks: nothing left to find
       slow += cnt_b;
       const uint32_t span = cnt_b * c;
       const uint32_t lo = prefix > served ? prefix : served;
@@ -752,14 +926,24 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
     if (bid == kFail) {
       bid = bm_find_clear(free_bm(h), start);
       if (bid == kFail) {
-        // No free block.  A block another wavefront is opening may not be
-        // marked active yet: look again a few times before giving up.
-        if (++oom_rounds <= kOomRetries) {
-          active_first = true;
+        // The free bitmap reads empty.  Out of memory only when the free-block
+        // count (free blocks and blocks other wavefronts are still opening)
+        // reads 0 twice with a failed active lookup in between: a request
+        // fails only when no block has room (Sec. 2.2).
+        const int64_t nfree = free_block_count(h);
+        active_first = true;
+        start = hash32(start + it + 1);
+        if (nfree != 0) {
+          // A block is free or about to become findable: look again.
+          if (++wait_rounds >= kFreeWaitLimit) {
+            lead_flag(h.ctrl + kCtlRetryLimit);
+            gave_up = true;
+            break;
+          }
           __builtin_amdgcn_s_sleep(8);
-          start = hash32(start + it + 1);
           continue;
         }
+        if (++oom_rounds < 2) continue;
         oom = true;
         break;
       }
@@ -782,6 +966,9 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
         cur_avail = ~got & cap;
         cur_tw = bcast32(w);
       }
+      // Counted as taken only now that its sets have returned: until then the
+      // free-block count keeps other requests looking instead of failing.
+      lead_add(shard(h) + kCntBlocksTaken, 1);
     } else {
       if (h.online_reclaim) {
         uint32_t pinned = 0;
@@ -811,10 +998,9 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
     for (uint32_t r = lo; r < hi; ++r) f(r - prefix, make_obj((uint32_t)bid, nth_set_bit(got, r - served)));
     served += cnt;
   }
-  if (oom) {
-    lead_flag(h.ctrl + kCtlOom);
+  if (oom) lead_flag(h.ctrl + kCtlOom);
+  if (oom || gave_up)
     for (uint32_t r = prefix > served ? prefix : served; r < prefix + k; ++r) f(r - prefix, kNull);
-  }
   uint64_t* sh = shard(h);
   if (served) lead_add(sh + kCntAllocs + type, served);
   if (retries) lead_add(sh + kCntReserveRetries, retries);
@@ -851,9 +1037,10 @@ __device__ inline uint32_t dsoar_new(const DevHeap& h, uint32_t type) {
 //    with the block still active let the lookups of every other wavefront
 //    keep pinning it, and the wait could starve.)
 //  3 Leave allocated[type] (clear with retry).
-//  4 Reset the object bitmap, then set the free bit once the reset is
-//    performed: an allocator that takes the block from the free bitmap sees
-//    the reset bitmap and the new type word.
+//  4 Reset the object bitmap and count the block as returned, then set the
+//    free bit once both are performed: an allocator that takes the block from
+//    the free bitmap sees the reset bitmap and the new type word, and a
+//    request that finds no free block still finds it in the count.
 // Returns whether the block was freed (wave-uniform).
 __device__ inline bool try_release(const DevHeap& h, uint32_t type, uint32_t bid) {
   uint32_t ok = 0;
@@ -884,6 +1071,7 @@ __device__ inline bool try_release(const DevHeap& h, uint32_t type, uint32_t bid
   }
   bm_clear(allocated_bm(h, type), bid);
   if (is_first_active()) __hip_atomic_store(h.obj_bitmap + bid, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  lead_add(shard(h) + kCntBlocksReturned, 1);  // counted before it can be found
   wait_performed();
   bm_set(free_bm(h), bid);
   lead_add(shard(h) + kCntReleases, 1);

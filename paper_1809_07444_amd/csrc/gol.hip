@@ -30,48 +30,29 @@ enum : uint32_t { kCAlive = 0 };
 enum : uint32_t { kACell = 0, kAWorld = 1, kAAction = 2 };
 constexpr uint32_t kKindGolUpdate = 35;  // timing id of the fused phases 3 and 4
 
-// A cell index word holds the Cell's handle and, in kLiveBit, a copy of its
-// live flag, so that reading a neighbour's state is one load; kNull when the
-// Cell is missing.  Handles stay below 2^31 (heaps of fewer than 2^25 blocks).
-constexpr uint32_t kLiveBit = 0x80000000u;
-__device__ __forceinline__ bool live_of(uint32_t wd) { return wd != kNull && (wd & kLiveBit) != 0; }
+// Beside the position -> Cell handle index, a live plane holds a copy of
+// every Cell's live flag, one byte per cell in the index's order (kDead,
+// kLive, or kNoCell where the Cell is missing, only after an out-of-memory
+// init).  The neighbourhood reads of phases 1 and 2 load these bytes: five
+// adjacent cells of a row are one pair of dword loads, and a 1024 x 1024
+// world's plane is 1 MB, so the rows around a wavefront's cells stay in its
+// XCD's L2 where four-byte index words did not.
+constexpr uint8_t kDead = 0, kLive = 1, kNoCell = 2;
 
 struct World {
-  const uint32_t* cells;  // global cell index -> Cell handle | kLiveBit if alive
+  const uint32_t* cells;  // global cell index -> Cell handle (kNull if missing)
+  const uint8_t* live;    // global cell index -> kDead / kLive / kNoCell
   const uint32_t* off;    // world -> first global cell index (num_worlds + 1 entries)
   const uint32_t* side;   // world -> side length
 };
 
-// Field f of the Cell at global index g; a scratch word when the Cell is
-// missing (only after an out-of-memory init, which the OOM flag reports).
-__device__ __forceinline__ uint32_t* cell_field(const DevHeap& h, const World& w, uint32_t g, uint32_t f) {
-  const uint32_t wd = w.cells[g];
-  return wd == kNull ? reinterpret_cast<uint32_t*>(h.ctrl + kCtlWords - 1)
-                     : field_ptr<uint32_t>(h, wd & ~kLiveBit, kCell, f);
-}
-
 // Sets the live state of the Cell at global index g (its field and the copy
-// in its index word); only the cell's own Alive or Candidate does this.
+// in the live plane); only the cell's own Alive or Candidate does this.
 __device__ __forceinline__ void set_live(const DevHeap& h, const World& w, uint32_t g, uint32_t live) {
-  uint32_t* ix = const_cast<uint32_t*>(w.cells) + g;
-  const uint32_t wd = *ix;
+  const uint32_t wd = w.cells[g];
   if (wd == kNull) return;
-  *field_ptr<uint32_t>(h, wd & ~kLiveBit, kCell, kCAlive) = live;
-  *ix = live ? (wd | kLiveBit) : (wd & ~kLiveBit);
-}
-
-// The eight torus neighbours of global cell g of world wid.
-template <class F>
-__device__ __forceinline__ void for_neighbours(const World& w, uint32_t wid, uint32_t g, F&& f) {
-  const uint32_t off = w.off[wid], side = w.side[wid];
-  const uint32_t local = g - off;
-  const uint32_t y = local / side, x = local - y * side;
-  const uint32_t xm = x == 0 ? side - 1 : x - 1, xp = x + 1 == side ? 0 : x + 1;
-  const uint32_t ym = y == 0 ? side - 1 : y - 1, yp = y + 1 == side ? 0 : y + 1;
-  const uint32_t rm = off + ym * side, r0 = off + y * side, rp = off + yp * side;
-  f(rm + xm); f(rm + x); f(rm + xp);
-  f(r0 + xm);            f(r0 + xp);
-  f(rp + xm); f(rp + x); f(rp + xp);
+  *field_ptr<uint32_t>(h, wd, kCell, kCAlive) = live;
+  const_cast<uint8_t*>(w.live)[g] = live ? kLive : kDead;
 }
 
 // Global index of neighbour d (0..7: the row above, left and right, the row
@@ -121,6 +102,43 @@ __device__ __forceinline__ uint32_t torus_add(uint32_t x, int dx, uint32_t side)
   return (uint32_t)v;
 }
 
+// The (2R + 1) x (2R + 1) neighbourhood of cell (x, y) of the world at `off`
+// with side `side`, from the live plane: bit (dy + R) * (2R + 1) + (dx + R)
+// of *alive is set for a live cell at offset (dx, dy), of *nocell for a
+// missing Cell; the centre is left out.  A row whose window does not wrap
+// around the torus is one aligned pair of dword loads shifted into place
+// (the plane is padded, so a read past the last cell stays in the buffer);
+// a row that wraps loads its cells one by one.
+template <int R>
+__device__ __forceinline__ void neighbourhood(const uint8_t* plane, uint32_t off, uint32_t side, uint32_t x,
+                                              uint32_t y, uint32_t* alive, uint32_t* nocell) {
+  constexpr int D = 2 * R + 1;
+  const bool inside = x >= (uint32_t)R && x + R < side;
+  uint32_t al = 0, nc = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const uint8_t* row = plane + off + (uint64_t)torus_add(y, i - R, side) * side;
+    uint64_t v = 0;
+    if (inside) {
+      const uintptr_t a = (uintptr_t)(row + x - R);
+      const uint32_t* a4 = reinterpret_cast<const uint32_t*>(a & ~(uintptr_t)3);
+      v = (((uint64_t)a4[1] << 32) | a4[0]) >> ((a & 3u) * 8u);
+    } else {
+#pragma unroll
+      for (int j = 0; j < D; ++j) v |= (uint64_t)row[torus_add(x, j - R, side)] << (8 * j);
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      if (i == R && j == R) continue;
+      const uint32_t b = (uint32_t)(v >> (8 * j)) & 0xFFu;
+      al |= (uint32_t)(b == kLive) << (i * D + j);
+      nc |= (uint32_t)(b == kNoCell) << (i * D + j);
+    }
+  }
+  *alive = al;
+  *nocell = nc;
+}
+
 struct AlivePrep {
   static constexpr uint32_t kKind = 30;
   using Args = World;
@@ -130,28 +148,14 @@ struct AlivePrep {
     const uint32_t off = w.off[wid], side = w.side[wid];
     const uint32_t local = g - off;
     const uint32_t y = local / side, x = local - y * side;
-    uint32_t row[5], col[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      row[i] = off + torus_add(y, i - 2, side) * side;
-      col[i] = torus_add(x, i - 2, side);
-    }
-    // Live states of the 24 surrounding cells: one load each, all independent.
-    uint32_t wd[25];
-#pragma unroll
-    for (uint32_t b = 0; b < 25; ++b) wd[b] = b == 12 ? kNull : w.cells[row[b / 5] + col[b % 5]];
-    uint32_t alive = 0, present = 0;
-#pragma unroll
-    for (uint32_t b = 0; b < 25; ++b) {
-      if (b == 12) continue;
-      present |= (uint32_t)(wd[b] != kNull) << b;  // missing only after an out-of-memory init
-      alive |= (uint32_t)live_of(wd[b]) << b;
-    }
+    // Live states of the 24 surrounding cells.
+    uint32_t alive, nocell;
+    neighbourhood<2>(w.live, off, side, x, y, &alive, &nocell);
     uint32_t claim = 0;
 #pragma unroll
     for (uint32_t d = 0; d < 8; ++d) {
       const uint32_t b = nb_bit(kDirX[d], kDirY[d]);
-      const bool dead = ((present & ~alive) >> b) & 1u;
+      const bool dead = (~(alive | nocell) >> b) & 1u;
       if (dead && !(alive & owner_mask(d))) claim |= 1u << d;
     }
     const uint32_t live = (uint32_t)__popc(alive & ring_mask());
@@ -174,9 +178,12 @@ struct CandPrep {
   static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& w) {
     const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
     const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
-    uint32_t live = 0;
-    for_neighbours(w, wid, g, [&](uint32_t n) { live += live_of(w.cells[n]) ? 1u : 0u; });
-    *field_ptr<uint32_t>(h, self, type, kAAction) = live == 3 ? 1u : 0u;
+    const uint32_t off = w.off[wid], side = w.side[wid];
+    const uint32_t local = g - off;
+    const uint32_t y = local / side, x = local - y * side;
+    uint32_t alive, nocell;
+    neighbourhood<1>(w.live, off, side, x, y, &alive, &nocell);
+    *field_ptr<uint32_t>(h, self, type, kAAction) = __popc(alive) == 3 ? 1u : 0u;
     return false;
   }
 };
@@ -228,7 +235,8 @@ __global__ void gol_init_kernel(DevHeap h, World w, uint32_t num_worlds, uint32_
   const uint32_t hc = dsoar_new(h, kCell);
   const uint32_t alive = grid[g] ? 1u : 0u;
   if (hc != kNull) *field_ptr<uint32_t>(h, hc, kCell, kCAlive) = alive;
-  const_cast<uint32_t*>(w.cells)[g] = hc == kNull ? kNull : (hc | (alive ? kLiveBit : 0u));
+  const_cast<uint32_t*>(w.cells)[g] = hc;
+  const_cast<uint8_t*>(w.live)[g] = hc == kNull ? kNoCell : (alive ? kLive : kDead);
   if (alive) {
     const uint32_t o = dsoar_new(h, kAlive);
     if (o != kNull) {
@@ -243,7 +251,7 @@ __global__ void gol_read_kernel(DevHeap h, World w, uint32_t off, uint32_t n, ui
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t wd = w.cells[off + i];
-  out[i] = wd == kNull ? 0xFF : (uint8_t)*field_ptr<uint32_t>(h, wd & ~kLiveBit, kCell, kCAlive);
+  out[i] = wd == kNull ? 0xFF : (uint8_t)*field_ptr<uint32_t>(h, wd, kCell, kCAlive);
 }
 
 // Records world slot's cell range in the world table.
@@ -260,7 +268,8 @@ __global__ void gol_admit_kernel(DevHeap h, World w, uint32_t slot, uint32_t off
   const uint32_t hc = dsoar_new(h, kCell);
   const uint32_t alive = grid[i] ? 1u : 0u;
   if (hc != kNull) *field_ptr<uint32_t>(h, hc, kCell, kCAlive) = alive;
-  const_cast<uint32_t*>(w.cells)[g] = hc == kNull ? kNull : (hc | (alive ? kLiveBit : 0u));
+  const_cast<uint32_t*>(w.cells)[g] = hc;
+  const_cast<uint8_t*>(w.live)[g] = hc == kNull ? kNoCell : (alive ? kLive : kDead);
   new_many(h, kAlive, alive, [&](uint32_t, uint32_t o) {
     if (o == kNull) return;
     *field_ptr<uint32_t>(h, o, kAlive, kACell) = g;
@@ -274,8 +283,9 @@ __global__ void gol_retire_cells_kernel(DevHeap h, World w, uint32_t off, uint32
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t* c = const_cast<uint32_t*>(w.cells) + off + i;
-  if (*c != kNull) dsoar_delete(h, *c & ~kLiveBit);
+  if (*c != kNull) dsoar_delete(h, *c);
   *c = kNull;
+  const_cast<uint8_t*>(w.live)[off + i] = kNoCell;
 }
 
 struct GolDeleteWorld {
@@ -287,7 +297,7 @@ struct GolDeleteWorld {
 };
 
 bool gol_heap_ok(const dsoar_heap* h) {
-  if (h->desc.num_types < 3 || h->desc.num_blocks >= (1u << 25)) return false;  // handles below kLiveBit
+  if (h->desc.num_types < 3) return false;
   const uint32_t want[3] = {1, 3, 3};
   for (uint32_t t = 0; t < 3; ++t) {
     const dsoar_type_layout& L = h->desc.types[t];
@@ -296,6 +306,21 @@ bool gol_heap_ok(const dsoar_heap* h) {
       if (L.field_bytes[f] != 4) return false;
   }
   return true;
+}
+
+// Device buffer of a world set: the world table (offsets and sides), the
+// cell index (4 bytes per cell) and the live plane (1 byte per cell, padded
+// so that a window load past the last cell stays inside).
+uint64_t table_head(uint32_t num_worlds) { return ((uint64_t)(2 * num_worlds + 1) * 4 + 255) / 256 * 256; }
+uint64_t index_bytes(uint64_t cells) { return (cells * 4 + 255) / 256 * 256; }
+uint64_t plane_bytes(uint64_t cells) { return (cells + 64 + 255) / 256 * 256; }
+
+void carve(World& w, uint8_t* dev_mem, uint32_t num_worlds, uint64_t cells) {
+  uint32_t* tab = (uint32_t*)dev_mem;
+  w.off = tab;
+  w.side = tab + num_worlds + 1;
+  w.cells = (const uint32_t*)(dev_mem + table_head(num_worlds));
+  w.live = dev_mem + table_head(num_worlds) + index_bytes(cells);
 }
 
 uint64_t gol_total_cells(uint32_t num_worlds, const uint32_t* sides) {
@@ -350,7 +375,7 @@ size_t dsoar_gol_bytes(uint32_t num_worlds, const uint32_t* sides) {
     if (sides[i] < 1 || sides[i] > 65535) return 0;
   const uint64_t total = gol_total_cells(num_worlds, sides);
   if (total >= (1ull << 32)) return 0;
-  return (size_t)(((uint64_t)(2 * num_worlds + 1) * 4 + 255) / 256 * 256 + total * 4);
+  return (size_t)(table_head(num_worlds) + index_bytes(total) + plane_bytes(total));
 }
 
 int dsoar_gol_create(dsoar_heap* heap, uint32_t num_worlds, const uint32_t* sides, void* dev_mem, size_t dev_bytes,
@@ -367,11 +392,8 @@ int dsoar_gol_create(dsoar_heap* heap, uint32_t num_worlds, const uint32_t* side
   g->heap = heap;
   g->num_worlds = num_worlds;
   g->total = (uint32_t)gol_total_cells(num_worlds, sides);
+  carve(g->w, (uint8_t*)dev_mem, num_worlds, g->total);
   uint32_t* tab = (uint32_t*)dev_mem;
-  const uint64_t head = ((uint64_t)(2 * num_worlds + 1) * 4 + 255) / 256 * 256;
-  g->w.off = tab;
-  g->w.side = tab + num_worlds + 1;
-  g->w.cells = (const uint32_t*)((uint8_t*)dev_mem + head);
   uint32_t* host = (uint32_t*)malloc((size_t)(2 * num_worlds + 1) * 4);
   if (!host) {
     delete g;
@@ -442,7 +464,7 @@ uint32_t dsoar_gol_total_cells(const dsoar_gol* g) { return g ? g->total : 0; }
 
 size_t dsoar_golpool_bytes(uint32_t max_worlds, uint32_t arena_cells) {
   if (max_worlds == 0 || max_worlds > (1u << 20) || arena_cells == 0) return 0;
-  return (size_t)(((uint64_t)(2 * max_worlds + 1) * 4 + 255) / 256 * 256 + (uint64_t)arena_cells * 4);
+  return (size_t)(table_head(max_worlds) + index_bytes(arena_cells) + plane_bytes(arena_cells));
 }
 
 int dsoar_golpool_create(dsoar_heap* heap, uint32_t max_worlds, uint32_t arena_cells, void* dev_mem,
@@ -467,11 +489,7 @@ int dsoar_golpool_create(dsoar_heap* heap, uint32_t max_worlds, uint32_t arena_c
     dsoar_gol_destroy(g);
     return DSOAR_ERR_INVALID_ARG;
   }
-  uint32_t* tab = (uint32_t*)dev_mem;
-  const uint64_t head = ((uint64_t)(2 * max_worlds + 1) * 4 + 255) / 256 * 256;
-  g->w.off = tab;
-  g->w.side = tab + max_worlds + 1;
-  g->w.cells = (const uint32_t*)((uint8_t*)dev_mem + head);
+  carve(g->w, (uint8_t*)dev_mem, max_worlds, arena_cells);
   *out = g;
   return DSOAR_OK;
 }

@@ -16,24 +16,19 @@ constexpr uint64_t kAlign = 256;
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
-// Words of all levels of a bitmap of nbits bits (levels bottom-up, each
-// ceil(nbits / 64^(l+1)) words), padded to 256 bytes.
-uint32_t bitmap_words(uint32_t nbits) {
-  uint32_t words = 0;
-  const uint32_t L = num_levels(nbits);
-  for (uint32_t k = 0; k < L; ++k) words += ((nbits - 1) >> (6 * k + 6)) + 1;
-  return (uint32_t)align_up(words, 32);
+// 32-bit units of all levels of a bitmap of nbits bits with containers of
+// 2^lg bits, padded to 256 bytes.
+uint32_t bitmap_units(uint32_t nbits, uint32_t lg) {
+  return (uint32_t)align_up(level_offset(nbits, lg, num_levels(nbits, lg)), 64);
 }
 
-uint32_t level_word_offset_host(uint32_t nbits, uint32_t l) {
-  uint32_t off = 0;
-  for (uint32_t k = 0; k < l; ++k) off += ((nbits - 1) >> (6 * k + 6)) + 1;
-  return off;
-}
+uint32_t width_lg(uint32_t width) { return width == 32 ? 5u : 6u; }
 
 bool desc_valid(const dsoar_heap_desc* d) {
-  if (!d || d->reserved != 0) return false;
-  if (d->num_blocks < 1 || d->num_blocks > (1u << 26)) return false;
+  if (!d || (d->bitmap_width != 0 && d->bitmap_width != 32 && d->bitmap_width != 64)) return false;
+  // Handles are block << 6 | slot in 32 bits and all ones is NULL: in a heap
+  // of 2^26 blocks slot 63 of the last block would have the NULL handle.
+  if (d->num_blocks < 1 || d->num_blocks >= (1u << 26)) return false;
   if (d->block_capacity != 0 && d->block_capacity != 32 && d->block_capacity != 64) return false;
   if (d->num_types < 1 || d->num_types > DSOAR_MAX_TYPES) return false;
   for (uint32_t t = 0; t < d->num_types; ++t) {
@@ -41,6 +36,14 @@ bool desc_valid(const dsoar_heap_desc* d) {
     if (L.num_fields < 1 || L.num_fields > DSOAR_MAX_FIELDS) return false;
     for (uint32_t f = 0; f < L.num_fields; ++f)
       if (L.field_bytes[f] != 4 && L.field_bytes[f] != 8) return false;
+    // A subclass names an earlier type and begins with its fields.
+    if (L.parent != 0) {
+      if (L.parent > t) return false;
+      const dsoar_type_layout& P = d->types[L.parent - 1];
+      if (L.num_fields < P.num_fields) return false;
+      for (uint32_t f = 0; f < P.num_fields; ++f)
+        if (L.field_bytes[f] != P.field_bytes[f]) return false;
+    }
   }
   return true;
 }
@@ -117,12 +120,14 @@ Plan make_plan(const dsoar_heap_desc* d) {
   p.pins_off = off;
   off = align_up(off + M * 4, kAlign);
   p.L.bitmaps_offset = off;
-  const uint32_t bm_words = bitmap_words((uint32_t)M);
-  p.L.bitmap_stride = (uint64_t)bm_words * 8;
-  p.L.num_levels = num_levels((uint32_t)M);
+  const uint32_t lg = width_lg(d->bitmap_width);
+  p.L.bitmap_width = 1u << lg;
+  p.L.bitmap_stride = (uint64_t)bitmap_units((uint32_t)M, lg) * 4;
+  p.L.num_levels = num_levels((uint32_t)M, lg);
   for (uint32_t l = 0; l < p.L.num_levels && l < 8; ++l) {
-    p.L.level_word_offset[l] = level_word_offset_host((uint32_t)M, l);
-    p.L.level_words[l] = (uint32_t)(((M - 1) >> (6 * l + 6)) + 1);
+    // In containers of the bitmap's width (levels start at even units).
+    p.L.level_word_offset[l] = level_offset((uint32_t)M, lg, l) >> (lg - 5);
+    p.L.level_words[l] = level_bits((uint32_t)M, lg, l + 1);
   }
   off = align_up(off + (1 + 2 * (uint64_t)d->num_types) * p.L.bitmap_stride, kAlign);
   p.ctrl_off = off;
@@ -147,34 +152,29 @@ Plan make_plan(const dsoar_heap_desc* d) {
 
 // ------------------------------------------------------------------ kernels
 
-// Bitmap initialisation: level l word i covers bits [64i, 64i+64) of level l;
-// when all_set, exactly the bits below the level's size are set (so every
-// level is the OR of the level below).
-__device__ inline uint64_t full_word(uint32_t nbits_level, uint32_t i) {
-  const uint32_t lo = i * 64;
-  if (lo >= nbits_level) return 0;
-  const uint32_t n = nbits_level - lo;
-  return n >= 64 ? ~0ull : ((1ull << n) - 1);
+// Bitmap initialisation, one 32-bit unit at a time: unit j of level l holds
+// the level's bits [32j, 32j + 32) at either container width; when all_set,
+// exactly the bits below the level's size are set (so every level is the OR
+// of the level below).
+__device__ inline uint32_t init_unit(uint32_t nbits, uint32_t lg, uint32_t u, bool all_set) {
+  if (!all_set) return 0;
+  const uint32_t L = num_levels(nbits, lg);
+  uint32_t off = 0;
+  for (uint32_t l = 0; l < L; ++l) {
+    const uint32_t n = level_bits(nbits, lg, l), units = level_units(n);
+    if (u < off + units) {
+      const uint32_t lo = (u - off) * 32;
+      if (lo >= n) return 0;
+      return n - lo >= 32 ? 0xFFFFFFFFu : ((1u << (n - lo)) - 1u);
+    }
+    off += units;
+  }
+  return 0;
 }
 
-__global__ void init_bitmap_kernel(uint64_t* bm, uint32_t nbits, uint32_t total_words, int all_set) {
-  const uint32_t L = num_levels(nbits);
-  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < total_words; w += gridDim.x * blockDim.x) {
-    uint64_t v = 0;
-    if (all_set) {
-      uint32_t off = 0, n = nbits;
-      for (uint32_t l = 0; l < L; ++l) {
-        const uint32_t words = ((nbits - 1) >> (6 * l + 6)) + 1;
-        if (w >= off && w < off + words) {
-          v = full_word(n, w - off);
-          break;
-        }
-        off += words;
-        n = words;
-      }
-    }
-    meta_store(bm + w, v);
-  }
+__global__ void init_bitmap_kernel(uint32_t* units, uint32_t nbits, uint32_t lg, uint32_t total_units, int all_set) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < total_units; u += gridDim.x * blockDim.x)
+    __hip_atomic_store(units + u, init_unit(nbits, lg, u, all_set != 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void init_heap_kernel(DevHeap h, uint64_t ctrl_words) {
@@ -187,25 +187,11 @@ __global__ void init_heap_kernel(DevHeap h, uint64_t ctrl_words) {
   }
   for (uint64_t w = tid; w < ctrl_words; w += nth) meta_store(h.ctrl + w, 0ull);
   // Bitmap 0 (free) all set, the others clear.
-  const uint32_t L = h.nlevels;
-  const uint64_t total = (uint64_t)(1 + 2 * h.num_types) * h.bm_words;
+  const uint64_t total = (uint64_t)(1 + 2 * h.num_types) * h.bm_units;
   for (uint64_t w = tid; w < total; w += nth) {
-    const uint32_t k = (uint32_t)(w / h.bm_words);
-    const uint32_t i = (uint32_t)(w % h.bm_words);
-    uint64_t v = 0;
-    if (k == 0) {
-      uint32_t off = 0, n = h.num_blocks;
-      for (uint32_t l = 0; l < L; ++l) {
-        const uint32_t words = ((h.num_blocks - 1) >> (6 * l + 6)) + 1;
-        if (i >= off && i < off + words) {
-          v = full_word(n, i - off);
-          break;
-        }
-        off += words;
-        n = words;
-      }
-    }
-    meta_store(h.bitmaps + w, v);
+    const uint32_t k = (uint32_t)(w / h.bm_units);
+    const uint32_t u = (uint32_t)(w % h.bm_units);
+    meta_store(h.bitmaps + w, init_unit(h.num_blocks, h.bm_lg, u, k == 0));
   }
 }
 
@@ -220,17 +206,6 @@ __global__ void init_scan_kernel(ScanState* st, uint64_t* flags, uint32_t num_ti
   for (uint32_t i = tid; i < num_tiles; i += gridDim.x * blockDim.x) flags[i] = 0;
 }
 
-// Clear / set several bits of one level-0 word with one atomic, with the
-// nested update the paper's single-bit operations would make (Alg. 2).
-__device__ inline void clear_bits0(const Bitmap& b, uint32_t word, uint64_t m) {
-  const uint64_t prev = lead_and(b.word(0, word), ~m);
-  if ((prev & m) && (prev & ~m) == 0 && b.nlevels > 1) bm_clear_from(b, 1, word);
-}
-__device__ inline void set_bits0(const Bitmap& b, uint32_t word, uint64_t m) {
-  const uint64_t prev = lead_or(b.word(0, word), m);
-  if (prev == 0 && (m & ~prev) && b.nlevels > 1) bm_set_from(b, 1, word);
-}
-
 // Quiescent reclamation of the blocks in `rc` (a wave's lanes, word `word`),
 // all of type t and empty: they leave allocated[t] and active[t] and become
 // free again (the block-state figure's transition back to free).  The three
@@ -242,20 +217,19 @@ __device__ inline void reclaim_word(const DevHeap& h, uint32_t t, uint32_t word,
     meta_store(tw, tw_freed(meta_load(tw)));
   }
   const Bitmap al = allocated_bm(h, t), ac = active_bm(h, t), fr = free_bm(h);
+  lead_add(shard(h) + kCntBlocksReturned, (uint64_t)__popcll(rc));
   uint64_t pa = 0, pc = 0, pf = 0;
   if (is_first_active()) {
-    pa = __hip_atomic_fetch_and(al.word(0, word), ~rc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    pc = __hip_atomic_fetch_and(ac.word(0, word), ~rc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    pf = __hip_atomic_fetch_or(fr.word(0, word), rc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pa = __hip_atomic_fetch_and(al.group(word), ~rc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pc = __hip_atomic_fetch_and(ac.group(word), ~rc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pf = __hip_atomic_fetch_or(fr.group(word), rc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   pa = bcast64(pa);
   pc = bcast64(pc);
   pf = bcast64(pf);
-  if (al.nlevels > 1) {
-    if ((pa & rc) && (pa & ~rc) == 0) bm_clear_from(al, 1, word);
-    if ((pc & rc) && (pc & ~rc) == 0) bm_clear_from(ac, 1, word);
-    if (pf == 0) bm_set_from(fr, 1, word);
-  }
+  group_clear_nested(al, word, pa, rc);
+  group_clear_nested(ac, word, pc, rc);
+  group_set_nested(fr, word, pf, rc & ~pf);
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -289,7 +263,7 @@ __global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeap h, u
   const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
   const uint32_t W0 = (h.num_blocks + 63) >> 6;
   const uint32_t word0 = (tile * kEnumWaves + wave) * WPW;
-  const uint64_t* alloc0 = allocated_bm(h, type).words;  // level 0 comes first
+  const uint64_t* alloc0 = allocated_bm(h, type).group(0);  // level 0 as 64-bit groups
   uint64_t w[WPW], live[WPW], snap[WPW];
 #pragma unroll
   for (uint32_t j = 0; j < WPW; ++j) w[j] = word0 + j < W0 ? load_u64(alloc0 + word0 + j) : 0ull;
@@ -373,6 +347,7 @@ __global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeap h, u
     if (empty[j]) reclaim_word(h, type, word0 + j, empty[j]);
   if (tile == out.num_tiles - 1 && threadIdx.x == 0) {
     __hip_atomic_store(&out.st->count, s_prefix + tile_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (out.count_out) *out.count_out = s_prefix + tile_total;
     __hip_atomic_store(&out.st->tile_counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&out.st->epoch, epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -412,7 +387,7 @@ __global__ void stats_kernel(DevHeap h, StatsOut* out, int check) {
     const uint64_t ob = in ? meta_load(h.obj_bitmap + b) : 0;
     const uint64_t cm = t < h.num_types ? h.cap_mask[t] : ~0ull;  // this block's type's slots
     const uint64_t obc = ob & cm;
-    const bool fr = (load_u64(free_bm(h).word(0, word)) >> lane) & 1ull;
+    const bool fr = (load_u64(free_bm(h).group(word)) >> lane) & 1ull;
     uint32_t v[DSOAR_INV_COUNT] = {0};
     if (in) {
       v[DSOAR_INV_BITMAP_RANGE] += (ob & ~cm) != 0;
@@ -420,8 +395,8 @@ __global__ void stats_kernel(DevHeap h, StatsOut* out, int check) {
       if (t != kTypeNone && t >= h.num_types) v[DSOAR_INV_FREE] += 1;
     }
     for (uint32_t u = 0; u < h.num_types; ++u) {
-      const bool al = (load_u64(allocated_bm(h, u).word(0, word)) >> lane) & 1ull;
-      const bool ac = (load_u64(active_bm(h, u).word(0, word)) >> lane) & 1ull;
+      const bool al = (load_u64(allocated_bm(h, u).group(word)) >> lane) & 1ull;
+      const bool ac = (load_u64(active_bm(h, u).group(word)) >> lane) & 1ull;
       if (in) {
         v[DSOAR_INV_ALLOCATED] += al != (t == u && obc != 0);
         v[DSOAR_INV_ACTIVE] += ac != (al && obc != cm);
@@ -451,25 +426,30 @@ __global__ void stats_kernel(DevHeap h, StatsOut* out, int check) {
       }
   }
   if (!check) return;
-  // Container consistency (Sec. 3): bit i of level l+1 == (word i of level l != 0),
-  // and no bit set at or beyond a level's size.
+  // Container consistency (Sec. 3): bit i of level l+1 == (container i of
+  // level l != 0), and no bit set at or beyond a level's size.
   const uint32_t nbm = 1 + 2 * h.num_types;
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
+  const uint32_t lg = h.bm_lg, cw = 1u << lg;
   for (uint32_t k = 0; k < nbm; ++k) {
     const Bitmap bm = heap_bitmap(h, k);
-    uint32_t n = h.num_blocks;
     for (uint32_t l = 0; l < bm.nlevels; ++l) {
-      const uint32_t words = ((n - 1) >> 6) + 1;
-      for (uint32_t i = tid; i < words; i += nth) {
-        const uint64_t w = meta_load(bm.word(l, i));
-        uint32_t bad = (w & ~full_word(n, i)) != 0;
+      const uint32_t n = level_bits(h.num_blocks, lg, l);
+      const uint32_t containers = level_bits(h.num_blocks, lg, l + 1);
+      const uint32_t* lv = bm.level(l);
+      for (uint32_t i = tid; i < containers; i += nth) {
+        uint64_t w = meta_load(lv + (i << (lg - 5)));
+        if (lg == 6) w |= (uint64_t)meta_load(lv + 2 * i + 1) << 32;
+        const uint32_t lo = i * cw;
+        const uint64_t valid = n - lo >= cw ? (lg == 6 ? ~0ull : 0xFFFFFFFFull) : ((1ull << (n - lo)) - 1);
+        uint32_t bad = (w & ~valid) != 0;
         if (l + 1 < bm.nlevels) {
-          const bool up = (meta_load(bm.word(l + 1, i >> 6)) >> (i & 63)) & 1ull;
-          bad += up != (w != 0);
+          const uint32_t* up = bm.level(l + 1);
+          const bool set = (meta_load(up + ((i >> lg) << (lg - 5)) + ((i & (cw - 1)) >> 5)) >> (i & 31)) & 1u;
+          bad += set != (w != 0);
         }
         if (bad) atomicAdd(&out->viol[DSOAR_INV_CONTAINER], bad);
       }
-      n = words;
     }
   }
 }
@@ -480,11 +460,15 @@ __global__ void zero_kernel(uint32_t* p, uint32_t n) {
 
 // ---------------------------------------------------- stand-alone bitmap ops
 // One wavefront per op, all lanes of the wavefront running it together.
-__global__ void bitmap_ops_kernel(uint64_t* words, uint32_t nbits, const uint32_t* ops, uint32_t n,
-                                  const uint32_t* starts, int32_t* results, uint64_t* retry_flag) {
+struct LevelOffsets {
+  uint32_t off[kMaxLevels];
+};
+
+__global__ void bitmap_ops_kernel(uint32_t* units, uint32_t nbits, uint32_t lg, LevelOffsets lv, const uint32_t* ops,
+                                  uint32_t n, const uint32_t* starts, int32_t* results, uint64_t* retry_flag) {
   const uint32_t op = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (op >= n) return;
-  const Bitmap b{words, nbits, num_levels(nbits), retry_flag};
+  const Bitmap b{units, nbits, num_levels(nbits, lg), lg, retry_flag, lv.off};
   const uint32_t kind = ops[2 * op], pos = ops[2 * op + 1];
   const uint32_t start = starts ? starts[op] : 0u;
   int32_t r = 0;
@@ -602,16 +586,21 @@ struct FieldGather {
 
 // ------------------------------------------------------ shared host helpers
 
-int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s) {
+int launch_enumerate_into(dsoar_heap* h, uint32_t type, const EnumOut& eo, hipStream_t s) {
   if (h->enum_wpw == kEnumWideWords)
     launch_timed(h, kKindEnumerate, enumerate_kernel<kEnumWideWords>, dim3(h->num_tiles), dim3(kEnumWaves * 64),
-                 s, h->dev, type, h->enum_out[type]);
+                 s, h->dev, type, eo);
   else
     launch_timed(h, kKindEnumerate, enumerate_kernel<1>, dim3(h->num_tiles), dim3(kEnumWaves * 64), s, h->dev,
-                 type, h->enum_out[type]);
+                 type, eo);
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }
+
+int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s) {
+  return launch_enumerate_into(h, type, h->enum_out[type], s);
+}
+
 
 int read_count(dsoar_heap* h, uint32_t type, hipStream_t s, uint32_t* count) {
   DSOAR_HIP(h, hipMemcpyAsync(count, &h->enum_out[type].st->count, 4, hipMemcpyDeviceToHost, s));
@@ -636,7 +625,7 @@ uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t cap = 65535u * 16u) {
 
 int init_device_state(dsoar_heap* h, hipStream_t s) {
   const uint64_t ctrl_words = kCtlWords + kShards * kShardStride;
-  const uint64_t work = std::max<uint64_t>(h->desc.num_blocks, (1 + 2 * h->desc.num_types) * (uint64_t)h->dev.bm_words);
+  const uint64_t work = std::max<uint64_t>(h->desc.num_blocks, (1 + 2 * h->desc.num_types) * (uint64_t)h->dev.bm_units);
   hipLaunchKernelGGL(init_heap_kernel, dim3(grid_for(work, 256, 8192)), dim3(256), 0, s, h->dev, ctrl_words);
   DSOAR_LAUNCHED(h);
   for (uint32_t t = 0; t < h->desc.num_types; ++t) {
@@ -683,6 +672,8 @@ int collect_stats(dsoar_heap* h, dsoar_stats* out, uint32_t* viol, int check, hi
     st.find_fails += c[kCntFindFails];
     st.method_atomics += c[kCntMethodAtomics];
     st.online_releases += c[kCntReleases];
+    st.blocks_taken += c[kCntBlocksTaken];
+    st.blocks_returned += c[kCntBlocksReturned];
   }
   for (uint32_t t = 0; t < kMaxTypes; ++t) {
     st.live_objects[t] = so.live[t];
@@ -700,6 +691,8 @@ int collect_stats(dsoar_heap* h, dsoar_stats* out, uint32_t* viol, int check, hi
     for (uint32_t k = 0; k < DSOAR_INV_COUNT; ++k) viol[k] = so.viol[k];
     for (uint32_t t = 0; t < h->desc.num_types; ++t)
       if (st.live_objects[t] != st.allocs[t] - st.frees[t]) viol[DSOAR_INV_LIVE_COUNT] += 1;
+    if ((uint64_t)st.free_blocks + st.blocks_taken != (uint64_t)st.num_blocks + st.blocks_returned)
+      viol[DSOAR_INV_FREE_COUNT] += 1;
   }
   return sticky_status(st);
 }
@@ -734,7 +727,7 @@ int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_byt
   d.obj_bitmap = (uint64_t*)(h->base + p.L.obj_bitmap_offset);
   d.block_type = (uint32_t*)(h->base + p.L.block_type_offset);
   d.pins = (uint32_t*)(h->base + p.pins_off);
-  d.bitmaps = (uint64_t*)(h->base + p.L.bitmaps_offset);
+  d.bitmaps = (uint32_t*)(h->base + p.L.bitmaps_offset);
   d.ctrl = (uint64_t*)(h->base + p.ctrl_off);
   d.block_stride = p.L.block_stride;
   for (uint32_t t = 0; t < kMaxTypes; ++t) {
@@ -745,11 +738,18 @@ int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_byt
   d.num_blocks = desc->num_blocks;
   d.num_types = desc->num_types;
   d.nlevels = p.L.num_levels;
-  d.bm_words = (uint32_t)(p.L.bitmap_stride / 8);
+  d.bm_lg = width_lg(desc->bitmap_width);
+  d.bm_units = (uint32_t)(p.L.bitmap_stride / 4);
+  for (uint32_t l = 0; l < kMaxLevels; ++l) d.bm_off[l] = level_offset(d.num_blocks, d.bm_lg, l);
+  d.search_start = kStartHashed;
   for (uint32_t t = 0; t < desc->num_types; ++t)
     for (uint32_t f = 0; f < desc->types[t].num_fields; ++f) {
       d.field_loc[t][f] = p.L.field_offset[t][f] | ((desc->types[t].field_bytes[f] == 8 ? 3u : 2u) << 24);
     }
+  // Inheritance (Sec. 1.2): each type's own bit and those of every type
+  // whose chain of parents reaches it (parents are declared earlier).
+  for (uint32_t u = 0; u < desc->num_types; ++u)
+    for (uint32_t a = u + 1; a != 0; a = desc->types[a - 1].parent) h->subtypes[a - 1] |= 1u << u;
   h->stats_dev = (StatsOut*)(h->base + p.stats_off);
   for (uint32_t t = 0; t < desc->num_types; ++t) {
     EnumOut& e = h->enum_out[t];
@@ -758,6 +758,7 @@ int dsoar_heap_create(const dsoar_heap_desc* desc, void* dev_mem, size_t dev_byt
     e.st = (ScanState*)(h->base + p.scan_off[t]);
     e.flags = (uint64_t*)(h->base + p.scan_off[t] + sizeof(ScanState));
     e.num_tiles = p.num_tiles;
+    e.count_out = nullptr;
   }
   int dev = 0;
   hipDeviceProp_t prop;
@@ -888,6 +889,16 @@ int dsoar_heap_set_type_policy(dsoar_heap* h, uint32_t type, uint32_t policy) {
   return DSOAR_OK;
 }
 
+int dsoar_heap_set_search(dsoar_heap* h, uint32_t policy) {
+  if (!heap_ok(h) || policy > DSOAR_SEARCH_XCD) return DSOAR_ERR_INVALID_ARG;
+  static_assert(DSOAR_SEARCH_HASHED == kStartHashed && DSOAR_SEARCH_LOWEST == kStartLowest &&
+                    DSOAR_SEARCH_XCD == kStartXcd,
+                "search policy numbering");
+  h->dev.search_start = policy;
+  h->config_epoch++;
+  return DSOAR_OK;
+}
+
 int dsoar_heap_set_reclaim(dsoar_heap* h, int online) {
   if (!heap_ok(h)) return DSOAR_ERR_INVALID_ARG;
   h->dev.online_reclaim = online ? 1u : 0u;
@@ -938,7 +949,7 @@ int dsoar_parallel_do(dsoar_heap* h, uint32_t type, uint32_t method, const void*
       if (!args || args_bytes != sizeof(dsoar_visit_args)) return DSOAR_ERR_INVALID_ARG;
       const dsoar_visit_args* a = (const dsoar_visit_args*)args;
       if (!a->counts_dev) return DSOAR_ERR_INVALID_ARG;
-      return launch_doall<VisitCount>(h, type, VisitCount::Args{a->counts_dev}, flags, s);
+      return launch_doall_tree<VisitCount>(h, type, VisitCount::Args{a->counts_dev}, flags, s);
     }
     case DSOAR_METHOD_DELETE_IF_MOD: {
       if (!args || args_bytes != sizeof(dsoar_mod_args)) return DSOAR_ERR_INVALID_ARG;
@@ -946,7 +957,8 @@ int dsoar_parallel_do(dsoar_heap* h, uint32_t type, uint32_t method, const void*
       if (a->field >= h->desc.types[type].num_fields || h->desc.types[type].field_bytes[a->field] != 4 ||
           a->modulus <= 0)
         return DSOAR_ERR_INVALID_ARG;
-      return launch_doall<DeleteIfMod>(h, type, DeleteIfMod::Args{a->field, a->modulus, a->residue}, flags, s);
+      return launch_doall_tree<DeleteIfMod>(h, type, DeleteIfMod::Args{a->field, a->modulus, a->residue}, flags,
+                                            s);
     }
     case DSOAR_METHOD_FIELD_GATHER: {
       if (!args || args_bytes != sizeof(dsoar_gather_args)) return DSOAR_ERR_INVALID_ARG;
@@ -957,7 +969,7 @@ int dsoar_parallel_do(dsoar_heap* h, uint32_t type, uint32_t method, const void*
         return DSOAR_ERR_INVALID_ARG;
       FieldGather::Args g{a->key_field, a->field, a->num_keys, L.field_bytes[a->field] == 8 ? 1u : 0u,
                           (uint8_t*)a->out_dev, a->present_dev};
-      return launch_doall<FieldGather>(h, type, g, flags, s);
+      return launch_doall_tree<FieldGather>(h, type, g, flags, s);
     }
     case DSOAR_METHOD_MICRO_UPDATE:
     case DSOAR_METHOD_MICRO_CULL:
@@ -1049,31 +1061,37 @@ int dsoar_abi_version(void) { return DSOAR_ABI_VERSION; }
 
 int dsoar_last_hip_error(const dsoar_heap* h) { return h ? (int)h->last_hip : -1; }
 
-size_t dsoar_bitmap_bytes(uint32_t nbits) {
-  if (nbits == 0 || nbits > (1u << 30)) return 0;
-  return (size_t)bitmap_words(nbits) * 8 + 256;  // + a retry-flag word
+size_t dsoar_bitmap_bytes(uint32_t nbits, uint32_t width) {
+  if (nbits == 0 || nbits > (1u << 30) || (width != 32 && width != 64)) return 0;
+  return (size_t)bitmap_units(nbits, width_lg(width)) * 4 + 256;  // + a retry-flag line
 }
 
-int dsoar_bitmap_init(void* bm_dev, uint32_t nbits, int all_set, void* stream) {
-  if (!bm_dev || nbits == 0 || nbits > (1u << 30) || ((uintptr_t)bm_dev & 7u)) return DSOAR_ERR_INVALID_ARG;
-  const uint32_t words = bitmap_words(nbits) + 32;
-  hipLaunchKernelGGL(init_bitmap_kernel, dim3(grid_for(words, 256, 8192)), dim3(256), 0, (hipStream_t)stream,
-                     (uint64_t*)bm_dev, nbits, words, all_set);
-  // The padding and flag words after the levels are cleared by the same kernel
-  // (full_word is 0 past the last level).
+int dsoar_bitmap_init(void* bm_dev, uint32_t nbits, uint32_t width, int all_set, void* stream) {
+  if (!bm_dev || nbits == 0 || nbits > (1u << 30) || (width != 32 && width != 64) || ((uintptr_t)bm_dev & 7u))
+    return DSOAR_ERR_INVALID_ARG;
+  const uint32_t lg = width_lg(width);
+  const uint32_t units = bitmap_units(nbits, lg) + 64;
+  // The padding and the flag line after the levels are cleared by the same
+  // kernel (init_unit is 0 past the last level).
+  hipLaunchKernelGGL(init_bitmap_kernel, dim3(grid_for(units, 256, 8192)), dim3(256), 0, (hipStream_t)stream,
+                     (uint32_t*)bm_dev, nbits, lg, units, all_set);
   if (hipGetLastError() != hipSuccess) return DSOAR_ERR_HIP;
   return DSOAR_OK;
 }
 
-int dsoar_bitmap_run(void* bm_dev, uint32_t nbits, const uint32_t* ops_dev, uint32_t n, const uint32_t* start_dev,
-                     int32_t* results_dev, void* stream) {
-  if (!bm_dev || nbits == 0 || nbits > (1u << 30) || (n && (!ops_dev || !results_dev)))
+int dsoar_bitmap_run(void* bm_dev, uint32_t nbits, uint32_t width, const uint32_t* ops_dev, uint32_t n,
+                     const uint32_t* start_dev, int32_t* results_dev, void* stream) {
+  if (!bm_dev || nbits == 0 || nbits > (1u << 30) || (width != 32 && width != 64) ||
+      (n && (!ops_dev || !results_dev)))
     return DSOAR_ERR_INVALID_ARG;
   if (n == 0) return DSOAR_OK;
-  uint64_t* words = (uint64_t*)bm_dev;
-  uint64_t* flag = words + bitmap_words(nbits);
+  const uint32_t lg = width_lg(width);
+  uint32_t* units = (uint32_t*)bm_dev;
+  uint64_t* flag = reinterpret_cast<uint64_t*>(units + bitmap_units(nbits, lg));
+  LevelOffsets lv;
+  for (uint32_t l = 0; l < kMaxLevels; ++l) lv.off[l] = level_offset(nbits, lg, l);
   hipLaunchKernelGGL(bitmap_ops_kernel, dim3(grid_for((uint64_t)n * 64, 256, 1u << 30)), dim3(256), 0,
-                     (hipStream_t)stream, words, nbits, ops_dev, n, start_dev, results_dev, flag);
+                     (hipStream_t)stream, units, nbits, lg, lv, ops_dev, n, start_dev, results_dev, flag);
   if (hipGetLastError() != hipSuccess) return DSOAR_ERR_HIP;
   return DSOAR_OK;
 }

@@ -36,6 +36,7 @@ struct EnumOut {
   ScanState* st;
   uint64_t* flags;      // num_tiles look-back words
   uint32_t num_tiles;
+  uint32_t* count_out;  // where the count also goes (nullptr: only st->count)
 };
 
 struct StatsOut {
@@ -64,6 +65,7 @@ struct dsoar_heap {
   uint32_t doall_wg_threads;   // workgroup size of do-all launches
   uint32_t doall_wgs_per_cu;   // persistent grid = num_cus * this
   uint32_t config_epoch;       // bumped when launch shape or policy change
+  uint32_t subtypes[dsoar::kMaxTypes];  // bit u of [t]: type u is t or inherits from t
   hipError_t last_hip;
   // Optional per-launch timing with HIP events on the launch stream.
   int timing;
@@ -481,6 +483,31 @@ int launch_doall(dsoar_heap* h, uint32_t type, const typename Method::Args& args
   launch_timed(h, Method::kKind, doall_kernel<Method>, dim3(grid), dim3(threads), s, h->dev, type,
                (const uint32_t*)eo.R, (const uint64_t*)eo.S, (const uint32_t*)&eo.st->count, args);
   DSOAR_LAUNCHED(h);
+  return DSOAR_OK;
+}
+
+// The do-all of Method over `type` and every type that inherits from it
+// (Sec. 1.2): the method reads the inherited fields by the parent's field
+// indices, which each subclass lays out in its own blocks.  Every type's
+// list is enumerated before any method runs, so the do-all visits exactly
+// the objects live when it starts; then one launch per type.
+template <class Method>
+int launch_doall_tree(dsoar_heap* h, uint32_t type, const typename Method::Args& args, uint32_t flags,
+                      hipStream_t s) {
+  if (type >= h->desc.num_types) return DSOAR_ERR_INVALID_ARG;
+  const uint32_t mask = h->subtypes[type];
+  if (mask == (1u << type)) return launch_doall<Method>(h, type, args, flags, s);
+  if (!(flags & DSOAR_DO_REUSE_ENUM))
+    for (uint32_t u = 0; u < h->desc.num_types; ++u)
+      if ((mask >> u) & 1u) {
+        const int rc = launch_enumerate(h, u, s);
+        if (rc) return rc;
+      }
+  for (uint32_t u = 0; u < h->desc.num_types; ++u)
+    if ((mask >> u) & 1u) {
+      const int rc = launch_doall<Method>(h, u, args, flags | DSOAR_DO_REUSE_ENUM, s);
+      if (rc) return rc;
+    }
   return DSOAR_OK;
 }
 

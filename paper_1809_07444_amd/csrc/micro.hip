@@ -82,8 +82,8 @@ int launch_create(dsoar_heap* h, uint32_t type, uint32_t n, uint32_t id_mul, con
 
 int micro_doall(dsoar_heap* h, uint32_t type, uint32_t method, uint32_t flags, hipStream_t s) {
   if (!micro_type_ok(h, type)) return DSOAR_ERR_INVALID_ARG;
-  if (method == DSOAR_METHOD_MICRO_UPDATE) return launch_doall<MicroUpdate>(h, type, {0}, flags, s);
-  return launch_doall<MicroCull>(h, type, {0}, flags, s);
+  if (method == DSOAR_METHOD_MICRO_UPDATE) return launch_doall_tree<MicroUpdate>(h, type, {0}, flags, s);
+  return launch_doall_tree<MicroCull>(h, type, {0}, flags, s);
 }
 
 }  // namespace dsoar

@@ -62,7 +62,6 @@ __device__ __forceinline__ int32_t uniform_int(uint64_t h, int32_t lo, int32_t h
 constexpr int32_t kOccupied = 0x80;
 constexpr int32_t kMaxSugar = 0x7F;
 __device__ __forceinline__ int32_t sugar_of(int32_t w) { return w & kMaxSugar; }
-__device__ __forceinline__ int32_t clamp_sugar(int32_t v) { return v < 0 ? 0 : (v > kMaxSugar ? kMaxSugar : v); }
 
 struct Grid {
   uint8_t* sugar;     // sugar | kOccupied when an agent stands there
@@ -298,14 +297,24 @@ __global__ void set_world_kernel(Grid g, uint32_t slot, uint32_t off, uint32_t s
   if (i < kMoveShards) g.w_moves[(uint64_t)slot * kMoveShards + i] = 0;
 }
 
+// Admission input check: *bad = 1 if any cell's sugar or capacity lies
+// outside 0..kMaxSugar (a cell keeps both in seven bits).
+__global__ void sugar_zero_kernel(uint32_t* bad) { *bad = 0; }
+__global__ void sugar_check_kernel(const int32_t* sugar, const int32_t* cap, uint32_t n, uint32_t* bad) {
+  bool out = false;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    out |= sugar[c] < 0 || sugar[c] > kMaxSugar || cap[c] < 0 || cap[c] > kMaxSugar;
+  if (__ballot(out) && is_first_active()) *bad = 1;
+}
+
 __global__ void sugar_admit_kernel(DevHeap h, Grid g, uint32_t slot, uint32_t off, uint32_t n, const int32_t* sugar,
                                    const int32_t* cap, const uint8_t* occ, const int32_t* as, const int32_t* am,
                                    const int32_t* av, const int32_t* aa) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const uint32_t q = off + c;
-  g.sugar[q] = (uint8_t)clamp_sugar(sugar[c]);
-  const_cast<int32_t*>(g.cap)[q] = clamp_sugar(cap[c]);
+  g.sugar[q] = (uint8_t)sugar[c];  // checked to be 0..kMaxSugar before the launch
+  const_cast<int32_t*>(g.cap)[q] = cap[c];
   g.req[q] = kInf;
   g.breq[q] = kInf;
   g.occ[q] = kNull;
@@ -353,6 +362,7 @@ using namespace dsoar;
 struct dsoar_sugar {
   dsoar_heap* heap;
   Grid g;
+  uint32_t* bad_input;  // device word: admission input outside 0..kMaxSugar
   uint64_t default_seed;
   uint32_t* h_off;
   uint32_t* h_side;
@@ -381,9 +391,11 @@ int sugar_one_step(dsoar_sugar* s, uint32_t flags, hipStream_t st) {
 
 size_t plane_bytes(uint64_t cells) { return (size_t)((cells * 4 + 255) / 256 * 256); }
 
+// World table: seeds, offsets, sides, steps; the move counters; one 256-byte
+// line for the admission input check.
 size_t table_bytes(uint32_t max_worlds) {
   return (size_t)(((uint64_t)max_worlds * (4 + 4 + 8 + 4) + 255) / 256 * 256 +
-                  (uint64_t)max_worlds * kMoveShards * 8);
+                  ((uint64_t)max_worlds * kMoveShards * 8 + 255) / 256 * 256 + 256);
 }
 
 }  // namespace
@@ -426,6 +438,7 @@ int dsoar_sugarpool_create(dsoar_heap* heap, uint32_t max_worlds, uint32_t arena
   g.w_side = g.w_off + max_worlds;
   g.w_step = g.w_side + max_worlds;
   g.w_moves = (uint64_t*)(b + ((uint64_t)max_worlds * 20 + 255) / 256 * 256);
+  s->bad_input = (uint32_t*)(b + table_bytes(max_worlds) - 256);
   uint8_t* planes = b + table_bytes(max_worlds);
   const uint64_t plane = plane_bytes(arena_cells);
   g.sugar = planes;  // one byte per cell in a plane sized like the others
@@ -456,6 +469,17 @@ int dsoar_sugar_admit(dsoar_sugar* s, uint32_t slot, uint32_t cell_offset, uint3
     if (s->live[k] && cell_offset < s->h_off[k] + (uint64_t)s->h_side[k] * s->h_side[k] && s->h_off[k] < cell_offset + n)
       return DSOAR_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
+  // Sugar and capacities outside the seven bits a cell keeps them in are
+  // refused before anything of the pool changes (synchronises the stream).
+  hipLaunchKernelGGL(sugar_zero_kernel, dim3(1), dim3(1), 0, st, s->bad_input);
+  DSOAR_LAUNCHED(s->heap);
+  hipLaunchKernelGGL(sugar_check_kernel, dim3((uint32_t)std::min<uint64_t>((n + 255) / 256, 4096)), dim3(256), 0, st,
+                     sugar_dev, cap_dev, (uint32_t)n, s->bad_input);
+  DSOAR_LAUNCHED(s->heap);
+  uint32_t bad = 0;
+  DSOAR_HIP(s->heap, hipMemcpyAsync(&bad, s->bad_input, 4, hipMemcpyDeviceToHost, st));
+  DSOAR_HIP(s->heap, hipStreamSynchronize(st));
+  if (bad) return DSOAR_ERR_INVALID_ARG;
   hipLaunchKernelGGL(set_world_kernel, dim3(1), dim3(kMoveShards), 0, st, s->g, slot, cell_offset, side, seed, step0);
   DSOAR_LAUNCHED(s->heap);
   launch_timed(s->heap, kKindSugarAdmit, sugar_admit_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), st, s->heap->dev, s->g, slot,

@@ -15,20 +15,25 @@ def _stream_ptr(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def make_desc(num_blocks: int, capacity: int, types: Sequence[Sequence[int]]) -> C.HeapDesc:
+def make_desc(num_blocks: int, capacity: int, types: Sequence[Sequence[int]], bitmap_width: int = 64,
+              parents: Sequence[int | None] | None = None) -> C.HeapDesc:
+    """Heap description: per type the byte width of every field; parents[t]
+    is the index of type t's parent type (None: no parent)."""
     if len(types) > C.MAX_TYPES:
         raise ValueError("too many types")
     d = C.HeapDesc()
     d.num_blocks = num_blocks
     d.block_capacity = capacity
     d.num_types = len(types)
-    d.reserved = 0
+    d.bitmap_width = bitmap_width
     for t, fields in enumerate(types):
         if len(fields) > C.MAX_FIELDS:
             raise ValueError("too many fields")
         d.types[t].num_fields = len(fields)
         for f, b in enumerate(fields):
             d.types[t].field_bytes[f] = b
+        p = parents[t] if parents is not None else None
+        d.types[t].parent = 0 if p is None else p + 1
     return d
 
 
@@ -42,9 +47,10 @@ class Heap:
     `types` lists, per type, the byte width (4 or 8) of every field."""
 
     def __init__(self, num_blocks: int, capacity: int = 64, types=((4, 4, 4),), device="cuda",
-                 stream=None):
+                 stream=None, bitmap_width: int = 64, parents=None):
         self.lib = C.load()
-        self.desc = make_desc(num_blocks, capacity, types)
+        self.desc = make_desc(num_blocks, capacity, types, bitmap_width, parents)
+        self.bitmap_width = bitmap_width
         self.types = [tuple(t) for t in types]
         self.num_blocks, self.capacity = num_blocks, capacity
         nbytes = int(self.lib.dsoar_heap_bytes(ctypes.byref(self.desc)))
@@ -83,6 +89,9 @@ class Heap:
 
     def set_type_policy(self, type_id: int, policy: int):
         C.check(self.lib.dsoar_heap_set_type_policy(self.h, type_id, policy), "dsoar_heap_set_type_policy")
+
+    def set_search(self, policy: int):
+        C.check(self.lib.dsoar_heap_set_search(self.h, policy), "dsoar_heap_set_search")
 
     def set_reclaim(self, online: bool):
         """Free emptied blocks at the delete that empties them (online) or at enumeration."""
@@ -130,8 +139,8 @@ class Heap:
             allocated_blocks=list(st.allocated_blocks[:nt]), active_blocks=list(st.active_blocks[:nt]),
             typed_blocks=list(st.typed_blocks[:nt]), reserve_retries=st.reserve_retries,
             slow_paths=st.slow_paths, find_fails=st.find_fails, method_atomics=st.method_atomics,
-            online_releases=st.online_releases,
-            free_blocks=st.free_blocks,
+            online_releases=st.online_releases, blocks_taken=st.blocks_taken,
+            blocks_returned=st.blocks_returned, free_blocks=st.free_blocks,
             num_blocks=st.num_blocks, oom=st.oom, retry_limit_hit=st.retry_limit_hit,
             double_free=st.double_free, status=rc)
 
@@ -235,23 +244,28 @@ class Heap:
         t8 = tw & 0xFF
         bt = torch.where(t8 == 0xFF, torch.full_like(t8, -1), t8)  # type, -1 = free
         nbm = 1 + 2 * len(self.types)
-        bms = b[L.bitmaps_offset: L.bitmaps_offset + nbm * L.bitmap_stride].view(torch.int64)
-        bms = bms.view(nbm, L.bitmap_stride // 8)
+        # One row per bitmap, one element per container (int64 or int32 by
+        # the heap's bitmap width), indexed by the levels' container offsets.
+        cw = L.bitmap_width
+        bms = b[L.bitmaps_offset: L.bitmaps_offset + nbm * L.bitmap_stride].view(
+            torch.int64 if cw == 64 else torch.int32)
+        bms = bms.view(nbm, L.bitmap_stride * 8 // cw)
         levels = [(L.level_word_offset[i], L.level_words[i]) for i in range(L.num_levels)]
-        return dict(obj_bitmap=ob, block_type=bt, bitmaps=bms, levels=levels)
+        return dict(obj_bitmap=ob, block_type=bt, bitmaps=bms, levels=levels, bitmap_width=cw)
 
 
 class DeviceBitmap:
     """A stand-alone device hierarchical bitmap (tests of the bitmap operations)."""
 
-    def __init__(self, nbits: int, all_set: bool = False, device="cuda"):
+    def __init__(self, nbits: int, all_set: bool = False, device="cuda", width: int = 64):
         self.lib = C.load()
         self.nbits = nbits
-        nbytes = int(self.lib.dsoar_bitmap_bytes(nbits))
+        self.width = width
+        nbytes = int(self.lib.dsoar_bitmap_bytes(nbits, width))
         if nbytes == 0:
             raise ValueError("bad bitmap size")
         self.buffer = torch.empty(nbytes // 8, dtype=torch.int64, device=device)
-        C.check(self.lib.dsoar_bitmap_init(self.buffer.data_ptr(), nbits, 1 if all_set else 0,
+        C.check(self.lib.dsoar_bitmap_init(self.buffer.data_ptr(), nbits, width, 1 if all_set else 0,
                                            _stream_ptr()), "dsoar_bitmap_init")
 
     def run(self, ops: torch.Tensor, starts: torch.Tensor | None = None) -> torch.Tensor:
@@ -263,18 +277,22 @@ class DeviceBitmap:
         if starts is not None:
             starts = starts.to(torch.int32).contiguous()
             st = starts.data_ptr()
-        C.check(self.lib.dsoar_bitmap_run(self.buffer.data_ptr(), self.nbits, ops.data_ptr(), n, st,
+        C.check(self.lib.dsoar_bitmap_run(self.buffer.data_ptr(), self.nbits, self.width, ops.data_ptr(), n, st,
                                           res.data_ptr(), _stream_ptr()), "dsoar_bitmap_run")
         return res[:n]
 
     def level_words(self):
+        """Per level, its containers (int64 at width 64, int32 at width 32);
+        levels start at 8-byte boundaries, level 0 first."""
+        units = self.buffer.view(torch.int32)
         out = []
         n, off = self.nbits, 0
         while True:
-            w = (n + 63) // 64
-            out.append(self.buffer[off: off + w])
-            off += w
-            if n <= 64:
+            c = -(-n // self.width)
+            lv = units[off: off + c * self.width // 32]
+            out.append(lv.view(torch.int64) if self.width == 64 else lv)
+            off += 2 * (-(-n // 64))
+            if n <= self.width:
                 break
-            n = w
+            n = c
         return out

@@ -10,6 +10,7 @@ so its result is the same whether it runs alone or in the mix."""
 from __future__ import annotations
 
 import ctypes
+import hashlib
 import time
 from dataclasses import dataclass, field
 
@@ -19,6 +20,21 @@ import torch
 from . import _capi as C
 from .apps import GOL_CAND, GOL_TYPES, SUGAR_TYPE, GameOfLife
 from .heap import Heap
+
+
+def result_digest(kind: str, res) -> str:
+    """SHA-256 of an episode's retired state (for comparing runs of the same
+    episode without keeping its arrays): the grid of a Game-of-Life world;
+    the sugar grid, occupancy, per-cell agent fields and move count of a
+    Sugarscape world."""
+    h = hashlib.sha256(kind.encode())
+    if kind == "gol":
+        h.update(np.ascontiguousarray(res, dtype=np.uint8).tobytes())
+    else:
+        for k in ("sugar", "occ", "a_sugar", "a_metab", "a_vision", "a_age"):
+            h.update(np.ascontiguousarray(res[k]).tobytes())
+        h.update(str(res["moves"]).encode())
+    return h.hexdigest()
 
 
 class RangeAllocator:
@@ -220,10 +236,23 @@ class Server:
         p = self.pools[spec.kind]
         return p.need(spec) <= p.blocks
 
-    def run(self, specs, inputs_of, keep_results: bool = True, max_wall: float = 600.0):
+    def check(self) -> dict:
+        """Invariant check of both pools' heaps at quiescence (sticky
+        out-of-memory, retry-limit and double-free flags included): {} when
+        everything holds, else the findings by pool."""
+        out = {}
+        for name, p in self.pools.items():
+            p.stream.synchronize()
+            c = p.heap.check()
+            if c:
+                out[name] = c
+        return out
+
+    def run(self, specs, inputs_of, keep_results: bool = True, max_wall: float = 600.0, digests: bool = False):
         """Runs the episodes to completion.  `inputs_of(spec)` returns a
         world's initial state.  Arrival times are seconds after the start on
-        the host clock.  Returns (records, results by episode id, stats)."""
+        the host clock.  Returns (records, results by episode id, stats); with
+        digests=True the results are result_digest() strings."""
         queue = sorted(specs, key=lambda e: (e.arrival, e.eid))
         for e in queue:
             if not self.fits_ever(e):
@@ -244,7 +273,9 @@ class Server:
                     done = time.perf_counter() - t0
                     records.append(Record(r.spec.eid, r.spec.kind, r.spec.side, r.spec.length, r.spec.arrival,
                                           r.admitted_at, done))
-                    if keep_results:
+                    if digests:
+                        results[r.spec.eid] = result_digest(r.spec.kind, res)
+                    elif keep_results:
                         results[r.spec.eid] = res
             # 2. admit arrived episodes in order while they fit
             now = time.perf_counter() - t0

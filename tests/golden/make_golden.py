@@ -2,7 +2,7 @@
 
 Every value here comes from the oracle (oracle/) run on the seeded inputs of
 synth/; nothing is taken from the device path.  Usage:
-    python tests/golden/make_golden.py [batched|sugarscape|all]
+    python tests/golden/make_golden.py [batched|sugarscape|serving|all]
 """
 from __future__ import annotations
 
@@ -74,9 +74,64 @@ def sugarscape(side=2048, n_agents=1 << 20, steps=500, seed=24301, every=100):
     print(path, out["oracle_seconds"], "s")
 
 
+def episode_digest(kind: str, res) -> dict:
+    """Canonical digest of an episode's final state: for the Game of Life the
+    grid (uint8, row-major); for Sugarscape the sugar grid (int32), the
+    occupancy (uint8), the agents' sugar, metabolism, vision and age per cell
+    (int32, 0 where no agent stands) and the number of moves."""
+    if kind == "gol":
+        g = np.ascontiguousarray(res, dtype=np.uint8)
+        return {"grid_sha256": digest(g), "population": int(g.sum())}
+    m = np.asarray(res["occ"]).astype(bool).ravel()
+    agents = np.stack([np.where(m, np.asarray(res[f]).ravel(), 0) for f in ("a_sugar", "a_metab", "a_vision", "a_age")])
+    return {"sugar_sha256": digest(np.asarray(res["sugar"], dtype=np.int32).ravel()),
+            "occ_sha256": digest(np.asarray(res["occ"], dtype=np.uint8).ravel()),
+            "agents_sha256": digest(agents.astype(np.int32)), "final_agents": int(m.sum()), "moves": int(res["moves"])}
+
+
+def serving_case(seed=24301, rate=40.0, n=10):
+    """The serving parity case at the sizes of the serving configuration:
+    the first n episodes of the Poisson stream (70 % Game of Life, side
+    128..2048, 50..300 generations; 30 % Sugarscape, side 256..1024, 10k..200k
+    agents, 100 steps) plus the two largest shapes the configuration allows,
+    a 2048^2 Game of Life of 240 generations and a 1024^2 Sugarscape world of
+    150,000 agents."""
+    from synth import rng
+    specs = W.serving_episodes(n, rate, seed=seed)
+    big_seeds = rng.hash4(seed, rng.S_EPISODE, 99, np.arange(2, dtype=np.uint64))
+    specs.append(W.EpisodeSpec(100, "gol", 2048, 240, int(big_seeds[0]), 0, 0.02))
+    specs.append(W.EpisodeSpec(101, "sugar", 1024, 100, int(big_seeds[1]), 150_000, 0.05))
+    eps = []
+    t0 = time.time()
+    for e in specs:
+        inp = W.episode_inputs(e)
+        if e.kind == "gol":
+            final, _ = oracle.gol_run(inp, e.length)
+            d = episode_digest("gol", final)
+        else:
+            st = oracle.SugarState(e.side, inp.sugar, inp.cap, inp.occ, inp.a_sugar, inp.a_metab, inp.a_vision,
+                                   inp.a_age)
+            ref = oracle.sugar_run(st, e.length, e.seed, W.SUGAR_RULES)
+            d = episode_digest("sugar", {"sugar": ref.sugar, "occ": ref.occ, "a_sugar": ref.a_sugar,
+                                         "a_metab": ref.a_metab, "a_vision": ref.a_vision, "a_age": ref.a_age,
+                                         "moves": ref.moves})
+        eps.append({"eid": e.eid, "kind": e.kind, "side": e.side, "length": e.length, "seed": str(e.seed),
+                    "agents": e.agents, "arrival": float(e.arrival), **d})
+        print(e.eid, e.kind, e.side, e.length, e.agents, round(time.time() - t0, 1), flush=True)
+    out = {"case": f"serving: first {n} episodes of the Poisson stream at {rate}/s (seed {seed}) plus a 2048^2 "
+                   f"Game of Life x 240 generations and a 1024^2 Sugarscape world with 150,000 agents x 100 steps",
+           "source": "oracle.gol_run / oracle.sugar_run on synth.workloads.episode_inputs", "rules": W.SUGAR_RULES,
+           "seed": seed, "rate": rate, "episodes": eps, "oracle_seconds": round(time.time() - t0, 1)}
+    path = os.path.join(HERE, f"serving_{n}plus2_seed{seed}.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(path, out["oracle_seconds"], "s")
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "all"
     if what in ("batched", "all"):
         batched()
     if what in ("sugarscape", "all"):
         sugarscape()
+    if what in ("serving", "all"):
+        serving_case()

@@ -44,7 +44,7 @@ def test_binding_covers_every_declared_symbol():
 
 def test_version_and_errors():
     lib = C.load()
-    assert lib.dsoar_abi_version() == 1
+    assert lib.dsoar_abi_version() == 2
     assert lib.dsoar_error_string(-2).startswith(b"out of memory")
     assert lib.dsoar_error_string(12345) == b"unknown status"
 
@@ -58,6 +58,12 @@ def test_heap_bytes_validates():
     for bad in [make_desc(0, 64, [(4,)]), make_desc(16, 48, [(4,)]), make_desc(16, 64, [(3,)]),
                 make_desc(16, 64, [])]:
         assert lib.dsoar_heap_bytes(ctypes.byref(bad)) == 0
+    # 2^26 blocks: slot 63 of the last block would have the NULL handle.
+    assert lib.dsoar_heap_bytes(ctypes.byref(make_desc(1 << 26, 64, [(4,)]))) == 0
+    assert lib.dsoar_heap_bytes(ctypes.byref(make_desc((1 << 26) - 1, 64, [(4,)]))) > 0
+    h = ctypes.c_void_p()
+    assert lib.dsoar_heap_create(ctypes.byref(make_desc(1 << 26, 64, [(4,)])), 256, 1 << 40, None,
+                                 ctypes.byref(h)) == C.ERR_INVALID_ARG
 
 
 def test_create_rejects_bad_buffers():
@@ -73,9 +79,28 @@ def test_create_rejects_bad_buffers():
 
 def test_bitmap_bytes():
     lib = C.load()
-    assert lib.dsoar_bitmap_bytes(0) == 0
-    assert lib.dsoar_bitmap_bytes(64) == 256 + 256
-    assert lib.dsoar_bitmap_bytes(1 << 30) > (1 << 27)
+    assert lib.dsoar_bitmap_bytes(0, 64) == 0
+    assert lib.dsoar_bitmap_bytes(64, 64) == 256 + 256
+    assert lib.dsoar_bitmap_bytes(64, 32) == 256 + 256      # two levels of 32-bit containers, padded
+    assert lib.dsoar_bitmap_bytes(64, 48) == 0
+    assert lib.dsoar_bitmap_bytes(1 << 30, 64) > (1 << 27)
+    # 32-bit containers: levels of 2^30, 2^25, 2^20, 2^15, 2^10, 2^5 bits.
+    assert lib.dsoar_bitmap_bytes(1 << 30, 32) >= 4 * (2 * sum(-(-(1 << (30 - 5 * k)) // 64) for k in range(6)))
+
+
+def test_descriptor_width_and_parents_validate():
+    lib = C.load()
+    ok = [make_desc(4096, 64, [(4, 4)], bitmap_width=w) for w in (0, 32, 64)]
+    assert all(lib.dsoar_heap_bytes(ctypes.byref(d)) > 0 for d in ok)
+    assert lib.dsoar_heap_bytes(ctypes.byref(make_desc(4096, 64, [(4, 4)], bitmap_width=16))) == 0
+    # Subclasses: declared after the parent, starting with its fields.
+    good = make_desc(4096, 0, [(4, 8), (4, 8, 4), (4, 8, 4, 4), (4,)], parents=[None, 0, 1, None])
+    assert lib.dsoar_heap_bytes(ctypes.byref(good)) > 0
+    for types, parents in [([(4, 8), (4, 4, 4)], [None, 0]),      # inherited widths differ
+                           ([(4, 8), (4,)], [None, 0]),            # fewer fields than the parent
+                           ([(4, 8), (4, 8, 4)], [1, None]),       # parent declared later
+                           ([(4, 8), (4, 8, 4)], [0, None])]:      # its own parent
+        assert lib.dsoar_heap_bytes(ctypes.byref(make_desc(64, 64, types, parents=parents))) == 0
 
 
 def test_application_entry_points_validate_without_a_gpu():

@@ -26,8 +26,14 @@ def oracle_finals(grids, gens):
     return [oracle.gol_run(g, gens)[0] for g in grids]
 
 
+H, LO, X = batch.C.SEARCH_HASHED, batch.C.SEARCH_LOWEST, batch.C.SEARCH_XCD
+
+
 @pytest.mark.parametrize("cfg", [batch.TuneConfig(64, 256, 8, 0), batch.TuneConfig(32, 1024, 2, 0),
-                                 batch.TuneConfig(64, 64, 16, batch.NEVER), batch.TuneConfig(32, 256, 4, batch.NEVER)])
+                                 batch.TuneConfig(64, 64, 16, batch.NEVER), batch.TuneConfig(32, 256, 4, batch.NEVER),
+                                 batch.TuneConfig(64, 256, 8, 0, 32, X), batch.TuneConfig(32, 1024, 2, 0, 32, H),
+                                 batch.TuneConfig(0, 256, 4, batch.NEVER, 32, LO),
+                                 batch.TuneConfig(64, 256, 8, 0, 64, LO), batch.TuneConfig(0, 64, 16, 0, 64, X)])
 def test_batched_matches_oracle_for_every_config(cfg):
     grids = small_batch()
     b = batch.BatchedGol(grids, cfg)
@@ -56,9 +62,11 @@ def test_plain_matches_batched():
 
 def test_autotune_small_space(tmp_path):
     grids = small_batch(seed=7, n=8)
-    space = {"capacity": [64, 32], "wg_threads": [256], "wgs_per_cu": [4], "bulk_min": [0]}
+    space = {"capacity": [64, 32], "bitmap_width": [64, 32], "wg_threads": [256], "wgs_per_cu": [4],
+             "bulk_min": [0], "search": [H, X]}
     best, table = batch.autotune(grids, 5, space, cache_path=str(tmp_path / "tune.json"))
-    assert len(table) == 2 and best.capacity in (64, 32)
+    assert len(table) == 8 and best.capacity in (64, 32) and best.bitmap_width in (64, 32)
+    assert {r["config"]["bitmap_width"] for r in table} == {64, 32}
     best2, table2 = batch.autotune(grids, 5, space, cache_path=str(tmp_path / "tune.json"))
     assert best2 == best and table2 == table           # served from the cache
 

@@ -11,24 +11,35 @@ from paper_1809_07444_amd import _capi as C  # noqa: E402
 from paper_1809_07444_amd.heap import DeviceBitmap  # noqa: E402
 
 
+WIDTHS = [64, 32]
+
+
 def words_np(bm):
-    return [w.cpu().numpy().view(np.uint64) for w in bm.level_words()]
+    return [w.cpu().numpy().view(np.uint64 if bm.width == 64 else np.uint32) for w in bm.level_words()]
 
 
 def assert_consistent(bm):
     lv = words_np(bm)
-    n = bm.nbits
+    n, cw = bm.nbits, bm.width
     for l, w in enumerate(lv):
         # no bits at or beyond the level's size
         for i, x in enumerate(w):
-            lo = 64 * i
-            if n - lo < 64:
+            lo = cw * i
+            if n - lo < cw:
                 assert int(x) >> max(n - lo, 0) == 0, (l, i)
         if l + 1 < len(lv):
             up = lv[l + 1]
             for i, x in enumerate(w):
-                assert ((int(up[i // 64]) >> (i % 64)) & 1) == (1 if int(x) else 0), (l, i)
+                assert ((int(up[i // cw]) >> (i % cw)) & 1) == (1 if int(x) else 0), (l, i)
         n = len(w)
+
+
+def assert_equals_oracle(bm, ref):
+    # Every level, container by container, equals the sequential model's.
+    lv = words_np(bm)
+    assert len(lv) == ref.nlevels
+    for l, w in enumerate(lv):
+        assert [int(x) for x in w] == [int(x) for x in ref.words(l)], l
 
 
 def ops_tensor(kinds, poss):
@@ -53,11 +64,29 @@ def test_width64_cascade_analogue_of_paper_example():
     assert_consistent(bm)
 
 
+def test_width32_cascade_analogue_of_paper_example():
+    # The same cascade with 32-bit containers (32^3 bits, three levels):
+    # clearing the only set bit of level-0 container 576 = 18 * 32 clears
+    # level-1 bit 576, which empties level-1 container 18 and clears top bit
+    # 18.  Bit 3 keeps top bit 0.
+    bm = DeviceBitmap(32 ** 3, width=32)
+    p1 = 18 * 1024
+    assert bm.run(ops_tensor([C.BM_TRY_SET, C.BM_TRY_SET], [p1, 3])).tolist() == [1, 1]
+    lv = words_np(bm)
+    assert len(lv) == 3 and int(lv[2][0]) == (1 << 18) | 1
+    assert bm.run(ops_tensor([C.BM_CLEAR], [p1])).tolist() == [0]
+    lv = words_np(bm)
+    assert int(lv[0][576]) == 0 and int(lv[1][18]) == 0 and int(lv[2][0]) == 1
+    assert_consistent(bm)
+
+
+@pytest.mark.parametrize("width", WIDTHS)
 @pytest.mark.parametrize("nbits,seed", [(4096, 1), (5000, 2), (64 ** 3 + 17, 3)])
-def test_concurrent_try_ops_exact(nbits, seed):
+def test_concurrent_try_ops_exact(nbits, seed, width):
+    import oracle
     rng = np.random.default_rng(seed)
     init = rng.random(nbits) < 0.3
-    bm = DeviceBitmap(nbits)
+    bm = DeviceBitmap(nbits, width=width)
     pos0 = np.nonzero(init)[0]
     assert (bm.run(ops_tensor(np.full(len(pos0), C.BM_TRY_SET), pos0)).cpu().numpy() == 1).all()
     assert_consistent(bm)
@@ -76,11 +105,16 @@ def test_concurrent_try_ops_exact(nbits, seed):
     got = np.unpackbits(lv0.view(np.uint8), bitorder="little")[:nbits].astype(bool)
     assert np.array_equal(got, final)
     assert_consistent(bm)
+    ref = oracle.Bitmap(nbits, width)
+    for p_ in np.nonzero(final)[0]:
+        ref.try_set(int(p_))
+    assert_equals_oracle(bm, ref)
 
 
-@pytest.mark.parametrize("nbits", [1, 64, 65, 4097, 30000])
-def test_find_clear_drains_exactly(nbits):
-    bm = DeviceBitmap(nbits, all_set=True)
+@pytest.mark.parametrize("width", WIDTHS)
+@pytest.mark.parametrize("nbits", [1, 32, 33, 64, 65, 4097, 30000])
+def test_find_clear_drains_exactly(nbits, width):
+    bm = DeviceBitmap(nbits, all_set=True, width=width)
     assert_consistent(bm)
     n = nbits + 100
     rng = np.random.default_rng(nbits)
@@ -92,10 +126,11 @@ def test_find_clear_drains_exactly(nbits):
     assert all(int(w.abs().sum()) == 0 for w in bm.level_words())
 
 
-def test_try_find_set_at_quiescence_brute_force():
+@pytest.mark.parametrize("width", WIDTHS)
+def test_try_find_set_at_quiescence_brute_force(width):
     rng = np.random.default_rng(5)
     for nbits, density in [(300, 0.0), (300, 0.01), (4096, 0.001), (70000, 0.0001)]:
-        bm = DeviceBitmap(nbits)
+        bm = DeviceBitmap(nbits, width=width)
         init = rng.random(nbits) < density
         pos0 = np.nonzero(init)[0]
         if len(pos0):
@@ -109,11 +144,12 @@ def test_try_find_set_at_quiescence_brute_force():
             assert np.isin(res, pos0).all()
 
 
-def test_set_clear_pairs_meet():
+@pytest.mark.parametrize("width", WIDTHS)
+def test_set_clear_pairs_meet(width):
     # set(pos) and clear(pos) issued together on a clear bit: clear retries
     # until the set lands (Sec. 2.1), so both finish and the bit ends clear.
     nbits = 8192
-    bm = DeviceBitmap(nbits)
+    bm = DeviceBitmap(nbits, width=width)
     pos = np.arange(0, nbits, 8)
     kinds = np.concatenate([np.full(len(pos), C.BM_CLEAR), np.full(len(pos), C.BM_SET)])
     res = bm.run(ops_tensor(kinds, np.concatenate([pos, pos]))).cpu().numpy()

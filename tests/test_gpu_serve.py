@@ -1,6 +1,8 @@
 """Serving with continuous batching: episodes admitted by free-block budget
 into resident world pools and stepped together.  Every result must equal the
 oracle's and the same episode run alone (tolerance 0: the work is integer)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -85,4 +87,42 @@ def test_poisson_arrivals_complete():
     assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
     for spec in specs[:6]:
         check_against_oracle(spec, results[spec.eid])
+    srv.close()
+
+
+def test_serving_config_sizes_against_oracle_digests():
+    # The serving configuration at its own sizes, on the server's default
+    # pools (2^21 Game-of-Life blocks, 256 slots, a 2^25-cell arena; 2^19
+    # Sugarscape blocks, 64 slots, a 2^23-cell arena): ten episodes of the
+    # Poisson stream plus a 2048^2 Game of Life of 240 generations and a
+    # 1024^2 Sugarscape world of 150,000 agents, arriving while others run.
+    # Every retired world equals the oracle's (stored digests written from
+    # oracle/ by tests/golden/make_golden.py) and the same episode run alone.
+    import json
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import episode_digest
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "serving_10plus2_seed24301.json")))
+    specs = [W.EpisodeSpec(e["eid"], e["kind"], e["side"], e["length"], int(e["seed"]), e["agents"], e["arrival"])
+             for e in gold["episodes"]]
+    assert max(s.side for s in specs if s.kind == "gol") == 2048
+    assert max(s.agents for s in specs if s.kind == "sugar") >= 100_000
+    want = {e["eid"]: {k: v for k, v in e.items() if k not in ("eid", "kind", "side", "length", "seed", "agents",
+                                                               "arrival")} for e in gold["episodes"]}
+    srv = serve.Server()
+    records, results, _ = srv.run(specs, W.episode_inputs)
+    assert sorted(r.eid for r in records) == sorted(s.eid for s in specs)
+    overlap = any(a.admitted < b.done and b.admitted < a.done for a in records for b in records if a.eid < b.eid)
+    assert overlap
+    for spec in specs:
+        assert episode_digest(spec.kind, results[spec.eid]) == want[spec.eid], spec
+    assert srv.check() == {}
+    for p in srv.pools.values():
+        assert p.budget == p.blocks and not p.resident
+    # Alone: one episode at a time through the same (now empty) pools.
+    for spec in specs:
+        _, alone, _ = srv.run([dataclasses.replace(spec, arrival=0.0)], W.episode_inputs, digests=True)
+        assert alone[spec.eid] == serve.result_digest(spec.kind, results[spec.eid]), spec
+    assert srv.check() == {}
     srv.close()

@@ -116,3 +116,30 @@ def test_full_config_2048_1M_agents_500_steps():
         assert hashlib.sha256(np.ascontiguousarray(agents).tobytes()).hexdigest() == cp["agents_sha256"]
         assert got.stats["allocs"] == [(1 << 20) + cp["births"]] and got.stats["frees"] == [cp["deaths"]]
         assert got.moves == cp["moves"]
+
+
+@pytest.mark.parametrize("field,value", [("cap", 200), ("sugar", 128), ("sugar", -1), ("cap", -5)])
+def test_c_abi_refuses_sugar_outside_a_cells_byte(field, value):
+    # Straight through the C ABI (the Python wrapper refuses such input
+    # itself): the library returns INVALID_ARG, creates no agent and leaves
+    # the world unadmitted.
+    import ctypes
+    import torch
+    inp = W.sugar_inputs(16, 20, seed=3)
+    sim = apps.Sugarscape(inp, RULES)
+    bad = [t.clone() for t in sim.inputs]
+    k = 0 if field == "sugar" else 1
+    bad[k][37] = value
+    sim.heap.reset()
+    rc = sim.lib.dsoar_sugar_init(sim.s, *[t.data_ptr() for t in bad], 0, sim.heap._s())
+    assert rc == C.ERR_INVALID_ARG
+    st = sim.heap.stats(raise_sticky=False)
+    assert st["allocs"] == [0] and st["live"] == [0]
+    assert sim.lib.dsoar_sugar_read(sim.s, *[t.data_ptr() for t in sim.out], None, sim.heap._s()) == \
+        C.ERR_INVALID_ARG  # slot 0 was never admitted
+    # The same world with the value in range is admitted and runs.
+    sim.init()
+    sim.step(3, C.DO_PERSISTENT)
+    ref = oracle.sugar_run(to_state(inp), 3, inp.seed, RULES)
+    compare(sim.read(), ref, int(inp.occ.sum()))
+    torch.cuda.synchronize()
