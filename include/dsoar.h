@@ -295,12 +295,15 @@ typedef struct { uint32_t field; int32_t modulus; int32_t residue; } dsoar_mod_a
 typedef struct { uint32_t key_field; uint32_t field; uint32_t num_keys; uint32_t reserved;
                  void* out_dev; uint8_t* present_dev; } dsoar_gather_args;
 
-/* Runs `method` once for every object of `type` that is live when the
- * enumeration runs (Sec. 2.3: c consecutive lanes per allocated block, lane
- * tid % c handles slot tid % c when that slot is allocated).  Objects created
- * during the do-all are not visited; a method may delete only `this`, which
- * takes effect when its wavefront finishes the block.  Errors: INVALID_ARG,
- * UNSUPPORTED (unknown method), HIP. */
+/* Runs `method` once for every object of `type`, and of every type that
+ * inherits from it (Sec. 1.2), that is live when the enumeration runs (Sec.
+ * 2.3: c consecutive lanes per allocated block, lane tid % c handles slot
+ * tid % c when that slot is allocated).  The lists of all those types are
+ * enumerated before any method runs; field indices in `args` name fields of
+ * `type`, which its subclasses inherit.  Objects created during the do-all
+ * are not visited; a method may delete only `this`, which takes effect when
+ * its wavefront finishes the block.  Errors: INVALID_ARG, UNSUPPORTED
+ * (unknown method), HIP. */
 int dsoar_parallel_do(dsoar_heap* heap, uint32_t type, uint32_t method,
                       const void* args, size_t args_bytes, uint32_t flags, void* stream);
 

@@ -37,8 +37,8 @@ struct Bodies {
   float dt, eps2, r2_merge;
 };
 
-template <class F>
-__device__ __forceinline__ F& fld(const DevHeap& h, uint32_t self, uint32_t f) {
+template <class F, class H>
+__device__ __forceinline__ F& fld(const H& h, uint32_t self, uint32_t f) {
   return *field_ptr<F>(h, self, kBody, f);
 }
 
@@ -79,7 +79,8 @@ struct BodyForce {
     sx = __builtin_fmaf(s, dx, sx);
     sy = __builtin_fmaf(s, dy, sy);
   }
-  static __device__ bool run_wave(const DevHeap& h, uint32_t, uint32_t self, bool live, const Args& a) {
+  template <class H>
+  static __device__ bool run_wave(const H& h, uint32_t, uint32_t self, bool live, const Args& a) {
     const float x = fld<float>(h, self, kX), y = fld<float>(h, self, kY);
     const uint32_t n = a.n;
     float sx = 0.0f, sy = 0.0f;
@@ -106,7 +107,8 @@ struct BodyForce {
 struct BodyMove {
   static constexpr uint32_t kKind = 61;
   using Args = Bodies;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
     const float vx = __builtin_fmaf(a.dt, fld<float>(h, self, kAX), fld<float>(h, self, kVX));
     const float vy = __builtin_fmaf(a.dt, fld<float>(h, self, kAY), fld<float>(h, self, kVY));
     const float x = __builtin_fmaf(a.dt, vx, fld<float>(h, self, kX));
@@ -137,7 +139,8 @@ struct BodyRoot {
     const float dx = from_lane(c.x, k) - x, dy = from_lane(c.y, k) - y;
     return __builtin_fmaf(dx, dx, dy * dy);
   }
-  static __device__ bool run_wave(const DevHeap& h, uint32_t, uint32_t self, bool live, const Args& a) {
+  template <class H>
+  static __device__ bool run_wave(const H& h, uint32_t, uint32_t self, bool live, const Args& a) {
     const float x = fld<float>(h, self, kX), y = fld<float>(h, self, kY);
     const uint32_t id = live ? fld<uint32_t>(h, self, kId) : 0u;  // id 0: nothing to search
     const uint32_t n = a.n, lane = lane_id();
@@ -172,7 +175,8 @@ struct BodyTarget {
   using Args = Bodies;
   // Few bodies per step are not roots, so the wavefront searches for each of
   // them in turn, 64 candidate ids at a time (one id per lane).
-  static __device__ bool run_wave(const DevHeap& h, uint32_t, uint32_t self, bool live, const Args& a) {
+  template <class H>
+  static __device__ bool run_wave(const H& h, uint32_t, uint32_t self, bool live, const Args& a) {
     const uint32_t id = live ? fld<uint32_t>(h, self, kId) : 0u;
     const bool need = live && a.T[id] != kRoot;
     uint64_t pending = __ballot(need);
@@ -209,7 +213,8 @@ struct BodyTarget {
 struct BodyMerge {
   static constexpr uint32_t kKind = 64;
   using Args = Bodies;
-  static __device__ bool run_wave(const DevHeap& h, uint32_t, uint32_t self, bool live, const Args& a) {
+  template <class H>
+  static __device__ bool run_wave(const H& h, uint32_t, uint32_t self, bool live, const Args& a) {
     const uint32_t id = live ? fld<uint32_t>(h, self, kId) : 0u;
     const bool root = live && a.T[id] == kRoot;
     if (!__ballot(root)) return false;
@@ -255,7 +260,8 @@ struct BodyMerge {
 struct BodyRemove {
   static constexpr uint32_t kKind = 65;
   using Args = Bodies;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
     const uint32_t id = fld<uint32_t>(h, self, kId);
     if (a.T[id] >= a.n) return false;  // a root or alone: stays
     a.P[id].z = 0.0f;
@@ -265,7 +271,8 @@ struct BodyRemove {
 };
 
 // Bodies with m > 0 become objects; every id's P and V entries are set.
-__global__ void collide_init_kernel(DevHeap h, Bodies a, const float* x, const float* y, const float* vx,
+template <uint32_t LG>
+__global__ void collide_init_kernel(DevHeapW<LG> h, Bodies a, const float* x, const float* y, const float* vx,
                                     const float* vy, const float* m) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
@@ -382,8 +389,11 @@ int dsoar_collide_destroy(dsoar_collide* c) {
 int dsoar_collide_init(dsoar_collide* c, const float* x_dev, const float* y_dev, const float* vx_dev,
                        const float* vy_dev, const float* m_dev, void* stream) {
   if (!c || !x_dev || !y_dev || !vx_dev || !vy_dev || !m_dev) return DSOAR_ERR_INVALID_ARG;
-  launch_timed(c->heap, kKindCollideInit, collide_init_kernel, dim3((c->a.n + 255) / 256), dim3(256), (hipStream_t)stream, c->heap->dev,
+  with_width(c->heap, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    launch_timed(c->heap, kKindCollideInit, collide_init_kernel<kLG>, dim3((c->a.n + 255) / 256), dim3(256), (hipStream_t)stream, DevHeapW<kLG>(c->heap->dev),
                      c->a, x_dev, y_dev, vx_dev, vy_dev, m_dev);
+  });
   DSOAR_LAUNCHED(c->heap);
   return DSOAR_OK;
 }

@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace dsoar {
 
 constexpr uint32_t kMaxTypes = 8;
@@ -108,6 +110,34 @@ struct DevHeap {
   // it with one scalar load.
   uint32_t field_loc[kMaxTypes][kMaxFields];
 };
+
+// A heap whose bitmap container width is known when the kernel is compiled:
+// the same data as DevHeap, with the width also a constant of the type.
+// Every device function of the heap takes its heap as a template parameter,
+// so a kernel that receives a DevHeapW<LG> runs code in which every width
+// test has folded away (as lean as if the heap had one width), while one
+// that receives a plain DevHeap reads the width at run time.
+template <uint32_t LG>
+struct DevHeapW : DevHeap {
+  static_assert(LG == 5 || LG == 6, "containers are 32 or 64 bits");
+  static constexpr uint32_t kLG = LG;
+  DevHeapW() = default;
+  __host__ __device__ explicit DevHeapW(const DevHeap& d) : DevHeap(d) {}
+};
+
+template <class H, class = void>
+struct HasFixedWidth : std::false_type {};
+template <class H>
+struct HasFixedWidth<H, std::void_t<decltype(H::kLG)>> : std::true_type {};
+
+// log2 of the heap's container width: the type's constant when it has one.
+template <class H>
+__device__ __forceinline__ uint32_t heap_lg(const H& h) {
+  if constexpr (HasFixedWidth<H>::value)
+    return H::kLG;
+  else
+    return h.bm_lg;
+}
 
 // ------------------------------------------------------------ wave helpers --
 
@@ -236,7 +266,8 @@ __device__ __forceinline__ void lead_flag(uint64_t* p) {
 
 // Counters are sharded by global wavefront index: same-address atomics
 // serialise (about 0.1 G/s on one word against about 20 G/s spread out).
-__device__ __forceinline__ uint64_t* shard(const DevHeap& h) {
+template <class H>
+__device__ __forceinline__ uint64_t* shard(const H& h) {
   const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   return h.ctrl + kCtlWords + (uint64_t)(wave & (kShards - 1)) * kShardStride;
 }
@@ -249,7 +280,8 @@ __device__ __forceinline__ uint64_t* shard(const DevHeap& h) {
 // returned), so their sum is the state at the instant between them.
 // Returns -1 when no two successive collects agreed (the counts are
 // changing: blocks may be free).
-__device__ __attribute__((noinline)) int64_t free_block_count(const DevHeap& h) {
+template <class H>
+__device__ inline int64_t free_block_count(const H& h) {
   const uint64_t am = active_mask();
   const uint32_t me = lanes_below(am), nact = (uint32_t)__popcll(am);
   uint64_t prev_sum = ~0ull;
@@ -277,7 +309,8 @@ __device__ __attribute__((noinline)) int64_t free_block_count(const DevHeap& h) 
 // Adds the active lanes' counts (each below 256) to counter `slot` of this
 // wavefront's shard with one atomic; exact under divergence (bit-sliced
 // ballots).  For methods that report their own atomic operations.
-__device__ inline void wave_count(const DevHeap& h, uint32_t slot, uint32_t k) {
+template <class H>
+__device__ inline void wave_count(const H& h, uint32_t slot, uint32_t k) {
   uint32_t n = 0;
 #pragma unroll
   for (uint32_t b = 0; b < 8; ++b) n += (uint32_t)__popcll(__ballot((k >> b) & 1u)) << b;
@@ -333,13 +366,17 @@ struct Bitmap {
   __device__ __forceinline__ uint32_t cmask() const { return (1u << lg) - 1u; }
 };
 
-__device__ __forceinline__ Bitmap heap_bitmap(const DevHeap& h, uint32_t k) {
-  return Bitmap{h.bitmaps + (uint64_t)k * h.bm_units, h.num_blocks, h.nlevels, h.bm_lg, h.ctrl + kCtlRetryLimit,
+template <class H>
+__device__ __forceinline__ Bitmap heap_bitmap(const H& h, uint32_t k) {
+  return Bitmap{h.bitmaps + (uint64_t)k * h.bm_units, h.num_blocks, h.nlevels, heap_lg(h), h.ctrl + kCtlRetryLimit,
                 h.bm_off};
 }
-__device__ __forceinline__ Bitmap free_bm(const DevHeap& h) { return heap_bitmap(h, 0); }
-__device__ __forceinline__ Bitmap allocated_bm(const DevHeap& h, uint32_t t) { return heap_bitmap(h, 1 + 2 * t); }
-__device__ __forceinline__ Bitmap active_bm(const DevHeap& h, uint32_t t) { return heap_bitmap(h, 2 + 2 * t); }
+template <class H>
+__device__ __forceinline__ Bitmap free_bm(const H& h) { return heap_bitmap(h, 0); }
+template <class H>
+__device__ __forceinline__ Bitmap allocated_bm(const H& h, uint32_t t) { return heap_bitmap(h, 1 + 2 * t); }
+template <class H>
+__device__ __forceinline__ Bitmap active_bm(const H& h, uint32_t t) { return heap_bitmap(h, 2 + 2 * t); }
 
 // The container of level-0 bit `pos` inside the group value v that holds it.
 __device__ __forceinline__ uint64_t group_part(const Bitmap& b, uint64_t v, uint32_t pos) {
@@ -349,7 +386,7 @@ __device__ __forceinline__ uint64_t group_part(const Bitmap& b, uint64_t v, uint
 // The 32-bit-container forms of the operations below are kept out of line:
 // inlined beside the 64-bit forms at every call site they would lengthen the
 // straight-line code each wavefront fetches, whatever width the heap uses.
-__device__ __attribute__((noinline)) uint64_t load_unit32(const uint32_t* p) {
+__device__ inline uint64_t load_unit32(const uint32_t* p) {
   return bcast32(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
@@ -365,7 +402,7 @@ __device__ __forceinline__ uint64_t load_top(const Bitmap& b) {
   return b.nlevels == 1 ? load_u64(b.group(0)) : load_container(b, b.nlevels - 1, 0);
 }
 
-__device__ __attribute__((noinline)) uint64_t bit_rmw32(uint32_t* w, uint32_t m, bool set) {
+__device__ inline uint64_t bit_rmw32(uint32_t* w, uint32_t m, bool set) {
   uint32_t r = 0;
   if (is_first_active())
     r = set ? __hip_atomic_fetch_or(w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
@@ -436,7 +473,7 @@ __device__ __forceinline__ bool bm_clear(const Bitmap& b, uint32_t pos) { return
 // The nested updates that an OR of m into level-0 group g (previous value
 // prev) makes: each container of the group that was empty and gained bits
 // sets its bit one level up (set's cascade, Sec. 2.1).
-__device__ __attribute__((noinline)) void group_set_nested32(const Bitmap& b, uint32_t g, uint64_t prev, uint64_t m) {
+__device__ inline void group_set_nested32(const Bitmap& b, uint32_t g, uint64_t prev, uint64_t m) {
   for (uint32_t half = 0; half < 2; ++half) {
     const uint64_t hm = 0xFFFFFFFFull << (32 * half);
     if ((m & hm) && !(prev & hm)) bm_set_from(b, 1, 2 * g + half);
@@ -454,7 +491,7 @@ __device__ inline void group_set_nested(const Bitmap& b, uint32_t g, uint64_t pr
 // The nested updates that an AND-NOT of m on level-0 group g (previous value
 // prev) makes: each container whose last set bits it removed clears its bit
 // one level up (Alg. 2 for several bits at once).
-__device__ __attribute__((noinline)) void group_clear_nested32(const Bitmap& b, uint32_t g, uint64_t prev,
+__device__ inline void group_clear_nested32(const Bitmap& b, uint32_t g, uint64_t prev,
                                                                uint64_t m) {
   for (uint32_t half = 0; half < 2; ++half) {
     const uint64_t hm = 0xFFFFFFFFull << (32 * half);
@@ -468,6 +505,44 @@ __device__ inline void group_clear_nested(const Bitmap& b, uint32_t g, uint64_t 
     return;
   }
   group_clear_nested32(b, g, prev, m);
+}
+
+// One leader atomic on the bits m of container c of level l >= 1 (OR when
+// set, AND-NOT otherwise); returns the container's previous value.
+__device__ inline uint64_t container_rmw(const Bitmap& b, uint32_t l, uint32_t c, uint64_t m, bool set) {
+  if (__builtin_expect(b.lg == 6, 1)) {
+    uint64_t* w = reinterpret_cast<uint64_t*>(b.level(l)) + c;
+    return set ? lead_or(w, m) : lead_and(w, ~m);
+  }
+  uint32_t* w = b.level(l) + c;
+  uint32_t r = 0;
+  if (is_first_active())
+    r = set ? __hip_atomic_fetch_or(w, (uint32_t)m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+            : __hip_atomic_fetch_and(w, ~(uint32_t)m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return bcast32(r);
+}
+
+// set(pos) / clear(pos) of Sec. 2.1 for every bit of m in container c of
+// level l >= 1, with one atomic: a container this made non-empty (empty)
+// sets (clears) its bit one level up, and bits another operation holds are
+// set (cleared) again one by one with the single-bit retry.
+__device__ inline void bm_set_bits_at(const Bitmap& b, uint32_t l, uint32_t c, uint64_t m) {
+  const uint64_t prev = container_rmw(b, l, c, m, true);
+  if (prev == 0 && l + 1 < b.nlevels) bm_set_from(b, l + 1, c);
+  uint64_t busy = prev & m;
+  while (busy) {
+    bm_set_from(b, l, (c << b.lg) + (uint32_t)__builtin_ctzll(busy));
+    busy &= busy - 1;
+  }
+}
+__device__ inline void bm_clear_bits_at(const Bitmap& b, uint32_t l, uint32_t c, uint64_t m) {
+  const uint64_t prev = container_rmw(b, l, c, m, false);
+  if ((prev & m) && (prev & ~m) == 0 && l + 1 < b.nlevels) bm_clear_from(b, l + 1, c);
+  uint64_t busy = m & ~prev;
+  while (busy) {
+    bm_clear_from(b, l, (c << b.lg) + (uint32_t)__builtin_ctzll(busy));
+    busy &= busy - 1;
+  }
 }
 
 // set(pos) for every bit of m in level-0 group g, with one atomic OR when no
@@ -624,7 +699,16 @@ __device__ inline int32_t bm_try_find_set(const Bitmap& b, uint32_t start) {
 // block's level-0 bit is set before its upper levels, so the top can read 0
 // while a bit is set below it.  The caller decides out of memory by the
 // free-block count, not by this FAIL.
-__device__ inline int32_t bm_find_clear(const Bitmap& b, uint32_t start) {
+// `hint` (optional) names a level-0 group to try first, one load and no
+// descent; a hint whose group reads empty or is out of range costs that load.
+__device__ inline int32_t bm_find_clear(const Bitmap& b, uint32_t start, uint32_t hint = kNull) {
+  if (hint < ((b.nbits + 63) >> 6)) {
+    const uint64_t w = load_u64(b.group(hint));
+    if (w) {
+      const uint32_t i = (hint << 6) | pick_bit(w, level_digit(start, 0, 6), 6);
+      if (i < b.nbits && bm_try_clear(b, i)) return (int32_t)i;
+    }
+  }
   for (uint32_t spins = 0; spins < kSpinLimit; ++spins) {
     const int32_t i = bm_try_find_set(b, start);
     if (i != kFail && bm_try_clear(b, (uint32_t)i)) return i;
@@ -641,10 +725,17 @@ __device__ inline int32_t bm_find_clear(const Bitmap& b, uint32_t start) {
 // the nested bits of the containers this emptied (Alg. 2 for several bits at
 // once).  Returns the bits gained (0 = the bitmap reads empty) and the group
 // in *word.
-__device__ inline uint64_t bm_take_word(const Bitmap& b, uint32_t start, uint32_t want, uint32_t* word) {
+// `hint` as for bm_find_clear.
+__device__ inline uint64_t bm_take_word(const Bitmap& b, uint32_t start, uint32_t want, uint32_t* word,
+                                        uint32_t hint = kNull) {
   for (uint32_t spins = 0; spins < kSpinLimit; ++spins) {
     uint64_t w = 0;
-    const int32_t found = bm_find_word(b, start, &w);
+    int32_t found = kFail;
+    if (spins == 0 && hint < ((b.nbits + 63) >> 6)) {
+      w = load_u64(b.group(hint));
+      if (w) found = (int32_t)hint;
+    }
+    if (found == kFail) found = bm_find_word(b, start, &w);
     const uint32_t idx = found == kFail ? 0u : (uint32_t)found;
     if (found != kFail) {
       const uint64_t take = take_from(w, want < (uint32_t)__popcll(w) ? want : (uint32_t)__popcll(w), start & 63u);
@@ -672,10 +763,12 @@ __device__ __forceinline__ uint32_t make_obj(uint32_t block, uint32_t slot) { re
 
 // Slots per block and the mask of valid object-bitmap bits of a type (the
 // type must be wave-uniform: read with scalar loads).
-__device__ __forceinline__ uint32_t cap_of(const DevHeap& h, uint32_t type) {
+template <class H>
+__device__ __forceinline__ uint32_t cap_of(const H& h, uint32_t type) {
   return h.capacity[__builtin_amdgcn_readfirstlane(type)];
 }
-__device__ __forceinline__ uint64_t capmask_of(const DevHeap& h, uint32_t type) {
+template <class H>
+__device__ __forceinline__ uint64_t capmask_of(const H& h, uint32_t type) {
   return h.cap_mask[__builtin_amdgcn_readfirstlane(type)];
 }
 
@@ -683,8 +776,8 @@ __device__ __forceinline__ uint64_t capmask_of(const DevHeap& h, uint32_t type) 
 // array inside the object's block, indexed by slot).  type and field must be
 // wave-uniform; they are read into scalar registers so that the layout table
 // is fetched with scalar loads, which never wait on the vector loads in flight.
-template <class F>
-__device__ __forceinline__ F* field_ptr(const DevHeap& h, uint32_t obj, uint32_t type, uint32_t field) {
+template <class F, class H>
+__device__ __forceinline__ F* field_ptr(const H& h, uint32_t obj, uint32_t type, uint32_t field) {
   const uint32_t t = __builtin_amdgcn_readfirstlane(type), f = __builtin_amdgcn_readfirstlane(field);
   const uint32_t loc = h.field_loc[t][f];
   return reinterpret_cast<F*>(h.data + (uint64_t)obj_block(obj) * h.block_stride + (loc & 0xFFFFFFu) +
@@ -708,7 +801,8 @@ __device__ __forceinline__ void wait_performed() {
 // type word still reads `w`; false (and no pin held) otherwise.  The pin is
 // performed before the type word is read again, and the releaser's type-word
 // store before it reads the pins, so at least one of the two sees the other.
-__device__ __forceinline__ bool pin_block(const DevHeap& h, uint32_t bid, uint32_t w) {
+template <class H>
+__device__ __forceinline__ bool pin_block(const H& h, uint32_t bid, uint32_t w) {
   __hip_atomic_fetch_add(h.pins + bid, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   wait_performed();
   if (__hip_atomic_load(h.block_type + bid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == w) return true;
@@ -716,7 +810,8 @@ __device__ __forceinline__ bool pin_block(const DevHeap& h, uint32_t bid, uint32
   return false;
 }
 // The reservation made under the pin is performed before the pin goes.
-__device__ __forceinline__ void unpin_block(const DevHeap& h, uint32_t bid) {
+template <class H>
+__device__ __forceinline__ void unpin_block(const H& h, uint32_t bid) {
   wait_performed();
   __hip_atomic_fetch_sub(h.pins + bid, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -729,7 +824,8 @@ __device__ __forceinline__ void unpin_block(const DevHeap& h, uint32_t bid) {
 // after the free-bitmap update that handed the block over has returned (the
 // block id comes from it), so with online reclamation it reads the version
 // the releaser stored before it set the free bit.
-__device__ __forceinline__ uint32_t publish_block(const DevHeap& h, uint32_t bid, uint32_t type, uint64_t bits) {
+template <class H>
+__device__ __forceinline__ uint32_t publish_block(const H& h, uint32_t bid, uint32_t type, uint64_t bits) {
   const uint32_t w = tw_with(__hip_atomic_load(h.block_type + bid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), type);
   __hip_atomic_store(h.obj_bitmap + bid, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   wait_performed();
@@ -737,18 +833,31 @@ __device__ __forceinline__ uint32_t publish_block(const DevHeap& h, uint32_t bid
   return w;
 }
 
+// Per-wavefront search hints in LDS, kept across the allocation requests a
+// wavefront makes within one kernel: slot kMaxTypes holds the level-0 group
+// of the free bitmap where it last took blocks, slot t the group of
+// active[t] where it last found a block with room.  A hint only replaces a
+// descent: its group is read again and used only if it still has set bits,
+// so a stale or never-written value costs one load.
+__device__ __forceinline__ uint32_t* wave_hints() {
+  __shared__ uint32_t s_hints[16 * (kMaxTypes + 1)];
+  return s_hints + ((threadIdx.x >> 6) & 15u) * (kMaxTypes + 1);
+}
+
 // Start value of this wavefront's bitmap searches (and slot rotation) under
 // the heap's search-start policy.  Workgroups are dispatched to the eight
 // XCDs round-robin, so blockIdx.x mod 8 is the XCD.
-__device__ __forceinline__ uint32_t search_start(const DevHeap& h) {
+template <class H>
+__device__ __forceinline__ uint32_t search_start(const H& h) {
   if (h.search_start == kStartLowest) return 0u;
   const uint32_t r = bcast32(hash32((blockIdx.x << 5) ^ (threadIdx.x >> 6) ^ 0x5bd1e995u));
   if (h.search_start != kStartXcd) return r;
-  const uint32_t tsh = h.bm_lg * (h.nlevels - 1);
+  const uint32_t lg = heap_lg(h);
+  const uint32_t tsh = lg * (h.nlevels - 1);
   const uint32_t sh = tsh >= 30 ? tsh - 30 : tsh;  // the top level's digit (as level_digit)
-  const uint32_t span = (1u << h.bm_lg) >> 3;             // an eighth of its values
+  const uint32_t span = (1u << lg) >> 3;                  // an eighth of its values
   const uint32_t digit = (blockIdx.x & 7u) * span + ((r >> sh) & (span - 1u));
-  return (r & ~(((1u << h.bm_lg) - 1u) << sh)) | (digit << sh);
+  return (r & ~(((1u << lg) - 1u) << sh)) | (digit << sh);
 }
 
 // Alg. 1 for all lanes of this wavefront that call it with the same `type`
@@ -773,8 +882,8 @@ __device__ __forceinline__ uint32_t search_start(const DevHeap& h) {
 // whose OR fills the block clears active[type] (Alg. 1, FULL).
 // Requests are numbered by lane order (exclusive prefix sums from bit-sliced
 // ballots, exact under any divergence) and handed out in that order.
-template <class F>
-__device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&& f) {
+template <class F, class H>
+__device__ inline void new_many(const H& h, uint32_t type, uint32_t k, F&& f) {
   uint32_t prefix = 0, n = 0;
 #pragma unroll
   for (uint32_t b = 0; b < 8; ++b) {
@@ -802,6 +911,9 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
   // lookups (until no free block is left).
   const uint32_t max_lookups = (h.bounded_types >> type) & 1u ? kBoundedPasses : kSpinLimit;
   uint32_t lookups = 0;
+  uint32_t* const hints = wave_hints();
+  uint32_t free_hint = bcast32(hints[kMaxTypes]), act_hint = bcast32(hints[type]);
+  const uint32_t groups = (h.num_blocks + 63) >> 6;
   for (uint32_t it = 0; served < n; ++it) {
     if (it >= kSpinLimit) {
       lead_flag(h.ctrl + kCtlRetryLimit);
@@ -810,25 +922,50 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
     }
     const uint32_t want = n - served;
     if (want >= c && (want >= h.bulk_min || none_active) && !active_first) {
-      // Whole free blocks, several from one free-bitmap word per atomic.
+      // Whole free blocks, several from one free-bitmap word per atomic.  A
+      // type with the fresh policy would open a block of its own for the
+      // rest of the request right after: that block is taken in the same
+      // atomic and published holding only the rest (and marked active).
       uint32_t word = 0;
-      const uint32_t nb = want / c < 64 ? want / c : 64;
-      const uint64_t blocks = bm_take_word(free_bm(h), start, nb, &word);
+      const uint32_t full = want / c, rest = want - full * c;
+      const bool with_rest = fresh && rest != 0 && full < 64;
+      const uint32_t nb = full < 64 ? full + (with_rest ? 1u : 0u) : 64u;
+      const uint64_t blocks = bm_take_word(free_bm(h), start, nb, &word, free_hint);
       if (blocks == 0) {
         active_first = true;  // no free block: use space left in active blocks
         continue;
       }
+      free_hint = word;
       const uint32_t cnt_b = (uint32_t)__popcll(blocks);
+      // With fewer blocks than asked for, all of them are filled.
+      const bool partial = with_rest && cnt_b == nb;
+      const uint64_t rest_bits = (1ull << rest) - 1;  // rest < c <= 64
       // Type words and object bitmaps of the new blocks, spread over the
       // active lanes; the blocks are ours alone until published.
-      const uint32_t me = lanes_below(active_mask()), nact = (uint32_t)__popcll(active_mask());
-      for (uint32_t j = me; j < cnt_b; j += nact) publish_block(h, word * 64 + nth_set_bit(blocks, j), type, cap);
+      const uint64_t am = active_mask();
+      const uint32_t me = lanes_below(am), nact = (uint32_t)__popcll(am);
+      uint32_t my_tw = 0;
+      for (uint32_t j = me; j < cnt_b; j += nact) {
+        const bool last = partial && j + 1 == cnt_b;
+        const uint32_t w = publish_block(h, word * 64 + nth_set_bit(blocks, j), type, last ? rest_bits : cap);
+        if (last) my_tw = w;
+      }
       const Bitmap alloc = allocated_bm(h, type);
       const uint64_t pa = lead_or(alloc.group(word), blocks);
       group_set_nested(alloc, word, pa, blocks & ~pa);
-      lead_add(shard(h) + kCntBlocksTaken, cnt_b);  // full blocks: nothing left to find
+      uint32_t span = cnt_b * c;
+      if (partial) {
+        // The block holding the rest stays findable for later requests.
+        const uint32_t lb = nth_set_bit(blocks, cnt_b - 1);
+        bm_set_bits0(active, word, 1ull << lb);
+        cur = (int32_t)(word * 64 + lb);
+        cur_avail = ~rest_bits & cap;
+        cur_tw = (uint32_t)__builtin_amdgcn_readlane(my_tw, nth_set_bit(am, (cnt_b - 1) % nact));
+        span = (cnt_b - 1) * c + rest;
+      }
+      // Counted as taken once nothing of them is left to publish.
+      lead_add(shard(h) + kCntBlocksTaken, cnt_b);
       slow += cnt_b;
-      const uint32_t span = cnt_b * c;
       const uint32_t lo = prefix > served ? prefix : served;
       const uint32_t hi = prefix + k < served + span ? prefix + k : served + span;
       for (uint32_t r = lo; r < hi; ++r) {
@@ -844,7 +981,12 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
     if (bid == kFail && (active_first || (!fresh && lookups < max_lookups))) {
       ++lookups;
       uint64_t wbits = 0;
-      const int32_t aw = bm_find_word(active, start, &wbits);
+      int32_t aw = kFail;
+      if (lookups == 1 && act_hint < groups) {  // where this wavefront last found room
+        wbits = load_u64(active.group(act_hint));
+        if (wbits) aw = (int32_t)act_hint;
+      }
+      if (aw == kFail) aw = bm_find_word(active, start, &wbits);
       if (aw == kFail) {
         ++fails;
         // No active block: whole free blocks for the rest while it fills them.
@@ -918,13 +1060,15 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
           served += gc;
           gained += gc;
         }
+        if (gained) act_hint = (uint32_t)aw;
         if (gained == 0 && cur == kFail) start = hash32(start + it + 1);
         continue;
       }
     }
     cur = kFail;
     if (bid == kFail) {
-      bid = bm_find_clear(free_bm(h), start);
+      bid = bm_find_clear(free_bm(h), start, free_hint);
+      if (bid != kFail) free_hint = (uint32_t)bid >> 6;
       if (bid == kFail) {
         // The free bitmap reads empty.  Out of memory only when the free-block
         // count (free blocks and blocks other wavefronts are still opening)
@@ -998,6 +1142,10 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
     for (uint32_t r = lo; r < hi; ++r) f(r - prefix, make_obj((uint32_t)bid, nth_set_bit(got, r - served)));
     served += cnt;
   }
+  if (is_first_active()) {
+    hints[kMaxTypes] = free_hint;
+    hints[type] = act_hint;
+  }
   if (oom) lead_flag(h.ctrl + kCtlOom);
   if (oom || gave_up)
     for (uint32_t r = prefix > served ? prefix : served; r < prefix + k; ++r) f(r - prefix, kNull);
@@ -1010,7 +1158,8 @@ __device__ inline void new_many(const DevHeap& h, uint32_t type, uint32_t k, F&&
 
 // Device `new`: every calling lane gets one object of `type`.  Lanes may pass
 // different types; each distinct type is served as one coalesced request.
-__device__ inline uint32_t dsoar_new(const DevHeap& h, uint32_t type) {
+template <class H>
+__device__ inline uint32_t dsoar_new(const H& h, uint32_t type) {
   uint32_t result = kNull;
   for (;;) {
     const uint32_t t0 = bcast32(type);
@@ -1042,7 +1191,8 @@ __device__ inline uint32_t dsoar_new(const DevHeap& h, uint32_t type) {
 //    the free bitmap sees the reset bitmap and the new type word, and a
 //    request that finds no free block still finds it in the count.
 // Returns whether the block was freed (wave-uniform).
-__device__ inline bool try_release(const DevHeap& h, uint32_t type, uint32_t bid) {
+template <class H>
+__device__ inline bool try_release(const H& h, uint32_t type, uint32_t bid) {
   uint32_t ok = 0;
   if (is_first_active()) {
     uint64_t expected = 0;
@@ -1082,7 +1232,8 @@ __device__ inline bool try_release(const DevHeap& h, uint32_t type, uint32_t bid
 // atomic AND on the object bitmap.  A block that was full becomes active
 // again.  Blocks that become empty stay allocated until quiescent reclaim.
 // Returns the number of objects removed (the caller counts them).
-__device__ inline uint32_t delete_mask(const DevHeap& h, uint32_t type, uint32_t bid, uint64_t mask) {
+template <class H>
+__device__ inline uint32_t delete_mask(const H& h, uint32_t type, uint32_t bid, uint64_t mask) {
   const uint64_t prev = lead_and(h.obj_bitmap + bid, ~mask);
   if ((prev & mask) != mask) lead_flag(h.ctrl + kCtlDoubleFree);
   const uint64_t removed = prev & mask;
@@ -1094,7 +1245,8 @@ __device__ inline uint32_t delete_mask(const DevHeap& h, uint32_t type, uint32_t
 
 // Device `delete` of arbitrary objects: lanes are grouped by block; each group
 // is one coalesced delete_mask.  NULL handles are ignored.
-__device__ inline void dsoar_delete(const DevHeap& h, uint32_t obj) {
+template <class H>
+__device__ inline void dsoar_delete(const H& h, uint32_t obj) {
   const bool valid = obj == kNull || (obj >> 6) < h.num_blocks;
   if (!__builtin_expect(__ballot(!valid) == 0, 1)) lead_flag(h.ctrl + kCtlDoubleFree);
   const bool mine = obj != kNull && valid;

@@ -48,7 +48,8 @@ struct World {
 
 // Sets the live state of the Cell at global index g (its field and the copy
 // in the live plane); only the cell's own Alive or Candidate does this.
-__device__ __forceinline__ void set_live(const DevHeap& h, const World& w, uint32_t g, uint32_t live) {
+template <class H>
+__device__ __forceinline__ void set_live(const H& h, const World& w, uint32_t g, uint32_t live) {
   const uint32_t wd = w.cells[g];
   if (wd == kNull) return;
   *field_ptr<uint32_t>(h, wd, kCell, kCAlive) = live;
@@ -142,7 +143,8 @@ __device__ __forceinline__ void neighbourhood(const uint8_t* plane, uint32_t off
 struct AlivePrep {
   static constexpr uint32_t kKind = 30;
   using Args = World;
-  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& w) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
     const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
     const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
     const uint32_t off = w.off[wid], side = w.side[wid];
@@ -175,7 +177,8 @@ struct AlivePrep {
 struct CandPrep {
   static constexpr uint32_t kKind = 31;
   using Args = World;
-  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& w) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
     const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
     const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
     const uint32_t off = w.off[wid], side = w.side[wid];
@@ -191,7 +194,8 @@ struct CandPrep {
 struct AliveUpdate {
   static constexpr uint32_t kKind = 32;
   using Args = World;
-  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& w) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
     if (*field_ptr<uint32_t>(h, self, type, kAAction) == 0) return false;
     set_live(h, w, *field_ptr<uint32_t>(h, self, type, kACell), 0);
     return true;
@@ -201,7 +205,8 @@ struct AliveUpdate {
 struct CandUpdate {
   static constexpr uint32_t kKind = 33;
   using Args = World;
-  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& w) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
     const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
     const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
     const bool born = *field_ptr<uint32_t>(h, self, type, kAAction) != 0;
@@ -229,7 +234,8 @@ __device__ __forceinline__ uint32_t world_of(const uint32_t* off, uint32_t num_w
 }
 
 // Creates every Cell (in position order) and an Alive for every live cell.
-__global__ void gol_init_kernel(DevHeap h, World w, uint32_t num_worlds, uint32_t total, const uint8_t* grid) {
+template <uint32_t LG>
+__global__ void gol_init_kernel(DevHeapW<LG> h, World w, uint32_t num_worlds, uint32_t total, const uint8_t* grid) {
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const uint32_t hc = dsoar_new(h, kCell);
@@ -261,7 +267,8 @@ __global__ void gol_set_slot_kernel(World w, uint32_t slot, uint32_t off, uint32
 }
 
 // Creates the objects of one world admitted into slot `slot`.
-__global__ void gol_admit_kernel(DevHeap h, World w, uint32_t slot, uint32_t off, uint32_t n, const uint8_t* grid) {
+template <uint32_t LG>
+__global__ void gol_admit_kernel(DevHeapW<LG> h, World w, uint32_t slot, uint32_t off, uint32_t n, const uint8_t* grid) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t g = off + i;
@@ -279,7 +286,8 @@ __global__ void gol_admit_kernel(DevHeap h, World w, uint32_t slot, uint32_t off
 }
 
 // Deletes the Cells of one world (the Alive objects go with GolDeleteWorld).
-__global__ void gol_retire_cells_kernel(DevHeap h, World w, uint32_t off, uint32_t n) {
+template <uint32_t LG>
+__global__ void gol_retire_cells_kernel(DevHeapW<LG> h, World w, uint32_t off, uint32_t n) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t* c = const_cast<uint32_t*>(w.cells) + off + i;
@@ -291,7 +299,8 @@ __global__ void gol_retire_cells_kernel(DevHeap h, World w, uint32_t off, uint32
 struct GolDeleteWorld {
   static constexpr uint32_t kKind = 34;
   struct Args { uint32_t slot; };
-  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& a) {
     return *field_ptr<uint32_t>(h, self, type, kAWorld) == a.slot;
   }
 };
@@ -429,8 +438,11 @@ int dsoar_gol_destroy(dsoar_gol* g) {
 
 int dsoar_gol_init(dsoar_gol* g, const uint8_t* grid_dev, void* stream) {
   if (!g || !grid_dev) return DSOAR_ERR_INVALID_ARG;
-  launch_timed(g->heap, kKindGolInit, gol_init_kernel, dim3((g->total + 255) / 256), dim3(256), (hipStream_t)stream, g->heap->dev,
+  with_width(g->heap, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    launch_timed(g->heap, kKindGolInit, gol_init_kernel<kLG>, dim3((g->total + 255) / 256), dim3(256), (hipStream_t)stream, DevHeapW<kLG>(g->heap->dev),
                      g->w, g->num_worlds, g->total, grid_dev);
+  });
   DSOAR_LAUNCHED(g->heap);
   return DSOAR_OK;
 }
@@ -506,8 +518,11 @@ int dsoar_gol_admit(dsoar_gol* g, uint32_t slot, uint32_t cell_offset, uint32_t 
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(gol_set_slot_kernel, dim3(1), dim3(1), 0, s, g->w, slot, cell_offset, side);
   DSOAR_LAUNCHED(g->heap);
-  launch_timed(g->heap, kKindGolAdmit, gol_admit_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), s, g->heap->dev, g->w, slot,
+  with_width(g->heap, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    launch_timed(g->heap, kKindGolAdmit, gol_admit_kernel<kLG>, dim3((uint32_t)((n + 255) / 256)), dim3(256), s, DevHeapW<kLG>(g->heap->dev), g->w, slot,
                      cell_offset, (uint32_t)n, grid_dev);
+  });
   DSOAR_LAUNCHED(g->heap);
   g->h_off[slot] = cell_offset;
   g->h_side[slot] = side;
@@ -521,8 +536,11 @@ int dsoar_gol_retire(dsoar_gol* g, uint32_t slot, void* stream) {
   int rc = launch_doall<GolDeleteWorld>(g->heap, kAlive, GolDeleteWorld::Args{slot}, 0, s);
   if (rc) return rc;
   const uint32_t n = g->h_side[slot] * g->h_side[slot];
-  hipLaunchKernelGGL(gol_retire_cells_kernel, dim3((n + 255) / 256), dim3(256), 0, s, g->heap->dev, g->w,
+  with_width(g->heap, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    hipLaunchKernelGGL(gol_retire_cells_kernel<kLG>, dim3((n + 255) / 256), dim3(256), 0, s, DevHeapW<kLG>(g->heap->dev), g->w,
                      g->h_off[slot], n);
+  });
   DSOAR_LAUNCHED(g->heap);
   g->live[slot] = 0;
   return DSOAR_OK;

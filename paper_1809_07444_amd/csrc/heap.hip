@@ -211,7 +211,8 @@ __global__ void init_scan_kernel(ScanState* st, uint64_t* flags, uint32_t num_ti
 // free again (the block-state figure's transition back to free).  The three
 // level-0 updates are issued together; each does the nested update its
 // single-bit counterpart would (Alg. 2).
-__device__ inline void reclaim_word(const DevHeap& h, uint32_t t, uint32_t word, uint64_t rc) {
+template <class H>
+__device__ inline void reclaim_word(const H& h, uint32_t t, uint32_t word, uint64_t rc) {
   if ((rc >> lane_id()) & 1ull) {
     uint32_t* tw = h.block_type + word * 64 + lane_id();
     meta_store(tw, tw_freed(meta_load(tw)));
@@ -232,6 +233,59 @@ __device__ inline void reclaim_word(const DevHeap& h, uint32_t t, uint32_t word,
   group_set_nested(fr, word, pf, rc & ~pf);
 }
 
+// Quiescent reclamation of the empty blocks rc[j] of WPW consecutive level-0
+// groups word0 + j (word0 a multiple of WPW), as reclaim_word does for each,
+// with the atomics batched: every group's three level-0 updates are issued
+// before any result is used, and the nested updates they call for land in
+// one level-1 container per bitmap (WPW groups of 64 blocks have consecutive
+// bits one level up), one atomic each.
+template <uint32_t WPW, class H>
+__device__ inline void reclaim_words(const H& h, uint32_t t, uint32_t word0, const uint64_t (&rc)[WPW]) {
+  uint64_t total = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < WPW; ++j) {
+    if ((rc[j] >> lane_id()) & 1ull) {
+      uint32_t* tw = h.block_type + (word0 + j) * 64 + lane_id();
+      meta_store(tw, tw_freed(meta_load(tw)));
+    }
+    total += (uint64_t)__popcll(rc[j]);
+  }
+  if (total == 0) return;
+  const Bitmap al = allocated_bm(h, t), ac = active_bm(h, t), fr = free_bm(h);
+  lead_add(shard(h) + kCntBlocksReturned, total);
+  uint64_t pa[WPW], pc[WPW], pf[WPW];
+  const bool leader = is_first_active();
+#pragma unroll
+  for (uint32_t j = 0; j < WPW; ++j) {
+    pa[j] = pc[j] = pf[j] = 0;
+    if (rc[j] && leader) {
+      pa[j] = __hip_atomic_fetch_and(al.group(word0 + j), ~rc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      pc[j] = __hip_atomic_fetch_and(ac.group(word0 + j), ~rc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      pf[j] = __hip_atomic_fetch_or(fr.group(word0 + j), rc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (al.nlevels == 1) return;
+  const uint32_t lg = al.lg, parts = 1u << (6 - lg);  // containers per group
+  const uint32_t first = word0 * parts;                // level-1 bit of the first container
+  const uint32_t c1 = first >> lg;                     // their level-1 container
+  uint64_t ma = 0, mc = 0, mf = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < WPW; ++j) {
+    if (!rc[j]) continue;
+    const uint64_t a = bcast64(pa[j]), c = bcast64(pc[j]), f = bcast64(pf[j]);
+    for (uint32_t p = 0; p < parts; ++p) {
+      const uint64_t pm = parts == 1 ? ~0ull : (0xFFFFFFFFull << (32 * p));
+      const uint64_t bit = 1ull << ((first + j * parts + p) & ((1u << lg) - 1u));
+      if ((a & rc[j] & pm) && !(a & ~rc[j] & pm)) ma |= bit;
+      if ((c & rc[j] & pm) && !(c & ~rc[j] & pm)) mc |= bit;
+      if ((rc[j] & ~f & pm) && !(f & pm)) mf |= bit;
+    }
+  }
+  if (ma) bm_clear_bits_at(al, 1, c1, ma);
+  if (mc) bm_clear_bits_at(ac, 1, c1, mc);
+  if (mf) bm_set_bits_at(fr, 1, c1, mf);
+}
+
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   for (int off = 32; off >= 1; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off);
   return v;
@@ -250,8 +304,8 @@ __device__ __forceinline__ uint64_t pack_flag(uint32_t epoch, uint64_t status, u
 // ticket counter.  Each wavefront covers
 // WPW level-0 words (64 blocks each); all their loads are issued before any
 // is used.  The heap is quiescent, so plain loads see the previous kernels.
-template <uint32_t WPW>
-__global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeap h, uint32_t type, EnumOut out) {
+template <uint32_t WPW, uint32_t LG>
+__global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeapW<LG> h, uint32_t type, EnumOut out) {
   __shared__ uint32_t s_tile, s_epoch, s_prefix;
   __shared__ uint32_t s_wave_total[kEnumWaves];
   if (threadIdx.x == 0) {
@@ -342,9 +396,7 @@ __global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeap h, u
   // Reclamation does not change the list, so it comes after the tile's
   // prefix is published and its entries are written: later tiles' look-back
   // never waits for these atomics.
-#pragma unroll
-  for (uint32_t j = 0; j < WPW; ++j)
-    if (empty[j]) reclaim_word(h, type, word0 + j, empty[j]);
+  reclaim_words<WPW>(h, type, word0, empty);
   if (tile == out.num_tiles - 1 && threadIdx.x == 0) {
     __hip_atomic_store(&out.st->count, s_prefix + tile_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (out.count_out) *out.count_out = s_prefix + tile_total;
@@ -486,13 +538,15 @@ __global__ void bitmap_ops_kernel(uint32_t* units, uint32_t nbits, uint32_t lg, 
 }
 
 // -------------------------------------------------------- generic kernels
-__global__ void alloc_n_kernel(DevHeap h, uint32_t type, uint32_t n, uint32_t* out) {
+template <uint32_t LG>
+__global__ void alloc_n_kernel(DevHeapW<LG> h, uint32_t type, uint32_t n, uint32_t* out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   out[i] = dsoar_new(h, type);
 }
 
-__global__ void free_n_kernel(DevHeap h, const uint32_t* objs, uint32_t n) {
+template <uint32_t LG>
+__global__ void free_n_kernel(DevHeapW<LG> h, const uint32_t* objs, uint32_t n) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   dsoar_delete(h, objs[i]);
@@ -506,7 +560,8 @@ __global__ void free_n_kernel(DevHeap h, const uint32_t* objs, uint32_t n) {
 // otherwise).  A field found overwritten (a slot handed out twice) counts in
 // errors[0].  Every lane of a wavefront runs every round (the heap calls are
 // wavefront operations).
-__global__ void churn_kernel(DevHeap h, uint32_t n, uint32_t rounds, uint32_t keep, uint32_t spread, uint32_t seed,
+template <uint32_t LG>
+__global__ void churn_kernel(DevHeapW<LG> h, uint32_t n, uint32_t rounds, uint32_t keep, uint32_t spread, uint32_t seed,
                              uint32_t* out, uint32_t* errors) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = i < n;
@@ -561,7 +616,8 @@ struct DeleteIfMod {
   static constexpr uint32_t kKind = 11;
   struct Args { uint32_t field; int32_t modulus; int32_t residue; };
   struct Pre { int32_t v; };
-  static __device__ Pre load(const DevHeap& h, uint32_t type, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ Pre load(const H& h, uint32_t type, uint32_t self, const Args& a) {
     return {*field_ptr<int32_t>(h, self, type, a.field)};
   }
   static __device__ bool apply(const DevHeap&, uint32_t, uint32_t, const Args& a, const Pre& p) {
@@ -572,7 +628,8 @@ struct DeleteIfMod {
 struct FieldGather {
   static constexpr uint32_t kKind = 12;
   struct Args { uint32_t key_field, field, num_keys, wide; uint8_t* out; uint8_t* present; };
-  static __device__ bool run(const DevHeap& h, uint32_t type, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& a) {
     const uint32_t key = *field_ptr<uint32_t>(h, self, type, a.key_field);
     if (key >= a.num_keys) return false;
     if (a.wide) reinterpret_cast<uint64_t*>(a.out)[key] = *field_ptr<uint64_t>(h, self, type, a.field);
@@ -588,11 +645,17 @@ struct FieldGather {
 
 int launch_enumerate_into(dsoar_heap* h, uint32_t type, const EnumOut& eo, hipStream_t s) {
   if (h->enum_wpw == kEnumWideWords)
-    launch_timed(h, kKindEnumerate, enumerate_kernel<kEnumWideWords>, dim3(h->num_tiles), dim3(kEnumWaves * 64),
-                 s, h->dev, type, eo);
+    with_width(h, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    launch_timed(h, kKindEnumerate, enumerate_kernel<kEnumWideWords, kLG>, dim3(h->num_tiles), dim3(kEnumWaves * 64),
+                 s, DevHeapW<kLG>(h->dev), type, eo);
+  });
   else
-    launch_timed(h, kKindEnumerate, enumerate_kernel<1>, dim3(h->num_tiles), dim3(kEnumWaves * 64), s, h->dev,
+    with_width(h, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    launch_timed(h, kKindEnumerate, enumerate_kernel<1, kLG>, dim3(h->num_tiles), dim3(kEnumWaves * 64), s, DevHeapW<kLG>(h->dev),
                  type, eo);
+  });
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }
@@ -994,8 +1057,11 @@ int dsoar_heap_check(dsoar_heap* h, uint32_t* violations, void* stream) {
 int dsoar_alloc_n(dsoar_heap* h, uint32_t type, uint32_t n, dsoar_obj* out_dev, void* stream) {
   if (!heap_ok(h) || type >= h->desc.num_types || (!out_dev && n)) return DSOAR_ERR_INVALID_ARG;
   if (n == 0) return DSOAR_OK;
-  hipLaunchKernelGGL(alloc_n_kernel, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, (hipStream_t)stream, h->dev,
+  with_width(h, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    hipLaunchKernelGGL(alloc_n_kernel<kLG>, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, (hipStream_t)stream, DevHeapW<kLG>(h->dev),
                      type, n, out_dev);
+  });
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }
@@ -1006,8 +1072,11 @@ int dsoar_stress_churn(dsoar_heap* h, uint32_t n, uint32_t rounds, uint32_t keep
     return DSOAR_ERR_INVALID_ARG;
   for (uint32_t t = 0; t < h->desc.num_types; ++t)
     if (h->desc.types[t].field_bytes[0] != 4) return DSOAR_ERR_INVALID_ARG;
-  hipLaunchKernelGGL(churn_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, h->dev, n, rounds, keep,
+  with_width(h, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    hipLaunchKernelGGL(churn_kernel<kLG>, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, DevHeapW<kLG>(h->dev), n, rounds, keep,
                      spread, seed, out_dev, errors_dev);
+  });
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }
@@ -1015,8 +1084,11 @@ int dsoar_stress_churn(dsoar_heap* h, uint32_t n, uint32_t rounds, uint32_t keep
 int dsoar_free_n(dsoar_heap* h, const dsoar_obj* objs_dev, uint32_t n, void* stream) {
   if (!heap_ok(h) || (!objs_dev && n)) return DSOAR_ERR_INVALID_ARG;
   if (n == 0) return DSOAR_OK;
-  hipLaunchKernelGGL(free_n_kernel, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, (hipStream_t)stream, h->dev,
+  with_width(h, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    hipLaunchKernelGGL(free_n_kernel<kLG>, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, (hipStream_t)stream, DevHeapW<kLG>(h->dev),
                      objs_dev, n);
+  });
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }

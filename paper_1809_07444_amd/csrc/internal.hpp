@@ -120,6 +120,18 @@ inline void launch_timed(dsoar_heap* h, uint32_t kind, K kernel, dim3 grid, dim3
   }
 }
 
+// Kernels that touch the block-state bitmaps are instantiated once per
+// container width, taking their heap as a DevHeapW<LG>; with_width calls f
+// with the width of this heap as a compile-time constant, for the launch of
+// the matching instance.
+template <class F>
+inline void with_width(const dsoar_heap* h, F&& f) {
+  if (h->dev.bm_lg == 6)
+    f(std::integral_constant<uint32_t, 6>{});
+  else
+    f(std::integral_constant<uint32_t, 5>{});
+}
+
 int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s);
 int read_count(dsoar_heap* h, uint32_t type, hipStream_t s, uint32_t* count);
 
@@ -129,7 +141,9 @@ int read_count(dsoar_heap* h, uint32_t type, hipStream_t s, uint32_t* count);
 //   static __device__ bool apply(const DevHeap&, uint32_t type, uint32_t self, const Args&, const Pre&);
 // load must not write memory and may read only fields of `self` (it also runs
 // for the empty slots of a listed block, whose values it must not use); apply
-// may write only the fields of `self` (besides creating objects).  The do-all then issues the loads of U blocks
+// may write the fields of `self`, create objects, and write state that no
+// load phase of the do-all reads (objects of other types, grids), since the
+// loads of later blocks are issued before earlier blocks are applied.  The do-all then issues the loads of U blocks
 // before it applies the method to any of them, so a wavefront keeps U times
 // more bytes in flight; this is what lets a do-all over a heap larger than
 // the caches approach the HBM bandwidth.
@@ -151,10 +165,10 @@ struct HasSplit<M, std::void_t<typename M::Pre>> : std::true_type {};
 template <class M, class = void>
 struct HasWave : std::false_type {};
 template <class M>
-struct HasWave<M, std::void_t<decltype(&M::run_wave)>> : std::true_type {};
+struct HasWave<M, std::void_t<decltype(&M::template run_wave<DevHeap>)>> : std::true_type {};
 
-template <class Method>
-__device__ __forceinline__ bool run_method(const DevHeap& h, uint32_t type, uint32_t self,
+template <class Method, class H>
+__device__ __forceinline__ bool run_method(const H& h, uint32_t type, uint32_t self,
                                            const typename Method::Args& a) {
   if constexpr (HasSplit<Method>::value)
     return Method::apply(h, type, self, a, Method::load(h, type, self, a));
@@ -164,8 +178,8 @@ __device__ __forceinline__ bool run_method(const DevHeap& h, uint32_t type, uint
 
 // The method on one lane's slot: every lane enters for a wavefront method,
 // only live lanes otherwise.
-template <class Method>
-__device__ __forceinline__ bool run_slot(const DevHeap& h, uint32_t type, uint32_t self, bool live,
+template <class Method, class H>
+__device__ __forceinline__ bool run_slot(const H& h, uint32_t type, uint32_t self, bool live,
                                          const typename Method::Args& a) {
   if constexpr (HasWave<Method>::value) {
     const bool del = Method::run_wave(h, type, self, live, a);
@@ -208,8 +222,8 @@ struct SplitPass {
 // (all slots of a listed block are addressable): the loads are straight-line
 // code.  The two pass buffers alternate so that no loaded value is copied
 // between registers before it is used.
-template <class Method, uint32_t U>
-__device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, const uint32_t* __restrict__ R,
+template <class Method, uint32_t U, class H>
+__device__ __forceinline__ void doall_split64(const H& h, uint32_t type, const uint32_t* __restrict__ R,
                                               const uint64_t* __restrict__ S, uint32_t count, uint32_t gw,
                                               uint32_t nw, const typename Method::Args& args, uint32_t& visits,
                                               uint32_t& freed) {
@@ -369,8 +383,8 @@ __device__ __forceinline__ void doall_split64(const DevHeap& h, uint32_t type, c
 // returning true to delete self, or the load / apply pair described above.
 // One wavefront's share of a do-all over one list: entries gw, gw + nw, ...
 // (or passes of several entries), visit and free counts accumulated.
-template <class Method>
-__device__ __forceinline__ void doall_list(const DevHeap& h, uint32_t type, const uint32_t* __restrict__ R,
+template <class Method, class H>
+__device__ __forceinline__ void doall_list(const H& h, uint32_t type, const uint32_t* __restrict__ R,
                                            const uint64_t* __restrict__ S, uint32_t count, uint32_t gw,
                                            uint32_t nw, const typename Method::Args& args, uint32_t& visits,
                                            uint32_t& freed) {
@@ -424,8 +438,8 @@ __device__ __forceinline__ uint32_t grid_wave() {
   return blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
-template <class Method>
-__global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, const uint32_t* __restrict__ R,
+template <class Method, uint32_t LG>
+__global__ void __launch_bounds__(1024) doall_kernel(DevHeapW<LG> h, uint32_t type, const uint32_t* __restrict__ R,
                                                       const uint64_t* __restrict__ S, const uint32_t* count_ptr,
                                                       typename Method::Args args) {
   const uint32_t nw = gridDim.x * (blockDim.x >> 6);
@@ -439,8 +453,8 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeap h, uint32_t type, c
 // takes its share of the first list, then of the second.  For methods that
 // may run at the same time (neither reads what the other writes, apart from
 // the heap's own atomics): one kernel boundary and one launch fewer.
-template <class M1, class M2>
-__global__ void __launch_bounds__(1024) doall2_kernel(DevHeap h, uint32_t t1, const uint32_t* __restrict__ R1,
+template <class M1, class M2, uint32_t LG>
+__global__ void __launch_bounds__(1024) doall2_kernel(DevHeapW<LG> h, uint32_t t1, const uint32_t* __restrict__ R1,
                                                        const uint64_t* __restrict__ S1, const uint32_t* c1,
                                                        typename M1::Args a1, uint32_t t2,
                                                        const uint32_t* __restrict__ R2,
@@ -480,8 +494,11 @@ int launch_doall(dsoar_heap* h, uint32_t type, const typename Method::Args& args
   } else {
     grid = h->num_cus * h->doall_wgs_per_cu;
   }
-  launch_timed(h, Method::kKind, doall_kernel<Method>, dim3(grid), dim3(threads), s, h->dev, type,
+  with_width(h, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    launch_timed(h, Method::kKind, doall_kernel<Method, kLG>, dim3(grid), dim3(threads), s, DevHeapW<kLG>(h->dev), type,
                (const uint32_t*)eo.R, (const uint64_t*)eo.S, (const uint32_t*)&eo.st->count, args);
+  });
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }
@@ -519,10 +536,13 @@ int launch_doall2(dsoar_heap* h, uint32_t t1, const typename M1::Args& a1, uint3
   if (t1 >= h->desc.num_types || t2 >= h->desc.num_types) return DSOAR_ERR_INVALID_ARG;
   const EnumOut& e1 = h->enum_out[t1];
   const EnumOut& e2 = h->enum_out[t2];
-  launch_timed(h, kind, doall2_kernel<M1, M2>, dim3(h->num_cus * h->doall_wgs_per_cu),
-               dim3(h->doall_wg_threads), s, h->dev, t1, (const uint32_t*)e1.R, (const uint64_t*)e1.S,
+  with_width(h, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    launch_timed(h, kind, doall2_kernel<M1, M2, kLG>, dim3(h->num_cus * h->doall_wgs_per_cu),
+               dim3(h->doall_wg_threads), s, DevHeapW<kLG>(h->dev), t1, (const uint32_t*)e1.R, (const uint64_t*)e1.S,
                (const uint32_t*)&e1.st->count, a1, t2, (const uint32_t*)e2.R, (const uint64_t*)e2.S,
                (const uint32_t*)&e2.st->count, a2);
+  });
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }

@@ -13,10 +13,12 @@ struct MicroUpdate {
   static constexpr uint32_t kKind = 20;
   struct Args { uint32_t unused; };
   struct Pre { float x, v; };
-  static __device__ Pre load(const DevHeap& h, uint32_t type, uint32_t self, const Args&) {
+  template <class H>
+  static __device__ Pre load(const H& h, uint32_t type, uint32_t self, const Args&) {
     return {*field_ptr<float>(h, self, type, kX), *field_ptr<float>(h, self, type, kV)};
   }
-  static __device__ bool apply(const DevHeap& h, uint32_t type, uint32_t self, const Args&, const Pre& p) {
+  template <class H>
+  static __device__ bool apply(const H& h, uint32_t type, uint32_t self, const Args&, const Pre& p) {
     *field_ptr<float>(h, self, type, kX) = __builtin_fmaf(0.01f, p.v, p.x);  // one rounding
     return false;
   }
@@ -26,7 +28,8 @@ struct MicroCull {
   static constexpr uint32_t kKind = 21;
   struct Args { uint32_t unused; };
   struct Pre { int32_t id; };
-  static __device__ Pre load(const DevHeap& h, uint32_t type, uint32_t self, const Args&) {
+  template <class H>
+  static __device__ Pre load(const H& h, uint32_t type, uint32_t self, const Args&) {
     return {*field_ptr<int32_t>(h, self, type, kId)};
   }
   static __device__ bool apply(const DevHeap&, uint32_t, uint32_t, const Args&, const Pre& p) {
@@ -45,7 +48,8 @@ constexpr uint32_t kCreatePerLane = 4;
 constexpr uint32_t kCreateWideMin = 1u << 22;
 constexpr uint32_t kCreateThreads = 256;
 
-__global__ void micro_create_kernel(DevHeap h, uint32_t type, uint32_t n, uint32_t per_lane, uint32_t id_mul,
+template <uint32_t LG>
+__global__ void micro_create_kernel(DevHeapW<LG> h, uint32_t type, uint32_t n, uint32_t per_lane, uint32_t id_mul,
                                     const float* xs, const float* vs) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t wave = (uint64_t)blockIdx.x * (kCreateThreads / 64) + (threadIdx.x >> 6);
@@ -72,8 +76,11 @@ int launch_create(dsoar_heap* h, uint32_t type, uint32_t n, uint32_t id_mul, con
   if (n == 0) return DSOAR_OK;
   const uint32_t per_lane = n >= kCreateWideMin ? kCreatePerLane : 1u;
   const uint64_t per_block = (uint64_t)kCreateThreads * per_lane;
-  launch_timed(h, kKindMicroCreate, micro_create_kernel, dim3((uint32_t)((n + per_block - 1) / per_block)),
-               dim3(kCreateThreads), s, h->dev, type, n, per_lane, id_mul, xs, vs);
+  with_width(h, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    launch_timed(h, kKindMicroCreate, micro_create_kernel<kLG>, dim3((uint32_t)((n + per_block - 1) / per_block)),
+               dim3(kCreateThreads), s, DevHeapW<kLG>(h->dev), type, n, per_lane, id_mul, xs, vs);
+  });
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }

@@ -89,8 +89,8 @@ __device__ __forceinline__ uint32_t wrap_cell(uint32_t off, int32_t side, int32_
   return off + (uint32_t)y * (uint32_t)side + (uint32_t)x;
 }
 
-template <class F>
-__device__ __forceinline__ F& af(const DevHeap& h, uint32_t self, uint32_t field) {
+template <class F, class H>
+__device__ __forceinline__ F& af(const H& h, uint32_t self, uint32_t field) {
   return *field_ptr<F>(h, self, kAgent, field);
 }
 
@@ -117,7 +117,8 @@ constexpr int32_t kMaxVision = 6;
 struct Choose {
   static constexpr uint32_t kKind = 40;
   using Args = Grid;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& g) {
     const uint32_t p = af<uint32_t>(h, self, kPos);
     const int32_t vision = af<int32_t>(h, self, kVision);
     const Where c = where(g, af<uint32_t>(h, self, kWorld), p);
@@ -165,7 +166,8 @@ struct Choose {
 struct Move {
   static constexpr uint32_t kKind = 41;
   using Args = Grid;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& g) {
     const uint32_t p = af<uint32_t>(h, self, kPos);
     const uint32_t q = af<uint32_t>(h, self, kTarget);
     const uint32_t wid = af<uint32_t>(h, self, kWorld);
@@ -195,7 +197,8 @@ struct Move {
 struct Eat {
   static constexpr uint32_t kKind = 42;
   using Args = Grid;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& g) {
     const uint32_t p = af<uint32_t>(h, self, kPos);
     const int32_t sugar = af<int32_t>(h, self, kSugar) + sugar_of(g.sugar[p]) - af<int32_t>(h, self, kMetab);
     const int32_t age = af<int32_t>(h, self, kAge) + 1;
@@ -214,7 +217,8 @@ struct Eat {
 struct Request {
   static constexpr uint32_t kKind = 43;
   using Args = Grid;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& g) {
     const int32_t sugar = af<int32_t>(h, self, kSugar), age = af<int32_t>(h, self, kAge);
     uint32_t best = kNull;
     if (sugar >= g.repro_min && age >= g.fertile_min && age <= g.fertile_max) {
@@ -236,7 +240,8 @@ struct Request {
 struct Birth {
   static constexpr uint32_t kKind = 44;
   using Args = Grid;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& g) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& g) {
     const uint32_t n = af<uint32_t>(h, self, kTarget);
     const uint32_t p = af<uint32_t>(h, self, kPos);
     const uint32_t wid = af<uint32_t>(h, self, kWorld);
@@ -269,7 +274,8 @@ struct Birth {
 struct SugarDeleteWorld {
   static constexpr uint32_t kKind = 45;
   struct Args { uint32_t slot; };
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
     return af<uint32_t>(h, self, kWorld) == a.slot;
   }
 };
@@ -307,7 +313,8 @@ __global__ void sugar_check_kernel(const int32_t* sugar, const int32_t* cap, uin
   if (__ballot(out) && is_first_active()) *bad = 1;
 }
 
-__global__ void sugar_admit_kernel(DevHeap h, Grid g, uint32_t slot, uint32_t off, uint32_t n, const int32_t* sugar,
+template <uint32_t LG>
+__global__ void sugar_admit_kernel(DevHeapW<LG> h, Grid g, uint32_t slot, uint32_t off, uint32_t n, const int32_t* sugar,
                                    const int32_t* cap, const uint8_t* occ, const int32_t* as, const int32_t* am,
                                    const int32_t* av, const int32_t* aa) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -482,9 +489,12 @@ int dsoar_sugar_admit(dsoar_sugar* s, uint32_t slot, uint32_t cell_offset, uint3
   if (bad) return DSOAR_ERR_INVALID_ARG;
   hipLaunchKernelGGL(set_world_kernel, dim3(1), dim3(kMoveShards), 0, st, s->g, slot, cell_offset, side, seed, step0);
   DSOAR_LAUNCHED(s->heap);
-  launch_timed(s->heap, kKindSugarAdmit, sugar_admit_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), st, s->heap->dev, s->g, slot,
+  with_width(s->heap, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    launch_timed(s->heap, kKindSugarAdmit, sugar_admit_kernel<kLG>, dim3((uint32_t)((n + 255) / 256)), dim3(256), st, DevHeapW<kLG>(s->heap->dev), s->g, slot,
                      cell_offset, (uint32_t)n, sugar_dev, cap_dev, occ_dev, a_sugar_dev, a_metab_dev, a_vision_dev,
                      a_age_dev);
+  });
   DSOAR_LAUNCHED(s->heap);
   s->h_off[slot] = cell_offset;
   s->h_side[slot] = side;

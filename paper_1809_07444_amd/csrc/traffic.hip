@@ -50,15 +50,16 @@ struct Road {
   uint32_t p_slow24, p_in24;
 };
 
-template <class F>
-__device__ __forceinline__ F& car(const DevHeap& h, uint32_t self, uint32_t field) {
+template <class F, class H>
+__device__ __forceinline__ F& car(const H& h, uint32_t self, uint32_t field) {
   return *field_ptr<F>(h, self, kCar, field);
 }
 
 struct Decide {
   static constexpr uint32_t kKind = 50;
   using Args = Road;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
     const uint32_t c = car<uint32_t>(h, self, kCellF);
     const int32_t v0 = car<int32_t>(h, self, kSpeed);
     const uint32_t i = c % a.length;
@@ -83,7 +84,8 @@ struct Decide {
 struct Drive {
   static constexpr uint32_t kKind = 51;
   using Args = Road;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
     const int32_t v = car<int32_t>(h, self, kNext);
     car<int32_t>(h, self, kSpeed) = v;
     if (v == 0) return false;
@@ -100,7 +102,8 @@ struct Drive {
 // step advances: each workgroup counts itself done after all its threads have
 // used t, and the last one to do so stores t + 1 (and resets the count), so no
 // thread of this launch can read the new value.
-__global__ void entry_kernel(DevHeap h, Road a) {
+template <uint32_t LG>
+__global__ void entry_kernel(DevHeapW<LG> h, Road a) {
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t t = a.step[0];
   if (r < a.roads) {
@@ -126,7 +129,8 @@ __global__ void entry_kernel(DevHeap h, Road a) {
 }
 
 // Initial state: a car in every cell whose speed is >= 0.
-__global__ void traffic_init_kernel(DevHeap h, Road a, const int32_t* vel, uint32_t step0) {
+template <uint32_t LG>
+__global__ void traffic_init_kernel(DevHeapW<LG> h, Road a, const int32_t* vel, uint32_t step0) {
   const uint64_t n = (uint64_t)a.roads * a.length;
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c == 0) {
@@ -182,7 +186,10 @@ int traffic_one_step(dsoar_traffic* t, uint32_t flags, hipStream_t st) {
   // Decide creates and deletes nothing: Drive reuses its list.
   if (!rc) rc = launch_doall<Drive>(h, kCar, t->a, base | DSOAR_DO_REUSE_ENUM, st);
   if (rc) return rc;
-  launch_timed(h, kKindTrafficEntry, entry_kernel, dim3((t->a.roads + 255) / 256), dim3(256), st, h->dev, t->a);
+  with_width(h, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    launch_timed(h, kKindTrafficEntry, entry_kernel<kLG>, dim3((t->a.roads + 255) / 256), dim3(256), st, DevHeapW<kLG>(h->dev), t->a);
+  });
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
 }
@@ -234,8 +241,11 @@ int dsoar_traffic_destroy(dsoar_traffic* t) {
 int dsoar_traffic_init(dsoar_traffic* t, const int32_t* vel_dev, uint32_t step0, void* stream) {
   if (!t || !vel_dev) return DSOAR_ERR_INVALID_ARG;
   const uint64_t n = (uint64_t)t->a.roads * t->a.length;
-  launch_timed(t->heap, kKindTrafficInit, traffic_init_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), (hipStream_t)stream,
-                     t->heap->dev, t->a, vel_dev, step0);
+  with_width(t->heap, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    launch_timed(t->heap, kKindTrafficInit, traffic_init_kernel<kLG>, dim3((uint32_t)((n + 255) / 256)), dim3(256), (hipStream_t)stream,
+                     DevHeapW<kLG>(t->heap->dev), t->a, vel_dev, step0);
+  });
   DSOAR_LAUNCHED(t->heap);
   return DSOAR_OK;
 }

@@ -81,19 +81,20 @@ __device__ __forceinline__ uint32_t nb(uint32_t side, uint32_t c, uint32_t d) {
   return ny * side + nx;
 }
 
-template <class F>
-__device__ __forceinline__ F& fish(const DevHeap& h, uint32_t self, uint32_t field) {
+template <class F, class H>
+__device__ __forceinline__ F& fish(const H& h, uint32_t self, uint32_t field) {
   return *field_ptr<F>(h, self, kFish, field);
 }
-template <class F>
-__device__ __forceinline__ F& shark(const DevHeap& h, uint32_t self, uint32_t field) {
+template <class F, class H>
+__device__ __forceinline__ F& shark(const H& h, uint32_t self, uint32_t field) {
   return *field_ptr<F>(h, self, kShark, field);
 }
 
 struct FishDecide {
   static constexpr uint32_t kKind = 70;
   using Args = Sea;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
     const uint32_t t = a.step[0];
     const uint32_t c = fish<uint32_t>(h, self, kPos);
     uint32_t opt[4], m = 0;
@@ -115,7 +116,8 @@ struct FishDecide {
 struct FishMove {
   static constexpr uint32_t kKind = 71;
   using Args = Sea;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
     const uint32_t t = a.step[0];
     const uint32_t c = fish<uint32_t>(h, self, kPos), target = fish<uint32_t>(h, self, kFTarget);
     const int32_t age = fish<int32_t>(h, self, kAge) + 1;
@@ -140,7 +142,8 @@ struct FishMove {
 struct SharkDecide {
   static constexpr uint32_t kKind = 72;
   using Args = Sea;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
     const uint32_t t = a.step[0];
     const uint32_t c = shark<uint32_t>(h, self, kPos);
     uint32_t fishn[4], empty[4], nf = 0, ne = 0;
@@ -167,7 +170,8 @@ struct SharkDecide {
 struct SharkMove {
   static constexpr uint32_t kKind = 73;
   using Args = Sea;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
     const uint32_t t = a.step[0];
     const uint32_t c = shark<uint32_t>(h, self, kPos), target = shark<uint32_t>(h, self, kSTarget);
     const bool won = target != kNone && a.req[target] == req_key(2 * t + 1, c);
@@ -202,7 +206,8 @@ struct SharkMove {
 struct FishEaten {
   static constexpr uint32_t kKind = 74;
   using Args = Sea;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
     return a.kind[fish<uint32_t>(h, self, kPos)] != kIsFish;
   }
 };
@@ -215,7 +220,8 @@ struct ReadArgs {
 struct FishRead {
   static constexpr uint32_t kKind = 75;
   using Args = ReadArgs;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
     a.age[fish<uint32_t>(h, self, kPos)] = fish<int32_t>(h, self, kAge);
     return false;
   }
@@ -224,7 +230,8 @@ struct FishRead {
 struct SharkRead {
   static constexpr uint32_t kKind = 76;
   using Args = ReadArgs;
-  static __device__ bool run(const DevHeap& h, uint32_t, uint32_t self, const Args& a) {
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
     const uint32_t c = shark<uint32_t>(h, self, kPos);
     a.age[c] = shark<int32_t>(h, self, kAge);
     a.energy[c] = shark<int32_t>(h, self, kEnergy);
@@ -235,7 +242,8 @@ struct SharkRead {
 __global__ void tick_kernel(Sea a) { a.step[0] += 1; }
 
 // Creates the objects of the initial sea, in cell order.
-__global__ void wator_init_kernel(DevHeap h, Sea a, const int32_t* kind, const int32_t* age, const int32_t* energy,
+template <uint32_t LG>
+__global__ void wator_init_kernel(DevHeapW<LG> h, Sea a, const int32_t* kind, const int32_t* age, const int32_t* energy,
                                   uint32_t step0) {
   const uint64_t n = (uint64_t)a.side * a.side;
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -361,8 +369,11 @@ int dsoar_wator_init(dsoar_wator* w, const int32_t* kind_dev, const int32_t* age
                      uint32_t step0, void* stream) {
   if (!w || !kind_dev || !age_dev || !energy_dev) return DSOAR_ERR_INVALID_ARG;
   const uint64_t n = (uint64_t)w->a.side * w->a.side;
-  launch_timed(w->heap, kKindWatorInit, wator_init_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), (hipStream_t)stream,
-                     w->heap->dev, w->a, kind_dev, age_dev, energy_dev, step0);
+  with_width(w->heap, [&](auto w_) {
+    constexpr uint32_t kLG = decltype(w_)::value;
+    launch_timed(w->heap, kKindWatorInit, wator_init_kernel<kLG>, dim3((uint32_t)((n + 255) / 256)), dim3(256), (hipStream_t)stream,
+                     DevHeapW<kLG>(w->heap->dev), w->a, kind_dev, age_dev, energy_dev, step0);
+  });
   DSOAR_LAUNCHED(w->heap);
   return DSOAR_OK;
 }

@@ -31,6 +31,20 @@ TRACE_NAMES = {
     "unsigned int, unsigned int, unsigned char const*)": "gol_init",
     "dsoar::(anonymous namespace)::regrow_kernel(dsoar::(anonymous namespace)::Grid)": "sugar_regrow",
     "dsoar::(anonymous namespace)::init_heap_kernel(dsoar::DevHeap, unsigned long)": None,
+    # Instances per bitmap container width.
+    "void dsoar::doall_kernel<dsoar::(anonymous namespace)::AlivePrep, 6u>(dsoar::DevHeapW<6u>, unsigned int, "
+    "unsigned int const*, unsigned long const*, unsigned int const*, "
+    "dsoar::(anonymous namespace)::AlivePrep::Args)": "gol_alive_prep",
+    "void dsoar::doall2_kernel<dsoar::(anonymous namespace)::AliveUpdate, dsoar::(anonymous namespace)::"
+    "CandUpdate, 5u>(dsoar::DevHeapW<5u>, unsigned int, unsigned int const*, unsigned long const*, "
+    "unsigned int const*, dsoar::(anonymous namespace)::AliveUpdate::Args, unsigned int, unsigned int const*, "
+    "unsigned long const*, unsigned int const*, dsoar::(anonymous namespace)::CandUpdate::Args)": "gol_update",
+    "void dsoar::(anonymous namespace)::enumerate_kernel<8u, 6u>(dsoar::DevHeapW<6u>, unsigned int, "
+    "dsoar::EnumOut)": "enumerate",
+    "void dsoar::(anonymous namespace)::gol_init_kernel<6u>(dsoar::DevHeapW<6u>, "
+    "dsoar::(anonymous namespace)::World, unsigned int, unsigned int, unsigned char const*)": "gol_init",
+    "void dsoar::(anonymous namespace)::entry_kernel<5u>(dsoar::DevHeapW<5u>, dsoar::(anonymous namespace)::Road)":
+        "traffic_entry",
     "void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add<int>, "
     "std::array<char*, 2ul> >(int, at::native::CUDAFunctorOnSelf_add<int>, std::array<char*, 2ul>)":
         "calibration",
