@@ -261,6 +261,21 @@ int dsoar_last_hip_error(const dsoar_heap* heap);
  * the heap. */
 int dsoar_enumerate(dsoar_heap* heap, uint32_t type, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the enumeration
+ * of dsoar_enumerate, block reclamation included, written to the caller's
+ * R_dev (uint32, at least num_blocks entries), S_dev (uint64, as many) and
+ * count_dev (one uint32), with the scan's ticket, epoch and look-back words
+ * in a fixed scratch array of the library (about 128 KiB per GPU, held until
+ * the process ends) instead of the heap's buffer; allocates nothing.  Covers
+ * heaps of up to 2^26 - 1 blocks, the largest dsoar_heap_create accepts;
+ * other arguments out of range: DSOAR_ERR_INVALID_ARG.  Every call on one GPU
+ * shares that GPU's scratch (each call clears what it needs first), so calls
+ * that overlap on one GPU, on different streams or from different threads,
+ * race and must be ordered by the caller. */
+int dsoar_enumerate_noalloc(dsoar_heap* heap, uint32_t type, uint32_t* R_dev, uint64_t* S_dev,
+                            uint32_t* count_dev, void* stream);
+
 /* Reads back the count of the last enumeration of `type` (synchronises). */
 int dsoar_enum_count(dsoar_heap* heap, uint32_t type, uint32_t* count, void* stream);
 

@@ -120,6 +120,7 @@ SIGNATURES = {
     "dsoar_heap_set_timing": (ctypes.c_int, [H, ctypes.c_int]),
     "dsoar_heap_timing": (ctypes.c_int, [H, vp, vp, vp, u32, ctypes.POINTER(u32)]),
     "dsoar_enumerate": (ctypes.c_int, [H, u32, vp]),
+    "dsoar_enumerate_noalloc": (ctypes.c_int, [H, u32, vp, vp, vp, vp]),
     "dsoar_enum_count": (ctypes.c_int, [H, u32, ctypes.POINTER(u32), vp]),
     "dsoar_enum_arrays": (ctypes.c_int, [H, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
     "dsoar_reclaim": (ctypes.c_int, [H, vp]),

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -664,6 +665,34 @@ int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s) {
   return launch_enumerate_into(h, type, h->enum_out[type], s);
 }
 
+// Scratch of the allocation-free enumeration (dsoar_enumerate_noalloc): the
+// scan state and one look-back word per tile, sized for the largest heap
+// (2^26 - 1 blocks: 2^20 level-0 groups, 64 per tile).  Each device holds
+// its own copy; host code uses the address hipGetSymbolAddress returns for
+// the current device, never the symbol itself.
+constexpr uint32_t kStaticTiles = 16384;
+constexpr uint32_t kScratchWords = 2 + kStaticTiles;  // ScanState, then the tile flags
+static_assert(sizeof(ScanState) == 16, "scan state is two words");
+static __device__ __align__(256) uint64_t scratch[kScratchWords];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// This device's copy of the scratch array (looked up once per device).
+static int scratch_ptr(dsoar_heap* h, uint64_t** out) {
+  int dev = 0;
+  DSOAR_HIP(h, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return DSOAR_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    DSOAR_HIP(h, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (uint64_t*)g_scratch_ptr[dev];
+  return DSOAR_OK;
+}
 
 int read_count(dsoar_heap* h, uint32_t type, hipStream_t s, uint32_t* count) {
   DSOAR_HIP(h, hipMemcpyAsync(count, &h->enum_out[type].st->count, 4, hipMemcpyDeviceToHost, s));
@@ -980,6 +1009,26 @@ int dsoar_heap_set_unroll(dsoar_heap* h, uint32_t blocks_per_pass) {
 int dsoar_enumerate(dsoar_heap* h, uint32_t type, void* stream) {
   if (!heap_ok(h) || type >= h->desc.num_types) return DSOAR_ERR_INVALID_ARG;
   return launch_enumerate(h, type, (hipStream_t)stream);
+}
+
+int dsoar_enumerate_noalloc(dsoar_heap* h, uint32_t type, uint32_t* R_dev, uint64_t* S_dev, uint32_t* count_dev,
+                            void* stream) {
+  if (!heap_ok(h) || type >= h->desc.num_types || !R_dev || !S_dev || !count_dev) return DSOAR_ERR_INVALID_ARG;
+  if (h->num_tiles > kStaticTiles) return DSOAR_ERR_INVALID_ARG;  // larger than the scratch covers
+  uint64_t* sp = nullptr;
+  const int rc = scratch_ptr(h, &sp);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  ScanState* st = reinterpret_cast<ScanState*>(sp);
+  uint64_t* flags = sp + 2;
+  // The scratch keeps the last call's contents: the ticket, epoch and this
+  // heap's tile flags start from zero (a fill kernel, so that the call can
+  // be captured in a graph).
+  hipLaunchKernelGGL(init_scan_kernel, dim3(grid_for(h->num_tiles, 256, 1024)), dim3(256), 0, s, st, flags,
+                     h->num_tiles);
+  DSOAR_LAUNCHED(h);
+  const EnumOut eo{R_dev, S_dev, st, flags, h->num_tiles, count_dev};
+  return launch_enumerate_into(h, type, eo, s);
 }
 
 int dsoar_enum_count(dsoar_heap* h, uint32_t type, uint32_t* count, void* stream) {
