@@ -33,27 +33,52 @@ constexpr uint32_t kKindGolUpdate = 35;  // timing id of the fused phases 3 and 
 // Beside the position -> Cell handle index, a live plane holds a copy of
 // every Cell's live flag, one byte per cell in the index's order (kDead,
 // kLive, or kNoCell where the Cell is missing, only after an out-of-memory
-// init).  The neighbourhood reads of phases 1 and 2 load these bytes: five
-// adjacent cells of a row are one pair of dword loads, and a 1024 x 1024
-// world's plane is 1 MB, so the rows around a wavefront's cells stay in its
-// XCD's L2 where four-byte index words did not.
+// init); phases 3 and 4 write it with plain byte stores.  At the start of
+// each generation a pack kernel turns it into a live-bit plane, one bit per
+// cell (bit g % 32 of word g / 32), which the neighbourhood reads of phases 1
+// and 2 load: a row's five cells are one pair of dword loads.  The bit plane
+// is an eighth of the byte plane (6 MB for 48.8 M cells), so the rows that
+// the neighbourhoods of a wavefront's scattered cells touch are fewer cache
+// lines, and more of them are shared with other wavefronts.
 constexpr uint8_t kDead = 0, kLive = 1, kNoCell = 2;
 
 struct World {
   const uint32_t* cells;  // global cell index -> Cell handle (kNull if missing)
   const uint8_t* live;    // global cell index -> kDead / kLive / kNoCell
+  const uint32_t* bits;   // live bits, packed from `live` each generation
   const uint32_t* off;    // world -> first global cell index (num_worlds + 1 entries)
   const uint32_t* side;   // world -> side length
+  uint32_t total;         // cells of the index (the arena in pool mode)
 };
 
 // Sets the live state of the Cell at global index g (its field and the copy
 // in the live plane); only the cell's own Alive or Candidate does this.
+// False if the Cell is missing (after an out-of-memory init).
 template <class H>
-__device__ __forceinline__ void set_live(const H& h, const World& w, uint32_t g, uint32_t live) {
+__device__ __forceinline__ bool set_live(const H& h, const World& w, uint32_t g, uint32_t live) {
   const uint32_t wd = w.cells[g];
-  if (wd == kNull) return;
+  if (wd == kNull) return false;
   *field_ptr<uint32_t>(h, wd, kCell, kCAlive) = live;
   const_cast<uint8_t*>(w.live)[g] = live ? kLive : kDead;
+  return true;
+}
+
+// The live-bit plane from the byte plane: word i holds cells 32i .. 32i + 31
+// (a live byte is 1; the byte plane is padded, so the last word's reads stay
+// in the buffer).
+__global__ void gol_pack_kernel(World w, uint32_t words) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= words) return;
+  const uint4* p = reinterpret_cast<const uint4*>(w.live + (uint64_t)i * 32);
+  const uint4 a = p[0], b = p[1];
+  const uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  uint32_t v = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k) {
+    const uint32_t x = d[k] & 0x01010101u;  // bit 0 of each byte: live (kNoCell is 2)
+    v |= ((x & 1u) | ((x >> 7) & 2u) | ((x >> 14) & 4u) | ((x >> 21) & 8u)) << (4 * k);
+  }
+  const_cast<uint32_t*>(w.bits)[i] = v;
 }
 
 // Global index of neighbour d (0..7: the row above, left and right, the row
@@ -104,40 +129,35 @@ __device__ __forceinline__ uint32_t torus_add(uint32_t x, int dx, uint32_t side)
 }
 
 // The (2R + 1) x (2R + 1) neighbourhood of cell (x, y) of the world at `off`
-// with side `side`, from the live plane: bit (dy + R) * (2R + 1) + (dx + R)
-// of *alive is set for a live cell at offset (dx, dy), of *nocell for a
-// missing Cell; the centre is left out.  A row whose window does not wrap
-// around the torus is one aligned pair of dword loads shifted into place
-// (the plane is padded, so a read past the last cell stays in the buffer);
-// a row that wraps loads its cells one by one.
+// with side `side`, from the live-bit plane: bit (dy + R) * (2R + 1) + (dx +
+// R) is set for a live cell at offset (dx, dy); the centre is left out.  A
+// row whose window does not wrap around the torus is one pair of dword loads
+// shifted into place (the bit plane is padded, so a read past the last cell
+// stays in the buffer); a row that wraps loads its cells one by one.
 template <int R>
-__device__ __forceinline__ void neighbourhood(const uint8_t* plane, uint32_t off, uint32_t side, uint32_t x,
-                                              uint32_t y, uint32_t* alive, uint32_t* nocell) {
+__device__ __forceinline__ uint32_t neighbourhood(const uint32_t* bits, uint32_t off, uint32_t side, uint32_t x,
+                                                  uint32_t y) {
   constexpr int D = 2 * R + 1;
   const bool inside = x >= (uint32_t)R && x + R < side;
-  uint32_t al = 0, nc = 0;
+  uint32_t al = 0;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    const uint8_t* row = plane + off + (uint64_t)torus_add(y, i - R, side) * side;
-    uint64_t v = 0;
+    const uint32_t rb = off + torus_add(y, i - R, side) * side;  // bit index of the row's first cell
+    uint32_t v = 0;
     if (inside) {
-      const uintptr_t a = (uintptr_t)(row + x - R);
-      const uint32_t* a4 = reinterpret_cast<const uint32_t*>(a & ~(uintptr_t)3);
-      v = (((uint64_t)a4[1] << 32) | a4[0]) >> ((a & 3u) * 8u);
+      const uint32_t a = rb + x - R;
+      const uint32_t* p = bits + (a >> 5);
+      v = (uint32_t)((((uint64_t)p[1] << 32) | p[0]) >> (a & 31u));
     } else {
 #pragma unroll
-      for (int j = 0; j < D; ++j) v |= (uint64_t)row[torus_add(x, j - R, side)] << (8 * j);
+      for (int j = 0; j < D; ++j) {
+        const uint32_t c = rb + torus_add(x, j - R, side);
+        v |= ((bits[c >> 5] >> (c & 31u)) & 1u) << j;
+      }
     }
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      if (i == R && j == R) continue;
-      const uint32_t b = (uint32_t)(v >> (8 * j)) & 0xFFu;
-      al |= (uint32_t)(b == kLive) << (i * D + j);
-      nc |= (uint32_t)(b == kNoCell) << (i * D + j);
-    }
+    al |= (v & ((1u << D) - 1u)) << (i * D);
   }
-  *alive = al;
-  *nocell = nc;
+  return al & ~(1u << (R * D + R));
 }
 
 struct AlivePrep {
@@ -150,14 +170,14 @@ struct AlivePrep {
     const uint32_t off = w.off[wid], side = w.side[wid];
     const uint32_t local = g - off;
     const uint32_t y = local / side, x = local - y * side;
-    // Live states of the 24 surrounding cells.
-    uint32_t alive, nocell;
-    neighbourhood<2>(w.live, off, side, x, y, &alive, &nocell);
+    // Live states of the 24 surrounding cells.  (A cell whose Cell is
+    // missing reads as dead; its Candidate never becomes an Alive.)
+    const uint32_t alive = neighbourhood<2>(w.bits, off, side, x, y);
     uint32_t claim = 0;
 #pragma unroll
     for (uint32_t d = 0; d < 8; ++d) {
       const uint32_t b = nb_bit(kDirX[d], kDirY[d]);
-      const bool dead = (~(alive | nocell) >> b) & 1u;
+      const bool dead = (~alive >> b) & 1u;
       if (dead && !(alive & owner_mask(d))) claim |= 1u << d;
     }
     const uint32_t live = (uint32_t)__popc(alive & ring_mask());
@@ -184,8 +204,7 @@ struct CandPrep {
     const uint32_t off = w.off[wid], side = w.side[wid];
     const uint32_t local = g - off;
     const uint32_t y = local / side, x = local - y * side;
-    uint32_t alive, nocell;
-    neighbourhood<1>(w.live, off, side, x, y, &alive, &nocell);
+    const uint32_t alive = neighbourhood<1>(w.bits, off, side, x, y);
     *field_ptr<uint32_t>(h, self, type, kAAction) = __popc(alive) == 3 ? 1u : 0u;
     return false;
   }
@@ -210,8 +229,7 @@ struct CandUpdate {
     const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
     const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
     const bool born = *field_ptr<uint32_t>(h, self, type, kAAction) != 0;
-    if (born) {
-      set_live(h, w, g, 1);
+    if (born && set_live(h, w, g, 1)) {
       const uint32_t o = dsoar_new(h, kAlive);
       if (o != kNull) {
         *field_ptr<uint32_t>(h, o, kAlive, kACell) = g;
@@ -318,11 +336,18 @@ bool gol_heap_ok(const dsoar_heap* h) {
 }
 
 // Device buffer of a world set: the world table (offsets and sides), the
-// cell index (4 bytes per cell) and the live plane (1 byte per cell, padded
-// so that a window load past the last cell stays inside).
+// cell index (4 bytes per cell), the live plane (1 byte per cell, padded so
+// that the pack kernel's last 32-byte read stays inside) and the live-bit
+// plane (padded by a word, so that a window's second dword load past the
+// last cell stays inside).
 uint64_t table_head(uint32_t num_worlds) { return ((uint64_t)(2 * num_worlds + 1) * 4 + 255) / 256 * 256; }
 uint64_t index_bytes(uint64_t cells) { return (cells * 4 + 255) / 256 * 256; }
 uint64_t plane_bytes(uint64_t cells) { return (cells + 64 + 255) / 256 * 256; }
+uint64_t bit_words(uint64_t cells) { return (cells + 31) / 32; }
+uint64_t bits_bytes(uint64_t cells) { return ((bit_words(cells) + 2) * 4 + 255) / 256 * 256; }
+uint64_t world_set_bytes(uint32_t num_worlds, uint64_t cells) {
+  return table_head(num_worlds) + index_bytes(cells) + plane_bytes(cells) + bits_bytes(cells);
+}
 
 void carve(World& w, uint8_t* dev_mem, uint32_t num_worlds, uint64_t cells) {
   uint32_t* tab = (uint32_t*)dev_mem;
@@ -330,6 +355,8 @@ void carve(World& w, uint8_t* dev_mem, uint32_t num_worlds, uint64_t cells) {
   w.side = tab + num_worlds + 1;
   w.cells = (const uint32_t*)(dev_mem + table_head(num_worlds));
   w.live = dev_mem + table_head(num_worlds) + index_bytes(cells);
+  w.bits = (const uint32_t*)(w.live + plane_bytes(cells));
+  w.total = (uint32_t)cells;
 }
 
 uint64_t gol_total_cells(uint32_t num_worlds, const uint32_t* sides) {
@@ -359,6 +386,9 @@ namespace {
 int gol_generation(dsoar_gol* g, uint32_t flags, hipStream_t s) {
   dsoar_heap* h = g->heap;
   const uint32_t base = flags & DSOAR_DO_PLAIN;
+  const uint32_t words = (uint32_t)bit_words(g->total);
+  gol_pack_kernel<<<(words + 255) / 256, 256, 0, s>>>(g->w, words);
+  DSOAR_LAUNCHED(h);
   int rc = launch_doall<AlivePrep>(h, kAlive, g->w, base, s);
   if (!rc) rc = launch_doall<CandPrep>(h, kCand, g->w, base, s);
   // Phase 2 creates and deletes nothing, phase 3 touches only Alive objects:
@@ -384,7 +414,7 @@ size_t dsoar_gol_bytes(uint32_t num_worlds, const uint32_t* sides) {
     if (sides[i] < 1 || sides[i] > 65535) return 0;
   const uint64_t total = gol_total_cells(num_worlds, sides);
   if (total >= (1ull << 32)) return 0;
-  return (size_t)(table_head(num_worlds) + index_bytes(total) + plane_bytes(total));
+  return (size_t)world_set_bytes(num_worlds, total);
 }
 
 int dsoar_gol_create(dsoar_heap* heap, uint32_t num_worlds, const uint32_t* sides, void* dev_mem, size_t dev_bytes,
@@ -476,7 +506,7 @@ uint32_t dsoar_gol_total_cells(const dsoar_gol* g) { return g ? g->total : 0; }
 
 size_t dsoar_golpool_bytes(uint32_t max_worlds, uint32_t arena_cells) {
   if (max_worlds == 0 || max_worlds > (1u << 20) || arena_cells == 0) return 0;
-  return (size_t)(table_head(max_worlds) + index_bytes(arena_cells) + plane_bytes(arena_cells));
+  return (size_t)world_set_bytes(max_worlds, arena_cells);
 }
 
 int dsoar_golpool_create(dsoar_heap* heap, uint32_t max_worlds, uint32_t arena_cells, void* dev_mem,
