@@ -85,11 +85,11 @@ def gol_kernel_bytes(kind, launches, st, M, init_alive):
     births, deaths = st["allocs"][A] - init_alive, st["frees"][A]
     if kind == "gol_alive_prep":
         # this: cell and world read, action written; new Candidates: their
-        # three fields; other: the live bytes of the 24 surrounding cells and
+        # three fields; other: the live bits of the 24 surrounding cells and
         # the world's offset and side.
-        return va * 12 + cands * 12 + va / 64 * 12, va * (24 + 8)
+        return va * 12 + cands * 12 + va / 64 * 12, va * (3 + 8)
     if kind == "gol_cand_prep":
-        return vk * 12 + vk / 64 * 12, vk * (8 + 8)
+        return vk * 12 + vk / 64 * 12, vk * (1 + 8)
     if kind == "gol_alive_update":
         # this: action read, and the cell of a dying one; other: its Cell's
         # index word and field and its live byte.
@@ -616,6 +616,7 @@ def serve_bench(args):
     their invariants and sticky flags; a sample is also checked against the
     oracle in the CPU-baseline leg."""
     import torch
+    from paper_1809_07444_amd import _capi as C
     from paper_1809_07444_amd import serve
     from synth import workloads as W
     torch.cuda.set_device(0)
@@ -654,9 +655,11 @@ def serve_bench(args):
             s, st, _ = run(specs, alone)
             sweep.append(dict(s, rate_fraction=f, rate_episodes_per_s=f * capacity, server_steps=st["server_steps"]))
             print(json.dumps({"progress": "serve", "rate_fraction": f, **s}), file=sys.stderr, flush=True)
-        # Profiled capacity run: per-launch timing on both pools.
+        # Profiled capacity run: per-launch timing on both pools, the steps
+        # launched eagerly (kernels inside a replayed graph carry no events).
         for p in srv.pools.values():
             p.heap.set_timing(True)
+            p.flags &= ~C.GRAPH
         run(base)
         roof, kernels = serve_roofline(srv, base)
     finally:

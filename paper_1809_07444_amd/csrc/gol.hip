@@ -2,8 +2,8 @@
 // worlds sharing one heap.
 //
 // Types: Cell {alive} is created once per grid position and found through a
-// position -> handle index (whose words also carry a copy of the live flag,
-// so neighbour reads take one load); Alive {cell, world, action} exists for every live
+// position -> handle index (a plane of live bits beside it copies the flags
+// for the neighbour reads); Alive {cell, world, action} exists for every live
 // cell; Candidate {cell, world, action} exists during a generation for every
 // dead cell next to a live one.  One generation is four do-alls:
 //   1 Alive:     count live neighbours -> action (die unless 2 or 3); create
@@ -30,55 +30,56 @@ enum : uint32_t { kCAlive = 0 };
 enum : uint32_t { kACell = 0, kAWorld = 1, kAAction = 2 };
 constexpr uint32_t kKindGolUpdate = 35;  // timing id of the fused phases 3 and 4
 
-// Beside the position -> Cell handle index, a live plane holds a copy of
-// every Cell's live flag, one byte per cell in the index's order (kDead,
-// kLive, or kNoCell where the Cell is missing, only after an out-of-memory
-// init); phases 3 and 4 write it with plain byte stores.  At the start of
-// each generation a pack kernel turns it into a live-bit plane, one bit per
-// cell (bit g % 32 of word g / 32), which the neighbourhood reads of phases 1
-// and 2 load: a row's five cells are one pair of dword loads.  The bit plane
-// is an eighth of the byte plane (6 MB for 48.8 M cells), so the rows that
-// the neighbourhoods of a wavefront's scattered cells touch are fewer cache
-// lines, and more of them are shared with other wavefronts.
-constexpr uint8_t kDead = 0, kLive = 1, kNoCell = 2;
-
+// Beside the position -> Cell handle index, a live-bit plane holds a copy of
+// every Cell's live flag, one bit per cell in the index's order (bit g % 32
+// of word g / 32; a cell whose Cell is missing, only after an out-of-memory
+// init, reads dead).  The neighbourhood reads of phases 1 and 2 load it: a
+// row's five cells are one pair of dword loads, and the plane of all 256
+// batched worlds (48.8 M cells) is 6 MB, so the rows that the neighbourhoods
+// of a wavefront's scattered cells touch are few cache lines, many of them
+// shared with other wavefronts.  Phases 3 and 4 (which read no neighbours)
+// flip the bits of the cells that die or are born with atomic AND / OR.
 struct World {
   const uint32_t* cells;  // global cell index -> Cell handle (kNull if missing)
-  const uint8_t* live;    // global cell index -> kDead / kLive / kNoCell
-  const uint32_t* bits;   // live bits, packed from `live` each generation
+  const uint32_t* bits;   // live bits
   const uint32_t* off;    // world -> first global cell index (num_worlds + 1 entries)
   const uint32_t* side;   // world -> side length
-  uint32_t total;         // cells of the index (the arena in pool mode)
 };
 
-// Sets the live state of the Cell at global index g (its field and the copy
-// in the live plane); only the cell's own Alive or Candidate does this.
-// False if the Cell is missing (after an out-of-memory init).
+// Sets the live state of the Cell at global index g (its field and its bit);
+// only the cell's own Alive or Candidate does this.  False if the Cell is
+// missing (after an out-of-memory init).
 template <class H>
 __device__ __forceinline__ bool set_live(const H& h, const World& w, uint32_t g, uint32_t live) {
   const uint32_t wd = w.cells[g];
   if (wd == kNull) return false;
   *field_ptr<uint32_t>(h, wd, kCell, kCAlive) = live;
-  const_cast<uint8_t*>(w.live)[g] = live ? kLive : kDead;
+  uint32_t* word = const_cast<uint32_t*>(w.bits) + (g >> 5);
+  const uint32_t bit = 1u << (g & 31u);
+  if (live)
+    __hip_atomic_fetch_or(word, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    __hip_atomic_fetch_and(word, ~bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return true;
 }
 
-// The live-bit plane from the byte plane: word i holds cells 32i .. 32i + 31
-// (a live byte is 1; the byte plane is padded, so the last word's reads stay
-// in the buffer).
-__global__ void gol_pack_kernel(World w, uint32_t words) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= words) return;
-  const uint4* p = reinterpret_cast<const uint4*>(w.live + (uint64_t)i * 32);
-  const uint4 a = p[0], b = p[1];
-  const uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-  uint32_t v = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < 8; ++k) {
-    const uint32_t x = d[k] & 0x01010101u;  // bit 0 of each byte: live (kNoCell is 2)
-    v |= ((x & 1u) | ((x >> 7) & 2u) | ((x >> 14) & 4u) | ((x >> 21) & 8u)) << (4 * k);
-  }
-  const_cast<uint32_t*>(w.bits)[i] = v;
+// Writes the live bits of a run of consecutive cells held by the lanes of a
+// wavefront in order (lane l: cell g of lane 0 plus l; lanes past the run's
+// end pass in = false): the lane at the head of each 32-bit word's part of
+// the run clears that part (if `clear`) and sets the bits of its live cells,
+// so that runs of other wavefronts or worlds that share the word stay intact.
+__device__ __forceinline__ void write_live_run(uint32_t* bits, uint32_t g, bool in, bool live, bool clear) {
+  const uint32_t lane = lane_id();
+  const uint64_t inm = __ballot(in), lm = __ballot(in && live);
+  const uint32_t sh = g & 31u;
+  if (!in || (lane != 0 && sh != 0)) return;
+  const uint32_t cnt = 32u - sh < 64u - lane ? 32u - sh : 64u - lane;  // lanes of this word, <= 32
+  const uint64_t run = ((1ull << cnt) - 1ull) << lane;
+  const uint32_t rm = (uint32_t)((inm & run) >> lane) << sh;
+  const uint32_t lv = (uint32_t)((lm & run) >> lane) << sh;
+  uint32_t* word = bits + (g >> 5);
+  if (clear) __hip_atomic_fetch_and(word, ~rm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (lv) __hip_atomic_fetch_or(word, lv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Global index of neighbour d (0..7: the row above, left and right, the row
@@ -260,7 +261,7 @@ __global__ void gol_init_kernel(DevHeapW<LG> h, World w, uint32_t num_worlds, ui
   const uint32_t alive = grid[g] ? 1u : 0u;
   if (hc != kNull) *field_ptr<uint32_t>(h, hc, kCell, kCAlive) = alive;
   const_cast<uint32_t*>(w.cells)[g] = hc;
-  const_cast<uint8_t*>(w.live)[g] = hc == kNull ? kNoCell : (alive ? kLive : kDead);
+  write_live_run(const_cast<uint32_t*>(w.bits), g, true, alive && hc != kNull, true);
   if (alive) {
     const uint32_t o = dsoar_new(h, kAlive);
     if (o != kNull) {
@@ -294,7 +295,7 @@ __global__ void gol_admit_kernel(DevHeapW<LG> h, World w, uint32_t slot, uint32_
   const uint32_t alive = grid[i] ? 1u : 0u;
   if (hc != kNull) *field_ptr<uint32_t>(h, hc, kCell, kCAlive) = alive;
   const_cast<uint32_t*>(w.cells)[g] = hc;
-  const_cast<uint8_t*>(w.live)[g] = hc == kNull ? kNoCell : (alive ? kLive : kDead);
+  write_live_run(const_cast<uint32_t*>(w.bits), g, true, alive && hc != kNull, true);
   new_many(h, kAlive, alive, [&](uint32_t, uint32_t o) {
     if (o == kNull) return;
     *field_ptr<uint32_t>(h, o, kAlive, kACell) = g;
@@ -311,7 +312,7 @@ __global__ void gol_retire_cells_kernel(DevHeapW<LG> h, World w, uint32_t off, u
   uint32_t* c = const_cast<uint32_t*>(w.cells) + off + i;
   if (*c != kNull) dsoar_delete(h, *c);
   *c = kNull;
-  const_cast<uint8_t*>(w.live)[off + i] = kNoCell;
+  write_live_run(const_cast<uint32_t*>(w.bits), off + i, true, false, true);
 }
 
 struct GolDeleteWorld {
@@ -336,17 +337,13 @@ bool gol_heap_ok(const dsoar_heap* h) {
 }
 
 // Device buffer of a world set: the world table (offsets and sides), the
-// cell index (4 bytes per cell), the live plane (1 byte per cell, padded so
-// that the pack kernel's last 32-byte read stays inside) and the live-bit
-// plane (padded by a word, so that a window's second dword load past the
-// last cell stays inside).
+// cell index (4 bytes per cell) and the live-bit plane (padded by two words,
+// so that a window's second dword load past the last cell stays inside).
 uint64_t table_head(uint32_t num_worlds) { return ((uint64_t)(2 * num_worlds + 1) * 4 + 255) / 256 * 256; }
 uint64_t index_bytes(uint64_t cells) { return (cells * 4 + 255) / 256 * 256; }
-uint64_t plane_bytes(uint64_t cells) { return (cells + 64 + 255) / 256 * 256; }
-uint64_t bit_words(uint64_t cells) { return (cells + 31) / 32; }
-uint64_t bits_bytes(uint64_t cells) { return ((bit_words(cells) + 2) * 4 + 255) / 256 * 256; }
+uint64_t bits_bytes(uint64_t cells) { return (((cells + 31) / 32 + 2) * 4 + 255) / 256 * 256; }
 uint64_t world_set_bytes(uint32_t num_worlds, uint64_t cells) {
-  return table_head(num_worlds) + index_bytes(cells) + plane_bytes(cells) + bits_bytes(cells);
+  return table_head(num_worlds) + index_bytes(cells) + bits_bytes(cells);
 }
 
 void carve(World& w, uint8_t* dev_mem, uint32_t num_worlds, uint64_t cells) {
@@ -354,9 +351,7 @@ void carve(World& w, uint8_t* dev_mem, uint32_t num_worlds, uint64_t cells) {
   w.off = tab;
   w.side = tab + num_worlds + 1;
   w.cells = (const uint32_t*)(dev_mem + table_head(num_worlds));
-  w.live = dev_mem + table_head(num_worlds) + index_bytes(cells);
-  w.bits = (const uint32_t*)(w.live + plane_bytes(cells));
-  w.total = (uint32_t)cells;
+  w.bits = (const uint32_t*)(dev_mem + table_head(num_worlds) + index_bytes(cells));
 }
 
 uint64_t gol_total_cells(uint32_t num_worlds, const uint32_t* sides) {
@@ -386,9 +381,6 @@ namespace {
 int gol_generation(dsoar_gol* g, uint32_t flags, hipStream_t s) {
   dsoar_heap* h = g->heap;
   const uint32_t base = flags & DSOAR_DO_PLAIN;
-  const uint32_t words = (uint32_t)bit_words(g->total);
-  gol_pack_kernel<<<(words + 255) / 256, 256, 0, s>>>(g->w, words);
-  DSOAR_LAUNCHED(h);
   int rc = launch_doall<AlivePrep>(h, kAlive, g->w, base, s);
   if (!rc) rc = launch_doall<CandPrep>(h, kCand, g->w, base, s);
   // Phase 2 creates and deletes nothing, phase 3 touches only Alive objects:
