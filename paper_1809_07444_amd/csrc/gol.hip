@@ -213,6 +213,7 @@ struct CandPrep {
 
 struct AliveUpdate {
   static constexpr uint32_t kKind = 32;
+  static constexpr bool kDeletesOnlyThis = true;
   using Args = World;
   template <class H>
   static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
@@ -224,6 +225,7 @@ struct AliveUpdate {
 
 struct CandUpdate {
   static constexpr uint32_t kKind = 33;
+  static constexpr bool kDeletesOnlyThis = true;
   using Args = World;
   template <class H>
   static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {

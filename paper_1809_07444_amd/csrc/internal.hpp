@@ -167,6 +167,20 @@ struct HasWave : std::false_type {};
 template <class M>
 struct HasWave<M, std::void_t<decltype(&M::template run_wave<DevHeap>)>> : std::true_type {};
 
+// A method may also declare
+//   static constexpr bool kDeletesOnlyThis = true;
+// when it deletes no object but `this` (and a two-list do-all pairs it only
+// with another such method).  Then a block whose snapshot is full is still
+// exactly full when its wavefront deletes from it: no other wavefront
+// removes its objects, and a full block is not active, so no allocation adds
+// to it.  Its object-bitmap AND needs no result, and the OR that returns the
+// block to active[type] is settled one list entry later.
+template <class M, class = void>
+struct DeletesOnlyThis : std::false_type {};
+template <class M>
+struct DeletesOnlyThis<M, std::void_t<decltype(M::kDeletesOnlyThis)>>
+    : std::integral_constant<bool, M::kDeletesOnlyThis> {};
+
 template <class Method, class H>
 __device__ __forceinline__ bool run_method(const H& h, uint32_t type, uint32_t self,
                                            const typename Method::Args& a) {
@@ -383,7 +397,7 @@ __device__ __forceinline__ void doall_split64(const H& h, uint32_t type, const u
 // returning true to delete self, or the load / apply pair described above.
 // One wavefront's share of a do-all over one list: entries gw, gw + nw, ...
 // (or passes of several entries), visit and free counts accumulated.
-template <class Method, class H>
+template <class Method, bool kOnlyThis, class H>
 __device__ __forceinline__ void doall_list(const H& h, uint32_t type, const uint32_t* __restrict__ R,
                                            const uint64_t* __restrict__ S, uint32_t count, uint32_t gw,
                                            uint32_t nw, const typename Method::Args& args, uint32_t& visits,
@@ -403,14 +417,31 @@ __device__ __forceinline__ void doall_list(const H& h, uint32_t type, const uint
     }
   }
   if (c == 64) {
+    const bool fast = kOnlyThis && !h.online_reclaim;
+    const Bitmap act = active_bm(h, type);
+    uint32_t pend_word = 0;
+    uint64_t pend_bits = 0, pend_prev = 0;
     for (uint32_t e = gw; e < count; e += nw) {
       const uint32_t bid = R[e];
       const uint64_t snap = S[e];
       visits += (uint32_t)__popcll(snap);
       const bool del = run_slot<Method>(h, type, make_obj(bid, lane), (snap >> lane) & 1ull, args);
       const uint64_t dm = __ballot(del);
-      if (dm) freed += delete_mask(h, type, bid, dm);
+      if (!dm) continue;
+      if (fast && snap == ~0ull) {
+        // A full block (see DeletesOnlyThis): nothing to wait for.
+        if (is_first_active())
+          __hip_atomic_fetch_and(h.obj_bitmap + bid, ~dm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        freed += (uint32_t)__popcll(dm);
+        if (pend_bits) bm_set_bits0_settle(act, pend_word, pend_bits, pend_prev);
+        pend_word = bid >> 6;
+        pend_bits = 1ull << (bid & 63u);
+        pend_prev = bm_set_bits0_issue(act, pend_word, pend_bits);
+      } else {
+        freed += delete_mask(h, type, bid, dm);
+      }
     }
+    if (pend_bits) bm_set_bits0_settle(act, pend_word, pend_bits, pend_prev);
   } else {
     // 64 / c blocks per wavefront: lane l handles slot l % c of entry
     // e0 + l / c (Fig. 4 with blocks smaller than a wavefront).
@@ -444,7 +475,8 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeapW<LG> h, uint32_t ty
                                                       typename Method::Args args) {
   const uint32_t nw = gridDim.x * (blockDim.x >> 6);
   uint32_t visits = 0, freed = 0;
-  doall_list<Method>(h, type, R, S, bcast32(*count_ptr), grid_wave(), nw, args, visits, freed);
+  doall_list<Method, DeletesOnlyThis<Method>::value>(h, type, R, S, bcast32(*count_ptr), grid_wave(), nw, args,
+                                                      visits, freed);
   if (visits) lead_add(shard(h) + kCntVisits + type, visits);
   if (freed) lead_add(shard(h) + kCntFrees + type, freed);
 }
@@ -462,11 +494,12 @@ __global__ void __launch_bounds__(1024) doall2_kernel(DevHeapW<LG> h, uint32_t t
                                                        typename M2::Args a2) {
   const uint32_t nw = gridDim.x * (blockDim.x >> 6), gw = grid_wave();
   uint32_t visits = 0, freed = 0;
-  doall_list<M1>(h, t1, R1, S1, bcast32(*c1), gw, nw, a1, visits, freed);
+  constexpr bool kOnlyThis = DeletesOnlyThis<M1>::value && DeletesOnlyThis<M2>::value;
+  doall_list<M1, kOnlyThis>(h, t1, R1, S1, bcast32(*c1), gw, nw, a1, visits, freed);
   if (visits) lead_add(shard(h) + kCntVisits + t1, visits);
   if (freed) lead_add(shard(h) + kCntFrees + t1, freed);
   visits = freed = 0;
-  doall_list<M2>(h, t2, R2, S2, bcast32(*c2), gw, nw, a2, visits, freed);
+  doall_list<M2, kOnlyThis>(h, t2, R2, S2, bcast32(*c2), gw, nw, a2, visits, freed);
   if (visits) lead_add(shard(h) + kCntVisits + t2, visits);
   if (freed) lead_add(shard(h) + kCntFrees + t2, freed);
 }
