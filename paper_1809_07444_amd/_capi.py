@@ -1,13 +1,17 @@
 """ctypes declarations of the C ABI in include/dsoar.h (argument marshalling only).
 
-Loading fails loudly when libdsoar.so is missing: there is no fallback path."""
+Loading fails loudly when libdsoar.so is missing: there is no fallback path.
+The stress tests select libdsoar_chaos.so (the same library built with
+pauses in the heap's race windows) with `using("chaos")`."""
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdsoar.so")
+LIB_PATHS = {"release": LIB_PATH, "chaos": os.path.join(HERE, "libdsoar_chaos.so")}
 
 MAX_TYPES = 8
 MAX_FIELDS = 8
@@ -183,7 +187,8 @@ SIGNATURES = {
     "dsoar_wator_read": (ctypes.c_int, [vp, vp, vp, vp, vp]),
 }
 
-_lib = None
+_libs: dict = {}
+_variant = "release"
 
 
 class DsoarError(RuntimeError):
@@ -192,20 +197,36 @@ class DsoarError(RuntimeError):
         super().__init__(f"{what}: {ERRORS.get(code, code)}")
 
 
-def load() -> ctypes.CDLL:
-    """Loads libdsoar.so from the package directory (never builds, never falls back)."""
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with "
+def load(variant: str | None = None) -> ctypes.CDLL:
+    """Loads the library of `variant` (default: the one `using` selected,
+    else the release build) from the package directory; never builds, never
+    falls back."""
+    v = variant or _variant
+    if v not in _libs:
+        path = LIB_PATHS[v]
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with "
                               "`python -m paper_1809_07444_amd.build` (hipcc, gfx950)")
-        lib = ctypes.CDLL(LIB_PATH)
+        lib = ctypes.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
-        _lib = lib
-    return _lib
+        _libs[v] = lib
+    return _libs[v]
+
+
+@contextlib.contextmanager
+def using(variant: str):
+    """Objects created inside the block bind to the library of `variant`."""
+    global _variant
+    if variant not in LIB_PATHS:
+        raise ValueError(variant)
+    old, _variant = _variant, variant
+    try:
+        yield load(variant)
+    finally:
+        _variant = old
 
 
 def check(code: int, what: str) -> int:

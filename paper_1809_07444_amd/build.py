@@ -1,4 +1,6 @@
-"""Builds libdsoar.so (HIP for gfx950) in the package directory."""
+"""Builds libdsoar.so (HIP for gfx950) in the package directory, and
+libdsoar_chaos.so: the same sources compiled with DSOAR_CHAOS, which puts
+short hash-chosen pauses into the heap's race windows for the stress tests."""
 from __future__ import annotations
 
 import glob
@@ -22,25 +24,39 @@ def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+VARIANTS = {"release": ("libdsoar.so", []), "chaos": ("libdsoar_chaos.so", ["-DDSOAR_CHAOS"])}
+
+
+def _compile(src: str, variant: str) -> str:
+    out_dir = os.path.join(BUILD, variant)
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, *VARIANTS[variant][1], "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        raise RuntimeError(f"hipcc failed for {src} ({variant}):\n{r.stderr}")
     return obj
 
 
-def build(jobs: int = 8) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, sources()))
-    tmp = LIB + ".tmp"
+def _link(objs: list[str], lib: str) -> str:
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(jobs: int = 8, variants=("release", "chaos")) -> str:
+    """Compiles every variant (all sources of all variants in one pool) and
+    returns the release library's path."""
+    for v in variants:
+        os.makedirs(os.path.join(BUILD, v), exist_ok=True)
+    work = [(src, v) for v in variants for src in sources()]
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda a: _compile(*a), work))
+    for v in variants:
+        _link([o for o, (_, ov) in zip(objs, work) if ov == v], os.path.join(HERE, VARIANTS[v][0]))
     return LIB
 
 

@@ -259,6 +259,7 @@ struct BodyMerge {
 
 struct BodyRemove {
   static constexpr uint32_t kKind = 65;
+  static constexpr bool kDeletesOnlyThis = true;
   using Args = Bodies;
   template <class H>
   static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {

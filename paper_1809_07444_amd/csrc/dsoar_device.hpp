@@ -218,6 +218,32 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   return x;
 }
 
+// Stress builds (compiled with DSOAR_CHAOS): at each named race window a
+// wavefront pauses, about one time in four, for a hash-chosen 0 to 7 sleeps
+// of 63 x 64 cycles (up to about 12 us at 2.4 GHz), so that other
+// wavefronts' atomics land inside windows that are otherwise a few cycles
+// wide.  Every bounded wait of the heap allows milliseconds, so a pause never
+// turns into a retry-limit error.  Release builds compile it away.
+enum : uint32_t {
+  kChaosFindReserve = 1,  // an active block's object bitmap read -> the reserving OR
+  kChaosTakePublish,      // free blocks taken -> their object bitmaps and type words written
+  kChaosPublishSets,      // new blocks published -> allocated / active bits set
+  kChaosNested,           // a container's update -> the nested bit one level up
+  kChaosDeleteActive,     // a full block's delete -> the block back in active
+  kChaosRelease,          // online release: between its steps
+};
+__device__ __forceinline__ void chaos_pause(uint32_t site) {
+#ifdef DSOAR_CHAOS
+  const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane(
+      (int)hash32((uint32_t)__builtin_readcyclecounter() ^ (site * 0x9E3779B9u) ^ (blockIdx.x << 6) ^
+                  (threadIdx.x >> 6)));
+  if ((r & 3u) != 0) return;
+  for (uint32_t i = (r >> 2) & 7u; i > 0; --i) __builtin_amdgcn_s_sleep(63);
+#else
+  (void)site;
+#endif
+}
+
 // ----------------------------------------------------------- memory access --
 
 // Agent-coherent load, made wave-uniform.
@@ -444,6 +470,7 @@ __device__ inline bool bm_set_from(const Bitmap& b, uint32_t level, uint32_t pos
     if (prev != 0 || level + 1 >= b.nlevels) return true;
     pos >>= b.lg;
     ++level;
+    chaos_pause(kChaosNested);
   }
 }
 
@@ -464,6 +491,7 @@ __device__ inline bool bm_clear_from(const Bitmap& b, uint32_t level, uint32_t p
     if (__popcll(prev) != 1 || level + 1 >= b.nlevels) return true;
     pos >>= b.lg;
     ++level;
+    chaos_pause(kChaosNested);
   }
 }
 
@@ -481,6 +509,7 @@ __device__ inline void group_set_nested32(const Bitmap& b, uint32_t g, uint64_t 
 }
 __device__ inline void group_set_nested(const Bitmap& b, uint32_t g, uint64_t prev, uint64_t m) {
   if (b.nlevels == 1) return;
+  chaos_pause(kChaosNested);
   if (__builtin_expect(b.lg == 6, 1)) {
     if (prev == 0 && m) bm_set_from(b, 1, g);
     return;
@@ -500,6 +529,7 @@ __device__ inline void group_clear_nested32(const Bitmap& b, uint32_t g, uint64_
 }
 __device__ inline void group_clear_nested(const Bitmap& b, uint32_t g, uint64_t prev, uint64_t m) {
   if (b.nlevels == 1) return;
+  chaos_pause(kChaosNested);
   if (__builtin_expect(b.lg == 6, 1)) {
     if ((prev & m) && (prev & ~m) == 0) bm_clear_from(b, 1, g);
     return;
@@ -936,6 +966,7 @@ __device__ inline void new_many(const H& h, uint32_t type, uint32_t k, F&& f) {
         continue;
       }
       free_hint = word;
+      chaos_pause(kChaosTakePublish);
       const uint32_t cnt_b = (uint32_t)__popcll(blocks);
       // With fewer blocks than asked for, all of them are filled.
       const bool partial = with_rest && cnt_b == nb;
@@ -950,6 +981,7 @@ __device__ inline void new_many(const H& h, uint32_t type, uint32_t k, F&& f) {
         const uint32_t w = publish_block(h, word * 64 + nth_set_bit(blocks, j), type, last ? rest_bits : cap);
         if (last) my_tw = w;
       }
+      chaos_pause(kChaosPublishSets);
       const Bitmap alloc = allocated_bm(h, type);
       const uint64_t pa = lead_or(alloc.group(word), blocks);
       group_set_nested(alloc, word, pa, blocks & ~pa);
@@ -1018,6 +1050,7 @@ __device__ inline void new_many(const H& h, uint32_t type, uint32_t k, F&& f) {
           }
           if (ok) my_av = ~meta_load(h.obj_bitmap + my_bid) & cap;
         }
+        chaos_pause(kChaosFindReserve);
         const uint32_t cnt = (uint32_t)__popcll(my_av);
         uint32_t excl = 0;
 #pragma unroll
@@ -1092,10 +1125,12 @@ __device__ inline void new_many(const H& h, uint32_t type, uint32_t k, F&& f) {
         break;
       }
       ++slow;
+      chaos_pause(kChaosTakePublish);
       // Fresh block: nobody else can see it until it is marked active.
       got = want >= c ? cap : ((1ull << want) - 1);
       uint32_t w = 0;
       if (is_first_active()) w = publish_block(h, (uint32_t)bid, type, got);
+      chaos_pause(kChaosPublishSets);
       // allocated[type] and, unless full, active[type]: both ORs are issued
       // before either result is used (each keeps set's retry and cascade).
       const Bitmap alloc = allocated_bm(h, type);
@@ -1208,6 +1243,7 @@ __device__ inline bool try_release(const H& h, uint32_t type, uint32_t bid) {
   // The freed type word is performed before the pins are read (pin_block).
   wait_performed();
   if (!bcast32(ok)) return false;
+  chaos_pause(kChaosRelease);
   bm_clear(active_bm(h, type), bid);
   for (uint32_t spins = 0;; ++spins) {
     uint32_t p = 0;
@@ -1223,6 +1259,7 @@ __device__ inline bool try_release(const H& h, uint32_t type, uint32_t bid) {
   if (is_first_active()) __hip_atomic_store(h.obj_bitmap + bid, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   lead_add(shard(h) + kCntBlocksReturned, 1);  // counted before it can be found
   wait_performed();
+  chaos_pause(kChaosRelease);
   bm_set(free_bm(h), bid);
   lead_add(shard(h) + kCntReleases, 1);
   return true;
@@ -1238,6 +1275,7 @@ __device__ inline uint32_t delete_mask(const H& h, uint32_t type, uint32_t bid, 
   if ((prev & mask) != mask) lead_flag(h.ctrl + kCtlDoubleFree);
   const uint64_t removed = prev & mask;
   const uint64_t cap = capmask_of(h, type);
+  chaos_pause(kChaosDeleteActive);
   if (removed && (prev & cap) == cap) bm_set(active_bm(h, type), bid);
   if (h.online_reclaim && removed && ((prev & ~mask) & cap) == 0) try_release(h, type, bid);
   return (uint32_t)__popcll(removed);

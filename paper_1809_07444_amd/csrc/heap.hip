@@ -615,6 +615,7 @@ struct VisitCount {
 
 struct DeleteIfMod {
   static constexpr uint32_t kKind = 11;
+  static constexpr bool kDeletesOnlyThis = true;
   struct Args { uint32_t field; int32_t modulus; int32_t residue; };
   struct Pre { int32_t v; };
   template <class H>

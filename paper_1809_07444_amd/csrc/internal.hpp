@@ -141,9 +141,13 @@ int read_count(dsoar_heap* h, uint32_t type, hipStream_t s, uint32_t* count);
 //   static __device__ bool apply(const DevHeap&, uint32_t type, uint32_t self, const Args&, const Pre&);
 // load must not write memory and may read only fields of `self` (it also runs
 // for the empty slots of a listed block, whose values it must not use); apply
-// may write the fields of `self`, create objects, and write state that no
-// load phase of the do-all reads (objects of other types, grids), since the
-// loads of later blocks are issued before earlier blocks are applied.  The do-all then issues the loads of U blocks
+// may write the fields of `self`, create objects of other types, and write
+// state that no load phase of the do-all reads (objects of other types,
+// grids), since the loads of later blocks are issued before earlier blocks
+// are applied.  (Creating objects of the do-all's own type is left to the
+// run form: the split do-all settles a pass's return of full blocks to
+// active[type] only after the next pass is applied, and a reservation in that
+// pass that filled such a block again would wait on it.)  The do-all then issues the loads of U blocks
 // before it applies the method to any of them, so a wavefront keeps U times
 // more bytes in flight; this is what lets a do-all over a heap larger than
 // the caches approach the HBM bandwidth.
@@ -174,7 +178,8 @@ struct HasWave<M, std::void_t<decltype(&M::template run_wave<DevHeap>)>> : std::
 // exactly full when its wavefront deletes from it: no other wavefront
 // removes its objects, and a full block is not active, so no allocation adds
 // to it.  Its object-bitmap AND needs no result, and the OR that returns the
-// block to active[type] is settled one list entry later.
+// block to active[type] is settled after the next entry's list reads, before
+// that entry's method runs.
 template <class M, class = void>
 struct DeletesOnlyThis : std::false_type {};
 template <class M>
@@ -425,6 +430,12 @@ __device__ __forceinline__ void doall_list(const H& h, uint32_t type, const uint
       const uint32_t bid = R[e];
       const uint64_t snap = S[e];
       visits += (uint32_t)__popcll(snap);
+      // The previous entry's active-bitmap OR is settled before this entry's
+      // method runs: a method that creates objects of this type may fill
+      // that block again, and the clear of its active bit that the filling
+      // reservation makes would wait for the nested set of this settle.
+      if (pend_bits) bm_set_bits0_settle(act, pend_word, pend_bits, pend_prev);
+      pend_bits = 0;
       const bool del = run_slot<Method>(h, type, make_obj(bid, lane), (snap >> lane) & 1ull, args);
       const uint64_t dm = __ballot(del);
       if (!dm) continue;
@@ -433,7 +444,7 @@ __device__ __forceinline__ void doall_list(const H& h, uint32_t type, const uint
         if (is_first_active())
           __hip_atomic_fetch_and(h.obj_bitmap + bid, ~dm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         freed += (uint32_t)__popcll(dm);
-        if (pend_bits) bm_set_bits0_settle(act, pend_word, pend_bits, pend_prev);
+        chaos_pause(kChaosDeleteActive);
         pend_word = bid >> 6;
         pend_bits = 1ull << (bid & 63u);
         pend_prev = bm_set_bits0_issue(act, pend_word, pend_bits);

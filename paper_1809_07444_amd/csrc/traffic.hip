@@ -83,6 +83,7 @@ struct Decide {
 
 struct Drive {
   static constexpr uint32_t kKind = 51;
+  static constexpr bool kDeletesOnlyThis = true;
   using Args = Road;
   template <class H>
   static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {

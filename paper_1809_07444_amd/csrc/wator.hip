@@ -169,6 +169,7 @@ struct SharkDecide {
 
 struct SharkMove {
   static constexpr uint32_t kKind = 73;
+  static constexpr bool kDeletesOnlyThis = true;
   using Args = Sea;
   template <class H>
   static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
@@ -205,6 +206,7 @@ struct SharkMove {
 
 struct FishEaten {
   static constexpr uint32_t kKind = 74;
+  static constexpr bool kDeletesOnlyThis = true;
   using Args = Sea;
   template <class H>
   static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {

@@ -2,7 +2,7 @@
 
 Every value here comes from the oracle (oracle/) run on the seeded inputs of
 synth/; nothing is taken from the device path.  Usage:
-    python tests/golden/make_golden.py [batched|sugarscape|serving|all]
+    python tests/golden/make_golden.py [batched|sugarscape|serving|wator|all]
 """
 from __future__ import annotations
 
@@ -127,6 +127,34 @@ def serving_case(seed=24301, rate=40.0, n=10):
     print(path, out["oracle_seconds"], "s")
 
 
+def wator(side=2048, steps=200, seed=24301, every=50):
+    inp = W.wator_inputs(side, seed=seed)
+    rules = W.WATOR_RULES
+    s = oracle.WatorState(inp.kind, inp.age, inp.energy)
+    checkpoints = []
+    t0 = time.time()
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        s = oracle.wator_run(s, k, seed, rules, step0=done)
+        done += k
+        checkpoints.append({
+            "step": done, "fish": int((s.kind == 1).sum()), "sharks": int((s.kind == 2).sum()),
+            "fish_born": s.fish_born, "sharks_born": s.sharks_born, "fish_eaten": s.fish_eaten,
+            "sharks_starved": s.sharks_starved, "kind_sha256": digest(s.kind), "age_sha256": digest(s.age),
+            "energy_sha256": digest(s.energy)})
+        print(checkpoints[-1]["step"], checkpoints[-1]["fish"], checkpoints[-1]["sharks"],
+              round(time.time() - t0, 1), flush=True)
+    out = {"case": f"wa-tor: {side}x{side} sea, fish 0.30, sharks 0.05, {steps} steps, seed {seed}",
+           "source": "oracle.wator_run on synth.workloads.wator_inputs", "rules": rules, "side": side,
+           "steps": steps, "seed": seed,
+           "initial": {"fish": int((inp.kind == 1).sum()), "sharks": int((inp.kind == 2).sum())},
+           "checkpoints": checkpoints, "oracle_seconds": round(time.time() - t0, 1)}
+    path = os.path.join(HERE, f"wator_{side}_{steps}s_seed{seed}.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(path, out["oracle_seconds"], "s")
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "all"
     if what in ("batched", "all"):
@@ -135,3 +163,5 @@ if __name__ == "__main__":
         sugarscape()
     if what in ("serving", "all"):
         serving_case()
+    if what in ("wator", "all"):
+        wator()

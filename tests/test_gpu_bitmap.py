@@ -155,3 +155,79 @@ def test_set_clear_pairs_meet(width):
     res = bm.run(ops_tensor(kinds, np.concatenate([pos, pos]))).cpu().numpy()
     assert (res == 0).all()
     assert all(int(w.abs().sum()) == 0 for w in bm.level_words())
+
+
+def inject(bm, edits):
+    """Host-side edits of raw level words (a summary left behind by an update
+    still on its way): edits = [(level, container, bits to OR, bits to clear)]."""
+    lv = bm.level_words()
+    for level, c, set_bits, clear_bits in edits:
+        w = lv[level][c:c + 1]
+        dt = np.uint64 if bm.width == 64 else np.uint32
+        x = (int(w.cpu().numpy().view(dt)[0]) | set_bits) & ~clear_bits & ((1 << bm.width) - 1)
+        w.copy_(torch.from_numpy(np.array([x], dtype=dt).view(np.int64 if bm.width == 64 else np.int32)))
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_stale_set_summaries_never_yield_a_clear_bit(width):
+    # Summary bits left set above empty containers (as while a clear's
+    # cascade is on its way): searches that descend into them must fail or
+    # retry elsewhere, never return a clear bit; a drain still hands out
+    # every real bit exactly once and leaves level 0 empty.
+    nbits = 64 ** 3
+    rng = np.random.default_rng(21)
+    bm = DeviceBitmap(nbits, width=width)
+    real = np.sort(rng.choice(nbits, 300, replace=False))
+    assert (bm.run(ops_tensor(np.full(len(real), C.BM_TRY_SET), real)).cpu().numpy() == 1).all()
+    used = set((real // width).tolist())
+    empty = [c for c in rng.permutation(nbits // width)[:400].tolist() if c not in used][:200]
+    edits = []
+    for c in empty:
+        # The level-1 bit of empty container c, and the bits above it, so
+        # that searches do reach it.
+        pos, level = c, 1
+        while level < len(bm.level_words()):
+            edits.append((level, pos // width, 1 << (pos % width), 0))
+            pos //= width
+            level += 1
+    inject(bm, edits)
+    n = 4096
+    starts = torch.tensor(rng.integers(0, 2 ** 31, size=n).astype(np.int32), device="cuda")
+    res = bm.run(ops_tensor(np.full(n, C.BM_TRY_FIND_SET), np.zeros(n, np.int64)), starts).cpu().numpy()
+    assert np.isin(res[res >= 0], real).all()
+    assert (res >= 0).any()
+    m = len(real)
+    starts = torch.tensor(rng.integers(0, 2 ** 31, size=m).astype(np.int32), device="cuda")
+    got = bm.run(ops_tensor(np.full(m, C.BM_FIND_CLEAR), np.zeros(m, np.int64)), starts).cpu().numpy()
+    assert sorted(got.tolist()) == real.tolist()
+    assert int(bm.level_words()[0].abs().sum()) == 0
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_stale_clear_summaries_hide_bits_until_the_cascade_lands(width):
+    # Set bits whose summary bit is still clear (as while a set's cascade is
+    # on its way): a search cannot reach them, so find_clear reports FAIL
+    # although bits are set (a FAIL does not prove the bitmap empty); once the
+    # host completes the cascade, a drain returns exactly those bits.
+    nbits = 64 ** 3
+    bm = DeviceBitmap(nbits, width=width)
+    real = np.array([5 * width + 1, 5 * width + 7, 900 * width + 3])
+    assert (bm.run(ops_tensor(np.full(len(real), C.BM_TRY_SET), real)).cpu().numpy() == 1).all()
+    before = [w.clone() for w in bm.level_words()]
+    lv = bm.level_words()
+    for lvl in range(1, len(lv)):
+        lv[lvl].zero_()  # every summary bit clear: only level 0 holds the bits
+    n = 64
+    starts = torch.tensor(np.arange(n, dtype=np.int32) * 7919, device="cuda")
+    res = bm.run(ops_tensor(np.full(n, C.BM_TRY_FIND_SET), np.zeros(n, np.int64)), starts).cpu().numpy()
+    assert (res == -1).all()
+    res = bm.run(ops_tensor(np.full(4, C.BM_FIND_CLEAR), np.zeros(4, np.int64)), starts[:4]).cpu().numpy()
+    assert (res == -1).all()
+    assert np.array_equal(words_np(bm)[0], before[0].cpu().numpy().view(words_np(bm)[0].dtype))
+    for lvl in range(1, len(lv)):
+        lv[lvl].copy_(before[lvl])  # the cascades land
+    assert_consistent(bm)
+    got = bm.run(ops_tensor(np.full(len(real), C.BM_FIND_CLEAR), np.zeros(len(real), np.int64)),
+                 starts[:len(real)]).cpu().numpy()
+    assert sorted(got.tolist()) == real.tolist()
+    assert all(int(w.abs().sum()) == 0 for w in bm.level_words())

@@ -78,3 +78,32 @@ def test_full_config_2048_first_steps():
     # The benchmark sea (2048 x 2048, fish 0.30, sharks 0.05), its first 20
     # steps against the oracle (graph replay, as timed).
     check(W.wator_inputs(2048), [20], flags=GRAPH)
+
+
+def test_benchmark_run_2048_200_steps_against_stored_oracle_digests():
+    # The benchmark's run (2048 x 2048, fish 0.30, sharks 0.05, seed 24301,
+    # graph replay) for all its 200 steps: the sea and the object churn at
+    # every 50th step equal the oracle's (digests written by
+    # tests/golden/make_golden.py), and no sticky flag is raised.
+    import hashlib
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "wator_2048_200s_seed24301.json")))
+    inp = W.wator_inputs(ref["side"], seed=ref["seed"])
+    sea = apps.Wator(inp, RULES)
+    sea.init()
+    f0, s0 = ref["initial"]["fish"], ref["initial"]["sharks"]
+    done = 0
+    for cp in ref["checkpoints"]:
+        sea.step(cp["step"] - done, GRAPH)
+        done = cp["step"]
+        got = sea.read()
+        for f in ("kind", "age", "energy"):
+            assert hashlib.sha256(np.ascontiguousarray(getattr(got, f)).tobytes()).hexdigest() == \
+                cp[f"{f}_sha256"], f"{f} differs after {done} steps"
+        st = got.stats
+        assert st["allocs"] == [f0 + cp["fish_born"], s0 + cp["sharks_born"]]
+        assert st["frees"] == [cp["fish_eaten"], cp["sharks_starved"]]
+        assert st["live"] == [cp["fish"], cp["sharks"]]
+    assert sea.heap.check() == {}
+    sea.close()
