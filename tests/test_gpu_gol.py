@@ -106,3 +106,27 @@ def test_full_config_1024_200_generations():
     # 1024 x 1024 torus, Bernoulli(0.1) alive, 200 generations (graph replay).
     g0 = W.gol_grid(1024, 1024)
     run_and_compare([g0], 200, flags=C.DO_PERSISTENT | C.GOL_GRAPH)
+
+
+@pytest.mark.parametrize("shift", [1, 8])
+def test_wide_init_from_an_unaligned_grid(shift):
+    # A world set of 2^22 cells or more is created 64 cells per lane, with
+    # 16-byte grid loads where the caller's grid allows them: a grid that
+    # starts 1 or 8 bytes past an aligned address takes the byte loads and
+    # gives the same world.  Two worlds whose boundary falls inside a lane's
+    # 64 cells check the per-cell world lookup.
+    g0 = W.gol_grid(2048, 2048, seed=9)
+    g1 = W.gol_grid(65, 65, seed=10)
+    gol = apps.GameOfLife([g1, g0])
+    flat = np.concatenate([g1.reshape(-1), g0.reshape(-1)])
+    buf = torch.zeros(flat.size + shift, dtype=torch.uint8, device="cuda")
+    buf[shift:] = torch.from_numpy(flat).cuda()
+    gol.heap.reset()
+    C.check(gol.lib.dsoar_gol_init(gol.g, buf.data_ptr() + shift, gol.heap._s()), "dsoar_gol_init")
+    gol.step(12, C.DO_PERSISTENT)
+    finals, allocs, frees = expected_counts([g1, g0], 12)
+    for a, b in zip(gol.read(), finals):
+        assert np.array_equal(a, b)
+    st = gol.heap.stats()
+    assert st["allocs"] == allocs and st["frees"] == frees
+    assert gol.heap.check() == {}
