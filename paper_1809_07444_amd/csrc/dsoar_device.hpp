@@ -913,7 +913,7 @@ __device__ __forceinline__ uint32_t search_start(const H& h) {
 // Requests are numbered by lane order (exclusive prefix sums from bit-sliced
 // ballots, exact under any divergence) and handed out in that order.
 template <class F, class H>
-__device__ inline void new_many(const H& h, uint32_t type, uint32_t k, F&& f) {
+__device__ __forceinline__ void new_many(const H& h, uint32_t type, uint32_t k, F&& f) {
   uint32_t prefix = 0, n = 0;
 #pragma unroll
   for (uint32_t b = 0; b < 8; ++b) {

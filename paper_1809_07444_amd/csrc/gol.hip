@@ -46,12 +46,11 @@ struct World {
   const uint32_t* side;   // world -> side length
 };
 
-// Sets the live state of the Cell at global index g (its field and its bit);
-// only the cell's own Alive or Candidate does this.  False if the Cell is
-// missing (after an out-of-memory init).
+// Sets the live state of the Cell at global index g, whose handle is wd
+// (its field and its bit); only the cell's own Alive or Candidate does this.
+// False if the Cell is missing (after an out-of-memory init).
 template <class H>
-__device__ __forceinline__ bool set_live(const H& h, const World& w, uint32_t g, uint32_t live) {
-  const uint32_t wd = w.cells[g];
+__device__ __forceinline__ bool set_cell_live(const H& h, const World& w, uint32_t g, uint32_t wd, uint32_t live) {
   if (wd == kNull) return false;
   *field_ptr<uint32_t>(h, wd, kCell, kCAlive) = live;
   uint32_t* word = const_cast<uint32_t*>(w.bits) + (g >> 5);
@@ -161,37 +160,90 @@ __device__ __forceinline__ uint32_t neighbourhood(const uint32_t* bits, uint32_t
   return al & ~(1u << (R * D + R));
 }
 
+// A listed object's cell position.  The do-all methods take two blocks per
+// wavefront pass (run_pair): each lane reads both of its slots' fields and
+// then both positions' neighbourhoods before it uses any of them (a
+// wavefront whose second block is absent skips its reads).  A slot that is
+// not live reads as world 0's corner (side 1 stands in when the world
+// table's slot 0 is empty), so no index is ever formed from its fields.
+struct CellPos {
+  uint32_t wid, off, side, x, y;
+};
+__device__ __forceinline__ CellPos cell_pos(const World& w, uint32_t g, uint32_t wid, bool live) {
+  const uint32_t wi = live ? wid : 0u;
+  const uint32_t o = w.off[wi], sd = w.side[wi];
+  CellPos p;
+  p.wid = wi;
+  p.off = live ? o : 0u;
+  p.side = live ? sd : 1u;
+  const uint32_t local = live ? g - p.off : 0u;
+  p.y = local / p.side;
+  p.x = local - p.y * p.side;
+  return p;
+}
+
 struct AlivePrep {
   static constexpr uint32_t kKind = 30;
   using Args = World;
   template <class H>
-  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
-    const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
-    const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
-    const uint32_t off = w.off[wid], side = w.side[wid];
-    const uint32_t local = g - off;
-    const uint32_t y = local / side, x = local - y * side;
+  static __device__ __forceinline__ void run_pair(const H& h, uint32_t type, uint32_t s0, bool l0, uint32_t s1,
+                                                  bool l1, const Args& w, bool& d0, bool& d1) {
+    const uint32_t self[2] = {s0, s1};
+    const bool lv[2] = {l0, l1};
+    const uint32_t n = __ballot(l1) ? 2u : 1u;  // objects this wavefront holds per lane
+    uint32_t g[2] = {0, 0}, wid[2] = {0, 0};
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      if (u >= n) break;
+      g[u] = *field_ptr<uint32_t>(h, self[u], type, kACell);
+      wid[u] = *field_ptr<uint32_t>(h, self[u], type, kAWorld);
+    }
+    CellPos p[2];
+    uint32_t alive[2] = {0, 0};
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) p[u] = cell_pos(w, g[u], wid[u], lv[u] && u < n);
     // Live states of the 24 surrounding cells.  (A cell whose Cell is
     // missing reads as dead; its Candidate never becomes an Alive.)
-    const uint32_t alive = neighbourhood<2>(w.bits, off, side, x, y);
-    uint32_t claim = 0;
 #pragma unroll
-    for (uint32_t d = 0; d < 8; ++d) {
-      const uint32_t b = nb_bit(kDirX[d], kDirY[d]);
-      const bool dead = (~alive >> b) & 1u;
-      if (dead && !(alive & owner_mask(d))) claim |= 1u << d;
+    for (uint32_t u = 0; u < 2; ++u) {
+      if (u >= n) break;
+      alive[u] = neighbourhood<2>(w.bits, p[u].off, p[u].side, p[u].x, p[u].y);
     }
-    const uint32_t live = (uint32_t)__popc(alive & ring_mask());
-    // One coalesced allocation for all of the wavefront's new Candidates.
-    new_many(h, kCand, (uint32_t)__popc(claim), [&](uint32_t j, uint32_t o) {
+    uint32_t claim[2];
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      claim[u] = 0;
+#pragma unroll
+      for (uint32_t d = 0; d < 8; ++d) {
+        const uint32_t b = nb_bit(kDirX[d], kDirY[d]);
+        const bool dead = (~alive[u] >> b) & 1u;
+        if (dead && !(alive[u] & owner_mask(d))) claim[u] |= 1u << d;
+      }
+      if (!lv[u]) claim[u] = 0;
+    }
+    // One coalesced allocation for the new Candidates of both blocks.
+    const uint32_t k0 = (uint32_t)__popc(claim[0]);
+    new_many(h, kCand, k0 + (uint32_t)__popc(claim[1]), [&](uint32_t j, uint32_t o) {
       if (o == kNull) return;
-      const uint32_t n = neighbour(off, side, x, y, nth_set_bit(claim, j));
+      const uint32_t u = j < k0 ? 0u : 1u;
+      const CellPos& q = u ? p[1] : p[0];
+      const uint32_t n = neighbour(q.off, q.side, q.x, q.y, nth_set_bit(claim[u], u ? j - k0 : j));
       *field_ptr<uint32_t>(h, o, kCand, kACell) = n;
-      *field_ptr<uint32_t>(h, o, kCand, kAWorld) = wid;
+      *field_ptr<uint32_t>(h, o, kCand, kAWorld) = q.wid;
       *field_ptr<uint32_t>(h, o, kCand, kAAction) = 0;
     });
-    *field_ptr<uint32_t>(h, self, type, kAAction) = (live == 2 || live == 3) ? 0u : 1u;
-    return false;
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      const uint32_t live = (uint32_t)__popc(alive[u] & ring_mask());
+      if (lv[u]) *field_ptr<uint32_t>(h, self[u], type, kAAction) = (live == 2 || live == 3) ? 0u : 1u;
+    }
+    d0 = d1 = false;
+  }
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
+    bool d0, d1;
+    run_pair(h, type, self, true, self, false, w, d0, d1);
+    return d0;
   }
 };
 
@@ -199,27 +251,72 @@ struct CandPrep {
   static constexpr uint32_t kKind = 31;
   using Args = World;
   template <class H>
+  static __device__ __forceinline__ void run_pair(const H& h, uint32_t type, uint32_t s0, bool l0, uint32_t s1,
+                                                  bool l1, const Args& w, bool& d0, bool& d1) {
+    const uint32_t self[2] = {s0, s1};
+    const bool lv[2] = {l0, l1};
+    const uint32_t n = __ballot(l1) ? 2u : 1u;
+    uint32_t g[2] = {0, 0}, wid[2] = {0, 0}, alive[2] = {0, 0};
+    CellPos p[2];
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      if (u >= n) break;
+      g[u] = *field_ptr<uint32_t>(h, self[u], type, kACell);
+      wid[u] = *field_ptr<uint32_t>(h, self[u], type, kAWorld);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) p[u] = cell_pos(w, g[u], wid[u], lv[u] && u < n);
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      if (u >= n) break;
+      alive[u] = neighbourhood<1>(w.bits, p[u].off, p[u].side, p[u].x, p[u].y);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u)
+      if (lv[u]) *field_ptr<uint32_t>(h, self[u], type, kAAction) = __popc(alive[u]) == 3 ? 1u : 0u;
+    d0 = d1 = false;
+  }
+  template <class H>
   static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
-    const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
-    const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
-    const uint32_t off = w.off[wid], side = w.side[wid];
-    const uint32_t local = g - off;
-    const uint32_t y = local / side, x = local - y * side;
-    const uint32_t alive = neighbourhood<1>(w.bits, off, side, x, y);
-    *field_ptr<uint32_t>(h, self, type, kAAction) = __popc(alive) == 3 ? 1u : 0u;
-    return false;
+    bool d0, d1;
+    run_pair(h, type, self, true, self, false, w, d0, d1);
+    return d0;
   }
 };
 
+// Phases 3 and 4 (the Cells of dying and born cells; each object deletes
+// itself only): loads of both slots first, then the Cells' handles of both.
 struct AliveUpdate {
   static constexpr uint32_t kKind = 32;
   static constexpr bool kDeletesOnlyThis = true;
   using Args = World;
   template <class H>
+  static __device__ __forceinline__ void run_pair(const H& h, uint32_t type, uint32_t s0, bool l0, uint32_t s1,
+                                                  bool l1, const Args& w, bool& d0, bool& d1) {
+    const uint32_t self[2] = {s0, s1};
+    const bool lv[2] = {l0, l1};
+    const uint32_t n = __ballot(l1) ? 2u : 1u;
+    bool dying[2] = {false, false};
+    uint32_t g[2] = {0, 0}, wd[2];
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      if (u >= n) break;
+      dying[u] = lv[u] && *field_ptr<uint32_t>(h, self[u], type, kAAction) != 0;
+      g[u] = *field_ptr<uint32_t>(h, self[u], type, kACell);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) wd[u] = u < n ? w.cells[dying[u] ? g[u] : 0u] : kNull;
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u)
+      if (dying[u]) set_cell_live(h, w, g[u], wd[u], 0);
+    d0 = dying[0];
+    d1 = dying[1];
+  }
+  template <class H>
   static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
-    if (*field_ptr<uint32_t>(h, self, type, kAAction) == 0) return false;
-    set_live(h, w, *field_ptr<uint32_t>(h, self, type, kACell), 0);
-    return true;
+    bool d0, d1;
+    run_pair(h, type, self, true, self, false, w, d0, d1);
+    return d0;
   }
 };
 
@@ -228,19 +325,42 @@ struct CandUpdate {
   static constexpr bool kDeletesOnlyThis = true;
   using Args = World;
   template <class H>
-  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
-    const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
-    const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
-    const bool born = *field_ptr<uint32_t>(h, self, type, kAAction) != 0;
-    if (born && set_live(h, w, g, 1)) {
-      const uint32_t o = dsoar_new(h, kAlive);
-      if (o != kNull) {
-        *field_ptr<uint32_t>(h, o, kAlive, kACell) = g;
-        *field_ptr<uint32_t>(h, o, kAlive, kAWorld) = wid;
-        *field_ptr<uint32_t>(h, o, kAlive, kAAction) = 0;
-      }
+  static __device__ __forceinline__ void run_pair(const H& h, uint32_t type, uint32_t s0, bool l0, uint32_t s1,
+                                                  bool l1, const Args& w, bool& d0, bool& d1) {
+    const uint32_t self[2] = {s0, s1};
+    const bool lv[2] = {l0, l1};
+    const uint32_t n = __ballot(l1) ? 2u : 1u;
+    bool born[2] = {false, false};
+    uint32_t g[2] = {0, 0}, wid[2] = {0, 0}, wd[2];
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      if (u >= n) break;
+      g[u] = *field_ptr<uint32_t>(h, self[u], type, kACell);
+      wid[u] = *field_ptr<uint32_t>(h, self[u], type, kAWorld);
+      born[u] = lv[u] && *field_ptr<uint32_t>(h, self[u], type, kAAction) != 0;
     }
-    return true;
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) wd[u] = u < n ? w.cells[born[u] ? g[u] : 0u] : kNull;
+    uint32_t nb = 0;  // bit u: cell u is born and has its Cell
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u)
+      if (born[u] && set_cell_live(h, w, g[u], wd[u], 1)) nb |= 1u << u;
+    // One allocation for the Alive objects of both blocks' births.
+    new_many(h, kAlive, (uint32_t)__popc(nb), [&](uint32_t j, uint32_t o) {
+      if (o == kNull) return;
+      const uint32_t u = nth_set_bit(nb, j);
+      *field_ptr<uint32_t>(h, o, kAlive, kACell) = u ? g[1] : g[0];
+      *field_ptr<uint32_t>(h, o, kAlive, kAWorld) = u ? wid[1] : wid[0];
+      *field_ptr<uint32_t>(h, o, kAlive, kAAction) = 0;
+    });
+    d0 = l0;
+    d1 = l1;
+  }
+  template <class H>
+  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
+    bool d0, d1;
+    run_pair(h, type, self, true, self, false, w, d0, d1);
+    return d0;
   }
 };
 

@@ -171,6 +171,21 @@ struct HasWave : std::false_type {};
 template <class M>
 struct HasWave<M, std::void_t<decltype(&M::template run_wave<DevHeap>)>> : std::true_type {};
 
+// Or a method may take two list entries per wavefront pass (capacity 64, on
+// lists of at least two entries per wavefront):
+//   static __device__ void run_pair(const DevHeap&, uint32_t type, uint32_t self0, bool live0,
+//                                   uint32_t self1, bool live1, const Args&, bool& del0, bool& del1);
+// Lane l holds slot l of both blocks and enters when either slot is live.
+// The method issues the loads of both objects before it uses any, and makes
+// one wavefront request for the objects both create, so one chain of
+// dependent loads and allocation atomics serves two blocks.  Empty slots'
+// fields hold anything: the method must not index memory with them.  It
+// still provides `run` (capacity 32, and callers of single objects).
+template <class M, class = void>
+struct HasPair : std::false_type {};
+template <class M>
+struct HasPair<M, std::void_t<decltype(&M::template run_pair<DevHeap>)>> : std::true_type {};
+
 // A method may also declare
 //   static constexpr bool kDeletesOnlyThis = true;
 // when it deletes no object but `this` (and a two-list do-all pairs it only
@@ -426,33 +441,60 @@ __device__ __forceinline__ void doall_list(const H& h, uint32_t type, const uint
     const Bitmap act = active_bm(h, type);
     uint32_t pend_word = 0;
     uint64_t pend_bits = 0, pend_prev = 0;
-    for (uint32_t e = gw; e < count; e += nw) {
-      const uint32_t bid = R[e];
-      const uint64_t snap = S[e];
-      visits += (uint32_t)__popcll(snap);
-      // The previous entry's active-bitmap OR is settled before this entry's
-      // method runs: a method that creates objects of this type may fill
-      // that block again, and the clear of its active bit that the filling
-      // reservation makes would wait for the nested set of this settle.
+    // The last block's active-bitmap OR is settled before the next method
+    // runs: a method that creates objects of this type may fill that block
+    // again, and the clear of its active bit that the filling reservation
+    // makes would wait for the nested set of this settle.
+    auto settle = [&]() {
       if (pend_bits) bm_set_bits0_settle(act, pend_word, pend_bits, pend_prev);
       pend_bits = 0;
-      const bool del = run_slot<Method>(h, type, make_obj(bid, lane), (snap >> lane) & 1ull, args);
-      const uint64_t dm = __ballot(del);
-      if (!dm) continue;
+    };
+    auto remove = [&](uint32_t bid, uint64_t snap, uint64_t dm) {
       if (fast && snap == ~0ull) {
         // A full block (see DeletesOnlyThis): nothing to wait for.
         if (is_first_active())
           __hip_atomic_fetch_and(h.obj_bitmap + bid, ~dm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         freed += (uint32_t)__popcll(dm);
         chaos_pause(kChaosDeleteActive);
+        settle();
         pend_word = bid >> 6;
         pend_bits = 1ull << (bid & 63u);
         pend_prev = bm_set_bits0_issue(act, pend_word, pend_bits);
       } else {
         freed += delete_mask(h, type, bid, dm);
       }
+    };
+    if constexpr (HasPair<Method>::value) {
+      // Pairs only when every wavefront gets two entries or more: on a short
+      // list they would leave half the wavefronts without work, and each
+      // pass then takes one entry (the same code, its second slot empty, so
+      // that the method is inlined once).
+      const uint32_t per = count >= 2 * nw ? 2u : 1u;
+      for (uint32_t e = per * gw; e < count; e += per * nw) {
+        const bool has1 = per == 2 && e + 1 < count;
+        const uint32_t b0 = R[e], b1 = has1 ? R[e + 1] : b0;
+        const uint64_t s0 = S[e], s1 = has1 ? S[e + 1] : 0ull;
+        visits += (uint32_t)(__popcll(s0) + __popcll(s1));
+        settle();
+        const bool l0 = (s0 >> lane) & 1ull, l1 = (s1 >> lane) & 1ull;
+        bool d0 = false, d1 = false;
+        if (l0 || l1) Method::run_pair(h, type, make_obj(b0, lane), l0, make_obj(b1, lane), l1, args, d0, d1);
+        const uint64_t dm0 = __ballot(l0 && d0), dm1 = __ballot(l1 && d1);
+        if (dm0) remove(b0, s0, dm0);
+        if (dm1) remove(b1, s1, dm1);
+      }
+    } else {
+      for (uint32_t e = gw; e < count; e += nw) {
+        const uint32_t bid = R[e];
+        const uint64_t snap = S[e];
+        visits += (uint32_t)__popcll(snap);
+        settle();
+        const bool del = run_slot<Method>(h, type, make_obj(bid, lane), (snap >> lane) & 1ull, args);
+        const uint64_t dm = __ballot(del);
+        if (dm) remove(bid, snap, dm);
+      }
     }
-    if (pend_bits) bm_set_bits0_settle(act, pend_word, pend_bits, pend_prev);
+    settle();
   } else {
     // 64 / c blocks per wavefront: lane l handles slot l % c of entry
     // e0 + l / c (Fig. 4 with blocks smaller than a wavefront).
