@@ -657,11 +657,15 @@ def serve_bench(args):
             print(json.dumps({"progress": "serve", "rate_fraction": f, **s}), file=sys.stderr, flush=True)
         # Profiled capacity run: per-launch timing on both pools, the steps
         # launched eagerly (kernels inside a replayed graph carry no events).
-        for p in srv.pools.values():
+        # The pools' counters run over their whole life: the byte models take
+        # the difference over this run.
+        st0 = {}
+        for name, p in srv.pools.items():
             p.heap.set_timing(True)
             p.flags &= ~C.GRAPH
+            st0[name] = p.heap.stats()
         run(base)
-        roof, kernels = serve_roofline(srv, base)
+        roof, kernels = serve_roofline(srv, base, st0)
     finally:
         srv.close()
     if mismatches:
@@ -679,10 +683,20 @@ def serve_bench(args):
     print(json.dumps(out))
 
 
-def serve_roofline(srv, specs):
+def stats_delta(after: dict, before: dict, keys=("allocs", "frees", "visits")) -> dict:
+    """The cumulative per-type counters `keys` of `after` minus those of
+    `before`; other entries as in `after`."""
+    out = dict(after)
+    for k in keys:
+        if k in after and k in before:
+            out[k] = [x - y for x, y in zip(after[k], before[k])]
+    return out
+
+
+def serve_roofline(srv, specs, st0):
     """Dominant kernel of a profiled serving run over both pools, with its
     algorithmic bytes (the Game-of-Life and Sugarscape byte models over the
-    pool's own counters for that run)."""
+    pool's own counters for that run: their change since `st0`)."""
     from synth import workloads as W
     gol_alive0 = sum(int(W.episode_inputs(e).sum()) for e in specs if e.kind == "gol")
     sugar_agents0 = sum(int(W.episode_inputs(e).occ.sum()) for e in specs if e.kind == "sugar")
@@ -690,7 +704,7 @@ def serve_roofline(srv, specs):
     kernels, best = {}, None
     for name, p in srv.pools.items():
         kern = p.heap.timing()
-        st = p.heap.stats()
+        st = stats_delta(p.heap.stats(), st0[name])
         p.heap.set_timing(False)
         for kind, (launches, tot_ms) in kern.items():
             if name == "gol":

@@ -165,6 +165,21 @@ def test_game_of_life_equals_oracle_under_chaos(capacity, width, online, flags):
     assert gol.heap.check() == {}
 
 
+def test_game_of_life_paired_passes_under_chaos():
+    # 256 persistent wavefronts: the Alive and Candidate lists of a 1024^2
+    # world go two blocks per pass.
+    grids = [W.gol_grid(1024, 1024, seed=33)]
+    gol = apps.GameOfLife(grids)
+    gol.heap.set_launch(64, 1)
+    gol.init()
+    gol.step(20, C.DO_PERSISTENT)
+    finals, allocs, frees = gol_expected(grids, 20)
+    assert np.array_equal(gol.read()[0], finals[0])
+    st = gol.heap.stats()
+    assert st["allocs"] == allocs and st["frees"] == frees
+    assert gol.heap.check() == {}
+
+
 @pytest.mark.parametrize("cap,flags", [(64, C.DO_PERSISTENT), (32, C.DO_PLAIN)])
 def test_microbenchmark_equals_oracle_under_chaos(cap, flags):
     inp = W.micro_inputs(20000, 4, seed=17)

@@ -130,3 +130,24 @@ def test_wide_init_from_an_unaligned_grid(shift):
     st = gol.heap.stats()
     assert st["allocs"] == allocs and st["frees"] == frees
     assert gol.heap.check() == {}
+
+
+@pytest.mark.parametrize("capacity,flags", [(64, C.DO_PERSISTENT), (64, C.DO_PERSISTENT | C.GOL_GRAPH),
+                                            (32, C.DO_PERSISTENT)])
+def test_paired_passes_on_a_small_grid(capacity, flags):
+    # With one 64-thread workgroup per CU the persistent do-all has 256
+    # wavefronts, so lists of 512 blocks or more go two entries per pass
+    # (the pair form, one allocation request for both blocks) and shorter
+    # ones one entry per pass: about 1,600 Alive and 2,000 Candidate blocks
+    # here, and a ragged last pair.  Capacity 32 takes the per-lane form.
+    grids = [W.gol_grid(1024, 1024, seed=31), W.gol_grid(300, 300, seed=32)]
+    gol = apps.GameOfLife(grids, capacity=capacity)
+    gol.heap.set_launch(64, 1)
+    gol.init()
+    gol.step(40, flags)
+    finals, allocs, frees = expected_counts(grids, 40)
+    for a, b in zip(gol.read(), finals):
+        assert np.array_equal(a, b)
+    st = gol.heap.stats()
+    assert st["allocs"] == allocs and st["frees"] == frees
+    assert gol.heap.check() == {}
