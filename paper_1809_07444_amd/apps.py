@@ -76,14 +76,17 @@ GOL_CELL, GOL_ALIVE, GOL_CAND = 0, 1, 2
 def gol_blocks_for(total_cells: int, capacity: int = 64) -> int:
     """Heap size for a Game of Life state: one block per `capacity` cells for
     the Cells and twice as many again for Alive and Candidate objects (at most
-    one of them per cell, plus partly filled blocks), rounded up to a power of
-    two.  Capacity 0 (per-type capacities by object size): Cells {4 B} have
-    64 slots, Alive and Candidate {3 x 4 B} 16."""
+    one of them per cell, plus partly filled blocks), rounded up to a multiple
+    of 4096 blocks (64 level-0 bitmap words).  Not to a power of two: every
+    enumeration scans the whole allocated bitmap, so a heap no larger than
+    this rule asks for keeps that scan short.  Capacity 0 (per-type
+    capacities by object size): Cells {4 B} have 64 slots, Alive and
+    Candidate {3 x 4 B} 16."""
     if capacity == 0:
         need = max(64, -(-total_cells // 64) + 2 * -(-total_cells // 16))
     else:
         need = max(64, 3 * -(-total_cells // capacity))
-    return 1 << (need - 1).bit_length()
+    return -(-need // 4096) * 4096
 
 
 class GameOfLife:
