@@ -112,3 +112,42 @@ def test_split_runs_equal_one_run(orc):
     for f in ("sugar", "occ", "a_sugar", "a_metab", "a_vision", "a_age"):
         assert np.array_equal(getattr(a, f), getattr(b, f))
     assert (a.births, a.deaths, a.moves) == (b.births, b.deaths, b.moves)
+
+
+def ledger(s):
+    m = s.occ.astype(bool)
+    return int(s.a_sugar[m].sum()) + int(s.sugar.sum())
+
+
+@pytest.mark.parametrize("side,agents,seed,rules", [
+    (64, 60, 5, RULES),                                             # births and deaths
+    (48, 600, 6, dict(RULES, max_age=10 ** 6, fertile_min=2, fertile_max=1)),  # neither: every step checked
+])
+def test_sugar_ledger(orc, side, agents, seed, rules):
+    # The sugar of all agents and all cells changes in a step by the regrowth
+    # (each cell's sugar + 1, capped, minus its sugar), minus the metabolism of
+    # the agents that started the step, minus the sugar the dead take with
+    # them; eating moves sugar from a cell to an agent and a birth from the
+    # parent to the child, so neither changes the total.  On steps without
+    # deaths the last term is 0, and the equation is closed from the state
+    # before the step alone.
+    inp = W.sugar_inputs(side, agents, seed=seed)
+    a_sugar = inp.a_sugar.copy()
+    if rules is not RULES:
+        a_sugar[inp.occ.astype(bool)] += 200  # no starvation within the run
+    s = orc.SugarState(side, inp.sugar, inp.cap, inp.occ, a_sugar, inp.a_metab, inp.a_vision, inp.a_age)
+    checked = births_checked = 0
+    for k in range(40):
+        r = orc.sugar_run(s, 1, seed, rules, step0=k)
+        if r.deaths == s.deaths:
+            regrow = int((np.minimum(s.sugar + 1, s.cap) - s.sugar).sum())
+            metab = int(s.a_metab[s.occ.astype(bool)].sum())
+            assert ledger(r) == ledger(s) + regrow - metab, k
+            checked += 1
+            births_checked += r.births - s.births
+        s = r
+    assert checked >= (40 if rules is not RULES else 5)
+    if rules is RULES:
+        assert births_checked > 0  # the parent-to-child transfer is among the checked steps
+    if rules is not RULES:
+        assert s.births == 0 and s.deaths == 0
