@@ -137,7 +137,7 @@ Plan make_plan(const dsoar_heap_desc* d) {
   off = align_up(off + sizeof(StatsOut), kAlign);
   const uint64_t W0 = (M + 63) / 64;
   p.enum_wpw = W0 > kEnumWideFrom ? kEnumWideWords : 1;
-  const uint64_t tile_words = (uint64_t)kEnumWaves * p.enum_wpw;
+  const uint64_t tile_words = (uint64_t)enum_waves(p.enum_wpw) * p.enum_wpw;
   p.num_tiles = (uint32_t)((W0 + tile_words - 1) / tile_words);
   for (uint32_t t = 0; t < d->num_types; ++t) {
     p.R_off[t] = off;
@@ -306,7 +306,8 @@ __device__ __forceinline__ uint64_t pack_flag(uint32_t epoch, uint64_t status, u
 // WPW level-0 words (64 blocks each); all their loads are issued before any
 // is used.  The heap is quiescent, so plain loads see the previous kernels.
 template <uint32_t WPW, uint32_t LG>
-__global__ void __launch_bounds__(kEnumWaves * 64) enumerate_kernel(DevHeapW<LG> h, uint32_t type, EnumOut out) {
+__global__ void __launch_bounds__(enum_waves(WPW) * 64) enumerate_kernel(DevHeapW<LG> h, uint32_t type, EnumOut out) {
+  constexpr uint32_t kEnumWaves = enum_waves(WPW);
   __shared__ uint32_t s_tile, s_epoch, s_prefix;
   __shared__ uint32_t s_wave_total[kEnumWaves];
   if (threadIdx.x == 0) {
@@ -649,13 +650,15 @@ int launch_enumerate_into(dsoar_heap* h, uint32_t type, const EnumOut& eo, hipSt
   if (h->enum_wpw == kEnumWideWords)
     with_width(h, [&](auto w_) {
     constexpr uint32_t kLG = decltype(w_)::value;
-    launch_timed(h, kKindEnumerate, enumerate_kernel<kEnumWideWords, kLG>, dim3(h->num_tiles), dim3(kEnumWaves * 64),
+    launch_timed(h, kKindEnumerate, enumerate_kernel<kEnumWideWords, kLG>, dim3(h->num_tiles),
+                 dim3(enum_waves(kEnumWideWords) * 64),
                  s, DevHeapW<kLG>(h->dev), type, eo);
   });
   else
     with_width(h, [&](auto w_) {
     constexpr uint32_t kLG = decltype(w_)::value;
-    launch_timed(h, kKindEnumerate, enumerate_kernel<1, kLG>, dim3(h->num_tiles), dim3(kEnumWaves * 64), s, DevHeapW<kLG>(h->dev),
+    launch_timed(h, kKindEnumerate, enumerate_kernel<1, kLG>, dim3(h->num_tiles), dim3(enum_waves(1) * 64), s,
+                 DevHeapW<kLG>(h->dev),
                  type, eo);
   });
   DSOAR_LAUNCHED(h);
@@ -668,7 +671,7 @@ int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s) {
 
 // Scratch of the allocation-free enumeration (dsoar_enumerate_noalloc): the
 // scan state and one look-back word per tile, sized for the largest heap
-// (2^26 - 1 blocks: 2^20 level-0 groups, 64 per tile).  Each device holds
+// (2^26 - 1 blocks: 2^20 level-0 groups, at least 64 per tile).  Each device holds
 // its own copy; host code uses the address hipGetSymbolAddress returns for
 // the current device, never the symbol itself.
 constexpr uint32_t kStaticTiles = 16384;

@@ -15,11 +15,14 @@ namespace dsoar {
 
 // Enumeration tiling: one wavefront scans 1 word of the level-0 allocated[T]
 // bitmap (64 blocks), or kEnumWideWords words when the bitmap has more than
-// kEnumWideFrom words; a workgroup of kEnumWaves wavefronts is one tile of
-// the decoupled look-back scan.
-constexpr uint32_t kEnumWaves = 8;
+// kEnumWideFrom words; a workgroup of enum_waves(WPW) wavefronts is one tile
+// of the decoupled look-back scan.  Wide scans take 16 wavefronts per tile:
+// half the tiles, so a shorter look-back chain (a 2^22-block heap's scan 33
+// -> 22 us); narrow ones keep 8, which spreads a small heap's few words over
+// more workgroups.
 constexpr uint32_t kEnumWideWords = 8;
 constexpr uint32_t kEnumWideFrom = 16384;
+constexpr uint32_t enum_waves(uint32_t wpw) { return wpw > 1 ? 16u : 8u; }
 
 // Per-type scan state: tile ticket, epoch (so the look-back flags never need
 // clearing between launches), the resulting count, then one flag per tile.
