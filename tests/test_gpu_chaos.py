@@ -189,3 +189,60 @@ def test_microbenchmark_equals_oracle_under_chaos(cap, flags):
     assert np.array_equal(res.present.astype(bool), p)
     assert np.array_equal(res.x[p].view(np.uint32), ref.x[p].view(np.uint32))
     assert res.stats["allocs"] == [ref.allocs] and res.stats["frees"] == [ref.frees]
+
+
+@pytest.mark.parametrize("online", [False, True])
+def test_sugarscape_equals_oracle_under_chaos(online):
+    # Births (new agents of the agents' own type) and deaths in the same
+    # steps, on a crowded 64 x 64 torus.
+    inp = W.sugar_inputs(64, 1500, seed=13)
+    rules = W.SUGAR_RULES
+    sim = apps.Sugarscape(inp, rules)
+    sim.heap.set_reclaim(online)
+    sim.init()
+    sim.step(25, C.DO_PERSISTENT | C.GRAPH)
+    ref = oracle.sugar_run(oracle.SugarState(inp.side, inp.sugar, inp.cap, inp.occ, inp.a_sugar, inp.a_metab,
+                                             inp.a_vision, inp.a_age), 25, inp.seed, rules)
+    got = sim.read()
+    assert np.array_equal(got.sugar, ref.sugar) and np.array_equal(got.occ, ref.occ)
+    m = ref.occ.astype(bool)
+    for f in ("a_sugar", "a_metab", "a_vision", "a_age"):
+        assert np.array_equal(getattr(got, f)[m], getattr(ref, f)[m]), f
+    n0 = int(inp.occ.sum())
+    assert got.stats["allocs"] == [n0 + ref.births] and got.stats["frees"] == [ref.deaths]
+    assert sim.heap.check() == {}
+
+
+@pytest.mark.parametrize("online", [False, True])
+def test_wator_equals_oracle_under_chaos(online):
+    # Sharks that starve (delete themselves) and breed (new sharks) in the
+    # same do-all, fish eaten and born: the pattern of the settle ordering.
+    inp = W.wator_inputs(128, seed=14)
+    rules = W.WATOR_RULES
+    sea = apps.Wator(inp, rules)
+    sea.heap.set_reclaim(online)
+    sea.init()
+    sea.step(30, C.DO_PERSISTENT | C.GRAPH)
+    ref = oracle.wator_run(oracle.WatorState(inp.kind, inp.age, inp.energy), 30, inp.seed, rules)
+    got = sea.read()
+    for f in ("kind", "age", "energy"):
+        assert np.array_equal(getattr(got, f), getattr(ref, f)), f
+    f0, s0 = int((inp.kind == 1).sum()), int((inp.kind == 2).sum())
+    assert got.stats["allocs"] == [f0 + ref.fish_born, s0 + ref.sharks_born]
+    assert got.stats["frees"] == [ref.fish_eaten, ref.sharks_starved]
+    assert sea.heap.check() == {}
+    sea.close()
+
+
+def test_traffic_equals_oracle_under_chaos():
+    # Cars enter (new, into nearly full active blocks) and leave (delete).
+    inp = W.traffic_inputs(37, 211, seed=15)
+    rules = W.TRAFFIC_RULES
+    sim = apps.Traffic(inp, rules)
+    sim.init()
+    sim.step(60, C.DO_PERSISTENT | C.GRAPH)
+    r = oracle.traffic_run(inp.vel, 60, inp.seed, rules)
+    assert np.array_equal(sim.read(), r.vel)
+    st = sim.heap.stats()
+    assert st["allocs"] == [int((inp.vel >= 0).sum()) + r.entries] and st["frees"] == [r.exits]
+    assert sim.heap.check() == {}
