@@ -2,7 +2,7 @@
 
 Every value here comes from the oracle (oracle/) run on the seeded inputs of
 synth/; nothing is taken from the device path.  Usage:
-    python tests/golden/make_golden.py [batched|sugarscape|serving|wator|all]
+    python tests/golden/make_golden.py [batched|sugarscape|serving|wator|collisions|nbody|all]
 """
 from __future__ import annotations
 
@@ -155,6 +155,31 @@ def wator(side=2048, steps=200, seed=24301, every=50):
     print(path, out["oracle_seconds"], "s")
 
 
+def collisions(n=65536, steps=20, seed=24301, every=5, merge=True):
+    inp = W.collide_inputs(n, seed=seed, box=32.0)
+    params = W.COLLIDE_PARAMS if merge else dict(W.COLLIDE_PARAMS, r2_merge=0.0)
+    s = oracle.CollideState(inp.x, inp.y, inp.vx, inp.vy, inp.m)
+    checkpoints = []
+    t0 = time.time()
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        s = oracle.collide_run(s, k, params)
+        done += k
+        cp = {"step": done, "merges": int(s.merges), "live": int((s.m > 0).sum())}
+        for f in ("x", "y", "vx", "vy", "m"):
+            cp[f + "_sha256"] = digest(getattr(s, f).view(np.uint32))
+        checkpoints.append(cp)
+        print(done, cp["live"], round(time.time() - t0, 1), flush=True)
+    name = "collisions" if merge else "nbody"
+    out = {"case": f"{name}: {n} bodies in a 32 x 32 box, {steps} steps, seed {seed}",
+           "source": "oracle.collide_run on synth.workloads.collide_inputs", "params": params, "bodies": n,
+           "steps": steps, "seed": seed, "checkpoints": checkpoints, "oracle_seconds": round(time.time() - t0, 1)}
+    path = os.path.join(HERE, f"{name}_{n}_{steps}s_seed{seed}.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(path, out["oracle_seconds"], "s")
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "all"
     if what in ("batched", "all"):
@@ -165,3 +190,7 @@ if __name__ == "__main__":
         serving_case()
     if what in ("wator", "all"):
         wator()
+    if what in ("collisions", "all"):
+        collisions()
+    if what in ("nbody", "all"):
+        collisions(merge=False)

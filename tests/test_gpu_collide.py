@@ -96,3 +96,30 @@ def test_benchmark_size_first_step():
     inp = W.collide_inputs(65536, box=32.0)
     ref = check(inp, W.COLLIDE_PARAMS, [1], flags=GRAPH)
     assert ref.merges > 0
+
+
+@pytest.mark.parametrize("name,merge", [("collisions", True), ("nbody", False)])
+def test_benchmark_run_against_stored_oracle_digests(name, merge):
+    # The benchmark's 65,536 bodies in a 32 x 32 box for all its 20 steps
+    # (graph replay, as timed): every body's position, velocity and mass,
+    # bit for bit, at every fifth step equal the oracle's (digests written by
+    # tests/golden/make_golden.py), and the merges and live bodies too.
+    import hashlib
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      f"{name}_65536_20s_seed24301.json")))
+    params = W.COLLIDE_PARAMS if merge else dict(W.COLLIDE_PARAMS, r2_merge=0.0)
+    inp = W.collide_inputs(ref["bodies"], seed=ref["seed"], box=32.0)
+    sim = apps.Collisions(inp, params)
+    sim.init()
+    done = 0
+    for cp in ref["checkpoints"]:
+        sim.step(cp["step"] - done, GRAPH)
+        done = cp["step"]
+        got = sim.read()
+        for f in FIELDS:
+            h = hashlib.sha256(np.ascontiguousarray(getattr(got, f).view(np.uint32)).tobytes()).hexdigest()
+            assert h == cp[f + "_sha256"], f"{f} differs after {done} steps"
+        assert got.stats["frees"] == [cp["merges"]] and got.stats["live"] == [cp["live"]]
+    assert sim.heap.check() == {}
