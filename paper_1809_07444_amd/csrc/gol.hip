@@ -240,10 +240,30 @@ struct AlivePrep {
     d0 = d1 = false;
   }
   template <class H>
-  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
-    bool d0, d1;
-    run_pair(h, type, self, true, self, false, w, d0, d1);
-    return d0;
+  static __device__ __forceinline__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
+    const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
+    const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
+    const uint32_t off = w.off[wid], side = w.side[wid];
+    const uint32_t local = g - off;
+    const uint32_t y = local / side, x = local - y * side;
+    const uint32_t alive = neighbourhood<2>(w.bits, off, side, x, y);
+    uint32_t claim = 0;
+#pragma unroll
+    for (uint32_t d = 0; d < 8; ++d) {
+      const uint32_t b = nb_bit(kDirX[d], kDirY[d]);
+      const bool dead = (~alive >> b) & 1u;
+      if (dead && !(alive & owner_mask(d))) claim |= 1u << d;
+    }
+    const uint32_t live = (uint32_t)__popc(alive & ring_mask());
+    new_many(h, kCand, (uint32_t)__popc(claim), [&](uint32_t j, uint32_t o) {
+      if (o == kNull) return;
+      const uint32_t n = neighbour(off, side, x, y, nth_set_bit(claim, j));
+      *field_ptr<uint32_t>(h, o, kCand, kACell) = n;
+      *field_ptr<uint32_t>(h, o, kCand, kAWorld) = wid;
+      *field_ptr<uint32_t>(h, o, kCand, kAAction) = 0;
+    });
+    *field_ptr<uint32_t>(h, self, type, kAAction) = (live == 2 || live == 3) ? 0u : 1u;
+    return false;
   }
 };
 
@@ -277,10 +297,15 @@ struct CandPrep {
     d0 = d1 = false;
   }
   template <class H>
-  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
-    bool d0, d1;
-    run_pair(h, type, self, true, self, false, w, d0, d1);
-    return d0;
+  static __device__ __forceinline__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
+    const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
+    const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
+    const uint32_t off = w.off[wid], side = w.side[wid];
+    const uint32_t local = g - off;
+    const uint32_t y = local / side, x = local - y * side;
+    const uint32_t alive = neighbourhood<1>(w.bits, off, side, x, y);
+    *field_ptr<uint32_t>(h, self, type, kAAction) = __popc(alive) == 3 ? 1u : 0u;
+    return false;
   }
 };
 
@@ -313,10 +338,11 @@ struct AliveUpdate {
     d1 = dying[1];
   }
   template <class H>
-  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
-    bool d0, d1;
-    run_pair(h, type, self, true, self, false, w, d0, d1);
-    return d0;
+  static __device__ __forceinline__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
+    if (*field_ptr<uint32_t>(h, self, type, kAAction) == 0) return false;
+    const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
+    set_cell_live(h, w, g, w.cells[g], 0);
+    return true;
   }
 };
 
@@ -357,10 +383,19 @@ struct CandUpdate {
     d1 = l1;
   }
   template <class H>
-  static __device__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
-    bool d0, d1;
-    run_pair(h, type, self, true, self, false, w, d0, d1);
-    return d0;
+  static __device__ __forceinline__ bool run(const H& h, uint32_t type, uint32_t self, const Args& w) {
+    const uint32_t g = *field_ptr<uint32_t>(h, self, type, kACell);
+    const uint32_t wid = *field_ptr<uint32_t>(h, self, type, kAWorld);
+    const bool born = *field_ptr<uint32_t>(h, self, type, kAAction) != 0;
+    if (born && set_cell_live(h, w, g, w.cells[g], 1)) {
+      const uint32_t o = dsoar_new(h, kAlive);
+      if (o != kNull) {
+        *field_ptr<uint32_t>(h, o, kAlive, kACell) = g;
+        *field_ptr<uint32_t>(h, o, kAlive, kAWorld) = wid;
+        *field_ptr<uint32_t>(h, o, kAlive, kAAction) = 0;
+      }
+    }
+    return true;
   }
 };
 

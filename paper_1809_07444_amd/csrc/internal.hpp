@@ -183,7 +183,8 @@ struct HasWave<M, std::void_t<decltype(&M::template run_wave<DevHeap>)>> : std::
 // one wavefront request for the objects both create, so one chain of
 // dependent loads and allocation atomics serves two blocks.  Empty slots'
 // fields hold anything: the method must not index memory with them.  It
-// still provides `run` (capacity 32, and callers of single objects).
+// still provides `run` (capacity 32, lists of fewer than two entries per
+// wavefront, and callers of single objects).
 template <class M, class = void>
 struct HasPair : std::false_type {};
 template <class M>
@@ -467,21 +468,23 @@ __device__ __forceinline__ void doall_list(const H& h, uint32_t type, const uint
         freed += delete_mask(h, type, bid, dm);
       }
     };
-    if constexpr (HasPair<Method>::value) {
+    bool pairs = false;
+    if constexpr (HasPair<Method>::value) pairs = count >= 2 * nw;
+    if (pairs) {
       // Pairs only when every wavefront gets two entries or more: on a short
-      // list they would leave half the wavefronts without work, and each
-      // pass then takes one entry (the same code, its second slot empty, so
-      // that the method is inlined once).
-      const uint32_t per = count >= 2 * nw ? 2u : 1u;
+      // list they would leave half the wavefronts without work, and the
+      // method's single-object form runs instead.
+      const uint32_t per = 2;
       for (uint32_t e = per * gw; e < count; e += per * nw) {
-        const bool has1 = per == 2 && e + 1 < count;
+        const bool has1 = e + 1 < count;
         const uint32_t b0 = R[e], b1 = has1 ? R[e + 1] : b0;
         const uint64_t s0 = S[e], s1 = has1 ? S[e + 1] : 0ull;
         visits += (uint32_t)(__popcll(s0) + __popcll(s1));
         settle();
         const bool l0 = (s0 >> lane) & 1ull, l1 = (s1 >> lane) & 1ull;
         bool d0 = false, d1 = false;
-        if (l0 || l1) Method::run_pair(h, type, make_obj(b0, lane), l0, make_obj(b1, lane), l1, args, d0, d1);
+        if constexpr (HasPair<Method>::value)
+          if (l0 || l1) Method::run_pair(h, type, make_obj(b0, lane), l0, make_obj(b1, lane), l1, args, d0, d1);
         const uint64_t dm0 = __ballot(l0 && d0), dm1 = __ballot(l1 && d1);
         if (dm0) remove(b0, s0, dm0);
         if (dm1) remove(b1, s1, dm1);
