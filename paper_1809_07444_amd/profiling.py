@@ -9,8 +9,8 @@ what the same counters read for the calibration kernel of known size that
 benchmark reports the traffic only while the sources still hash the same.
 
     python -m paper_1809_07444_amd.profiling --workload gol \\
-        --fetch gpurun_out/pmc_fetch/gol_counter_collection.csv \\
-        --write gpurun_out/pmc_write/gol_counter_collection.csv \\
+        --fetch out/pmc_fetch/gol_counter_collection.csv \\
+        --write out/pmc_write/gol_counter_collection.csv \\
         --command "<the rocprofv3 commands>" --out profiles/traffic_gol.txt
 """
 from __future__ import annotations
