@@ -338,9 +338,11 @@ int dsoar_heap_stats(dsoar_heap* heap, dsoar_stats* out, void* stream);
  * Synchronises `stream`. */
 int dsoar_heap_check(dsoar_heap* heap, uint32_t* violations, void* stream);
 
-/* Device entry points for callers without their own kernels: n lanes each
- * call device new (out_dev[i] = handle or DSOAR_NULL), or each delete
- * objs_dev[i] (DSOAR_NULL entries are skipped). */
+/* Device entry points for callers without their own kernels: for each of n
+ * entries (0 <= n <= 2^32 - 1, taken by wavefronts 64 consecutive entries at
+ * a time) a lane calls device new (out_dev[i] = handle or DSOAR_NULL), or
+ * device delete of objs_dev[i] (DSOAR_NULL entries are skipped; a handle
+ * outside the heap or of a free slot sets the sticky DOUBLE_FREE flag). */
 int dsoar_alloc_n(dsoar_heap* heap, uint32_t type, uint32_t n, dsoar_obj* out_dev, void* stream);
 int dsoar_free_n(dsoar_heap* heap, const dsoar_obj* objs_dev, uint32_t n, void* stream);
 
@@ -350,11 +352,14 @@ int dsoar_free_n(dsoar_heap* heap, const dsoar_obj* objs_dev, uint32_t n, void* 
  * every type), and deletes it at once unless a hash of (seed, lane, round)
  * is 0 mod keep; kept handles go to out_dev[lane * rounds + r] (DSOAR_NULL
  * otherwise).  errors_dev[0] (device, zeroed by the caller) counts fields
- * found overwritten, i.e. slots handed out twice. */
+ * found overwritten, i.e. slots handed out twice.  INVALID_ARG unless
+ * 1 <= n <= 2^31 and n * rounds <= 2^32. */
 int dsoar_stress_churn(dsoar_heap* heap, uint32_t n, uint32_t rounds, uint32_t keep, uint32_t spread,
                        uint32_t seed, dsoar_obj* out_dev, uint32_t* errors_dev, void* stream);
 
-/* Copies a 4-byte field of n objects to/from a dense device array. */
+/* Copies a 4-byte field of n objects to/from a dense device array.
+ * DSOAR_NULL and handles outside the heap (block >= num_blocks, or slot >=
+ * the type's capacity) are skipped: their array entries are left as they are. */
 int dsoar_field_read(dsoar_heap* heap, uint32_t type, uint32_t field, const dsoar_obj* objs_dev,
                      uint32_t n, uint32_t* out_dev, void* stream);
 int dsoar_field_write(dsoar_heap* heap, uint32_t type, uint32_t field, const dsoar_obj* objs_dev,

@@ -392,7 +392,7 @@ int dsoar_collide_init(dsoar_collide* c, const float* x_dev, const float* y_dev,
   if (!c || !x_dev || !y_dev || !vx_dev || !vy_dev || !m_dev) return DSOAR_ERR_INVALID_ARG;
   with_width(c->heap, [&](auto w_) {
     constexpr uint32_t kLG = decltype(w_)::value;
-    launch_timed(c->heap, kKindCollideInit, collide_init_kernel<kLG>, dim3((c->a.n + 255) / 256), dim3(256), (hipStream_t)stream, DevHeapW<kLG>(c->heap->dev),
+    launch_timed(c->heap, kKindCollideInit, collide_init_kernel<kLG>, dim3((uint32_t)(((uint64_t)c->a.n + 255) / 256)), dim3(256), (hipStream_t)stream, DevHeapW<kLG>(c->heap->dev),
                      c->a, x_dev, y_dev, vx_dev, vy_dev, m_dev);
   });
   DSOAR_LAUNCHED(c->heap);
@@ -417,7 +417,7 @@ int dsoar_collide_step(dsoar_collide* c, uint32_t steps, uint32_t flags, void* s
 int dsoar_collide_read(dsoar_collide* c, float* x_dev, float* y_dev, float* vx_dev, float* vy_dev, float* m_dev,
                        void* stream) {
   if (!c || !x_dev || !y_dev || !vx_dev || !vy_dev || !m_dev) return DSOAR_ERR_INVALID_ARG;
-  hipLaunchKernelGGL(collide_read_kernel, dim3((c->a.n + 255) / 256), dim3(256), 0, (hipStream_t)stream, c->a, x_dev,
+  hipLaunchKernelGGL(collide_read_kernel, dim3((uint32_t)(((uint64_t)c->a.n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, c->a, x_dev,
                      y_dev, vx_dev, vy_dev, m_dev);
   DSOAR_LAUNCHED(c->heap);
   return DSOAR_OK;

@@ -727,7 +727,7 @@ int dsoar_gol_step(dsoar_gol* g, uint32_t generations, uint32_t flags, void* str
 
 int dsoar_gol_read(dsoar_gol* g, uint8_t* grid_dev, void* stream) {
   if (!g || !grid_dev) return DSOAR_ERR_INVALID_ARG;
-  hipLaunchKernelGGL(gol_read_kernel, dim3((g->total + 255) / 256), dim3(256), 0, (hipStream_t)stream, g->heap->dev,
+  hipLaunchKernelGGL(gol_read_kernel, dim3((uint32_t)(((uint64_t)g->total + 255) / 256)), dim3(256), 0, (hipStream_t)stream, g->heap->dev,
                      g->w, 0u, g->total, grid_dev);
   DSOAR_LAUNCHED(g->heap);
   return DSOAR_OK;
@@ -808,7 +808,7 @@ int dsoar_gol_retire(dsoar_gol* g, uint32_t slot, void* stream) {
   const uint32_t n = g->h_side[slot] * g->h_side[slot];
   with_width(g->heap, [&](auto w_) {
     constexpr uint32_t kLG = decltype(w_)::value;
-    hipLaunchKernelGGL(gol_retire_cells_kernel<kLG>, dim3((n + 255) / 256), dim3(256), 0, s, DevHeapW<kLG>(g->heap->dev), g->w,
+    hipLaunchKernelGGL(gol_retire_cells_kernel<kLG>, dim3((uint32_t)(((uint64_t)n + 255) / 256)), dim3(256), 0, s, DevHeapW<kLG>(g->heap->dev), g->w,
                      g->h_off[slot], n);
   });
   DSOAR_LAUNCHED(g->heap);
@@ -819,7 +819,7 @@ int dsoar_gol_retire(dsoar_gol* g, uint32_t slot, void* stream) {
 int dsoar_gol_read_world(dsoar_gol* g, uint32_t slot, uint8_t* grid_dev, void* stream) {
   if (!g || !g->live || slot >= g->num_worlds || !g->live[slot] || !grid_dev) return DSOAR_ERR_INVALID_ARG;
   const uint32_t n = g->h_side[slot] * g->h_side[slot];
-  hipLaunchKernelGGL(gol_read_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, g->heap->dev, g->w,
+  hipLaunchKernelGGL(gol_read_kernel, dim3((uint32_t)(((uint64_t)n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, g->heap->dev, g->w,
                      g->h_off[slot], n, grid_dev);
   DSOAR_LAUNCHED(g->heap);
   return DSOAR_OK;

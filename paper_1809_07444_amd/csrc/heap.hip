@@ -520,38 +520,43 @@ struct LevelOffsets {
 
 __global__ void bitmap_ops_kernel(uint32_t* units, uint32_t nbits, uint32_t lg, LevelOffsets lv, const uint32_t* ops,
                                   uint32_t n, const uint32_t* starts, int32_t* results, uint64_t* retry_flag) {
-  const uint32_t op = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (op >= n) return;
   const Bitmap b{units, nbits, num_levels(nbits, lg), lg, retry_flag, lv.off};
-  const uint32_t kind = ops[2 * op], pos = ops[2 * op + 1];
-  const uint32_t start = starts ? starts[op] : 0u;
-  int32_t r = 0;
-  const bool pos_ok = pos < nbits;
-  switch (kind) {
-    case DSOAR_BM_TRY_SET: r = pos_ok ? (bm_try_set(b, pos) ? 1 : 0) : -2; break;
-    case DSOAR_BM_TRY_CLEAR: r = pos_ok ? (bm_try_clear(b, pos) ? 1 : 0) : -2; break;
-    case DSOAR_BM_SET: r = pos_ok ? (bm_set(b, pos) ? 0 : -3) : -2; break;
-    case DSOAR_BM_CLEAR: r = pos_ok ? (bm_clear(b, pos) ? 0 : -3) : -2; break;
-    case DSOAR_BM_TRY_FIND_SET: r = bm_try_find_set(b, start); break;
-    case DSOAR_BM_FIND_CLEAR: r = bm_find_clear(b, start); break;
-    default: r = -2;
+  // One wavefront per operation, with the grid's stride in wavefronts.
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t op = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; op < n; op += waves) {
+    const uint32_t kind = ops[2 * op], pos = ops[2 * op + 1];
+    const uint32_t start = starts ? starts[op] : 0u;
+    int32_t r = 0;
+    const bool pos_ok = pos < nbits;
+    switch (kind) {
+      case DSOAR_BM_TRY_SET: r = pos_ok ? (bm_try_set(b, pos) ? 1 : 0) : -2; break;
+      case DSOAR_BM_TRY_CLEAR: r = pos_ok ? (bm_try_clear(b, pos) ? 1 : 0) : -2; break;
+      case DSOAR_BM_SET: r = pos_ok ? (bm_set(b, pos) ? 0 : -3) : -2; break;
+      case DSOAR_BM_CLEAR: r = pos_ok ? (bm_clear(b, pos) ? 0 : -3) : -2; break;
+      case DSOAR_BM_TRY_FIND_SET: r = bm_try_find_set(b, start); break;
+      case DSOAR_BM_FIND_CLEAR: r = bm_find_clear(b, start); break;
+      default: r = -2;
+    }
+    if (lane_id() == 0) results[op] = r;
   }
-  if (lane_id() == 0) results[op] = r;
 }
 
 // -------------------------------------------------------- generic kernels
+// The element kernels below loop over their items with the grid's stride (a
+// multiple of 64, so a wavefront's lanes stay one aligned group of items and
+// only the last group can be partial): a dispatch counts its work-items in 32
+// bits, so n up to 2^32 - 1 takes a capped grid, not one lane per item.
+__device__ __forceinline__ uint64_t first_item() { return (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ uint64_t item_stride() { return (uint64_t)gridDim.x * blockDim.x; }
+
 template <uint32_t LG>
 __global__ void alloc_n_kernel(DevHeapW<LG> h, uint32_t type, uint32_t n, uint32_t* out) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  out[i] = dsoar_new(h, type);
+  for (uint64_t i = first_item(); i < n; i += item_stride()) out[i] = dsoar_new(h, type);
 }
 
 template <uint32_t LG>
 __global__ void free_n_kernel(DevHeapW<LG> h, const uint32_t* objs, uint32_t n) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  dsoar_delete(h, objs[i]);
+  for (uint64_t i = first_item(); i < n; i += item_stride()) dsoar_delete(h, objs[i]);
 }
 
 // Allocation/deletion stress: lane i runs `rounds` rounds; in round r its
@@ -593,13 +598,14 @@ __global__ void churn_kernel(DevHeapW<LG> h, uint32_t n, uint32_t rounds, uint32
 
 __global__ void field_rw_kernel(DevHeap h, uint32_t type, uint32_t field, const uint32_t* objs, uint32_t n,
                                 uint32_t* data, int write) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t o = objs[i];
-  if (o == kNull) return;
-  uint32_t* p = field_ptr<uint32_t>(h, o, type, field);
-  if (write) *p = data[i];
-  else data[i] = *p;
+  for (uint64_t i = first_item(); i < n; i += item_stride()) {
+    const uint32_t o = objs[i];
+    // NULL and handles outside the heap's blocks or the type's slots are skipped.
+    if (o == kNull || obj_block(o) >= h.num_blocks || obj_slot(o) >= h.capacity[type]) continue;
+    uint32_t* p = field_ptr<uint32_t>(h, o, type, field);
+    if (write) *p = data[i];
+    else data[i] = *p;
+  }
 }
 
 // ---------------------------------------------------------- built-in methods
@@ -713,10 +719,14 @@ using namespace dsoar;
 
 namespace {
 
+// Workgroups for n items of `threads` lanes: enough to cover them, at most
+// `cap`, and fewer than 2^32 work-items in all (a dispatch's 32-bit limit).
+// Kernels launched with a capped grid loop over their items.
 uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t cap = 65535u * 16u) {
   uint64_t g = (n + threads - 1) / threads;
   if (g < 1) g = 1;
-  return (uint32_t)std::min<uint64_t>(g, cap);
+  g = std::min<uint64_t>(g, cap);
+  return (uint32_t)std::min<uint64_t>(g, 0xFFFFFFFFull / threads);
 }
 
 int init_device_state(dsoar_heap* h, hipStream_t s) {
@@ -1112,7 +1122,7 @@ int dsoar_alloc_n(dsoar_heap* h, uint32_t type, uint32_t n, dsoar_obj* out_dev, 
   if (n == 0) return DSOAR_OK;
   with_width(h, [&](auto w_) {
     constexpr uint32_t kLG = decltype(w_)::value;
-    hipLaunchKernelGGL(alloc_n_kernel<kLG>, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, (hipStream_t)stream, DevHeapW<kLG>(h->dev),
+    hipLaunchKernelGGL(alloc_n_kernel<kLG>, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, (hipStream_t)stream, DevHeapW<kLG>(h->dev),
                      type, n, out_dev);
   });
   DSOAR_LAUNCHED(h);
@@ -1121,13 +1131,14 @@ int dsoar_alloc_n(dsoar_heap* h, uint32_t type, uint32_t n, dsoar_obj* out_dev, 
 
 int dsoar_stress_churn(dsoar_heap* h, uint32_t n, uint32_t rounds, uint32_t keep, uint32_t spread, uint32_t seed,
                        dsoar_obj* out_dev, uint32_t* errors_dev, void* stream) {
-  if (!heap_ok(h) || n == 0 || rounds == 0 || keep == 0 || !out_dev || !errors_dev || (uint64_t)n * rounds > (1ull << 32))
+  if (!heap_ok(h) || n == 0 || n > (1u << 31) || rounds == 0 || keep == 0 || !out_dev || !errors_dev ||
+      (uint64_t)n * rounds > (1ull << 32))
     return DSOAR_ERR_INVALID_ARG;
   for (uint32_t t = 0; t < h->desc.num_types; ++t)
     if (h->desc.types[t].field_bytes[0] != 4) return DSOAR_ERR_INVALID_ARG;
   with_width(h, [&](auto w_) {
     constexpr uint32_t kLG = decltype(w_)::value;
-    hipLaunchKernelGGL(churn_kernel<kLG>, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, DevHeapW<kLG>(h->dev), n, rounds, keep,
+    hipLaunchKernelGGL(churn_kernel<kLG>, dim3((uint32_t)(((uint64_t)n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, DevHeapW<kLG>(h->dev), n, rounds, keep,
                      spread, seed, out_dev, errors_dev);
   });
   DSOAR_LAUNCHED(h);
@@ -1139,7 +1150,7 @@ int dsoar_free_n(dsoar_heap* h, const dsoar_obj* objs_dev, uint32_t n, void* str
   if (n == 0) return DSOAR_OK;
   with_width(h, [&](auto w_) {
     constexpr uint32_t kLG = decltype(w_)::value;
-    hipLaunchKernelGGL(free_n_kernel<kLG>, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, (hipStream_t)stream, DevHeapW<kLG>(h->dev),
+    hipLaunchKernelGGL(free_n_kernel<kLG>, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, (hipStream_t)stream, DevHeapW<kLG>(h->dev),
                      objs_dev, n);
   });
   DSOAR_LAUNCHED(h);
@@ -1152,7 +1163,7 @@ static int field_rw(dsoar_heap* h, uint32_t type, uint32_t field, const dsoar_ob
       h->desc.types[type].field_bytes[field] != 4 || (n && (!objs || !data)))
     return DSOAR_ERR_INVALID_ARG;
   if (n == 0) return DSOAR_OK;
-  hipLaunchKernelGGL(field_rw_kernel, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, (hipStream_t)stream, h->dev,
+  hipLaunchKernelGGL(field_rw_kernel, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, (hipStream_t)stream, h->dev,
                      type, field, objs, n, data, write);
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
@@ -1215,7 +1226,7 @@ int dsoar_bitmap_run(void* bm_dev, uint32_t nbits, uint32_t width, const uint32_
   uint64_t* flag = reinterpret_cast<uint64_t*>(units + bitmap_units(nbits, lg));
   LevelOffsets lv;
   for (uint32_t l = 0; l < kMaxLevels; ++l) lv.off[l] = level_offset(nbits, lg, l);
-  hipLaunchKernelGGL(bitmap_ops_kernel, dim3(grid_for((uint64_t)n * 64, 256, 1u << 30)), dim3(256), 0,
+  hipLaunchKernelGGL(bitmap_ops_kernel, dim3(grid_for((uint64_t)n * 64, 256, 1u << 20)), dim3(256), 0,
                      (hipStream_t)stream, units, nbits, lg, lv, ops_dev, n, start_dev, results_dev, flag);
   if (hipGetLastError() != hipSuccess) return DSOAR_ERR_HIP;
   return DSOAR_OK;

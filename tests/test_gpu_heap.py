@@ -251,6 +251,20 @@ def test_field_roundtrip_and_delete_if_mod():
     assert heap.check() == {}
 
 
+def test_field_access_skips_handles_outside_the_heap():
+    # 8 blocks of 32 slots: a slot >= 32, a block >= 8, NULL and a block near
+    # the top of the handle range are skipped by reads and writes alike.
+    heap = Heap(8, 32, [(4,)])
+    h = heap.alloc_n(0, 3)
+    heap.field_write(0, 0, h, torch.tensor([7, 8, 9], dtype=torch.int32, device="cuda"))
+    bad = torch.tensor([40, 8 << 6, -1, ((1 << 26) - 2) << 6], dtype=torch.int64).to(torch.int32).cuda()
+    heap.field_write(0, 0, bad, torch.full((4,), 5, dtype=torch.int32, device="cuda"))
+    objs = torch.cat([h, bad])
+    assert heap.field_read(0, 0, objs).cpu().tolist() == [7, 8, 9, 0, 0, 0, 0]
+    assert heap.stats()["live"] == [3]
+    assert heap.check() == {}
+
+
 def test_enumeration_matches_brute_force_and_reclaims():
     rng = np.random.default_rng(3)
     M = 3000  # ragged: not a multiple of 64, several scan tiles

@@ -1,0 +1,83 @@
+"""The largest heap the handle format allows, filled to capacity and drained.
+
+A handle is block << 6 | slot in 32 bits and DSOAR_NULL is all ones (slot 63
+of block 2^26 - 1), so a heap holds at most 2^26 - 1 blocks of 64 slots:
+handles then reach 2^32 - 65, the field data spans 16 GiB and the bitmaps
+have 5 levels at width 64 (6 at width 32).  Device new fills the heap to
+exactly its capacity (Sec. 2.2: a request fails only when no block has room),
+the do-all visits every object once, one more request fails as out of memory,
+and device delete plus quiescent reclamation return every block.  About 40
+GiB of device memory per case.
+"""
+import pytest
+import torch
+
+from paper_1809_07444_amd import _capi as C
+from paper_1809_07444_amd.heap import Heap
+
+M = (1 << 26) - 1
+N = M * 64          # 2^32 - 64 objects
+CHUNK = 1 << 28
+
+
+def _step(msg):
+    print(f"[max heap] {msg}", flush=True)
+
+
+def _covers_every_slot(h: torch.Tensor) -> bool:
+    """True when the N handles are N distinct slots below N (no NULL)."""
+    seen = torch.zeros(N, dtype=torch.bool, device=h.device)
+    for i in range(0, N, CHUNK):
+        part = h[i:i + CHUNK].to(torch.int64) & 0xFFFFFFFF
+        if not bool((part < N).all()):  # checked before the values index anything
+            return False
+        seen[part] = True
+        del part
+    ok = bool(seen.all())
+    del seen
+    return ok
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("width", [64, 32])
+def test_largest_heap_fills_to_capacity_and_drains(width):
+    _step(f"width {width}: create {M} blocks")
+    heap = Heap(M, 64, [(4,)], bitmap_width=width)
+    assert heap.layout().num_levels == (5 if width == 64 else 6)
+    try:
+        _step(f"width {width}: {N} device new")
+        h = heap.alloc_n(0, N)
+        torch.cuda.synchronize()
+        st = heap.stats()
+        assert st["live"] == [N] and st["allocs"] == [N]
+        assert st["allocated_blocks"] == [M] and st["active_blocks"] == [0] and st["free_blocks"] == 0
+        _step(f"width {width}: handle coverage")
+        assert _covers_every_slot(h)
+        _step(f"width {width}: do-all visit counts")
+        counts = heap.visit_counts(0)
+        visited_once = bool((counts == 1).all())
+        del counts
+        assert visited_once
+        assert heap.enum_count(0) == M
+        R, S = heap.enum_arrays(0, M)
+        assert torch.equal(R, torch.arange(M, dtype=torch.int32, device=R.device))
+        assert bool((S == -1).all())
+        assert heap.check() == {}
+        _step(f"width {width}: one request more")
+        extra = heap.alloc_n(0, 64)
+        assert bool((extra == -1).all())  # DSOAR_NULL read as int32
+        st = heap.stats(raise_sticky=False)
+        assert st["oom"] == 1 and st["status"] == C.ERR_OOM and st["live"] == [N]
+        _step(f"width {width}: {N} device delete")
+        heap.free_n(h)
+        del h
+        heap.enumerate(0)  # quiescent reclamation of every emptied block
+        st = heap.stats(raise_sticky=False)
+        assert st["live"] == [0] and st["frees"] == [N]
+        assert st["allocated_blocks"] == [0] and st["active_blocks"] == [0] and st["free_blocks"] == M
+        assert st["blocks_returned"] == M and st["double_free"] == 0
+        assert heap.check() == {"sticky": "DSOAR_ERR_OOM"}
+    finally:
+        heap.close()
+        del heap
+        torch.cuda.empty_cache()
