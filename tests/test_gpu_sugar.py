@@ -62,7 +62,8 @@ def test_hand_case(flags):
 
 
 @pytest.mark.parametrize("side,agents,seed,cap", [(16, 40, 1, 64), (33, 300, 2, 32), (64, 1000, 3, 64),
-                                                   (64, 3000, 4, 32), (1, 1, 5, 64), (2, 3, 6, 64)])
+                                                   (64, 3000, 4, 32), (1, 1, 5, 64), (2, 3, 6, 64),
+                                                   (8, 0, 7, 64)])  # no agents: regrowth only
 def test_random_worlds(side, agents, seed, cap):
     inp = W.sugar_inputs(side, agents, seed=seed)
     sim = apps.Sugarscape(inp, RULES, capacity=cap)
