@@ -5,9 +5,10 @@ of block 2^26 - 1), so a heap holds at most 2^26 - 1 blocks of 64 slots:
 handles then reach 2^32 - 65, the field data spans 16 GiB and the bitmaps
 have 5 levels at width 64 (6 at width 32).  Device new fills the heap to
 exactly its capacity (Sec. 2.2: a request fails only when no block has room),
-the do-all visits every object once, one more request fails as out of memory,
-and device delete plus quiescent reclamation return every block.  About 40
-GiB of device memory per case.
+the do-all visits every object once, the enumeration and its allocation-free
+variant list every block, one more request fails as out of memory, and device
+delete plus quiescent reclamation return every block.  About 40 GiB of device
+memory per case.
 """
 import pytest
 import torch
@@ -62,6 +63,15 @@ def test_largest_heap_fills_to_capacity_and_drains(width):
         R, S = heap.enum_arrays(0, M)
         assert torch.equal(R, torch.arange(M, dtype=torch.int32, device=R.device))
         assert bool((S == -1).all())
+        _step(f"width {width}: allocation-free enumeration")
+        R2 = torch.full((M,), -1, dtype=torch.int32, device=R.device)
+        S2 = torch.zeros(M, dtype=torch.int64, device=R.device)
+        cnt = torch.full((1,), -1, dtype=torch.int32, device=R.device)
+        assert heap.lib.dsoar_enumerate_noalloc(heap.h, 0, R2.data_ptr(), S2.data_ptr(), cnt.data_ptr(),
+                                                heap._s()) == C.OK
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == M and torch.equal(R2, R) and torch.equal(S2, S)
+        del R2, S2
         assert heap.check() == {}
         _step(f"width {width}: one request more")
         extra = heap.alloc_n(0, 64)
