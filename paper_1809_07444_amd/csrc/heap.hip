@@ -681,6 +681,9 @@ int launch_enumerate(dsoar_heap* h, uint32_t type, hipStream_t s) {
 // its own copy; host code uses the address hipGetSymbolAddress returns for
 // the current device, never the symbol itself.
 constexpr uint32_t kStaticTiles = 16384;
+static_assert((1u << 20) / (enum_waves(kEnumWideWords) * kEnumWideWords) <= kStaticTiles &&
+                  kEnumWideFrom / enum_waves(1) <= kStaticTiles,
+              "the scratch covers the tiles of every heap size");
 constexpr uint32_t kScratchWords = 2 + kStaticTiles;  // ScanState, then the tile flags
 static_assert(sizeof(ScanState) == 16, "scan state is two words");
 static __device__ __align__(256) uint64_t scratch[kScratchWords];

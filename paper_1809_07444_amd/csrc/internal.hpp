@@ -17,11 +17,12 @@ namespace dsoar {
 // bitmap (64 blocks), or kEnumWideWords words when the bitmap has more than
 // kEnumWideFrom words; a workgroup of enum_waves(WPW) wavefronts is one tile
 // of the decoupled look-back scan.  Wide scans take 16 wavefronts per tile:
-// half the tiles, so a shorter look-back chain (a 2^22-block heap's scan 33
-// -> 22 us); narrow ones keep 8, which spreads a small heap's few words over
-// more workgroups.
+// far fewer tiles, so a shorter look-back chain (a 2^22-block heap's scan 33
+// -> 22 us, a 2^18-block one's 13.7 -> 8.5 us); narrow ones keep 8, which
+// spreads a small heap's few words over more workgroups (768 words: 6.9
+// against 11.5 us wide).
 constexpr uint32_t kEnumWideWords = 8;
-constexpr uint32_t kEnumWideFrom = 16384;
+constexpr uint32_t kEnumWideFrom = 2048;
 constexpr uint32_t enum_waves(uint32_t wpw) { return wpw > 1 ? 16u : 8u; }
 
 // Per-type scan state: tile ticket, epoch (so the look-back flags never need
