@@ -321,13 +321,24 @@ __global__ void __launch_bounds__(enum_waves(WPW) * 64) enumerate_kernel(DevHeap
   const uint32_t word0 = (tile * kEnumWaves + wave) * WPW;
   const uint64_t* alloc0 = allocated_bm(h, type).group(0);  // level 0 as 64-bit groups
   uint64_t w[WPW], live[WPW], snap[WPW];
+  if constexpr (WPW == 1) {
+    // Narrow tiles (heaps of at most kEnumWideFrom words, 1 MiB of object
+    // bitmaps): every block's object bitmap is loaded together with the
+    // allocated word, one round trip instead of two, and kept where the
+    // allocated bit is set.
+    const uint32_t b = word0 * 64 + lane;
+    const uint64_t ob = b < h.num_blocks ? meta_load(h.obj_bitmap + b) : 0ull;
+    w[0] = word0 < W0 ? load_u64(alloc0 + word0) : 0ull;
+    snap[0] = ((w[0] >> lane) & 1ull) ? ob : 0ull;
+  } else {
 #pragma unroll
-  for (uint32_t j = 0; j < WPW; ++j) w[j] = word0 + j < W0 ? load_u64(alloc0 + word0 + j) : 0ull;
+    for (uint32_t j = 0; j < WPW; ++j) w[j] = word0 + j < W0 ? load_u64(alloc0 + word0 + j) : 0ull;
 #pragma unroll
-  for (uint32_t j = 0; j < WPW; ++j) {
-    const uint32_t b = (word0 + j) * 64 + lane;
-    const bool bit = ((w[j] >> lane) & 1ull) && b < h.num_blocks;
-    snap[j] = bit ? meta_load(h.obj_bitmap + b) : 0ull;
+    for (uint32_t j = 0; j < WPW; ++j) {
+      const uint32_t b = (word0 + j) * 64 + lane;
+      const bool bit = ((w[j] >> lane) & 1ull) && b < h.num_blocks;
+      snap[j] = bit ? meta_load(h.obj_bitmap + b) : 0ull;
+    }
   }
   uint32_t wave_total = 0;
   uint64_t empty[WPW];  // allocated blocks without objects: reclaimed at the end

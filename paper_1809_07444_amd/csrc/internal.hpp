@@ -469,6 +469,13 @@ __device__ __forceinline__ void doall_list(const H& h, uint32_t type, const uint
         freed += delete_mask(h, type, bid, dm);
       }
     };
+    // This wavefront's first entry of the single-object loop, loaded before
+    // the count is known (R and S hold num_blocks entries, so the load stays
+    // in bounds): on lists of about one entry per wavefront the count's load
+    // and the entry's then take one round trip instead of two.
+    const uint32_t first = gw < h.num_blocks ? gw : h.num_blocks - 1;
+    const uint32_t first_bid = R[first];
+    const uint64_t first_snap = S[first];
     bool pairs = false;
     if constexpr (HasPair<Method>::value) pairs = count >= 2 * nw;
     if (pairs) {
@@ -492,8 +499,8 @@ __device__ __forceinline__ void doall_list(const H& h, uint32_t type, const uint
       }
     } else {
       for (uint32_t e = gw; e < count; e += nw) {
-        const uint32_t bid = R[e];
-        const uint64_t snap = S[e];
+        const uint32_t bid = e == gw ? first_bid : R[e];
+        const uint64_t snap = e == gw ? first_snap : S[e];
         visits += (uint32_t)__popcll(snap);
         settle();
         const bool del = run_slot<Method>(h, type, make_obj(bid, lane), (snap >> lane) & 1ull, args);
