@@ -1,8 +1,11 @@
-"""A Game-of-Life world pool driven through the C ABI directly: admission's
+"""World pools (Game of Life and Sugarscape) driven through the C ABI directly: admission's
 argument checks (an occupied or missing slot, side 0, a cell range past the
 arena's end or overlapping a resident world) leave the pool untouched, and
 worlds admitted flush against the arena's end and into the cells a retired
-world left step exactly as the oracle's B3/S23 stencil."""
+world left step exactly as the oracle does (the B3/S23 stencil, the Sugarscape
+rules with each world's own seed)."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -61,6 +64,68 @@ def test_admission_checks_and_reused_cells():
         assert np.array_equal(read(pool, 1, 30), oracle.gol_run(gB, 8)[0])
         assert np.array_equal(read(pool, 0, 10), oracle.gol_run(gC, 3)[0])
         assert np.array_equal(read(pool, 2, 10), oracle.gol_run(gD, 3)[0])
+        assert pool.heap.check() == {}
+    finally:
+        pool.close()
+
+
+RULES = W.SUGAR_RULES
+
+
+def sugar_admit(pool, slot, off, inp):
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in
+           (inp.sugar, inp.cap, inp.occ, inp.a_sugar, inp.a_metab, inp.a_vision, inp.a_age)]
+    rc = pool.lib.dsoar_sugar_admit(pool.p, slot, off, inp.side, inp.seed, 0, *[t.data_ptr() for t in dev],
+                                    pool.heap._s())
+    pool.stream.synchronize()
+    return rc
+
+
+def sugar_check(pool, slot, inp, steps):
+    n = inp.side * inp.side
+    outs = [torch.empty(n, dtype=dt, device="cuda") for dt in
+            (torch.int32, torch.uint8, torch.int32, torch.int32, torch.int32, torch.int32)]
+    moves = ctypes.c_uint64()
+    C.check(pool.lib.dsoar_sugar_read_world(pool.p, slot, *[t.data_ptr() for t in outs], ctypes.byref(moves),
+                                            pool.heap._s()), "dsoar_sugar_read_world")
+    pool.stream.synchronize()
+    got = [t.cpu().numpy() for t in outs]
+    st = oracle.SugarState(inp.side, inp.sugar, inp.cap, inp.occ, inp.a_sugar, inp.a_metab, inp.a_vision,
+                           inp.a_age)
+    ref = oracle.sugar_run(st, steps, inp.seed, RULES)
+    assert np.array_equal(got[0], ref.sugar) and np.array_equal(got[1], ref.occ)
+    m = ref.occ.astype(bool)
+    for g, f in zip(got[2:], ("a_sugar", "a_metab", "a_vision", "a_age")):
+        assert np.array_equal(g[m], getattr(ref, f)[m])
+    assert int(moves.value) == ref.moves
+
+
+def sugar_step(pool, steps):
+    C.check(pool.lib.dsoar_sugar_step(pool.p, steps, C.DO_PERSISTENT, pool.heap._s()), "dsoar_sugar_step")
+    pool.stream.synchronize()
+
+
+def test_sugar_pool_admission_checks_and_reused_cells():
+    pool = Pool("sugar", 512, 4, ARENA, rules=RULES, graph=False)
+    try:
+        iA, iB = W.sugar_inputs(20, 60, seed=5), W.sugar_inputs(30, 150, seed=6)
+        iC = W.sugar_inputs(10, 20, seed=7)
+        assert sugar_admit(pool, 0, 0, iA) == C.OK                         # cells [0, 400)
+        live0 = pool.heap.stats()["live"]
+        assert sugar_admit(pool, 1, ARENA - 900 + 1, iB) == C.ERR_INVALID_ARG  # one cell past the end
+        assert sugar_admit(pool, 0, 1000, iC) == C.ERR_INVALID_ARG         # slot 0 is occupied
+        assert sugar_admit(pool, 4, 1000, iC) == C.ERR_INVALID_ARG         # only slots 0 .. 3
+        assert sugar_admit(pool, 2, 399, iC) == C.ERR_INVALID_ARG          # overlaps [0, 400)
+        assert pool.heap.stats()["live"] == live0                          # rejected calls changed nothing
+        assert sugar_admit(pool, 1, ARENA - 900, iB) == C.OK               # flush against the end
+        sugar_step(pool, 4)
+        sugar_check(pool, 0, iA, 4)
+        sugar_check(pool, 1, iB, 4)
+        C.check(pool.lib.dsoar_sugar_retire(pool.p, 0, pool.heap._s()), "dsoar_sugar_retire")
+        assert sugar_admit(pool, 0, 50, iC) == C.OK                        # inside the retired world's cells
+        sugar_step(pool, 3)
+        sugar_check(pool, 1, iB, 7)
+        sugar_check(pool, 0, iC, 3)
         assert pool.heap.check() == {}
     finally:
         pool.close()
