@@ -313,6 +313,7 @@ struct CandPrep {
 // itself only): loads of both slots first, then the Cells' handles of both.
 struct AliveUpdate {
   static constexpr uint32_t kKind = 32;
+  static constexpr uint32_t kMinWaves = 8;
   static constexpr bool kDeletesOnlyThis = true;
   using Args = World;
   template <class H>
@@ -348,6 +349,7 @@ struct AliveUpdate {
 
 struct CandUpdate {
   static constexpr uint32_t kKind = 33;
+  static constexpr uint32_t kMinWaves = 8;
   static constexpr bool kDeletesOnlyThis = true;
   using Args = World;
   template <class H>

@@ -206,6 +206,20 @@ template <class M>
 struct DeletesOnlyThis<M, std::void_t<decltype(M::kDeletesOnlyThis)>>
     : std::integral_constant<bool, M::kDeletesOnlyThis> {};
 
+// A method may also declare
+//   static constexpr uint32_t kMinWaves = 8;
+// to have its do-all kernels on large heaps compiled for at least that many
+// wavefronts per SIMD: the allocation path holds about 104 scalar registers,
+// which leaves room for seven, and on long lists chains of dependent atomics
+// want every wavefront the SIMD can hold (scalar values beyond the budget
+// live in vector lanes).  On small heaps, whose lists give a wavefront about
+// one entry, more resident wavefronts gain nothing and the spills of the
+// tighter budget lengthen the chain, so they keep the unconstrained kernel.
+template <class M, class = void>
+struct MinWaves : std::integral_constant<uint32_t, 1> {};
+template <class M>
+struct MinWaves<M, std::void_t<decltype(M::kMinWaves)>> : std::integral_constant<uint32_t, M::kMinWaves> {};
+
 template <class Method, class H>
 __device__ __forceinline__ bool run_method(const H& h, uint32_t type, uint32_t self,
                                            const typename Method::Args& a) {
@@ -536,8 +550,9 @@ __device__ __forceinline__ uint32_t grid_wave() {
   return blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
-template <class Method, uint32_t LG>
-__global__ void __launch_bounds__(1024) doall_kernel(DevHeapW<LG> h, uint32_t type, const uint32_t* __restrict__ R,
+template <class Method, uint32_t LG, bool kMany = false>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kMany ? MinWaves<Method>::value : 1)))
+doall_kernel(DevHeapW<LG> h, uint32_t type, const uint32_t* __restrict__ R,
                                                       const uint64_t* __restrict__ S, const uint32_t* count_ptr,
                                                       typename Method::Args args) {
   const uint32_t nw = gridDim.x * (blockDim.x >> 6);
@@ -552,8 +567,12 @@ __global__ void __launch_bounds__(1024) doall_kernel(DevHeapW<LG> h, uint32_t ty
 // takes its share of the first list, then of the second.  For methods that
 // may run at the same time (neither reads what the other writes, apart from
 // the heap's own atomics): one kernel boundary and one launch fewer.
-template <class M1, class M2, uint32_t LG>
-__global__ void __launch_bounds__(1024) doall2_kernel(DevHeapW<LG> h, uint32_t t1, const uint32_t* __restrict__ R1,
+template <class M1, class M2, uint32_t LG, bool kMany = false>
+__global__ void __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(!kMany ? 1u
+                                          : MinWaves<M1>::value > MinWaves<M2>::value ? MinWaves<M1>::value
+                                                                                      : MinWaves<M2>::value)))
+doall2_kernel(DevHeapW<LG> h, uint32_t t1, const uint32_t* __restrict__ R1,
                                                        const uint64_t* __restrict__ S1, const uint32_t* c1,
                                                        typename M1::Args a1, uint32_t t2,
                                                        const uint32_t* __restrict__ R2,
@@ -570,6 +589,10 @@ __global__ void __launch_bounds__(1024) doall2_kernel(DevHeapW<LG> h, uint32_t t
   if (visits) lead_add(shard(h) + kCntVisits + t2, visits);
   if (freed) lead_add(shard(h) + kCntFrees + t2, freed);
 }
+
+// Large heaps: those whose enumeration takes wide tiles (more than
+// kEnumWideFrom level-0 words, 131,072 blocks).
+inline bool large_heap(const dsoar_heap* h) { return h->enum_wpw == kEnumWideWords; }
 
 // Enumerate (unless reusing) and launch the do-all of Method over `type`.
 template <class Method>
@@ -596,8 +619,16 @@ int launch_doall(dsoar_heap* h, uint32_t type, const typename Method::Args& args
   }
   with_width(h, [&](auto w_) {
     constexpr uint32_t kLG = decltype(w_)::value;
-    launch_timed(h, Method::kKind, doall_kernel<Method, kLG>, dim3(grid), dim3(threads), s, DevHeapW<kLG>(h->dev), type,
-               (const uint32_t*)eo.R, (const uint64_t*)eo.S, (const uint32_t*)&eo.st->count, args);
+    auto go = [&](auto kernel) {
+      launch_timed(h, Method::kKind, kernel, dim3(grid), dim3(threads), s, DevHeapW<kLG>(h->dev), type,
+                   (const uint32_t*)eo.R, (const uint64_t*)eo.S, (const uint32_t*)&eo.st->count, args);
+    };
+    if constexpr (MinWaves<Method>::value > 1) {
+      if (large_heap(h)) go(doall_kernel<Method, kLG, true>);
+      else go(doall_kernel<Method, kLG, false>);
+    } else {
+      go(doall_kernel<Method, kLG, false>);
+    }
   });
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
@@ -638,10 +669,18 @@ int launch_doall2(dsoar_heap* h, uint32_t t1, const typename M1::Args& a1, uint3
   const EnumOut& e2 = h->enum_out[t2];
   with_width(h, [&](auto w_) {
     constexpr uint32_t kLG = decltype(w_)::value;
-    launch_timed(h, kind, doall2_kernel<M1, M2, kLG>, dim3(h->num_cus * h->doall_wgs_per_cu),
-               dim3(h->doall_wg_threads), s, DevHeapW<kLG>(h->dev), t1, (const uint32_t*)e1.R, (const uint64_t*)e1.S,
-               (const uint32_t*)&e1.st->count, a1, t2, (const uint32_t*)e2.R, (const uint64_t*)e2.S,
-               (const uint32_t*)&e2.st->count, a2);
+    auto go = [&](auto kernel) {
+      launch_timed(h, kind, kernel, dim3(h->num_cus * h->doall_wgs_per_cu), dim3(h->doall_wg_threads), s,
+                   DevHeapW<kLG>(h->dev), t1, (const uint32_t*)e1.R, (const uint64_t*)e1.S,
+                   (const uint32_t*)&e1.st->count, a1, t2, (const uint32_t*)e2.R, (const uint64_t*)e2.S,
+                   (const uint32_t*)&e2.st->count, a2);
+    };
+    if constexpr (MinWaves<M1>::value > 1 || MinWaves<M2>::value > 1) {
+      if (large_heap(h)) go(doall2_kernel<M1, M2, kLG, true>);
+      else go(doall2_kernel<M1, M2, kLG, false>);
+    } else {
+      go(doall2_kernel<M1, M2, kLG, false>);
+    }
   });
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;

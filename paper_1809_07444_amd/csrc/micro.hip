@@ -26,6 +26,7 @@ struct MicroUpdate {
 
 struct MicroCull {
   static constexpr uint32_t kKind = 21;
+  static constexpr uint32_t kMinWaves = 8;
   struct Args { uint32_t unused; };
   struct Pre { int32_t id; };
   template <class H>

@@ -196,6 +196,7 @@ struct Move {
 
 struct Eat {
   static constexpr uint32_t kKind = 42;
+  static constexpr uint32_t kMinWaves = 8;
   static constexpr bool kDeletesOnlyThis = true;
   using Args = Grid;
   template <class H>
@@ -240,6 +241,7 @@ struct Request {
 
 struct Birth {
   static constexpr uint32_t kKind = 44;
+  static constexpr uint32_t kMinWaves = 8;
   using Args = Grid;
   template <class H>
   static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& g) {

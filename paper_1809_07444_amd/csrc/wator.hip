@@ -115,6 +115,7 @@ struct FishDecide {
 
 struct FishMove {
   static constexpr uint32_t kKind = 71;
+  static constexpr uint32_t kMinWaves = 8;
   using Args = Sea;
   template <class H>
   static __device__ bool run(const H& h, uint32_t, uint32_t self, const Args& a) {
@@ -169,6 +170,7 @@ struct SharkDecide {
 
 struct SharkMove {
   static constexpr uint32_t kKind = 73;
+  static constexpr uint32_t kMinWaves = 8;
   static constexpr bool kDeletesOnlyThis = true;
   using Args = Sea;
   template <class H>

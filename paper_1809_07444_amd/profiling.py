@@ -59,12 +59,14 @@ PLAIN_KIND = [
 def kernel_kind(name: str) -> str | None:
     """Kernel kind of a rocprofv3 kernel name, 'calibration' for the add, or None."""
     # Kernels that touch the bitmaps are instantiated per container width: a
-    # trailing template argument such as ", 6u" follows the methods.
+    # trailing template argument such as ", 6u" follows the methods, and
+    # do-alls may add ", true" / ", false" (the large-heap variant).
+    tail = r"(?:,\s*\d+u)?(?:,\s*(?:true|false))?>"
     m2 = re.search(r"doall2_kernel<(?:[\w:]*::|\(anonymous namespace\)::)*(\w+),\s*"
-                   r"(?:[\w:]*::|\(anonymous namespace\)::)*(\w+)(?:,\s*\d+u)?>", name)
+                   r"(?:[\w:]*::|\(anonymous namespace\)::)*(\w+)" + tail, name)
     if m2:
         return METHOD2_KIND.get((m2.group(1), m2.group(2)))
-    m = re.search(r"doall_kernel<(?:[\w:]*::|\(anonymous namespace\)::)*(\w+)(?:,\s*\d+u)?>", name)
+    m = re.search(r"doall_kernel<(?:[\w:]*::|\(anonymous namespace\)::)*(\w+)" + tail, name)
     if m:
         return METHOD_KIND.get(m.group(1))
     if "enumerate_kernel" in name:

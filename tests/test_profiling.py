@@ -41,6 +41,14 @@ TRACE_NAMES = {
     "unsigned long const*, unsigned int const*, dsoar::(anonymous namespace)::CandUpdate::Args)": "gol_update",
     "void dsoar::(anonymous namespace)::enumerate_kernel<8u, 6u>(dsoar::DevHeapW<6u>, unsigned int, "
     "dsoar::EnumOut)": "enumerate",
+    # Do-alls instantiated for large heaps (more resident wavefronts) or not.
+    "void dsoar::doall2_kernel<dsoar::(anonymous namespace)::AliveUpdate, dsoar::(anonymous namespace)::"
+    "CandUpdate, 6u, true>(dsoar::DevHeapW<6u>, unsigned int, unsigned int const*, unsigned long const*, "
+    "unsigned int const*, dsoar::(anonymous namespace)::AliveUpdate::Args, unsigned int, unsigned int const*, "
+    "unsigned long const*, unsigned int const*, dsoar::(anonymous namespace)::CandUpdate::Args)": "gol_update",
+    "void dsoar::doall_kernel<dsoar::(anonymous namespace)::Eat, 6u, false>(dsoar::DevHeapW<6u>, unsigned int, "
+    "unsigned int const*, unsigned long const*, unsigned int const*, "
+    "dsoar::(anonymous namespace)::Eat::Args)": "sugar_eat",
     "void dsoar::(anonymous namespace)::gol_init_kernel<6u>(dsoar::DevHeapW<6u>, "
     "dsoar::(anonymous namespace)::World, unsigned int, unsigned int, unsigned char const*)": "gol_init",
     "void dsoar::(anonymous namespace)::entry_kernel<5u>(dsoar::DevHeapW<5u>, dsoar::(anonymous namespace)::Road)":
