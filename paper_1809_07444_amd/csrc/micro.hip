@@ -49,9 +49,14 @@ constexpr uint32_t kCreatePerLane = 4;
 constexpr uint32_t kCreateWideMin = 1u << 22;
 constexpr uint32_t kCreateThreads = 256;
 
-template <uint32_t LG>
-__global__ void micro_create_kernel(DevHeapW<LG> h, uint32_t type, uint32_t n, uint32_t per_lane, uint32_t id_mul,
-                                    const float* xs, const float* vs) {
+// Large creations are compiled for 8 wavefronts per SIMD (the allocation
+// path's scalar registers leave room for 7 otherwise): their grids are many
+// times the resident wavefronts, and more of them hide more of each
+// request's chain of atomics.
+template <uint32_t LG, bool kWide>
+__global__ void __attribute__((amdgpu_waves_per_eu(kWide ? 8 : 1)))
+micro_create_kernel(DevHeapW<LG> h, uint32_t type, uint32_t n, uint32_t per_lane, uint32_t id_mul, const float* xs,
+                    const float* vs) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t wave = (uint64_t)blockIdx.x * (kCreateThreads / 64) + (threadIdx.x >> 6);
   const uint64_t base = wave * (64u * per_lane) + lane;
@@ -79,8 +84,13 @@ int launch_create(dsoar_heap* h, uint32_t type, uint32_t n, uint32_t id_mul, con
   const uint64_t per_block = (uint64_t)kCreateThreads * per_lane;
   with_width(h, [&](auto w_) {
     constexpr uint32_t kLG = decltype(w_)::value;
-    launch_timed(h, kKindMicroCreate, micro_create_kernel<kLG>, dim3((uint32_t)((n + per_block - 1) / per_block)),
-               dim3(kCreateThreads), s, DevHeapW<kLG>(h->dev), type, n, per_lane, id_mul, xs, vs);
+    const dim3 grid((uint32_t)((n + per_block - 1) / per_block));
+    if (per_lane > 1)
+      launch_timed(h, kKindMicroCreate, micro_create_kernel<kLG, true>, grid, dim3(kCreateThreads), s,
+                   DevHeapW<kLG>(h->dev), type, n, per_lane, id_mul, xs, vs);
+    else
+      launch_timed(h, kKindMicroCreate, micro_create_kernel<kLG, false>, grid, dim3(kCreateThreads), s,
+                   DevHeapW<kLG>(h->dev), type, n, per_lane, id_mul, xs, vs);
   });
   DSOAR_LAUNCHED(h);
   return DSOAR_OK;
